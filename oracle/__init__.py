@@ -1,0 +1,11 @@
+"""FP64 CPU oracle for geodesic-shooting PDE-constrained LDDMM (EPDiff constraint,
+semi-Lagrangian state transport, adjoint / incremental adjoint Jacobi sweeps,
+Gauss-Newton-Krylov optimisation).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or load
+this package: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the HIP
+library and imports nothing from ``paper_1807_04638_amd``.
+"""
+
+from .lddmm_oracle import *  # noqa: F401,F403

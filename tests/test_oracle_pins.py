@@ -1,0 +1,436 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every check compares the oracle with something other than itself: closed forms
+(single Fourier modes, the v0 = 0 special case), exact identities of the
+discretisation (adjointness, antisymmetry, symmetry of the Gauss-Newton
+Hessian), library routines (scipy's periodic linear interpolation, numpy's
+roll, a dense eigen-solve) and finite differences.  ``test_planted_mistakes``
+checks that plausible implementation slips make at least one pin fail.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+import oracle as O
+from synth import phantom, random_field, random_velocity
+
+
+def P(n=(8, 8, 8), alpha=0.01, s=2, nt=10, sigma2=1.0):
+    return O.Params(tuple(n), alpha, s, nt, sigma2)
+
+
+def smooth_case(n, nt=10, alpha=0.05, amp=0.1, seed=0):
+    """Analytic smooth images, velocity and direction sampled on an n-grid."""
+    p = P(n, alpha=alpha, nt=nt)
+    x = O.grid_coords(p)
+    I0 = 0.5 + 0.3 * np.sin(x[0]) * np.cos(2 * x[1]) + 0.2 * np.cos(x[2] + x[0])
+    I1 = 0.5 + 0.3 * np.sin(x[0] + 0.2) * np.cos(2 * x[1] - 0.1) + 0.2 * np.cos(x[2] + x[0] + 0.15)
+    v0 = amp * np.stack([np.sin(x[1]), np.cos(x[2] + x[0]), np.sin(x[0] - x[1])])
+    d = np.stack([np.cos(x[2]), np.sin(x[0] + 2 * x[1]), np.cos(x[1])])
+    return p, I0, I1, v0, d
+
+
+def phantom_case(n=(12, 10, 14), nt=6, seed=0, amp=1.5):
+    p = P(n, alpha=0.01, nt=nt)
+    I0 = phantom(n, 4, (1.5, 3.0), False, 1000 + seed)
+    I1 = phantom(n, 4, (1.5, 3.0), False, 1100 + seed)
+    v0 = random_velocity(n, 2000 + seed, amp, kc=2.0)
+    return p, I0, I1, v0
+
+
+# --------------------------------------------------------------------------- P-1
+@pytest.mark.parametrize("n", [(8, 8, 8), (6, 10, 12)])
+def test_L_K_single_modes(n):
+    p = P(n, alpha=0.03, s=2)
+    x = O.grid_coords(p)
+    for k in [(0, 0, 0), (1, 0, 0), (0, 2, 0), (0, 0, 3), (1, -2, 2), (n[0] // 2, 1, n[2] // 2)]:
+        f = np.cos(k[0] * x[0] + k[1] * x[1] + k[2] * x[2] + 0.3)
+        lam = (1.0 + p.alpha * (k[0] ** 2 + k[1] ** 2 + k[2] ** 2)) ** p.s
+        np.testing.assert_allclose(O.apply_L(f, p), lam * f, rtol=0, atol=1e-12 * lam)
+        np.testing.assert_allclose(O.apply_K(f, p), f / lam, rtol=0, atol=1e-13)
+
+
+def test_L_K_inverse_random_and_power():
+    p = P((8, 6, 10), alpha=0.02, s=3)
+    f = random_field(p.n, 1, kc=3.0)
+    np.testing.assert_allclose(O.apply_K(O.apply_L(f, p), p), f, atol=1e-12)
+    # s = 1 squared equals s = 2 (integer power of the symbol)
+    p1 = P(p.n, alpha=0.02, s=1)
+    p2 = P(p.n, alpha=0.02, s=2)
+    np.testing.assert_allclose(O.apply_L(O.apply_L(f, p1), p1), O.apply_L(f, p2), atol=1e-11)
+
+
+# --------------------------------------------------------------------------- P-2
+def test_central_difference_modes():
+    p = P((8, 12, 10))
+    x = O.grid_coords(p)
+    k = (2, 3, 1)
+    phase = k[0] * x[0] + k[1] * x[1] + k[2] * x[2]
+    f = np.cos(phase)
+    for d in range(3):
+        expect = -np.sin(k[d] * p.h[d]) / p.h[d] * np.sin(phase)
+        np.testing.assert_allclose(O.ddx(f, d, p), expect, atol=1e-13)
+    # one-sided index check: delta_0 f[i] uses f[i+1] - f[i-1] in the first array axis
+    g = np.zeros(p.n)
+    g[3, 4, 5] = 1.0
+    dg = O.ddx(g, 0, p)
+    assert dg[2, 4, 5] == pytest.approx(1.0 / (2 * p.h[0]))
+    assert dg[4, 4, 5] == pytest.approx(-1.0 / (2 * p.h[0]))
+
+
+# --------------------------------------------------------------------------- P-3
+def test_ad_identities():
+    p = P((8, 6, 10))
+    v, w, mu = random_field(p.n, 1, 2.0), random_field(p.n, 2, 2.0), random_field(p.n, 3, 2.0)
+    a = O.inner(O.ad_star(v, mu, p), w, p)
+    b = O.inner(mu, O.ad(v, w, p), p)
+    assert abs(a - b) <= 1e-13 * (abs(a) + abs(b) + 1e-30) * 10
+    np.testing.assert_allclose(O.ad(v, v, p), 0.0, atol=1e-12)
+    np.testing.assert_allclose(O.ad(v, w, p), -O.ad(w, v, p), atol=1e-12)
+
+
+def test_ad_constant_velocity_closed_form():
+    p = P((8, 6, 10))
+    c = np.array([0.7, -1.3, 0.4])
+    vc = c[:, None, None, None] * np.ones((3,) + p.n)
+    w = random_field(p.n, 4, 2.0)
+    # ad_c w = -(Dw) c = -sum_d c_d delta_d w ; ad*_c mu = sum_d c_d delta_d mu
+    dir_deriv = sum(c[d] * np.stack([O.ddx(w[k], d, p) for k in range(3)]) for d in range(3))
+    np.testing.assert_allclose(O.ad(vc, w, p), -dir_deriv, atol=1e-12)
+    np.testing.assert_allclose(O.ad_star(vc, w, p), dir_deriv, atol=1e-12)
+    # ad*_w c for constant momentum c: (Dw)^T c + c div w
+    div = sum(O.ddx(w[d], d, p) for d in range(3))
+    expect = np.stack([sum(O.ddx(w[d], k, p) * c[d] for d in range(3)) + c[k] * div for k in range(3)])
+    np.testing.assert_allclose(O.ad_star(w, vc, p), expect, atol=1e-12)
+
+
+def test_ad_star_matches_printed_expanded_form_in_the_continuum():
+    """Conservative ad* equals (Dv)^T mu + D(mu) v + mu div v up to O(h^2) (product rule)."""
+    errs = []
+    for N in (16, 32):
+        p = P((N, N, N))
+        x = O.grid_coords(p)
+        v = np.stack([np.sin(x[0] + x[1]), np.cos(x[1] + x[2]), np.sin(x[2] + x[0])])
+        mu = np.stack([np.cos(x[0] + 2 * x[2]), np.sin(x[1] + x[0]), np.cos(x[2] + x[1])])
+        div = sum(O.ddx(v[d], d, p) for d in range(3))
+        expanded = np.stack([
+            sum(O.ddx(v[d], c, p) * mu[d] + O.ddx(mu[c], d, p) * v[d] for d in range(3)) + mu[c] * div
+            for c in range(3)
+        ])
+        errs.append(np.abs(O.ad_star(v, mu, p) - expanded).max())
+    assert errs[0] < 0.5 and errs[1] < errs[0] / 3.5, errs
+
+
+# --------------------------------------------------------------------------- P-4
+def test_interp_matches_scipy_grid_wrap():
+    p = P((8, 6, 10))
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal(p.n)
+    y = rng.uniform(-7.0, 14.0, size=(3, 5, 4, 3))
+    got = O.interp(f, y, p)
+    coords = np.stack([y[d] / p.h[d] for d in range(3)]).reshape(3, -1)
+    ref = ndi.map_coordinates(f, coords, order=1, mode="grid-wrap").reshape(y.shape[1:])
+    np.testing.assert_allclose(got, ref, atol=1e-13)
+
+
+def test_interp_integer_shift_is_roll():
+    p = P((8, 6, 10))
+    f = np.random.default_rng(6).standard_normal((3,) + p.n)
+    x = O.grid_coords(p)
+    shift = np.array([2, -1, 3])
+    y = x + (shift * np.array(p.h))[:, None, None, None]
+    np.testing.assert_allclose(O.interp(f, y, p), np.roll(f, tuple(-shift), axis=(1, 2, 3)), atol=1e-14)
+
+
+# --------------------------------------------------------------------------- P-5
+def test_shoot_zero_velocity_is_identity():
+    p, I0, _, _ = phantom_case()
+    tr = O.shoot(np.zeros((3,) + p.n), p, I0)
+    assert np.all(tr.v[-1] == 0.0) and np.all(tr.u == 0.0)
+    np.testing.assert_array_equal(tr.J1, I0)
+
+
+def test_shoot_constant_velocity_translates():
+    p, I0, _, _ = phantom_case(n=(8, 10, 12), nt=4)
+    shift = np.array([1, -2, 3])
+    c = shift * np.array(p.h)
+    v0 = c[:, None, None, None] * np.ones((3,) + p.n)
+    tr = O.shoot(v0, p, I0)
+    np.testing.assert_allclose(tr.v[-1], v0, atol=1e-13)
+    np.testing.assert_allclose(tr.u, -v0, atol=1e-13)
+    np.testing.assert_allclose(tr.J1, np.roll(I0, tuple(shift), axis=(0, 1, 2)), atol=1e-12)
+
+
+def test_sl_stationary_shear_exact():
+    p = P((8, 6, 10), nt=5)
+    x = O.grid_coords(p)
+    v = np.stack([np.zeros(p.n), np.zeros(p.n), 0.8 * np.sin(x[0])])
+    u = O.sl_transport([v] * (p.nt + 1), p)
+    np.testing.assert_allclose(u, -v, atol=1e-14)
+
+
+# --------------------------------------------------------------------------- P-6
+def test_dot_product_tangent_vs_backward():
+    p, I0, I1, v0 = phantom_case()
+    lin = O.linearize(v0, I0, I1, p)
+    UT = random_field(p.n, 11, 2.0)
+    dv = random_field(p.n, 12, 2.0)
+    X, _ = O.tangent(dv, lin.tr, p)
+    _, w0 = O.backward_sweep(UT, lin.tr, p)
+    a = O.inner(UT, X, p)
+    b = O.inner_V(w0, dv, p)
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+# --------------------------------------------------------------------------- P-7 / P-8
+def test_gradient_at_zero_closed_form():
+    p, I0, I1, _ = phantom_case()
+    g, _ = O.gradient(np.zeros((3,) + p.n), I0, I1, p)
+    gI0 = O.grad(I0, p)
+    expect = -(2.0 / p.sigma2) * O.apply_K((I0 - I1)[None] * gI0, p)
+    np.testing.assert_allclose(g, expect, atol=1e-13 * np.abs(expect).max() + 1e-15)
+
+
+def test_hessvec_at_zero_closed_form():
+    p, I0, I1, _ = phantom_case()
+    p.sigma2 = 0.5
+    lin = O.linearize(np.zeros((3,) + p.n), I0, I1, p)
+    dv = random_field(p.n, 13, 2.0)
+    gI0 = O.grad(I0, p)
+    expect = 2 * dv + (2.0 / p.sigma2) * O.apply_K(np.sum(gI0 * dv, axis=0)[None] * gI0, p)
+    np.testing.assert_allclose(O.hessvec(dv, lin, p), expect, atol=1e-12 * np.abs(expect).max())
+
+
+# --------------------------------------------------------------------------- P-9
+def _dense_hessian(lin, p):
+    m = 3 * int(np.prod(p.n))
+    H = np.empty((m, m))
+    e = np.zeros(m)
+    for j in range(m):
+        e[:] = 0.0
+        e[j] = 1.0
+        H[:, j] = O.hessvec(e.reshape((3,) + p.n), lin, p).ravel()
+    return H
+
+
+def _dense_L(p):
+    m = 3 * int(np.prod(p.n))
+    Lm = np.empty((m, m))
+    e = np.zeros(m)
+    for j in range(m):
+        e[:] = 0.0
+        e[j] = 1.0
+        Lm[:, j] = O.apply_L(e.reshape((3,) + p.n), p).ravel()
+    return Lm
+
+
+def test_brute_force_hessian_and_cg():
+    n = (4, 4, 6)
+    p = P(n, alpha=0.05, nt=4, sigma2=0.002)
+    I0 = phantom(n, 3, (1.0, 2.0), False, 1000)
+    I1 = phantom(n, 3, (1.0, 2.0), False, 1001)
+    v0 = random_velocity(n, 2000, 0.5, kc=1.5)
+    lin = O.linearize(v0, I0, I1, p)
+    H = _dense_hessian(lin, p)
+    Lm = _dense_L(p)
+    LH = Lm @ H
+    assert np.abs(LH - LH.T).max() <= 1e-10 * np.abs(LH).max()
+    # generalized eigenvalues of the pencil (L H, L): the V-spectrum of H is >= 2
+    Lc = np.linalg.cholesky(0.5 * (Lm + Lm.T))
+    Li = np.linalg.inv(Lc)
+    S = Li @ (0.5 * (LH + LH.T)) @ Li.T
+    ev = np.linalg.eigvalsh(S)
+    assert ev.min() >= 2.0 * (1 - 1e-10)
+    assert ev.max() > 2.5  # the data term is not negligible in this case
+    # CG in V converges to the dense solution of H x = -g
+    g, _ = O.gradient(v0, I0, I1, p, lin)
+    x_dense = np.linalg.solve(H, -g.ravel())
+    x_cg, its = O.cg_v(lambda d: O.hessvec(d, lin, p), g, p, 1e-12, 400)
+    np.testing.assert_allclose(x_cg.ravel(), x_dense, atol=1e-8 * np.abs(x_dense).max())
+
+
+def test_first_gn_step_from_zero_matches_dense_solve():
+    n = (4, 6, 4)
+    p = P(n, alpha=0.05, nt=3, sigma2=0.3)
+    I0 = phantom(n, 3, (1.0, 2.0), False, 1002)
+    I1 = phantom(n, 3, (1.0, 2.0), False, 1003)
+    zero = np.zeros((3,) + n)
+    lin = O.linearize(zero, I0, I1, p)
+    H = _dense_hessian(lin, p)
+    # closed form at v0 = 0: H = 2 I + (2/sigma2) K [(grad I0 . dv) grad I0], g from P-7
+    gI0 = O.grad(I0, p)
+    g = -(2.0 / p.sigma2) * O.apply_K((I0 - I1)[None] * gI0, p)
+    step = np.linalg.solve(H, -g.ravel()).reshape(g.shape)
+    x_cg, _ = O.cg_v(lambda d: O.hessvec(d, lin, p), g, p, 1e-13, 400)
+    np.testing.assert_allclose(x_cg, step, atol=1e-9 * np.abs(step).max())
+
+
+# --------------------------------------------------------------------------- P-10 / P-11
+def test_hessian_symmetric_and_bounded_below():
+    p, I0, I1, v0 = phantom_case(n=(10, 12, 8))
+    p.sigma2 = 0.1
+    lin = O.linearize(v0, I0, I1, p)
+    a, b = random_field(p.n, 21, 2.0), random_field(p.n, 22, 2.0)
+    Ha, Hb = O.hessvec(a, lin, p), O.hessvec(b, lin, p)
+    x1, x2 = O.inner_V(a, Hb, p), O.inner_V(Ha, b, p)
+    assert abs(x1 - x2) <= 1e-12 * max(abs(x1), abs(x2))
+    for f, Hf in ((a, Ha), (b, Hb)):
+        assert O.inner_V(f, Hf, p) >= 2.0 * O.inner_V(f, f, p) * (1 - 1e-12)
+
+
+# --------------------------------------------------------------------------- P-12
+def test_tangent_momentum_is_linearised_shooting():
+    p, I0, I1, v0 = phantom_case(n=(10, 8, 12), nt=5, amp=2.0)
+    d = random_field(p.n, 31, 2.0)
+    lin = O.linearize(v0, I0, I1, p)
+    _, dmu = O.tangent(d, lin.tr, p)
+    eps = 1e-4 * np.abs(v0).max()
+    vp = O.shoot(v0 + eps * d, p).v[-1]
+    vm = O.shoot(v0 - eps * d, p).v[-1]
+    fd = (vp - vm) / (2 * eps)
+    an = O.apply_K(dmu, p)
+    assert np.linalg.norm(an - fd) <= 1e-7 * np.linalg.norm(fd)
+
+
+# --------------------------------------------------------------------------- P-13
+def test_time_convergence_orders():
+    """Heun is second order in the state; on the quadratic invariant <mu, v> its
+    dt^2 error term cancels, so the drift falls as dt^3 (ratio ~8 per halving)."""
+    n = (16, 16, 16)
+    drifts, v1 = [], []
+    for nt in (10, 20, 40, 80):
+        p = P(n, alpha=0.01, nt=nt)
+        v0 = random_velocity(n, 2001, 3.0, kc=2.0)
+        tr = O.shoot(v0, p)
+        drifts.append(abs(tr.drift[-1]))
+        v1.append(tr.v[-1])
+    r1, r2 = drifts[0] / drifts[1], drifts[1] / drifts[2]
+    assert 6.5 <= r1 <= 10.0 and 6.5 <= r2 <= 10.0, drifts
+    e = [np.abs(v1[k] - v1[k + 1]).max() for k in range(3)]
+    assert 3.5 <= e[0] / e[1] <= 5.5 and 3.5 <= e[1] / e[2] <= 5.5, e
+
+
+# --------------------------------------------------------------------------- P-14
+def test_gradient_vs_finite_differences_converges():
+    gaps = []
+    for N in (16, 32):
+        p, I0, I1, v0, _ = smooth_case((N, N, N))
+        g, lin = O.gradient(v0, I0, I1, p)
+        # data-term part of the gradient as direction, so the check is not the quadratic E_reg
+        d = g - 2 * v0
+        d = d / math.sqrt(O.inner_V(d, d, p))
+        eps = 1e-4
+        fd = (O.energy(v0 + eps * d, I0, I1, p) - O.energy(v0 - eps * d, I0, I1, p)) / (2 * eps)
+        an = O.inner_V(g, d, p)
+        gaps.append(abs(fd - an) / abs(fd))
+    assert gaps[0] <= 5e-2 and gaps[1] <= gaps[0] / 1.7, gaps
+
+
+def test_regularisation_gradient_exact():
+    p, I0, I1, v0 = phantom_case()
+    d = random_field(p.n, 41, 2.0)
+    eps = 1e-3
+    ep = O.energy_terms(v0 + eps * d, I0, I1, p)[1]
+    em = O.energy_terms(v0 - eps * d, I0, I1, p)[1]
+    assert (ep - em) / (2 * eps) == pytest.approx(2 * O.inner_V(v0, d, p), rel=1e-10)
+
+
+# --------------------------------------------------------------------------- P-15
+def test_jacobi_incremental_image_matches_literal_transport():
+    errs = []
+    for N in (24, 48):
+        p, I0, I1, v0, d = smooth_case((N, N, N), nt=8, amp=0.2)
+        lin = O.linearize(v0, I0, I1, p)
+        a = O.incremental_image(d, lin, p)
+        b = O.incremental_image_literal(d, lin, I0, p)
+        errs.append(np.linalg.norm(a - b) / np.linalg.norm(b))
+    assert errs[0] < 0.1 and errs[1] < errs[0] / 1.7, errs
+
+
+# --------------------------------------------------------------------------- metrics
+def test_jacobian_det_closed_form_and_mse():
+    p = P((8, 6, 10))
+    x = O.grid_coords(p)
+    a = 0.3
+    u = np.stack([a * np.sin(x[0]), np.zeros(p.n), np.zeros(p.n)])
+    np.testing.assert_allclose(O.jacobian_det(u, p), 1 + a * np.cos(x[0]) * np.sin(p.h[0]) / p.h[0], atol=1e-14)
+    I0 = np.cos(x[1])
+    I1 = np.zeros(p.n)
+    assert O.mse_rel(I0, I0, I1, p) == pytest.approx(100.0)
+    assert O.mse_rel(I1, I0, I1, p) == 0.0
+
+
+def test_gn_solve_decreases_energy():
+    p, I0, _, _ = phantom_case(n=(12, 12, 12), nt=5)
+    vt = random_velocity(p.n, 2100, 1.0, kc=2.0)
+    I1 = O.shoot(vt, p, I0).J1
+    v, log, lin = O.gn_solve(I0, I1, p, gn_iters=3, cg_iters=10)
+    # accepted Armijo steps decrease E strictly; a failed line search (tau = 0) keeps v0
+    Es = [it.E for it in log] + [lin.E]
+    for k, it in enumerate(log):
+        assert (Es[k + 1] < Es[k]) if it.tau > 0 else (Es[k + 1] == Es[k]), Es
+    assert log[0].tau > 0 and Es[-1] < 0.95 * Es[0]
+    assert log[0].g_inf_rel == 1.0 and all(it.cg_iters >= 1 for it in log)
+
+
+# --------------------------------------------------------------------------- planted mistakes
+def _fails(check):
+    try:
+        check()
+    except AssertionError:
+        return True
+    return False
+
+
+def test_planted_mistakes(monkeypatch):
+    """Each plausible slip, planted in the oracle on the CPU, is caught by some pin."""
+    import oracle.lddmm_oracle as OM
+
+    def plant(name, fn):
+        monkeypatch.setattr(OM, name, fn)
+        monkeypatch.setattr(O, name, fn)
+
+    orig = {k: getattr(OM, k) for k in ("ad", "ad_star", "backward_sweep", "symbol_L", "sl_step")}
+
+    def ad_transposed(v, w, p):  # (Dv)^T w - (Dw)^T v: antisymmetric, but wrong
+        out = np.zeros_like(w)
+        for c in range(3):
+            for d in range(3):
+                out[c] += OM.ddx(v[d], c, p) * w[d] - OM.ddx(w[d], c, p) * v[d]
+        return out
+
+    def ad_star_sign(v, mu, p):  # wrong sign on the divergence part
+        out = np.zeros_like(mu)
+        for c in range(3):
+            for d in range(3):
+                out[c] += OM.ddx(v[d], c, p) * mu[d] - OM.ddx(mu[c] * v[d], d, p)
+        return out
+
+    def bw_wrong_order(U_T, tr, p):  # forward stage order instead of the transposed one
+        swapped = OM.Trajectory(tr.mu_star + [tr.mu[-1]], tr.v_star + [tr.v[-1]], tr.mu[:-1], tr.v[:-1])
+        return orig["backward_sweep"](U_T, swapped, p)
+
+    def symbol_wrong_power(p):
+        return orig["symbol_L"](p) * orig["symbol_L"](OM.Params(p.n, p.alpha, 1, p.nt))
+
+    def sl_forward_foot(u, v_old, v_new, p, x=None):  # foot point traced forward, not back
+        if x is None:
+            x = OM.grid_coords(p)
+        X = x + 0.5 * p.dt * (v_new + OM.interp(v_old, x + p.dt * v_new, p))
+        return OM.interp(u, X, p) + (X - x)
+
+    cases = [
+        ("ad", ad_transposed, [test_ad_constant_velocity_closed_form]),
+        ("ad_star", ad_star_sign, [test_ad_identities, test_dot_product_tangent_vs_backward]),
+        ("backward_sweep", bw_wrong_order, [test_dot_product_tangent_vs_backward]),
+        ("symbol_L", symbol_wrong_power, [lambda: test_L_K_single_modes((8, 8, 8))]),
+        ("sl_step", sl_forward_foot, [test_shoot_constant_velocity_translates, test_sl_stationary_shear_exact]),
+    ]
+    for name, bad, checks in cases:
+        plant(name, bad)
+        for check in checks:
+            assert _fails(check), (name, check)
+        plant(name, orig[name])
