@@ -1,0 +1,193 @@
+/*
+ * lddmm.h - C ABI of the MI355X (gfx950) library for geodesic-shooting
+ * PDE-constrained LDDMM with inexact Gauss-Newton-Krylov optimisation
+ * (M. Hernandez, arXiv 1807.04638).
+ *
+ * Problem (Section 3): minimise over the initial velocity v0
+ *     E(v0) = <L v0, v0>_{L2} + sigma^-2 || J_1 - I_1 ||^2_{L2}
+ * subject to the EPDiff equation  d_t v + ad^dagger_v v = 0,  v(0) = v0
+ * (Section 2.2) and the state equation  d_t J + grad J . v = 0,  J(0) = I_0
+ * (Section 2.3), with L = (Id - alpha Laplacian)^s and K = L^-1 (Section 2.1).
+ *
+ * Discretisation (the paper gives none): periodic box [0, 2 pi)^3 with
+ * h_d = 2 pi / N_d; L and K applied spectrally with integer wavenumbers;
+ * second-order central differences; ad*_v mu in conservative form; Heun (RK2)
+ * time stepping of the momentum mu = L v with dt = 1/nt; semi-Lagrangian
+ * transport of the inverse-map displacement u with periodic trilinear
+ * interpolation and J_1 = I_0 o (id + u_1).
+ *
+ * Layouts.  A scalar field is N0*N1*N2 contiguous elements, C order (x2 fastest).
+ * A vector field is three such scalar fields back to back (SoA [3][N0][N1][N2]).
+ * The element type is float (LDDMM_F32) or double (LDDMM_F64) as chosen at
+ * creation; inner products, energies and CG scalars are always accumulated in
+ * double.  Every field pointer is a DEVICE pointer on the device that was
+ * current when the context was created; the caller owns it and the library
+ * keeps no pointer past the call.  Pointers may not alias one another unless a
+ * function says so.
+ *
+ * Streams.  All device work of a context is ordered on the hipStream_t given
+ * at creation (NULL = the legacy default stream).  Functions that return host
+ * scalars (energies, reports) synchronise that stream before returning; the
+ * others only enqueue work.  A context is not thread-safe: use one per host
+ * thread.
+ *
+ * Errors.  Every function returns LDDMM_OK (0) or a negative LDDMM_E* code;
+ * outputs are unspecified on error.  lddmm_last_error() gives a message.
+ */
+#ifndef LDDMM_H
+#define LDDMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LDDMM_OK 0
+#define LDDMM_EINVAL (-1)       /* bad argument (NULL pointer, size, dtype)            */
+#define LDDMM_EUNSUPPORTED (-2) /* grid size with a prime factor > 7, odd N2, N_d < 4  */
+#define LDDMM_ENOMEM (-3)       /* device allocation failed                            */
+#define LDDMM_EHIP (-4)         /* a HIP runtime call failed                           */
+#define LDDMM_ENONFINITE (-5)   /* an input field holds NaN or Inf                     */
+#define LDDMM_ESTATE (-6)       /* call order (e.g. hessvec before any linearization)  */
+#define LDDMM_ELINESEARCH (-7)  /* Armijo line search found no decrease               */
+
+#define LDDMM_F32 0
+#define LDDMM_F64 1
+
+#define LDDMM_OP_K 0 /* K = (Id - alpha Laplacian)^-s */
+#define LDDMM_OP_L 1 /* L = (Id - alpha Laplacian)^s  */
+
+typedef struct lddmm_ctx lddmm_ctx;
+
+/* Model and grid.  n[d] = N_d (each a product of 2, 3, 5, 7; N2 even; N_d >= 4),
+ * nt >= 1 Heun steps on [0, 1], s >= 1 and alpha > 0 of L, sigma2 > 0 the
+ * image-noise variance of the data term (Section 3 energy).
+ * mem_budget_bytes and checkpoint_every are reserved (0). */
+typedef struct {
+  int32_t n[3];
+  int32_t nt;
+  int32_t s;
+  int32_t dtype;
+  double alpha;
+  double sigma2;
+  int64_t mem_budget_bytes;
+  int32_t checkpoint_every;
+  int32_t reserved;
+} lddmm_params;
+
+/* Inexact Gauss-Newton-Krylov settings (Section 3 update and PCG system).
+ * Zero fields take the defaults in brackets. */
+typedef struct {
+  int32_t gn_iters;     /* outer iterations [10]                                  */
+  int32_t cg_iters;     /* CG iterations per outer iteration [20]                 */
+  int32_t max_halvings; /* Armijo step halvings [10]                              */
+  int32_t reserved;
+  double c1;            /* Armijo constant [1e-4]                                 */
+  double gtol;          /* stop when ||g||_V / ||g_0||_V <= gtol [1e-3]           */
+  double eta_max;       /* forcing term eta = min(eta_max, sqrt(||g||/||g_0||)) [0.5] */
+} lddmm_solve_opts;
+
+/* One record per outer iteration, taken at the iterate before its update. */
+typedef struct {
+  double E, E_reg, E_data; /* energy and its two terms                          */
+  double mse_rel;          /* 100 ||J_1 - I_1||^2 / ||I_0 - I_1||^2 (percent)   */
+  double g_norm_V;         /* ||g||_V                                           */
+  double g_inf_rel;        /* ||g||_inf / ||g_0||_inf                           */
+  double eta;              /* CG forcing term                                   */
+  double tau;              /* accepted Armijo step (0 = line search failed)     */
+  int32_t cg_iters;        /* CG iterations (= Hessian-vector products)         */
+  int32_t ls_trials;       /* energies evaluated by the line search             */
+} lddmm_iter_log;
+
+typedef struct {
+  int32_t iters;       /* outer iterations performed                              */
+  int32_t cg_total;    /* sum of CG iterations                                    */
+  int32_t hessvecs;    /* Hessian-vector products                                 */
+  int32_t gradients;   /* gradients (each = shoot with store + backward sweep)    */
+  int32_t shoots;      /* line-search shoots without store                        */
+  int32_t stop_reason; /* 0 iteration cap, 1 gradient tolerance, 2 line search    */
+  double E_first, E_final;
+  double mse_rel_final;
+  double g_rel_final;  /* ||g||_V / ||g_0||_V at the last linearization            */
+} lddmm_solve_report;
+
+/* Create a context: validates params, allocates the workspace and the trajectory
+ * store (4 nt + 2 vector fields) on the current device, builds FFT tables.
+ * hip_stream is a hipStream_t (may be NULL). */
+int lddmm_create(const lddmm_params* params, void* hip_stream, lddmm_ctx** out);
+int lddmm_destroy(lddmm_ctx* ctx);
+
+/* Copy the template I_0 and target I_1 (device scalar fields) into the context.
+ * Invalidates any linearization.  LDDMM_ENONFINITE if either holds NaN/Inf. */
+int lddmm_set_images(lddmm_ctx* ctx, const void* I0, const void* I1);
+
+/* Spectral operator (Section 2.1): out = K in or L in for a field of ncomp
+ * components (1 or 3).  in == out is allowed. */
+int lddmm_apply_operator(lddmm_ctx* ctx, int op, int ncomp, const void* in, void* out);
+
+/* FP64 L2 inner product h0 h1 h2 sum_i sum_c a_c[i] b_c[i] over ncomp components. */
+int lddmm_dot(lddmm_ctx* ctx, int ncomp, const void* a, const void* b, double* out);
+
+/* Forward geodesic shooting (Section 3 constraints): EPDiff from v0 (vector
+ * field), transport of the displacement and J_1 = I_0 o (id + u_1).  Any of
+ * J1 (scalar), u1, v1 (vector) and energy may be NULL.  Does not store the
+ * trajectory and does not change the current linearization.  If energy is not
+ * NULL, *energy = E(v0) (needs images; synchronises). */
+int lddmm_shoot(lddmm_ctx* ctx, const void* v0, void* J1, void* u1, void* v1, double* energy);
+
+/* Shoot with trajectory store and form the final conditions at v0: residual
+ * J_1 - I_1, energy, G = grad_h J_1.  Becomes the current linearization. */
+int lddmm_linearize(lddmm_ctx* ctx, const void* v0, double* energy);
+
+/* V-gradient g = 2 v0 + w_0 (Section 3: gradient at t = 1, lambda(1) grad J_1,
+ * carried to t = 0 by the reduced adjoint Jacobi equations of Section 2.2).
+ * Linearizes at v0 first.  energy may be NULL. */
+int lddmm_gradient(lddmm_ctx* ctx, const void* v0, void* g, double* energy);
+
+/* Gauss-Newton Hessian-vector product in V (Section 3: incremental EPDiff and
+ * incremental state forward, incremental adjoint Jacobi backward):
+ * hv = 2 dv + w_0 with w from the final condition -(2/sigma2) dm_1 grad J_1,
+ * dm_1 = -grad J_1 . X_1.  v0 == NULL reuses the current linearization
+ * (LDDMM_ESTATE if there is none); otherwise linearizes at v0 first.
+ * Enqueue-only when v0 == NULL. */
+int lddmm_hessvec(lddmm_ctx* ctx, const void* v0, const void* dv, void* hv);
+
+/* Backward of J_1 w.r.t. v0 at the current linearization for a plain-array
+ * cotangent gbar = dl/dJ_1 (scalar field): gbar_v0 = L w_0 with
+ * U^(1) = -gbar grad J_1 (the quadrature weights of the pairing cancel). */
+int lddmm_vjp(lddmm_ctx* ctx, const void* gbar_J1, void* gbar_v0);
+
+/* CG in V for H x = -g at the current linearization (Section 2.3 reduced
+ * system with preconditioner K; Section 3 "CG on V"): stops when
+ * ||r||_V <= eta ||g||_V or after maxit iterations; *iters = iterations done. */
+int lddmm_cg_solve(lddmm_ctx* ctx, const void* g, void* x, double eta, int maxit, int* iters);
+
+/* Inexact Gauss-Newton-Krylov solve from v0_inout (updated in place).
+ * opts may be NULL (defaults); report and log (capacity log_cap) may be NULL. */
+int lddmm_gn_solve(lddmm_ctx* ctx, void* v0_inout, const lddmm_solve_opts* opts,
+                   lddmm_solve_report* report, lddmm_iter_log* log, int log_cap);
+
+/* Jacobian determinant det(I + D_h u) (central differences) of a displacement u
+ * (vector field) into det (scalar field), plus its extrema (either may be NULL;
+ * synchronises when requested). */
+int lddmm_jacobian_det(lddmm_ctx* ctx, const void* u, void* det, double* det_min, double* det_max);
+
+/* Per-kernel timing with HIP events recorded on the context stream.  enable=1
+ * clears and starts, 0 stops.  lddmm_profile_read fills up to cap entries of
+ * names (each a static string), launch counts and total milliseconds and
+ * returns the number of kernel kinds (synchronises). */
+int lddmm_profile_enable(lddmm_ctx* ctx, int enable);
+int lddmm_profile_read(lddmm_ctx* ctx, const char** names, int64_t* counts, double* total_ms, int cap);
+
+/* Bytes of device memory held by the context. */
+int lddmm_memory_bytes(lddmm_ctx* ctx, int64_t* bytes);
+
+const char* lddmm_strerror(int status);
+const char* lddmm_last_error(lddmm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDDMM_H */

@@ -1,0 +1,513 @@
+// fft.hip - spectral application of L = (Id - alpha Laplacian)^s and K = L^-1
+// (Section 2.1 of the paper) on the periodic grid, with integer wavenumbers.
+//
+// Per component: real 3D FFT -> multiply by (1 + alpha |k|^2)^(+-s) / N -> inverse.
+// Spectrum layout (per component): [x0 or k0 slot][k1 slot][k2 slot], M = N2/2 + 1
+// columns; slots are digit-reversed positions of the DIF outputs (the symbol
+// only needs |k|^2 of each slot, so the spectrum is never reordered).
+//
+// x2 (contiguous) real transform: the N2 reals of a row are read as N2/2
+// complex pairs, transformed with length H = N2/2, and split into the H + 1
+// non-negative frequencies (the even/odd half-length method); the inverse
+// recombines them before a length-H inverse transform.
+//
+// Fused path (the (x1, x2) half-plane fits one workgroup's LDS):
+//   pass 1  plane: rows (x2, real) + columns (x1)     real field  -> spectrum
+//   pass 2  pencil: x0 forward, symbol, x0 inverse    spectrum in place
+//   pass 3  plane: columns (x1) inverse + rows (x2)   spectrum    -> real field
+// Split path: rows, x1 pencils, x0 pencils with symbol, x1 pencils, rows.
+#include <cmath>
+#include <cstring>
+
+#include "lddmm.h"
+#include "lddmm_internal.h"
+
+namespace lddmm {
+
+// --------------------------------------------------------------------------
+// LDS drivers
+// --------------------------------------------------------------------------
+#define LDDMM_FFT_STAGE(R)                                                             \
+  case R:                                                                              \
+    for (int b = tid; b < total; b += nthr)                                            \
+      fft_stage_item<T, R, INV, SEQ_FAST>(buf, b, n, L, count, es, ss, tw);            \
+    break;
+
+// Full transform (all stages) of `count` sequences held in LDS.  Ends with a
+// barrier.  Forward = DIF (natural -> digit-reversed), inverse = DIT.
+template <typename T, bool INV, bool SEQ_FAST>
+__device__ void lds_fft(cplx<T>* buf, const FftPlan& pl, int count, int es, int ss, const cplx<T>* tw) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int n = pl.n;
+  for (int i = 0; i < pl.nf; ++i) {
+    const int st = INV ? pl.nf - 1 - i : i;
+    const int r = pl.radix[st];
+    const int L = stage_length(pl, st);
+    const int total = count * (n / r);
+    switch (r) {
+      LDDMM_FFT_STAGE(8)
+      LDDMM_FFT_STAGE(4)
+      LDDMM_FFT_STAGE(2)
+      LDDMM_FFT_STAGE(3)
+      LDDMM_FFT_STAGE(5)
+      LDDMM_FFT_STAGE(7)
+      default:
+        break;
+    }
+    __syncthreads();
+  }
+}
+
+// Rows of H complex pairs at A[r * M + j]: forward transform then split into the
+// N2/2 + 1 real-signal frequencies X[k]; X[k] lands in column slot2[k].
+template <typename T>
+__device__ void rows_r2c(cplx<T>* A, int count, int H, int M, const FftPlan& p2, const cplx<T>* tw2,
+                         const cplx<T>* twr, const int* slot2) {
+  lds_fft<T, false, false>(A, p2, count, 1, M, tw2);
+  const int per = H / 2 + 1;
+  for (int idx = threadIdx.x; idx < count * per; idx += blockDim.x) {
+    const int r = idx / per, k = idx - r * per;
+    cplx<T>* row = A + r * M;
+    if (k == 0) {
+      const cplx<T> z = row[0];
+      row[0] = {z.x + z.y, T(0)};
+      row[H] = {z.x - z.y, T(0)};
+    } else {
+      const int sk = slot2[k], sm = slot2[H - k];
+      const cplx<T> a = row[sk], b = row[sm];
+      // even part e = (a + conj b) / 2, odd part o = (a - conj b) / 2
+      const cplx<T> e = {T(0.5) * (a.x + b.x), T(0.5) * (a.y - b.y)};
+      const cplx<T> o = {T(0.5) * (a.x - b.x), T(0.5) * (a.y + b.y)};
+      const cplx<T> wo = c_mul(twr[k], o);
+      // X[k] = e - i w o ;  X[H-k] = conj(e) - i conj(w o)
+      row[sk] = {e.x + wo.y, e.y - wo.x};
+      if (sm != sk) row[sm] = {e.x - wo.y, -e.y - wo.x};
+    }
+  }
+  __syncthreads();
+}
+
+// Inverse of rows_r2c (times N2): recombine X[k], X[H-k] into the half-length
+// spectrum and run the inverse transform; row r then holds pairs (x[2j], x[2j+1]).
+template <typename T>
+__device__ void rows_c2r(cplx<T>* A, int count, int H, int M, const FftPlan& p2, const cplx<T>* tw2,
+                         const cplx<T>* twr, const int* slot2) {
+  const int per = H / 2 + 1;
+  for (int idx = threadIdx.x; idx < count * per; idx += blockDim.x) {
+    const int r = idx / per, k = idx - r * per;
+    cplx<T>* row = A + r * M;
+    if (k == 0) {
+      const cplx<T> a = row[0], b = row[H];
+      const cplx<T> p = {a.x + b.x, a.y - b.y};
+      const cplx<T> q = {a.x - b.x, a.y + b.y};
+      row[0] = {p.x - q.y, p.y + q.x};
+    } else {
+      const int sk = slot2[k], sm = slot2[H - k];
+      const cplx<T> a = row[sk], b = row[sm];
+      const cplx<T> p = {a.x + b.x, a.y - b.y};  // X[k] + conj X[H-k]
+      const cplx<T> q = {a.x - b.x, a.y + b.y};  // X[k] - conj X[H-k]
+      const cplx<T> t = c_mulc(q, twr[k]);       // conj(w) q
+      row[sk] = {p.x - t.y, p.y + t.x};          // p + i t
+      if (sm != sk) row[sm] = {p.x + t.y, -p.y + t.x};  // conj(p) + i conj(t)
+    }
+  }
+  __syncthreads();
+  lds_fft<T, true, false>(A, p2, count, 1, M, tw2);
+}
+
+template <typename T>
+__device__ void load_table(cplx<T>* dst, const cplx<T>* src, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// --------------------------------------------------------------------------
+// Kernels
+// --------------------------------------------------------------------------
+template <typename T>
+struct PlaneArgs {
+  int n0, n1, n2, H, M;
+  long long N;
+  FftPlan p1, p2;
+  const cplx<T>* tw1;
+  const cplx<T>* tw2;
+  const cplx<T>* twr;
+  const int* slot2;
+};
+
+// LDS carve-up shared by the plane and row kernels: A | tw1 | tw2 | twr | slot2
+template <typename T>
+struct PlaneLds {
+  cplx<T>* A;
+  cplx<T>* tw1;
+  cplx<T>* tw2;
+  cplx<T>* twr;
+  int* slot2;
+};
+
+template <typename T>
+__device__ PlaneLds<T> carve(unsigned char* smem, int rows, const PlaneArgs<T>& a, bool with_tw1) {
+  PlaneLds<T> L;
+  L.A = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* p = L.A + rows * a.M;
+  L.tw1 = p;
+  if (with_tw1) p += a.n1;
+  L.tw2 = p;
+  p += a.H;
+  L.twr = p;
+  p += a.H / 2 + 1;
+  L.slot2 = reinterpret_cast<int*>(p);
+  if (with_tw1) load_table(L.tw1, a.tw1, a.n1);
+  load_table(L.tw2, a.tw2, a.H);
+  load_table(L.twr, a.twr, a.H / 2 + 1);
+  for (int i = threadIdx.x; i <= a.H; i += blockDim.x) L.slot2[i] = a.slot2[i];
+  return L;
+}
+
+// One (x0, component) plane: real rows -> x2 spectrum -> x1 columns.
+template <typename T>
+__global__ void __launch_bounds__(512) k_plane_fwd(const T* __restrict__ in, cplx<T>* __restrict__ spec,
+                                                   PlaneArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int x0 = blockIdx.x, comp = blockIdx.y;
+  PlaneLds<T> L = carve(smem, a.n1, a, true);
+  const cplx<T>* src = reinterpret_cast<const cplx<T>*>(in + comp * a.N + (long long)x0 * a.n1 * a.n2);
+  const int tot = a.n1 * a.H;
+  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+    const int j1 = idx / a.H;
+    L.A[j1 * a.M + (idx - j1 * a.H)] = src[idx];
+  }
+  __syncthreads();
+  rows_r2c(L.A, a.n1, a.H, a.M, a.p2, L.tw2, L.twr, L.slot2);
+  lds_fft<T, false, true>(L.A, a.p1, a.M, a.M, 1, L.tw1);
+  cplx<T>* dst = spec + ((long long)comp * a.n0 + x0) * a.n1 * a.M;
+  const int tot2 = a.n1 * a.M;
+  for (int idx = threadIdx.x; idx < tot2; idx += blockDim.x) dst[idx] = L.A[idx];
+}
+
+// One (x0, component) plane: x1 columns inverse -> x2 rows inverse -> real rows.
+template <typename T>
+__global__ void __launch_bounds__(512) k_plane_inv(const cplx<T>* __restrict__ spec, T* __restrict__ out,
+                                                   PlaneArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int x0 = blockIdx.x, comp = blockIdx.y;
+  PlaneLds<T> L = carve(smem, a.n1, a, true);
+  const cplx<T>* src = spec + ((long long)comp * a.n0 + x0) * a.n1 * a.M;
+  const int tot2 = a.n1 * a.M;
+  for (int idx = threadIdx.x; idx < tot2; idx += blockDim.x) L.A[idx] = src[idx];
+  __syncthreads();
+  lds_fft<T, true, true>(L.A, a.p1, a.M, a.M, 1, L.tw1);
+  rows_c2r(L.A, a.n1, a.H, a.M, a.p2, L.tw2, L.twr, L.slot2);
+  cplx<T>* dst = reinterpret_cast<cplx<T>*>(out + comp * a.N + (long long)x0 * a.n1 * a.n2);
+  const int tot = a.n1 * a.H;
+  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+    const int j1 = idx / a.H;
+    dst[idx] = L.A[j1 * a.M + (idx - j1 * a.H)];
+  }
+}
+
+// Split path: `rb` consecutive rows (flat x0 * n1 + x1) per workgroup.
+template <typename T>
+__global__ void __launch_bounds__(256) k_rows_fwd(const T* __restrict__ in, cplx<T>* __restrict__ spec,
+                                                  PlaneArgs<T> a, int rb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int comp = blockIdx.y;
+  const long long rows = (long long)a.n0 * a.n1;
+  const long long r0 = (long long)blockIdx.x * rb;
+  const int cnt = (int)((rows - r0) < rb ? (rows - r0) : rb);
+  PlaneLds<T> L = carve(smem, rb, a, false);
+  const cplx<T>* src = reinterpret_cast<const cplx<T>*>(in + comp * a.N) + r0 * a.H;
+  for (int idx = threadIdx.x; idx < cnt * a.H; idx += blockDim.x) {
+    const int r = idx / a.H;
+    L.A[r * a.M + (idx - r * a.H)] = src[idx];
+  }
+  __syncthreads();
+  rows_r2c(L.A, cnt, a.H, a.M, a.p2, L.tw2, L.twr, L.slot2);
+  cplx<T>* dst = spec + ((long long)comp * rows + r0) * a.M;
+  for (int idx = threadIdx.x; idx < cnt * a.M; idx += blockDim.x) dst[idx] = L.A[idx];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_rows_inv(const cplx<T>* __restrict__ spec, T* __restrict__ out,
+                                                  PlaneArgs<T> a, int rb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int comp = blockIdx.y;
+  const long long rows = (long long)a.n0 * a.n1;
+  const long long r0 = (long long)blockIdx.x * rb;
+  const int cnt = (int)((rows - r0) < rb ? (rows - r0) : rb);
+  PlaneLds<T> L = carve(smem, rb, a, false);
+  const cplx<T>* src = spec + ((long long)comp * rows + r0) * a.M;
+  for (int idx = threadIdx.x; idx < cnt * a.M; idx += blockDim.x) L.A[idx] = src[idx];
+  __syncthreads();
+  rows_c2r(L.A, cnt, a.H, a.M, a.p2, L.tw2, L.twr, L.slot2);
+  cplx<T>* dst = reinterpret_cast<cplx<T>*>(out + comp * a.N) + r0 * a.H;
+  for (int idx = threadIdx.x; idx < cnt * a.H; idx += blockDim.x) {
+    const int r = idx / a.H;
+    dst[idx] = L.A[r * a.M + (idx - r * a.H)];
+  }
+}
+
+template <typename T>
+struct PencilArgs {
+  FftPlan pl;              // transform along the pencil
+  int es;                  // element stride (complex units)
+  int nin;                 // sequences per outer index (contiguous)
+  long long outer_stride;  // complex units between outer indices
+  int tb;                  // sequences per workgroup
+  const cplx<T>* tw;
+  // symbol (MODE 2, x0 pencils): slot q = k1slot * M + k2slot
+  int M;
+  T alpha;
+  int s;
+  int op;
+  T scale;
+  const T* ksq0;
+  const T* ksq1;
+  const T* ksq2;
+};
+
+// MODE 0: forward only, 1: inverse only, 2: forward, symbol, inverse.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_pencil(cplx<T>* __restrict__ spec, PencilArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = a.pl.n, tb = a.tb;
+  cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* tw = A + n * tb;
+  T* ksq0 = reinterpret_cast<T*>(tw + n);
+  load_table(tw, a.tw, n);
+  if (MODE == 2)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) ksq0[i] = a.ksq0[i];
+  const int q0 = blockIdx.x * tb;
+  const int cnt = (a.nin - q0) < tb ? (a.nin - q0) : tb;
+  cplx<T>* base = spec + blockIdx.y * a.outer_stride + q0;
+  for (int idx = threadIdx.x; idx < n * tb; idx += blockDim.x) {
+    const int j = idx / tb, t = idx - j * tb;
+    A[idx] = t < cnt ? base[(long long)j * a.es + t] : cplx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  if (MODE != 1) lds_fft<T, false, true>(A, a.pl, tb, tb, 1, tw);
+  if (MODE == 2) {
+    for (int idx = threadIdx.x; idx < n * tb; idx += blockDim.x) {
+      const int j = idx / tb, t = idx - j * tb;
+      if (t < cnt) {
+        const int q = q0 + t;
+        const int s1 = q / a.M, s2 = q - s1 * a.M;
+        const T base_sym = T(1) + a.alpha * (ksq0[j] + a.ksq1[s1] + a.ksq2[s2]);
+        T pw = base_sym;
+        for (int i = 1; i < a.s; ++i) pw *= base_sym;
+        const T f = a.op == LDDMM_OP_K ? a.scale / pw : a.scale * pw;
+        A[idx] = c_scale(A[idx], f);
+      }
+    }
+    __syncthreads();
+  }
+  if (MODE != 0) lds_fft<T, true, true>(A, a.pl, tb, tb, 1, tw);
+  for (int idx = threadIdx.x; idx < n * tb; idx += blockDim.x) {
+    const int j = idx / tb, t = idx - j * tb;
+    if (t < cnt) base[(long long)j * a.es + t] = A[idx];
+  }
+}
+
+// --------------------------------------------------------------------------
+// Host side
+// --------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+std::vector<cplx<T>> twiddles(int n, int count) {
+  std::vector<cplx<T>> t(count);
+  for (int m = 0; m < count; ++m) {
+    const double ang = -2.0 * M_PI * double(m) / double(n);
+    t[m] = {T(std::cos(ang)), T(std::sin(ang))};
+  }
+  return t;
+}
+
+template <typename V>
+int upload(V** dst, const std::vector<V>& src, size_t& bytes) {
+  const size_t b = src.size() * sizeof(V);
+  if (hipMalloc(reinterpret_cast<void**>(dst), b) != hipSuccess) return LDDMM_ENOMEM;
+  bytes += b;
+  return hipMemcpy(*dst, src.data(), b, hipMemcpyHostToDevice) == hipSuccess ? 0 : LDDMM_EHIP;
+}
+
+int fold_sq(int k, int n) {
+  const int a = k <= n - k ? k : n - k;
+  return a * a;
+}
+
+}  // namespace
+
+template <typename T>
+int spectral_init(SpectralPlan<T>& sp, const int n[3], size_t max_lds, std::string& err) {
+  sp = SpectralPlan<T>();
+  sp.n0 = n[0];
+  sp.n1 = n[1];
+  sp.n2 = n[2];
+  if (n[0] < 4 || n[1] < 4 || n[2] < 4 || (n[2] & 1)) {
+    err = "grid sizes must be >= 4 and N2 even";
+    return LDDMM_EUNSUPPORTED;
+  }
+  sp.H = n[2] / 2;
+  sp.M = sp.H + 1;
+  if (!make_plan(n[0], sp.p0) || !make_plan(n[1], sp.p1) || !make_plan(sp.H, sp.p2)) {
+    err = "grid sizes N0, N1 and N2/2 must factor into 2, 3, 5, 7";
+    return LDDMM_EUNSUPPORTED;
+  }
+  const int H = sp.H, M = sp.M;
+  int rc = 0;
+  size_t& by = sp.bytes;
+  if ((rc = upload(&sp.tw0, twiddles<T>(n[0], n[0]), by))) return rc;
+  if ((rc = upload(&sp.tw1, twiddles<T>(n[1], n[1]), by))) return rc;
+  if ((rc = upload(&sp.tw2, twiddles<T>(H, H), by))) return rc;
+  if ((rc = upload(&sp.twr, twiddles<T>(n[2], H / 2 + 1), by))) return rc;
+  std::vector<int> slot(H + 1);
+  for (int p = 0; p < H; ++p) slot[digit_reverse(sp.p2, p)] = p;
+  slot[H] = H;
+  if ((rc = upload(&sp.slot2, slot, by))) return rc;
+  std::vector<T> k0(n[0]), k1(n[1]), k2(M);
+  for (int p = 0; p < n[0]; ++p) k0[p] = T(fold_sq(digit_reverse(sp.p0, p), n[0]));
+  for (int p = 0; p < n[1]; ++p) k1[p] = T(fold_sq(digit_reverse(sp.p1, p), n[1]));
+  for (int p = 0; p < H; ++p) {
+    const int k = digit_reverse(sp.p2, p);
+    k2[p] = T(k * k);
+  }
+  k2[H] = T(H * H);
+  if ((rc = upload(&sp.ksq0, k0, by))) return rc;
+  if ((rc = upload(&sp.ksq1, k1, by))) return rc;
+  if ((rc = upload(&sp.ksq2, k2, by))) return rc;
+  const size_t cb = sizeof(cplx<T>);
+  const size_t spec_bytes = size_t(3) * n[0] * n[1] * M * cb;
+  if (hipMalloc(reinterpret_cast<void**>(&sp.spec), spec_bytes) != hipSuccess) {
+    err = "out of device memory (spectrum workspace)";
+    return LDDMM_ENOMEM;
+  }
+  by += spec_bytes;
+
+  const size_t tables = size_t(H + H / 2 + 1) * cb + size_t(H + 1) * sizeof(int);
+  sp.plane_lds = size_t(n[1]) * M * cb + size_t(n[1]) * cb + tables;
+  sp.fused = sp.plane_lds <= max_lds;
+  // pencils: 256-byte rows of tb complex values
+  int tb = int(256 / cb);
+  while (tb > 1 && (size_t(n[0]) * tb + n[0]) * cb + n[0] * sizeof(T) > max_lds) tb /= 2;
+  while (tb > 1 && !sp.fused && (size_t(n[1]) * tb + n[1]) * cb > max_lds) tb /= 2;
+  sp.pencil_tb = tb;
+  sp.pencil0_lds = (size_t(n[0]) * tb + n[0]) * cb + n[0] * sizeof(T);
+  sp.pencil1_lds = (size_t(n[1]) * tb + n[1]) * cb;
+  int rb = 16;
+  while (rb > 1 && size_t(rb) * M * cb + tables > max_lds) rb /= 2;
+  sp.rows_rb = rb;
+  sp.rows_lds = size_t(rb) * M * cb + tables;
+  if (sp.pencil0_lds > max_lds || sp.rows_lds > max_lds || (!sp.fused && sp.pencil1_lds > max_lds)) {
+    err = "grid too large for the LDS-staged transforms";
+    return LDDMM_EUNSUPPORTED;
+  }
+  const void* fns[] = {(const void*)k_plane_fwd<T>,  (const void*)k_plane_inv<T>, (const void*)k_rows_fwd<T>,
+                       (const void*)k_rows_inv<T>,   (const void*)k_pencil<T, 0>, (const void*)k_pencil<T, 1>,
+                       (const void*)k_pencil<T, 2>};
+  for (const void* f : fns)
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(max_lds)) != hipSuccess) {
+      err = "hipFuncSetAttribute(MaxDynamicSharedMemorySize) failed";
+      return LDDMM_EHIP;
+    }
+  return 0;
+}
+
+template <typename T>
+void spectral_free(SpectralPlan<T>& sp) {
+  void* ptrs[] = {sp.tw0, sp.tw1, sp.tw2, sp.twr, sp.slot2, sp.ksq0, sp.ksq1, sp.ksq2, sp.spec};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  sp = SpectralPlan<T>();
+}
+
+template <typename T>
+void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, double alpha, int s, int op,
+                    hipStream_t st, Profiler* prof) {
+  PlaneArgs<T> pa;
+  pa.n0 = sp.n0;
+  pa.n1 = sp.n1;
+  pa.n2 = sp.n2;
+  pa.H = sp.H;
+  pa.M = sp.M;
+  pa.N = (long long)sp.n0 * sp.n1 * sp.n2;
+  pa.p1 = sp.p1;
+  pa.p2 = sp.p2;
+  pa.tw1 = sp.tw1;
+  pa.tw2 = sp.tw2;
+  pa.twr = sp.twr;
+  pa.slot2 = sp.slot2;
+
+  const int P = sp.n1 * sp.M;
+  PencilArgs<T> k0;
+  k0.pl = sp.p0;
+  k0.es = P;
+  k0.nin = P;
+  k0.outer_stride = (long long)sp.n0 * P;
+  k0.tb = sp.pencil_tb;
+  k0.tw = sp.tw0;
+  k0.M = sp.M;
+  k0.alpha = T(alpha);
+  k0.s = s;
+  k0.op = op;
+  k0.scale = T(1.0 / (double(sp.n0) * sp.n1 * sp.n2));
+  k0.ksq0 = sp.ksq0;
+  k0.ksq1 = sp.ksq1;
+  k0.ksq2 = sp.ksq2;
+  const dim3 g0((P + sp.pencil_tb - 1) / sp.pencil_tb, ncomp);
+
+  if (sp.fused) {
+    {
+      KernelTimer t(prof, "fft_plane_fwd", st);
+      k_plane_fwd<T><<<dim3(sp.n0, ncomp), 512, sp.plane_lds, st>>>(in, sp.spec, pa);
+    }
+    {
+      KernelTimer t(prof, "fft_pencil_symbol", st);
+      k_pencil<T, 2><<<g0, 256, sp.pencil0_lds, st>>>(sp.spec, k0);
+    }
+    {
+      KernelTimer t(prof, "fft_plane_inv", st);
+      k_plane_inv<T><<<dim3(sp.n0, ncomp), 512, sp.plane_lds, st>>>(sp.spec, out, pa);
+    }
+    return;
+  }
+  PencilArgs<T> k1 = k0;
+  k1.pl = sp.p1;
+  k1.es = sp.M;
+  k1.nin = sp.M;
+  k1.outer_stride = (long long)sp.n1 * sp.M;
+  k1.tw = sp.tw1;
+  const dim3 g1((sp.M + sp.pencil_tb - 1) / sp.pencil_tb, ncomp * sp.n0);
+  const long long rows = (long long)sp.n0 * sp.n1;
+  const dim3 gr((unsigned)((rows + sp.rows_rb - 1) / sp.rows_rb), ncomp);
+  {
+    KernelTimer t(prof, "fft_rows_fwd", st);
+    k_rows_fwd<T><<<gr, 256, sp.rows_lds, st>>>(in, sp.spec, pa, sp.rows_rb);
+  }
+  {
+    KernelTimer t(prof, "fft_pencil_x1_fwd", st);
+    k_pencil<T, 0><<<g1, 256, sp.pencil1_lds, st>>>(sp.spec, k1);
+  }
+  {
+    KernelTimer t(prof, "fft_pencil_symbol", st);
+    k_pencil<T, 2><<<g0, 256, sp.pencil0_lds, st>>>(sp.spec, k0);
+  }
+  {
+    KernelTimer t(prof, "fft_pencil_x1_inv", st);
+    k_pencil<T, 1><<<g1, 256, sp.pencil1_lds, st>>>(sp.spec, k1);
+  }
+  {
+    KernelTimer t(prof, "fft_rows_inv", st);
+    k_rows_inv<T><<<gr, 256, sp.rows_lds, st>>>(sp.spec, out, pa, sp.rows_rb);
+  }
+}
+
+template int spectral_init<float>(SpectralPlan<float>&, const int[3], size_t, std::string&);
+template int spectral_init<double>(SpectralPlan<double>&, const int[3], size_t, std::string&);
+template void spectral_free<float>(SpectralPlan<float>&);
+template void spectral_free<double>(SpectralPlan<double>&);
+template void spectral_apply<float>(const SpectralPlan<float>&, const float*, float*, int, double, int, int,
+                                    hipStream_t, Profiler*);
+template void spectral_apply<double>(const SpectralPlan<double>&, const double*, double*, int, double, int, int,
+                                     hipStream_t, Profiler*);
+
+}  // namespace lddmm

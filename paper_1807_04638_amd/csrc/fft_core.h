@@ -1,0 +1,259 @@
+// fft_core.h - mixed-radix in-place FFT building blocks (radix 2, 3, 4, 5, 7, 8).
+//
+// The spectral operators L = (Id - alpha Laplacian)^s and K = L^-1 (Section 2.1
+// of the paper) are applied as forward FFT -> real symbol -> inverse FFT.  Since
+// the symbol is pointwise, the spectrum never has to be in natural order:
+//   forward  = decimation-in-frequency (Gentleman-Sande), natural input ->
+//              digit-reversed output, twiddle after each butterfly;
+//   inverse  = decimation-in-time (Cooley-Tukey), digit-reversed input ->
+//              natural output, conjugate twiddle before each butterfly.
+// Each stage updates its butterflies' elements in place (every element belongs
+// to exactly one butterfly per stage), so a stage needs no staging copy, no
+// register-resident sweep and only one barrier.
+//
+// All functions are __host__ __device__: kernels run them on LDS with one
+// butterfly per thread, and a host program can run the very same stage code
+// sequentially (a stage has no intra-stage hazards).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace lddmm {
+
+#define LD_HD __host__ __device__ __forceinline__
+
+template <typename T>
+struct cplx {
+  T x, y;
+};
+
+template <typename T>
+LD_HD cplx<T> c_add(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+LD_HD cplx<T> c_sub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+LD_HD cplx<T> c_mul(cplx<T> a, cplx<T> b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+// a * conj(b)
+template <typename T>
+LD_HD cplx<T> c_mulc(cplx<T> a, cplx<T> b) { return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }
+template <typename T>
+LD_HD cplx<T> c_conj(cplx<T> a) { return {a.x, -a.y}; }
+template <typename T>
+LD_HD cplx<T> c_scale(cplx<T> a, T s) { return {a.x * s, a.y * s}; }
+// a * (DIR i): DIR = +1 multiplies by i, DIR = -1 by -i.
+template <int DIR, typename T>
+LD_HD cplx<T> c_mul_i(cplx<T> a) {
+  return DIR > 0 ? cplx<T>{-a.y, a.x} : cplx<T>{a.y, -a.x};
+}
+
+constexpr int kMaxFactors = 16;
+
+// Factorisation of one transform length; radix[s] is used by DIF stage s.
+struct FftPlan {
+  int n;
+  int nf;
+  int radix[kMaxFactors];
+};
+
+// cos / sin of 2 pi m / R for the odd radices (m in [0, R)).
+LD_HD constexpr double root_cos(int R, int m) {
+  return R == 3 ? (m == 0 ? 1.0 : -0.5)
+       : R == 5 ? (m == 0 ? 1.0 : (m == 1 || m == 4) ? 0.30901699437494742410 : -0.80901699437494742410)
+       : (m == 0 ? 1.0
+          : (m == 1 || m == 6) ? 0.62348980185873353053
+          : (m == 2 || m == 5) ? -0.22252093395631440429
+                               : -0.90096886790241912624);
+}
+LD_HD constexpr double root_sin(int R, int m) {
+  return R == 3 ? (m == 0 ? 0.0 : m == 1 ? 0.86602540378443864676 : -0.86602540378443864676)
+       : R == 5 ? (m == 0 ? 0.0
+                   : m == 1 ? 0.95105651629515357212
+                   : m == 2 ? 0.58778525229247312917
+                   : m == 3 ? -0.58778525229247312917
+                            : -0.95105651629515357212)
+       : (m == 0 ? 0.0
+          : m == 1 ? 0.78183148246802980871
+          : m == 2 ? 0.97492791218182360702
+          : m == 3 ? 0.43388373911755812048
+          : m == 4 ? -0.43388373911755812048
+          : m == 5 ? -0.97492791218182360702
+                   : -0.78183148246802980871);
+}
+
+// In-register DFT of size R with kernel exp(DIR 2 pi i j k / R).
+template <typename T, int R, int DIR>
+struct Dft {
+  // odd radix: pair j with R - j
+  static LD_HD void run(cplx<T>* a) {
+    constexpr int H = (R - 1) / 2;
+    cplx<T> b[H + 1], d[H + 1];
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+      b[j] = c_add(a[j], a[R - j]);
+      d[j] = c_sub(a[j], a[R - j]);
+    }
+    cplx<T> y0 = a[0];
+#pragma unroll
+    for (int j = 1; j <= H; ++j) y0 = c_add(y0, b[j]);
+    cplx<T> out[R];
+    out[0] = y0;
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+      cplx<T> A = a[0], B = {T(0), T(0)};
+#pragma unroll
+      for (int j = 1; j <= H; ++j) {
+        const int m = (j * k) % R;
+        const T cc = T(root_cos(R, m));
+        const T ss = T(root_sin(R, m));
+        A = c_add(A, c_scale(b[j], cc));
+        B = c_add(B, c_scale(d[j], ss));
+      }
+      const cplx<T> iB = c_mul_i<DIR>(B);
+      out[k] = c_add(A, iB);
+      out[R - k] = c_sub(A, iB);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) a[k] = out[k];
+  }
+};
+
+template <typename T, int DIR>
+struct Dft<T, 2, DIR> {
+  static LD_HD void run(cplx<T>* a) {
+    const cplx<T> t = a[0];
+    a[0] = c_add(t, a[1]);
+    a[1] = c_sub(t, a[1]);
+  }
+};
+
+template <typename T, int DIR>
+struct Dft<T, 4, DIR> {
+  static LD_HD void run(cplx<T>* a) {
+    const cplx<T> t0 = c_add(a[0], a[2]);
+    const cplx<T> t1 = c_sub(a[0], a[2]);
+    const cplx<T> t2 = c_add(a[1], a[3]);
+    const cplx<T> t3 = c_mul_i<DIR>(c_sub(a[1], a[3]));
+    a[0] = c_add(t0, t2);
+    a[2] = c_sub(t0, t2);
+    a[1] = c_add(t1, t3);
+    a[3] = c_sub(t1, t3);
+  }
+};
+
+template <typename T, int DIR>
+struct Dft<T, 8, DIR> {
+  // 8 = 2 x 4: radix-2 split of (a_j, a_{j+4}), twiddles W8^j, two DFT4s.
+  static LD_HD void run(cplx<T>* a) {
+    constexpr T r = T(0.70710678118654752440);
+    cplx<T> b[4], c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      b[j] = c_add(a[j], a[j + 4]);
+      c[j] = c_sub(a[j], a[j + 4]);
+    }
+    // c1 *= (r, DIR r), c2 *= DIR i, c3 *= (-r, DIR r)
+    c[1] = cplx<T>{r * (c[1].x - T(DIR) * c[1].y), r * (c[1].y + T(DIR) * c[1].x)};
+    c[2] = c_mul_i<DIR>(c[2]);
+    c[3] = cplx<T>{-r * (c[3].x + T(DIR) * c[3].y), r * (T(DIR) * c[3].x - c[3].y)};
+    Dft<T, 4, DIR>::run(b);
+    Dft<T, 4, DIR>::run(c);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[2 * k] = b[k];
+      a[2 * k + 1] = c[k];
+    }
+  }
+};
+
+// One butterfly of DIF stage with sub-length L = R * stride.  Elements at
+// base + t * step (t < R); j = position inside the sub-block; tw[m] =
+// exp(-2 pi i m / n); twstep = n / L.
+template <typename T, int R>
+LD_HD void dif_butterfly(cplx<T>* buf, int base, int step, int j, int twstep, const cplx<T>* tw) {
+  cplx<T> a[R];
+#pragma unroll
+  for (int t = 0; t < R; ++t) a[t] = buf[base + t * step];
+  Dft<T, R, -1>::run(a);
+  buf[base] = a[0];
+#pragma unroll
+  for (int q = 1; q < R; ++q) buf[base + q * step] = c_mul(a[q], tw[j * q * twstep]);
+}
+
+// Inverse of dif_butterfly up to the factor R (conjugate twiddle, then DFT).
+template <typename T, int R>
+LD_HD void dit_butterfly(cplx<T>* buf, int base, int step, int j, int twstep, const cplx<T>* tw) {
+  cplx<T> a[R];
+  a[0] = buf[base];
+#pragma unroll
+  for (int q = 1; q < R; ++q) a[q] = c_mulc(buf[base + q * step], tw[j * q * twstep]);
+  Dft<T, R, +1>::run(a);
+#pragma unroll
+  for (int t = 0; t < R; ++t) buf[base + t * step] = a[t];
+}
+
+// All butterflies of one stage over `count` sequences of length n; element e of
+// sequence s sits at buf[s * ss + e * es].  Butterfly b of the stage is handled
+// by the caller's index `b` in [0, count * n / R).  SEQ_FAST maps consecutive b
+// to consecutive sequences (use when sequences are contiguous, es > 1);
+// otherwise to consecutive butterflies of one sequence (es == 1).
+template <typename T, int R, bool INV, bool SEQ_FAST>
+LD_HD void fft_stage_item(cplx<T>* buf, int b, int n, int L, int count, int es, int ss, const cplx<T>* tw) {
+  const int stride = L / R;
+  const int nbf = n / R;
+  int s, u;
+  if (SEQ_FAST) {
+    u = b / count;
+    s = b - u * count;
+  } else {
+    s = b / nbf;
+    u = b - s * nbf;
+  }
+  const int blk = u / stride;
+  const int j = u - blk * stride;
+  const int base = s * ss + (blk * L + j) * es;
+  if (INV)
+    dit_butterfly<T, R>(buf, base, stride * es, j, n / L, tw);
+  else
+    dif_butterfly<T, R>(buf, base, stride * es, j, n / L, tw);
+}
+
+// Sub-length of stage `st` (DIF order): n / (radix[0] ... radix[st-1]).
+LD_HD int stage_length(const FftPlan& pl, int st) {
+  int L = pl.n;
+  for (int i = 0; i < st; ++i) L /= pl.radix[i];
+  return L;
+}
+
+// Factor n into radices, largest power-of-two radices first (8, then one 4 or 2),
+// then 3, 5, 7.  False if another prime divides n.
+inline bool make_plan(int n, FftPlan& pl) {
+  pl.n = n;
+  pl.nf = 0;
+  for (int i = 0; i < kMaxFactors; ++i) pl.radix[i] = 0;
+  if (n < 1) return false;
+  int m = n;
+  const int order[] = {8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 4, 2, 3, 3, 3, 3, 3, 3, 3, 3, 5, 5, 5, 5, 5, 7, 7, 7, 7};
+  for (int r : order) {
+    if (m % r != 0) continue;
+    if (r == 2 && m % 4 == 0) continue;
+    if (pl.nf >= kMaxFactors) return false;
+    pl.radix[pl.nf++] = r;
+    m /= r;
+  }
+  return m == 1;
+}
+
+// DIF output slot p holds frequency digit_reverse(p).
+inline __host__ __device__ int digit_reverse(const FftPlan& pl, int p) {
+  int k = 0, mult = 1, span = pl.n, rem = p;
+  for (int s = 0; s < pl.nf; ++s) {
+    span /= pl.radix[s];
+    const int d = rem / span;
+    rem -= d * span;
+    k += d * mult;
+    mult *= pl.radix[s];
+  }
+  return k;
+}
+
+}  // namespace lddmm

@@ -1,0 +1,693 @@
+// lddmm_api.cpp - host engine and C ABI of the LDDMM hot path.
+//
+// The engine owns the device workspace of one registration problem and drives
+// the kernels of fft.hip / stencil.hip / sl.hip / reduce.hip on one stream:
+//   shoot      EPDiff in momentum form with Heun steps (Section 2.2), optional
+//              trajectory store and semi-Lagrangian state transport (Section 2.3)
+//   gradient   final condition lambda(1) grad J_1 (Section 3) carried back by the
+//              adjoint Jacobi sweep (the transposed Heun step of the tangent sweep)
+//   hessvec    forward tangent sweep (incremental EPDiff + Jacobi field), the
+//              Gauss-Newton final condition, the same adjoint sweep (Section 3)
+//   cg / gn    CG in the V inner product and the inexact Gauss-Newton loop with
+//              Armijo backtracking (Section 2.3 reduced KKT system, Section 3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "lddmm.h"
+#include "lddmm_internal.h"
+
+namespace lddmm {
+
+// ---------------------------------------------------------------------------
+// Profiler
+// ---------------------------------------------------------------------------
+hipEvent_t Profiler::take() {
+  if (!pool_.empty()) {
+    hipEvent_t e = pool_.back();
+    pool_.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+void Profiler::begin(const char* name, hipStream_t st) {
+  int kind = -1;
+  for (size_t i = 0; i < kinds_.size(); ++i)
+    if (kinds_[i] == name || std::strcmp(kinds_[i], name) == 0) {
+      kind = int(i);
+      break;
+    }
+  if (kind < 0) {
+    kinds_.push_back(name);
+    kind = int(kinds_.size()) - 1;
+  }
+  Rec r{kind, take(), take()};
+  (void)hipEventRecord(r.a, st);
+  recs_.push_back(r);
+  open_ = int(recs_.size()) - 1;
+}
+
+void Profiler::end(hipStream_t st) {
+  if (open_ >= 0) (void)hipEventRecord(recs_[open_].b, st);
+  open_ = -1;
+}
+
+int Profiler::read(const char** names, int64_t* counts, double* total_ms, int cap) {
+  std::vector<int64_t> c(kinds_.size(), 0);
+  std::vector<double> ms(kinds_.size(), 0.0);
+  for (auto& r : recs_) {
+    (void)hipEventSynchronize(r.b);
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+      c[r.kind] += 1;
+      ms[r.kind] += t;
+    }
+  }
+  const int n = int(kinds_.size());
+  for (int i = 0; i < n && i < cap; ++i) {
+    if (names) names[i] = kinds_[i];
+    if (counts) counts[i] = c[i];
+    if (total_ms) total_ms[i] = ms[i];
+  }
+  return n;
+}
+
+void Profiler::clear() {
+  for (auto& r : recs_) {
+    pool_.push_back(r.a);
+    pool_.push_back(r.b);
+  }
+  recs_.clear();
+  kinds_.clear();
+  open_ = -1;
+}
+
+Profiler::~Profiler() {
+  clear();
+  for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
+}
+
+// ---------------------------------------------------------------------------
+// Engine
+// ---------------------------------------------------------------------------
+template <typename T>
+class Engine {
+ public:
+  lddmm_params P{};
+  Grid g{};
+  long long N = 0;
+  double cell = 0.0, dt = 0.0;
+  hipStream_t st = nullptr;
+  std::string* err = nullptr;
+  Profiler prof;
+  SpectralPlan<T> sp;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+
+  // images and final conditions
+  T *I0 = nullptr, *I1 = nullptr, *J1 = nullptr, *Jtmp = nullptr, *res = nullptr, *G = nullptr, *lin_v0 = nullptr;
+  // trajectory store: mu_n, v_n (n <= nt), Heun predictors mu*_n, v*_n (n < nt)
+  std::vector<T*> tmu, tv, tmus, tvs;
+  // shooting scratch (no store) and displacement ping-pong
+  T *sm[2] = {nullptr, nullptr}, *sv[2] = {nullptr, nullptr}, *sms = nullptr, *svs = nullptr;
+  T *u[2] = {nullptr, nullptr};
+  // tangent (X, dmu) and adjoint (U^, w) states, predictors and K-argument
+  T *X = nullptr, *Mu = nullptr, *Xs = nullptr, *Mus = nullptr, *W = nullptr;
+  T *U = nullptr, *Wh = nullptr, *Us = nullptr, *Whs = nullptr, *Z = nullptr;
+  // CG and Gauss-Newton vectors
+  T *cr = nullptr, *cd = nullptr, *cHd = nullptr, *cLr = nullptr, *cLd = nullptr, *cx = nullptr;
+  T *gv = nullptr, *Lg = nullptr, *trial = nullptr, *tmpS = nullptr;
+  double* partials = nullptr;
+  double* dres = nullptr;
+  double* hres = nullptr;  // pinned host mirror of dres
+
+  bool have_images = false, linearized = false;
+  double E = 0, Ereg = 0, Edata = 0, base_sq = 0;
+
+  ~Engine() {
+    spectral_free(sp);
+    for (void* p : allocs) (void)hipFree(p);
+    if (hres) (void)hipHostFree(hres);
+  }
+
+  int fail(int code, const std::string& msg) {
+    if (err) *err = msg;
+    return code;
+  }
+
+  int alloc(T** p, long long count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, size_t(count) * sizeof(T)) != hipSuccess) return LDDMM_ENOMEM;
+    allocs.push_back(q);
+    bytes += size_t(count) * sizeof(T);
+    *p = static_cast<T*>(q);
+    return 0;
+  }
+
+  int init(const lddmm_params& p, hipStream_t stream, std::string* e) {
+    P = p;
+    st = stream;
+    err = e;
+    g.n0 = p.n[0];
+    g.n1 = p.n[1];
+    g.n2 = p.n[2];
+    g.N = (long long)p.n[0] * p.n[1] * p.n[2];
+    g.h0 = 2.0 * M_PI / p.n[0];
+    g.h1 = 2.0 * M_PI / p.n[1];
+    g.h2 = 2.0 * M_PI / p.n[2];
+    N = g.N;
+    cell = g.h0 * g.h1 * g.h2;
+    dt = 1.0 / p.nt;
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      return fail(LDDMM_EHIP, "cannot query the device");
+    std::string msg;
+    int rc = spectral_init(sp, p.n, size_t(lds), msg);
+    if (rc) return fail(rc, msg);
+    bytes += sp.bytes;
+    const long long V = 3 * N;
+    T** vecs[] = {&G, &lin_v0, &sm[0], &sm[1], &sv[0], &sv[1], &sms, &svs, &u[0], &u[1], &X, &Mu, &Xs, &Mus, &W,
+                  &U, &Wh, &Us, &Whs, &Z, &cr, &cd, &cHd, &cLr, &cLd, &cx, &gv, &Lg, &trial};
+    for (T** q : vecs)
+      if (alloc(q, V)) return fail(LDDMM_ENOMEM, "out of device memory (workspace)");
+    T** scal[] = {&I0, &I1, &J1, &Jtmp, &res, &tmpS};
+    for (T** q : scal)
+      if (alloc(q, N)) return fail(LDDMM_ENOMEM, "out of device memory (images)");
+    tmu.resize(p.nt + 1);
+    tv.resize(p.nt + 1);
+    tmus.resize(p.nt);
+    tvs.resize(p.nt);
+    for (auto* vec : {&tmu, &tv, &tmus, &tvs})
+      for (T*& q : *vec)
+        if (alloc(&q, V)) return fail(LDDMM_ENOMEM, "out of device memory (trajectory store)");
+    void* q = nullptr;
+    if (hipMalloc(&q, sizeof(double) * 2 * kReduceBlocks) != hipSuccess) return fail(LDDMM_ENOMEM, "partials");
+    allocs.push_back(q);
+    partials = static_cast<double*>(q);
+    if (hipMalloc(&q, sizeof(double) * 8) != hipSuccess) return fail(LDDMM_ENOMEM, "results");
+    allocs.push_back(q);
+    dres = static_cast<double*>(q);
+    if (hipHostMalloc(reinterpret_cast<void**>(&hres), sizeof(double) * 8, hipHostMallocDefault) != hipSuccess)
+      return fail(LDDMM_ENOMEM, "pinned results");
+    return 0;
+  }
+
+  int hip_status(const char* where) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(LDDMM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+    return 0;
+  }
+
+  // ---- primitives -------------------------------------------------------
+  void applyK(const T* in, T* out, int ncomp = 3) {
+    spectral_apply(sp, in, out, ncomp, P.alpha, P.s, LDDMM_OP_K, st, &prof);
+  }
+  void applyL(const T* in, T* out, int ncomp = 3) {
+    spectral_apply(sp, in, out, ncomp, P.alpha, P.s, LDDMM_OP_L, st, &prof);
+  }
+  void copy(T* dst, const T* src, long long count) {
+    (void)hipMemcpyAsync(dst, src, size_t(count) * sizeof(T), hipMemcpyDeviceToDevice, st);
+  }
+  // copy dres[0 .. k) to the pinned host mirror and wait
+  void fetch(int k) {
+    (void)hipMemcpyAsync(hres, dres, sizeof(double) * k, hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+  }
+  // dres[slot] = sum a.b over ncomp components (FP64), enqueued only
+  void dot_dev(const T* a, const T* b, int ncomp, int slot) {
+    launch_dot(a, b, ncomp * N, partials, dres + slot, st, &prof);
+  }
+  // h0 h1 h2 sum a.b over ncomp components (FP64), synchronising
+  double dot(const T* a, const T* b, int ncomp = 3) {
+    dot_dev(a, b, ncomp, 0);
+    fetch(1);
+    return cell * hres[0];
+  }
+  int check_finite(const T* a, long long count, const char* what) {
+    launch_check(a, count, partials, dres, st, &prof);
+    fetch(2);
+    if (hres[0] != 0.0) return fail(LDDMM_ENONFINITE, std::string(what) + " holds NaN or Inf");
+    return 0;
+  }
+  double maxabs(const T* a, long long count) {
+    launch_check(a, count, partials, dres, st, &prof);
+    fetch(2);
+    return hres[1];
+  }
+
+  // ---- forward shooting ---------------------------------------------------
+  // EPDiff (momentum form, Heun) from v0; store => trajectory arrays; with_sl =>
+  // u transported and J composed into Jout; want_energy => dres[2] = <L v0, v0>
+  // and dres[3] = ||Jout - I1||^2 (sums without the cell factor).  Returns the
+  // final (mu, v).
+  void shoot_core(const T* v0, bool store, bool with_sl, T* Jout, T** mu_last, T** v_last,
+                  bool want_energy = false) {
+    T* mu_cur = store ? tmu[0] : sm[0];
+    T* v_cur = store ? tv[0] : sv[0];
+    applyL(v0, mu_cur);
+    copy(v_cur, v0, 3 * N);
+    if (want_energy) dot_dev(mu_cur, v0, 3, 2);
+    if (with_sl) launch_fill<T>(3 * N, T(0), u[0], st, &prof);
+    for (int n = 0; n < P.nt; ++n) {
+      T* ms = store ? tmus[n] : sms;
+      T* vs = store ? tvs[n] : svs;
+      launch_epdiff_stage<T>(g, v_cur, mu_cur, nullptr, ms, dt, 0.0, 1.0, st, &prof);
+      applyK(ms, vs);
+      T* mu_next = store ? tmu[n + 1] : sm[(n + 1) & 1];
+      T* v_next = store ? tv[n + 1] : sv[(n + 1) & 1];
+      launch_epdiff_stage<T>(g, vs, ms, mu_cur, mu_next, dt, 0.5, 0.5, st, &prof);
+      applyK(mu_next, v_next);
+      if (with_sl) launch_sl_step<T>(g, u[n & 1], v_cur, v_next, u[(n + 1) & 1], dt, st, &prof);
+      mu_cur = mu_next;
+      v_cur = v_next;
+    }
+    if (with_sl) launch_compose<T>(g, I0, u[P.nt & 1], Jout, st, &prof);
+    if (want_energy) {
+      launch_axpbyz<T>(N, 1.0, Jout, -1.0, I1, tmpS, st, &prof);
+      dot_dev(tmpS, tmpS, 1, 3);
+    }
+    if (mu_last) *mu_last = mu_cur;
+    if (v_last) *v_last = v_cur;
+  }
+
+  T* final_u() { return u[P.nt & 1]; }
+
+  // Energy terms left in dres[2], dres[3] by shoot_core(want_energy).
+  double fetch_energy() {
+    (void)hipMemcpyAsync(hres, dres + 2, sizeof(double) * 2, hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    return cell * hres[0] + cell * hres[1] / P.sigma2;
+  }
+
+  int shoot(const T* v0, T* Jo, T* uo, T* vo, double* energy_out) {
+    if (int rc = check_finite(v0, 3 * N, "v0")) return rc;
+    const bool need_img = Jo || uo || energy_out;
+    if (need_img && !have_images) return fail(LDDMM_ESTATE, "images not set");
+    T *ml = nullptr, *vl = nullptr;
+    shoot_core(v0, false, need_img, Jtmp, &ml, &vl, energy_out != nullptr);
+    if (Jo) copy(Jo, Jtmp, N);
+    if (uo) copy(uo, final_u(), 3 * N);
+    if (vo) copy(vo, vl, 3 * N);
+    if (energy_out) *energy_out = fetch_energy();
+    return hip_status("shoot");
+  }
+
+  int linearize(const T* v0, double* energy_out) {
+    if (!have_images) return fail(LDDMM_ESTATE, "images not set");
+    if (int rc = check_finite(v0, 3 * N, "v0")) return rc;
+    linearize_nocheck(v0);
+    if (energy_out) *energy_out = E;
+    return hip_status("linearize");
+  }
+
+  void linearize_nocheck(const T* v0) {
+    if (v0 != lin_v0) copy(lin_v0, v0, 3 * N);
+    shoot_core(lin_v0, true, true, J1, nullptr, nullptr);
+    launch_residual_grad<T>(g, J1, I1, res, G, st, &prof);
+    Ereg = dot(tmu[0], lin_v0);
+    Edata = dot(res, res, 1) / P.sigma2;
+    E = Ereg + Edata;
+    linearized = true;
+  }
+
+  // ---- adjoint Jacobi sweep (transposed Heun) ------------------------------
+  // Input: U holds U^(1).  Output: Wh holds w_0 (U holds U^_0).
+  void backward() {
+    launch_fill<T>(3 * N, T(0), Wh, st, &prof);
+    for (int n = P.nt - 1; n >= 0; --n) {
+      launch_adjoint_pre<T>(g, U, Wh, tmus[n], Z, st, &prof);
+      applyK(Z, Z);
+      launch_adjoint_post<T>(g, U, Wh, Z, tvs[n], nullptr, nullptr, Us, Whs, dt, 0.0, 1.0, st, &prof);
+      launch_adjoint_pre<T>(g, Us, Whs, tmu[n], Z, st, &prof);
+      applyK(Z, Z);
+      launch_adjoint_post<T>(g, Us, Whs, Z, tv[n], U, Wh, U, Wh, dt, 0.5, 0.5, st, &prof);
+    }
+  }
+
+  // ---- tangent sweep: X_nt from X_0 = 0, dmu_0 = L dv ------------------------
+  void tangent(const T* dv) {
+    applyL(dv, Mu);
+    launch_fill<T>(3 * N, T(0), X, st, &prof);
+    for (int n = 0; n < P.nt; ++n) {
+      applyK(Mu, W);
+      launch_tangent_stage<T>(g, X, Mu, W, tv[n], tmu[n], nullptr, nullptr, Xs, Mus, dt, 0.0, 1.0, st, &prof);
+      applyK(Mus, W);
+      launch_tangent_stage<T>(g, Xs, Mus, W, tvs[n], tmus[n], X, Mu, X, Mu, dt, 0.5, 0.5, st, &prof);
+    }
+  }
+
+  void gradient_core(T* gout) {
+    launch_scalar_times_vec<T>(g, res, G, -2.0 / P.sigma2, U, st, &prof);
+    backward();
+    launch_axpbyz<T>(3 * N, 2.0, lin_v0, 1.0, Wh, gout, st, &prof);
+  }
+
+  int gradient(const T* v0, T* gout, double* energy_out) {
+    if (int rc = linearize(v0, energy_out)) return rc;
+    gradient_core(gout);
+    return hip_status("gradient");
+  }
+
+  void hessvec_core(const T* dv, T* hv) {
+    tangent(dv);
+    launch_gn_final<T>(g, G, X, 2.0 / P.sigma2, U, st, &prof);
+    backward();
+    launch_axpbyz<T>(3 * N, 2.0, dv, 1.0, Wh, hv, st, &prof);
+  }
+
+  int hessvec(const T* v0, const T* dv, T* hv) {
+    if (v0) {
+      if (int rc = linearize(v0, nullptr)) return rc;
+    } else if (!linearized) {
+      return fail(LDDMM_ESTATE, "hessvec without a linearization");
+    }
+    hessvec_core(dv, hv);
+    return hip_status("hessvec");
+  }
+
+  int vjp(const T* gbar, T* out) {
+    if (!linearized) return fail(LDDMM_ESTATE, "vjp without a linearization");
+    launch_scalar_times_vec<T>(g, gbar, G, -1.0, U, st, &prof);
+    backward();
+    applyL(Wh, out);
+    return hip_status("vjp");
+  }
+
+  // ---- CG in V -------------------------------------------------------------
+  // Solves H x = -g; ||r||_V <= eta ||g||_V or maxit.  Uses cr/cd/cHd/cLr/cLd.
+  int cg(const T* gin, T* x, double eta, int maxit, int* iters) {
+    const long long V = 3 * N;
+    launch_axpbyz<T>(V, -1.0, gin, 0.0, gin, cr, st, &prof);
+    copy(cd, cr, V);
+    launch_fill<T>(V, T(0), x, st, &prof);
+    applyL(cr, cLr);
+    copy(cLd, cLr, V);
+    double rr = dot(cLr, cr);
+    const double tol = eta * std::sqrt(rr);
+    int it = 0;
+    for (it = 1; it <= maxit; ++it) {
+      hessvec_core(cd, cHd);
+      const double dHd = dot(cLd, cHd);
+      if (!(dHd > 0.0)) {
+        --it;
+        break;
+      }
+      const double a = rr / dHd;
+      launch_axpby<T>(V, a, cd, 1.0, x, st, &prof);
+      launch_axpby<T>(V, -a, cHd, 1.0, cr, st, &prof);
+      applyL(cr, cLr);
+      const double rr_new = dot(cLr, cr);
+      if (std::sqrt(rr_new) <= tol) break;
+      const double beta = rr_new / rr;
+      launch_axpby<T>(V, 1.0, cr, beta, cd, st, &prof);
+      launch_axpby<T>(V, 1.0, cLr, beta, cLd, st, &prof);
+      rr = rr_new;
+    }
+    if (it > maxit) it = maxit;
+    if (iters) *iters = it;
+    return 0;
+  }
+
+  int cg_solve(const T* gin, T* x, double eta, int maxit, int* iters) {
+    if (!linearized) return fail(LDDMM_ESTATE, "cg_solve without a linearization");
+    if (maxit < 0 || !(eta >= 0.0)) return fail(LDDMM_EINVAL, "bad CG settings");
+    cg(gin, x, eta, maxit, iters);
+    return hip_status("cg_solve");
+  }
+
+  // ---- inexact Gauss-Newton-Krylov -----------------------------------------
+  int gn_solve(T* v, const lddmm_solve_opts* o, lddmm_solve_report* rep, lddmm_iter_log* log, int log_cap) {
+    if (!have_images) return fail(LDDMM_ESTATE, "images not set");
+    if (int rc = check_finite(v, 3 * N, "v0")) return rc;
+    lddmm_solve_opts op{};
+    if (o) op = *o;
+    if (op.gn_iters <= 0) op.gn_iters = 10;
+    if (op.cg_iters <= 0) op.cg_iters = 20;
+    if (op.max_halvings <= 0) op.max_halvings = 10;
+    if (op.c1 <= 0) op.c1 = 1e-4;
+    if (op.gtol <= 0) op.gtol = 1e-3;
+    if (op.eta_max <= 0) op.eta_max = 0.5;
+    lddmm_solve_report R{};
+    const long long V = 3 * N;
+    double g0 = 0, ginf0 = 0;
+    for (int k = 0; k < op.gn_iters; ++k) {
+      linearize_nocheck(v);
+      gradient_core(gv);
+      R.gradients++;
+      if (k == 0) R.E_first = E;
+      applyL(gv, Lg);
+      const double gn = std::sqrt(std::max(0.0, dot(Lg, gv)));
+      const double ginf = maxabs(gv, V);
+      if (k == 0) {
+        g0 = gn;
+        ginf0 = ginf;
+      }
+      R.g_rel_final = g0 > 0 ? gn / g0 : 0.0;
+      if (g0 == 0.0 || gn / g0 <= op.gtol) {
+        R.stop_reason = 1;
+        break;
+      }
+      const double eta = std::min(op.eta_max, std::sqrt(gn / g0));
+      int its = 0;
+      cg(gv, cx, eta, op.cg_iters, &its);
+      R.cg_total += its;
+      R.hessvecs += its;
+      const double gp = dot(Lg, cx);
+      double tau = 1.0;
+      bool accepted = false;
+      int trials = 0;
+      for (int h = 0; h <= op.max_halvings; ++h) {
+        launch_axpbyz<T>(V, 1.0, v, tau, cx, trial, st, &prof);
+        shoot_core(trial, false, true, Jtmp, nullptr, nullptr, true);
+        const double et = fetch_energy();
+        R.shoots++;
+        trials++;
+        if (et <= E + op.c1 * tau * gp) {
+          accepted = true;
+          break;
+        }
+        tau *= 0.5;
+      }
+      if (log && k < log_cap) {
+        lddmm_iter_log& L = log[k];
+        L.E = E;
+        L.E_reg = Ereg;
+        L.E_data = Edata;
+        L.mse_rel = base_sq > 0 ? 100.0 * Edata * P.sigma2 / base_sq : 0.0;
+        L.g_norm_V = gn;
+        L.g_inf_rel = ginf0 > 0 ? ginf / ginf0 : 0.0;
+        L.eta = eta;
+        L.tau = accepted ? tau : 0.0;
+        L.cg_iters = its;
+        L.ls_trials = trials;
+      }
+      R.iters = k + 1;
+      if (!accepted) {
+        R.stop_reason = 2;
+        break;
+      }
+      copy(v, trial, V);
+    }
+    linearize_nocheck(v);
+    R.E_final = E;
+    R.mse_rel_final = base_sq > 0 ? 100.0 * Edata * P.sigma2 / base_sq : 0.0;
+    if (rep) *rep = R;
+    return hip_status("gn_solve");
+  }
+
+  int set_images(const T* a, const T* b) {
+    if (int rc = check_finite(a, N, "I0")) return rc;
+    if (int rc = check_finite(b, N, "I1")) return rc;
+    copy(I0, a, N);
+    copy(I1, b, N);
+    launch_axpbyz<T>(N, 1.0, I0, -1.0, I1, tmpS, st, &prof);
+    base_sq = dot(tmpS, tmpS, 1);
+    have_images = true;
+    linearized = false;
+    return hip_status("set_images");
+  }
+
+  int jacobian(const T* uin, T* det, double* mn, double* mx) {
+    T* out = det ? det : tmpS;
+    launch_jacobian_det<T>(g, uin, out, st, &prof);
+    if (mn || mx) {
+      launch_minmax<T>(out, N, partials, dres, st, &prof);
+      fetch(2);
+      if (mn) *mn = hres[0];
+      if (mx) *mx = hres[1];
+    }
+    return hip_status("jacobian_det");
+  }
+};
+
+}  // namespace lddmm
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+struct lddmm_ctx {
+  int dtype = LDDMM_F32;
+  std::unique_ptr<lddmm::Engine<float>> f;
+  std::unique_ptr<lddmm::Engine<double>> d;
+  std::string err;
+};
+
+#define LDDMM_DISPATCH(ctx, call)                                                  \
+  do {                                                                             \
+    if (!(ctx)) return LDDMM_EINVAL;                                               \
+    (ctx)->err.clear();                                                            \
+    if ((ctx)->dtype == LDDMM_F32) {                                               \
+      auto& E = *(ctx)->f;                                                         \
+      using T = float;                                                             \
+      return call;                                                                 \
+    } else {                                                                       \
+      auto& E = *(ctx)->d;                                                         \
+      using T = double;                                                            \
+      return call;                                                                 \
+    }                                                                              \
+  } while (0)
+
+static bool good_size(int n) {
+  if (n < 4) return false;
+  for (int p : {2, 3, 5, 7})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+extern "C" {
+
+int lddmm_create(const lddmm_params* params, void* hip_stream, lddmm_ctx** out) {
+  if (!params || !out) return LDDMM_EINVAL;
+  *out = nullptr;
+  const lddmm_params& p = *params;
+  if (p.dtype != LDDMM_F32 && p.dtype != LDDMM_F64) return LDDMM_EINVAL;
+  if (p.nt < 1 || p.s < 1 || !(p.alpha > 0) || !(p.sigma2 > 0)) return LDDMM_EINVAL;
+  for (int d = 0; d < 3; ++d)
+    if (!good_size(p.n[d])) return LDDMM_EUNSUPPORTED;
+  if (p.n[2] & 1) return LDDMM_EUNSUPPORTED;
+  auto* c = new lddmm_ctx();
+  c->dtype = p.dtype;
+  int rc;
+  if (p.dtype == LDDMM_F32) {
+    c->f.reset(new lddmm::Engine<float>());
+    rc = c->f->init(p, static_cast<hipStream_t>(hip_stream), &c->err);
+  } else {
+    c->d.reset(new lddmm::Engine<double>());
+    rc = c->d->init(p, static_cast<hipStream_t>(hip_stream), &c->err);
+  }
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return LDDMM_OK;
+}
+
+int lddmm_destroy(lddmm_ctx* ctx) {
+  if (!ctx) return LDDMM_EINVAL;
+  if (ctx->f) (void)hipStreamSynchronize(ctx->f->st);
+  if (ctx->d) (void)hipStreamSynchronize(ctx->d->st);
+  delete ctx;
+  return LDDMM_OK;
+}
+
+int lddmm_set_images(lddmm_ctx* ctx, const void* I0, const void* I1) {
+  if (!I0 || !I1) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.set_images(static_cast<const T*>(I0), static_cast<const T*>(I1)));
+}
+
+int lddmm_apply_operator(lddmm_ctx* ctx, int op, int ncomp, const void* in, void* out) {
+  if (!in || !out || (op != LDDMM_OP_K && op != LDDMM_OP_L) || (ncomp != 1 && ncomp != 3)) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, ((op == LDDMM_OP_K ? E.applyK(static_cast<const T*>(in), static_cast<T*>(out), ncomp)
+                                         : E.applyL(static_cast<const T*>(in), static_cast<T*>(out), ncomp)),
+                        E.hip_status("apply_operator")));
+}
+
+int lddmm_dot(lddmm_ctx* ctx, int ncomp, const void* a, const void* b, double* out) {
+  if (!a || !b || !out || (ncomp != 1 && ncomp != 3)) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, (*out = E.dot(static_cast<const T*>(a), static_cast<const T*>(b), ncomp),
+                       E.hip_status("dot")));
+}
+
+int lddmm_shoot(lddmm_ctx* ctx, const void* v0, void* J1, void* u1, void* v1, double* energy) {
+  if (!v0) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.shoot(static_cast<const T*>(v0), static_cast<T*>(J1), static_cast<T*>(u1),
+                              static_cast<T*>(v1), energy));
+}
+
+int lddmm_linearize(lddmm_ctx* ctx, const void* v0, double* energy) {
+  if (!v0) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.linearize(static_cast<const T*>(v0), energy));
+}
+
+int lddmm_gradient(lddmm_ctx* ctx, const void* v0, void* g, double* energy) {
+  if (!v0 || !g) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.gradient(static_cast<const T*>(v0), static_cast<T*>(g), energy));
+}
+
+int lddmm_hessvec(lddmm_ctx* ctx, const void* v0, const void* dv, void* hv) {
+  if (!dv || !hv) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.hessvec(static_cast<const T*>(v0), static_cast<const T*>(dv), static_cast<T*>(hv)));
+}
+
+int lddmm_vjp(lddmm_ctx* ctx, const void* gbar_J1, void* gbar_v0) {
+  if (!gbar_J1 || !gbar_v0) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.vjp(static_cast<const T*>(gbar_J1), static_cast<T*>(gbar_v0)));
+}
+
+int lddmm_cg_solve(lddmm_ctx* ctx, const void* g, void* x, double eta, int maxit, int* iters) {
+  if (!g || !x) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.cg_solve(static_cast<const T*>(g), static_cast<T*>(x), eta, maxit, iters));
+}
+
+int lddmm_gn_solve(lddmm_ctx* ctx, void* v0_inout, const lddmm_solve_opts* opts, lddmm_solve_report* report,
+                   lddmm_iter_log* log, int log_cap) {
+  if (!v0_inout || log_cap < 0) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.gn_solve(static_cast<T*>(v0_inout), opts, report, log, log_cap));
+}
+
+int lddmm_jacobian_det(lddmm_ctx* ctx, const void* u, void* det, double* det_min, double* det_max) {
+  if (!u) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.jacobian(static_cast<const T*>(u), static_cast<T*>(det), det_min, det_max));
+}
+
+int lddmm_profile_enable(lddmm_ctx* ctx, int enable) {
+  LDDMM_DISPATCH(ctx, ((void)hipStreamSynchronize(E.st), E.prof.clear(), E.prof.enabled = enable != 0, 0));
+}
+
+int lddmm_profile_read(lddmm_ctx* ctx, const char** names, int64_t* counts, double* total_ms, int cap) {
+  if (cap < 0) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.prof.read(names, counts, total_ms, cap));
+}
+
+int lddmm_memory_bytes(lddmm_ctx* ctx, int64_t* bytes) {
+  if (!bytes) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, (*bytes = int64_t(E.bytes), 0));
+}
+
+const char* lddmm_strerror(int status) {
+  switch (status) {
+    case LDDMM_OK: return "ok";
+    case LDDMM_EINVAL: return "invalid argument";
+    case LDDMM_EUNSUPPORTED: return "unsupported grid size";
+    case LDDMM_ENOMEM: return "out of device memory";
+    case LDDMM_EHIP: return "HIP runtime error";
+    case LDDMM_ENONFINITE: return "non-finite input";
+    case LDDMM_ESTATE: return "invalid call order";
+    case LDDMM_ELINESEARCH: return "line search failed";
+    default: return "unknown status";
+  }
+}
+
+const char* lddmm_last_error(lddmm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,164 @@
+// lddmm_internal.h - declarations shared by the HIP kernel files and the host engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fft_core.h"
+
+namespace lddmm {
+
+// ---------------------------------------------------------------------------
+// Per-kernel timing with HIP events on the launch stream (enabled on request).
+// ---------------------------------------------------------------------------
+class Profiler {
+ public:
+  bool enabled = false;
+  void begin(const char* name, hipStream_t st);
+  void end(hipStream_t st);
+  int read(const char** names, int64_t* counts, double* total_ms, int cap);
+  void clear();
+  ~Profiler();
+
+ private:
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<const char*> kinds_;
+  std::vector<Rec> recs_;
+  std::vector<hipEvent_t> pool_;
+  int open_ = -1;
+  hipEvent_t take();
+};
+
+// RAII bracket around one launch: KernelTimer t(prof, "name", stream); launch(...);
+struct KernelTimer {
+  Profiler* p;
+  hipStream_t st;
+  KernelTimer(Profiler* prof, const char* name, hipStream_t s) : p(prof), st(s) {
+    if (p && p->enabled) p->begin(name, st);
+  }
+  ~KernelTimer() {
+    if (p && p->enabled) p->end(st);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Grid geometry passed by value to the field kernels.
+// ---------------------------------------------------------------------------
+struct Grid {
+  int n0, n1, n2;
+  long long N;           // n0 * n1 * n2
+  double h0, h1, h2;     // 2 pi / N_d
+};
+
+// ---------------------------------------------------------------------------
+// Spectral operator: 3D real FFT, symbol (1 + alpha |k|^2)^(+-s), inverse.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct SpectralPlan {
+  int n0 = 0, n1 = 0, n2 = 0, H = 0, M = 0;  // H = n2 / 2, M = H + 1 spectrum columns
+  FftPlan p0{}, p1{}, p2{};                  // lengths n0, n1, H
+  cplx<T>* tw0 = nullptr;                    // exp(-2 pi i m / n0), m < n0
+  cplx<T>* tw1 = nullptr;                    // exp(-2 pi i m / n1)
+  cplx<T>* tw2 = nullptr;                    // exp(-2 pi i m / H)
+  cplx<T>* twr = nullptr;                    // exp(-2 pi i k / n2), k <= H / 2
+  int* slot2 = nullptr;                      // x2 frequency k (0..H) -> spectrum column
+  T* ksq0 = nullptr;                         // squared wavenumber of each slot, per axis
+  T* ksq1 = nullptr;
+  T* ksq2 = nullptr;
+  cplx<T>* spec = nullptr;                   // workspace: 3 * n0 * n1 * M complex
+  bool fused = false;                        // (x2, x1) plane fits one workgroup's LDS
+  size_t plane_lds = 0, pencil0_lds = 0, pencil1_lds = 0, rows_lds = 0;
+  int pencil_tb = 0, rows_rb = 0;
+  size_t bytes = 0;                          // device memory held
+};
+
+// Returns 0 or a negative LDDMM_E* code.  max_lds = bytes of LDS per workgroup.
+template <typename T>
+int spectral_init(SpectralPlan<T>& sp, const int n[3], size_t max_lds, std::string& err);
+template <typename T>
+void spectral_free(SpectralPlan<T>& sp);
+// out = K in (op = 0) or L in (op = 1) for ncomp components; in == out allowed.
+template <typename T>
+void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, double alpha, int s, int op,
+                    hipStream_t st, Profiler* prof);
+
+// ---------------------------------------------------------------------------
+// Field kernels (stencils, Heun stages, final conditions) - stencil.hip
+// ---------------------------------------------------------------------------
+// mu_out = a0 * mu0 + a1 * (mu - dt ad*_v mu)      (EPDiff stage, momentum form)
+template <typename T>
+void launch_epdiff_stage(const Grid& g, const T* v, const T* mu, const T* mu0, T* mu_out, double dt, double a0,
+                         double a1, hipStream_t st, Profiler* prof);
+// Tangent stage at coefficients (v, mu) with W = K dmu:
+//   X_out   = a0 X0   + a1 (X   + dt (W + ad_v X))
+//   dmu_out = a0 dmu0 + a1 (dmu + dt (-ad*_W mu - ad*_v dmu))
+template <typename T>
+void launch_tangent_stage(const Grid& g, const T* X, const T* dmu, const T* W, const T* v, const T* mu,
+                          const T* X0, const T* dmu0, T* X_out, T* dmu_out, double dt, double a0, double a1,
+                          hipStream_t st, Profiler* prof);
+// Z = U + ad*_w mu   (argument of K in the adjoint stage)
+template <typename T>
+void launch_adjoint_pre(const Grid& g, const T* U, const T* w, const T* mu, T* Z, hipStream_t st, Profiler* prof);
+// Adjoint stage at v with KZ = K(U + ad*_w mu):
+//   U_out = a0 U0 + a1 (U + dt ad*_v U);  w_out = a0 w0 + a1 (w + dt (KZ - ad_v w))
+template <typename T>
+void launch_adjoint_post(const Grid& g, const T* U, const T* w, const T* KZ, const T* v, const T* U0,
+                         const T* w0, T* U_out, T* w_out, double dt, double a0, double a1, hipStream_t st,
+                         Profiler* prof);
+// r = J1 - I1, G = grad_h J1
+template <typename T>
+void launch_residual_grad(const Grid& g, const T* J1, const T* I1, T* r, T* G, hipStream_t st, Profiler* prof);
+// U = c * s * G  (pointwise scalar s times the vector G)
+template <typename T>
+void launch_scalar_times_vec(const Grid& g, const T* s, const T* G, double c, T* U, hipStream_t st,
+                             Profiler* prof);
+// U = c * (G . X) G
+template <typename T>
+void launch_gn_final(const Grid& g, const T* G, const T* X, double c, T* U, hipStream_t st, Profiler* prof);
+// det = det(I + D_h u)
+template <typename T>
+void launch_jacobian_det(const Grid& g, const T* u, T* det, hipStream_t st, Profiler* prof);
+
+// ---------------------------------------------------------------------------
+// Semi-Lagrangian transport - sl.hip
+// ---------------------------------------------------------------------------
+// u_new(x) = u_old(X) + (X - x), X = x - dt/2 (v_new(x) + v_old(x - dt v_new(x)))
+template <typename T>
+void launch_sl_step(const Grid& g, const T* u_old, const T* v_old, const T* v_new, T* u_new, double dt,
+                    hipStream_t st, Profiler* prof);
+// J(x) = I(x + u(x))
+template <typename T>
+void launch_compose(const Grid& g, const T* I, const T* u, T* J, hipStream_t st, Profiler* prof);
+
+// ---------------------------------------------------------------------------
+// Reductions and BLAS-1 - reduce.hip.  Reductions are deterministic two-stage
+// (fixed grid, fixed summation order, no atomics) and accumulate in double.
+// ---------------------------------------------------------------------------
+constexpr int kReduceBlocks = 1024;
+// out[0] = sum_i a[i] * b[i] over n elements (partials: kReduceBlocks doubles)
+template <typename T>
+void launch_dot(const T* a, const T* b, long long n, double* partials, double* out, hipStream_t st,
+                Profiler* prof);
+// out[0] = number of non-finite entries, out[1] = max |a|
+template <typename T>
+void launch_check(const T* a, long long n, double* partials, double* out, hipStream_t st, Profiler* prof);
+// out[0] = min a, out[1] = max a
+template <typename T>
+void launch_minmax(const T* a, long long n, double* partials, double* out, hipStream_t st, Profiler* prof);
+// y = alpha x + beta y
+template <typename T>
+void launch_axpby(long long n, double alpha, const T* x, double beta, T* y, hipStream_t st, Profiler* prof);
+// z = alpha x + beta y
+template <typename T>
+void launch_axpbyz(long long n, double alpha, const T* x, double beta, const T* y, T* z, hipStream_t st,
+                   Profiler* prof);
+template <typename T>
+void launch_fill(long long n, T value, T* y, hipStream_t st, Profiler* prof);
+
+}  // namespace lddmm

@@ -1,0 +1,216 @@
+// reduce.hip - FP64 reductions (inner products of the CG in V, energies, checks)
+// and BLAS-1 updates.
+//
+// Reductions are deterministic: a fixed grid of kReduceBlocks workgroups, each
+// summing a grid-strided share in double, a 64-lane wavefront shuffle tree, a
+// per-block slot in `partials`, then one workgroup summing the slots in a fixed
+// tree order.  No atomics, so repeated calls give bit-identical results.
+#include <cfloat>
+
+#include "lddmm.h"
+#include "lddmm_internal.h"
+
+namespace lddmm {
+
+namespace {
+
+constexpr int RT = 256;  // threads per reduction block (4 wavefronts)
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
+  return x;
+}
+__device__ __forceinline__ double wave_min(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = fmin(x, __shfl_down(x, off, 64));
+  return x;
+}
+
+// Block-wide combine of K values per thread; op 0 = sum, 1 = max, 2 = min.
+template <int K>
+__device__ void block_combine(double (&v)[K], const int (&op)[K], double* out) {
+  __shared__ double sh[K][RT / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    v[k] = op[k] == 0 ? wave_sum(v[k]) : op[k] == 1 ? wave_max(v[k]) : wave_min(v[k]);
+    if (lane == 0) sh[k][wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double a = sh[k][0];
+      for (int w = 1; w < RT / 64; ++w)
+        a = op[k] == 0 ? a + sh[k][w] : op[k] == 1 ? fmax(a, sh[k][w]) : fmin(a, sh[k][w]);
+      out[k] = a;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RT) k_dot(const T* __restrict__ a, const T* __restrict__ b, long long n,
+                                            double* __restrict__ partials) {
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)RT + threadIdx.x; i < n; i += (long long)gridDim.x * RT)
+    acc += double(a[i]) * double(b[i]);
+  double v[1] = {acc};
+  const int op[1] = {0};
+  double out[1];
+  block_combine<1>(v, op, out);
+  if (threadIdx.x == 0) partials[blockIdx.x] = out[0];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RT) k_check(const T* __restrict__ a, long long n, double* __restrict__ partials) {
+  double bad = 0.0, mx = 0.0;
+  for (long long i = blockIdx.x * (long long)RT + threadIdx.x; i < n; i += (long long)gridDim.x * RT) {
+    const double x = double(a[i]);
+    if (!isfinite(x))
+      bad += 1.0;
+    else
+      mx = fmax(mx, fabs(x));
+  }
+  double v[2] = {bad, mx};
+  const int op[2] = {0, 1};
+  double out[2];
+  block_combine<2>(v, op, out);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = out[0];
+    partials[2 * blockIdx.x + 1] = out[1];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RT) k_minmax(const T* __restrict__ a, long long n, double* __restrict__ partials) {
+  double mn = DBL_MAX, mx = -DBL_MAX;
+  for (long long i = blockIdx.x * (long long)RT + threadIdx.x; i < n; i += (long long)gridDim.x * RT) {
+    const double x = double(a[i]);
+    mn = fmin(mn, x);
+    mx = fmax(mx, x);
+  }
+  double v[2] = {mn, mx};
+  const int op[2] = {2, 1};
+  double out[2];
+  block_combine<2>(v, op, out);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = out[0];
+    partials[2 * blockIdx.x + 1] = out[1];
+  }
+}
+
+// Final stage: K interleaved values per partial slot, nparts slots, fixed order.
+template <int K>
+__global__ void __launch_bounds__(RT) k_finish(const double* __restrict__ partials, int nparts, int op0, int op1,
+                                               double* __restrict__ out) {
+  double v[K];
+  int op[K];
+  op[0] = op0;
+  if (K > 1) op[K - 1] = op1;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = op[k] == 0 ? 0.0 : op[k] == 1 ? -DBL_MAX : DBL_MAX;
+  for (int i = threadIdx.x; i < nparts; i += RT)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double x = partials[K * i + k];
+      v[k] = op[k] == 0 ? v[k] + x : op[k] == 1 ? fmax(v[k], x) : fmin(v[k], x);
+    }
+  double r[K];
+  block_combine<K>(v, op, r);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = r[k];
+}
+
+template <typename T>
+__global__ void k_axpby(long long n, T alpha, const T* x, T beta, T* y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = alpha * x[i] + beta * y[i];
+}
+
+template <typename T>
+__global__ void k_axpbyz(long long n, T alpha, const T* x, T beta, const T* y, T* z) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    z[i] = alpha * x[i] + beta * y[i];
+}
+
+template <typename T>
+__global__ void k_fill(long long n, T value, T* y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = value;
+}
+
+unsigned ew_blocks(long long n) {
+  const long long b = (n + 255) / 256;
+  return (unsigned)(b < 16384 ? b : 16384);
+}
+
+unsigned red_blocks(long long n) {
+  const long long b = (n + RT - 1) / RT;
+  return (unsigned)(b < kReduceBlocks ? (b > 0 ? b : 1) : kReduceBlocks);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_dot(const T* a, const T* b, long long n, double* partials, double* out, hipStream_t st,
+                Profiler* prof) {
+  KernelTimer t(prof, "dot", st);
+  const unsigned nb = red_blocks(n);
+  k_dot<T><<<nb, RT, 0, st>>>(a, b, n, partials);
+  k_finish<1><<<1, RT, 0, st>>>(partials, (int)nb, 0, 0, out);
+}
+
+template <typename T>
+void launch_check(const T* a, long long n, double* partials, double* out, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "check", st);
+  const unsigned nb = red_blocks(n);
+  k_check<T><<<nb, RT, 0, st>>>(a, n, partials);
+  k_finish<2><<<1, RT, 0, st>>>(partials, (int)nb, 0, 1, out);
+}
+
+template <typename T>
+void launch_minmax(const T* a, long long n, double* partials, double* out, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "minmax", st);
+  const unsigned nb = red_blocks(n);
+  k_minmax<T><<<nb, RT, 0, st>>>(a, n, partials);
+  k_finish<2><<<1, RT, 0, st>>>(partials, (int)nb, 2, 1, out);
+}
+
+template <typename T>
+void launch_axpby(long long n, double alpha, const T* x, double beta, T* y, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "axpby", st);
+  k_axpby<T><<<ew_blocks(n), 256, 0, st>>>(n, T(alpha), x, T(beta), y);
+}
+
+template <typename T>
+void launch_axpbyz(long long n, double alpha, const T* x, double beta, const T* y, T* z, hipStream_t st,
+                   Profiler* prof) {
+  KernelTimer t(prof, "axpby", st);
+  k_axpbyz<T><<<ew_blocks(n), 256, 0, st>>>(n, T(alpha), x, T(beta), y, z);
+}
+
+template <typename T>
+void launch_fill(long long n, T value, T* y, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "fill", st);
+  k_fill<T><<<ew_blocks(n), 256, 0, st>>>(n, value, y);
+}
+
+#define LDDMM_RINST(T)                                                                                       \
+  template void launch_dot<T>(const T*, const T*, long long, double*, double*, hipStream_t, Profiler*);     \
+  template void launch_check<T>(const T*, long long, double*, double*, hipStream_t, Profiler*);             \
+  template void launch_minmax<T>(const T*, long long, double*, double*, hipStream_t, Profiler*);            \
+  template void launch_axpby<T>(long long, double, const T*, double, T*, hipStream_t, Profiler*);           \
+  template void launch_axpbyz<T>(long long, double, const T*, double, const T*, T*, hipStream_t, Profiler*); \
+  template void launch_fill<T>(long long, T, T*, hipStream_t, Profiler*);
+
+LDDMM_RINST(float)
+LDDMM_RINST(double)
+
+}  // namespace lddmm

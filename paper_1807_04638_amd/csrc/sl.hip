@@ -1,0 +1,147 @@
+// sl.hip - semi-Lagrangian transport of the state equation (Section 2.3:
+// d_t J + grad J . v = 0, J(0) = I_0) through the inverse-map displacement
+// u = phi^-1 - id, and the final composition J_1 = I_0 o (id + u_1).
+//
+// One step, with grid-time velocities v_old = v_n and v_new = v_{n+1}:
+//   foot point  X = x - dt/2 (v_new(x) + v_old(x - dt v_new(x)))   (Heun backtrace)
+//   u_new(x)    = u_old(X) + (X - x)
+// Interpolation is periodic trilinear.  Each voxel's query point is handled as
+// its integer index plus a small offset in voxels, so the fractional weights
+// keep full precision in FP32 at any grid index.
+#include "lddmm.h"
+#include "lddmm_internal.h"
+
+namespace lddmm {
+
+namespace {
+
+constexpr int BX = 64, BY = 4;
+
+template <typename T>
+struct SlGeo {
+  int n0, n1, n2;
+  long long N;
+  T invh[3];
+};
+
+template <typename T>
+SlGeo<T> make_sl_geo(const Grid& g) {
+  SlGeo<T> o;
+  o.n0 = g.n0;
+  o.n1 = g.n1;
+  o.n2 = g.n2;
+  o.N = g.N;
+  o.invh[0] = T(1.0 / g.h0);
+  o.invh[1] = T(1.0 / g.h1);
+  o.invh[2] = T(1.0 / g.h2);
+  return o;
+}
+
+__device__ __forceinline__ int wrap(int j, int n) {
+  j %= n;
+  return j < 0 ? j + n : j;
+}
+
+// Corner offsets and weights of the trilinear stencil at voxel (i0, i1, i2)
+// displaced by (d0, d1, d2) voxels.
+template <typename T>
+struct Tri {
+  long long o[8];
+  T w[8];
+};
+
+template <typename T>
+__device__ __forceinline__ Tri<T> tri_setup(const SlGeo<T>& g, int i0, int i1, int i2, T d0, T d1, T d2) {
+  // offsets beyond a million voxels (or NaN) are clamped: the periodic wrap keeps
+  // every index in range and the integer conversion cannot overflow
+  constexpr T lim = T(1.0e6);
+  d0 = fmin(fmax(d0, -lim), lim);
+  d1 = fmin(fmax(d1, -lim), lim);
+  d2 = fmin(fmax(d2, -lim), lim);
+  const T f0 = floor(d0), f1 = floor(d1), f2 = floor(d2);
+  const T t0 = d0 - f0, t1 = d1 - f1, t2 = d2 - f2;
+  const int a0 = wrap(i0 + int(f0), g.n0), a1 = wrap(i1 + int(f1), g.n1), a2 = wrap(i2 + int(f2), g.n2);
+  const int b0 = a0 + 1 == g.n0 ? 0 : a0 + 1;
+  const int b1 = a1 + 1 == g.n1 ? 0 : a1 + 1;
+  const int b2 = a2 + 1 == g.n2 ? 0 : a2 + 1;
+  const long long s0 = (long long)g.n1 * g.n2;
+  const long long r0[2] = {a0 * s0, b0 * s0};
+  const long long r1[2] = {(long long)a1 * g.n2, (long long)b1 * g.n2};
+  const int r2[2] = {a2, b2};
+  const T w0[2] = {T(1) - t0, t0}, w1[2] = {T(1) - t1, t1}, w2[2] = {T(1) - t2, t2};
+  Tri<T> tr;
+#pragma unroll
+  for (int c0 = 0; c0 < 2; ++c0)
+#pragma unroll
+    for (int c1 = 0; c1 < 2; ++c1)
+#pragma unroll
+      for (int c2 = 0; c2 < 2; ++c2) {
+        const int k = c0 * 4 + c1 * 2 + c2;
+        tr.o[k] = r0[c0] + r1[c1] + r2[c2];
+        tr.w[k] = w0[c0] * w1[c1] * w2[c2];
+      }
+  return tr;
+}
+
+template <typename T>
+__device__ __forceinline__ T tri_eval(const Tri<T>& tr, const T* __restrict__ f) {
+  T acc = T(0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc += tr.w[k] * f[tr.o[k]];
+  return acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BX* BY)
+    k_sl_step(SlGeo<T> g, const T* __restrict__ u_old, const T* __restrict__ v_old, const T* __restrict__ v_new,
+              T* __restrict__ u_new, T dt) {
+  const int i2 = blockIdx.x * BX + threadIdx.x, i1 = blockIdx.y * BY + threadIdx.y, i0 = blockIdx.z;
+  if (i2 >= g.n2 || i1 >= g.n1) return;
+  const long long o = ((long long)i0 * g.n1 + i1) * g.n2 + i2;
+  T vn[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) vn[c] = v_new[c * g.N + o];
+  const Tri<T> tp = tri_setup(g, i0, i1, i2, -dt * vn[0] * g.invh[0], -dt * vn[1] * g.invh[1], -dt * vn[2] * g.invh[2]);
+  T disp[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) disp[c] = T(-0.5) * dt * (vn[c] + tri_eval(tp, v_old + c * g.N));
+  const Tri<T> tx = tri_setup(g, i0, i1, i2, disp[0] * g.invh[0], disp[1] * g.invh[1], disp[2] * g.invh[2]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u_new[c * g.N + o] = tri_eval(tx, u_old + c * g.N) + disp[c];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BX* BY)
+    k_compose(SlGeo<T> g, const T* __restrict__ I, const T* __restrict__ u, T* __restrict__ J) {
+  const int i2 = blockIdx.x * BX + threadIdx.x, i1 = blockIdx.y * BY + threadIdx.y, i0 = blockIdx.z;
+  if (i2 >= g.n2 || i1 >= g.n1) return;
+  const long long o = ((long long)i0 * g.n1 + i1) * g.n2 + i2;
+  const Tri<T> t = tri_setup(g, i0, i1, i2, u[o] * g.invh[0], u[g.N + o] * g.invh[1], u[2 * g.N + o] * g.invh[2]);
+  J[o] = tri_eval(t, I);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_sl_step(const Grid& g, const T* u_old, const T* v_old, const T* v_new, T* u_new, double dt,
+                    hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "sl_step", st);
+  const dim3 grid((g.n2 + BX - 1) / BX, (g.n1 + BY - 1) / BY, g.n0);
+  k_sl_step<T><<<grid, dim3(BX, BY), 0, st>>>(make_sl_geo<T>(g), u_old, v_old, v_new, u_new, T(dt));
+}
+
+template <typename T>
+void launch_compose(const Grid& g, const T* I, const T* u, T* J, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "compose", st);
+  const dim3 grid((g.n2 + BX - 1) / BX, (g.n1 + BY - 1) / BY, g.n0);
+  k_compose<T><<<grid, dim3(BX, BY), 0, st>>>(make_sl_geo<T>(g), I, u, J);
+}
+
+template void launch_sl_step<float>(const Grid&, const float*, const float*, const float*, float*, double,
+                                    hipStream_t, Profiler*);
+template void launch_sl_step<double>(const Grid&, const double*, const double*, const double*, double*, double,
+                                     hipStream_t, Profiler*);
+template void launch_compose<float>(const Grid&, const float*, const float*, float*, hipStream_t, Profiler*);
+template void launch_compose<double>(const Grid&, const double*, const double*, double*, hipStream_t, Profiler*);
+
+}  // namespace lddmm

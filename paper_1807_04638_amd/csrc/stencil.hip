@@ -1,0 +1,383 @@
+// stencil.hip - pointwise and 7-point-stencil kernels of the EPDiff shooting and
+// of the tangent / adjoint Jacobi sweeps.
+//
+// Operators (periodic grid, second-order central differences delta_d):
+//   (Dv)_{cd}      = delta_d v_c
+//   ad_v w         = (Dv) w - (Dw) v                          (Jacobi field, Section 3)
+//   ad*_v mu       = (Dv)^T mu + sum_d delta_d(mu v_d)        (EPDiff, Section 2.2)
+// ad* is the conservative form of the paper's (Dv)^T Lv + D(Lv) v + Lv div v; on
+// the grid it is the exact transpose of ad_v, which keeps the adjoint sweep the
+// exact transpose of the tangent sweep.
+//
+// Every kernel maps one thread to one voxel with a (64 x 4) block over (x2, x1)
+// and grid.z = x0; neighbours come through the cache hierarchy.
+#include "lddmm.h"
+#include "lddmm_internal.h"
+
+namespace lddmm {
+
+namespace {
+
+constexpr int BX = 64, BY = 4;
+
+template <typename T>
+struct Geo {
+  int n0, n1, n2;
+  long long N;
+  T inv2h[3];
+};
+
+template <typename T>
+Geo<T> make_geo(const Grid& g) {
+  Geo<T> o;
+  o.n0 = g.n0;
+  o.n1 = g.n1;
+  o.n2 = g.n2;
+  o.N = g.N;
+  o.inv2h[0] = T(0.5 / g.h0);
+  o.inv2h[1] = T(0.5 / g.h1);
+  o.inv2h[2] = T(0.5 / g.h2);
+  return o;
+}
+
+dim3 field_grid(const Grid& g) { return dim3((g.n2 + BX - 1) / BX, (g.n1 + BY - 1) / BY, g.n0); }
+
+// Linear offsets of the voxel and its six periodic neighbours:
+// 0 centre, 1 +x0, 2 -x0, 3 +x1, 4 -x1, 5 +x2, 6 -x2.
+struct Nbr {
+  long long o[7];
+};
+
+template <typename T>
+__device__ __forceinline__ bool voxel(const Geo<T>& g, int& i0, int& i1, int& i2) {
+  i2 = blockIdx.x * BX + threadIdx.x;
+  i1 = blockIdx.y * BY + threadIdx.y;
+  i0 = blockIdx.z;
+  return i2 < g.n2 && i1 < g.n1;
+}
+
+template <typename T>
+__device__ __forceinline__ Nbr neighbours(const Geo<T>& g, int i0, int i1, int i2) {
+  const int p0 = i0 + 1 == g.n0 ? 0 : i0 + 1, m0 = i0 == 0 ? g.n0 - 1 : i0 - 1;
+  const int p1 = i1 + 1 == g.n1 ? 0 : i1 + 1, m1 = i1 == 0 ? g.n1 - 1 : i1 - 1;
+  const int p2 = i2 + 1 == g.n2 ? 0 : i2 + 1, m2 = i2 == 0 ? g.n2 - 1 : i2 - 1;
+  const long long s0 = (long long)g.n1 * g.n2;
+  const long long r0 = i0 * s0, rp0 = p0 * s0, rm0 = m0 * s0;
+  const long long r1 = (long long)i1 * g.n2;
+  Nbr n;
+  n.o[0] = r0 + r1 + i2;
+  n.o[1] = rp0 + r1 + i2;
+  n.o[2] = rm0 + r1 + i2;
+  n.o[3] = r0 + (long long)p1 * g.n2 + i2;
+  n.o[4] = r0 + (long long)m1 * g.n2 + i2;
+  n.o[5] = r0 + r1 + p2;
+  n.o[6] = r0 + r1 + m2;
+  return n;
+}
+
+// Three components of a vector field at the 7 stencil points.
+template <typename T>
+struct St7 {
+  T f[7][3];
+};
+
+template <typename T>
+__device__ __forceinline__ void load7(St7<T>& s, const T* __restrict__ p, const Nbr& nb, long long N) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int k = 0; k < 7; ++k) s.f[k][c] = p[c * N + nb.o[k]];
+}
+
+template <typename T>
+__device__ __forceinline__ void load1(T out[3], const T* __restrict__ p, long long o, long long N) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) out[c] = p[c * N + o];
+}
+
+template <typename T>
+__device__ __forceinline__ void store1(T* __restrict__ p, const T v[3], long long o, long long N) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) p[c * N + o] = v[c];
+}
+
+// delta_d of component c
+template <typename T>
+__device__ __forceinline__ T dd(const St7<T>& s, int c, int d, const Geo<T>& g) {
+  return (s.f[1 + 2 * d][c] - s.f[2 + 2 * d][c]) * g.inv2h[d];
+}
+
+// ad_v w = (Dv) w - (Dw) v at the centre
+template <typename T>
+__device__ __forceinline__ void ad(const St7<T>& v, const St7<T>& w, const Geo<T>& g, T out[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T acc = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) acc += dd(v, c, d, g) * w.f[0][d] - dd(w, c, d, g) * v.f[0][d];
+    out[c] = acc;
+  }
+}
+
+// ad*_v mu = (Dv)^T mu + sum_d delta_d(mu v_d) at the centre
+template <typename T>
+__device__ __forceinline__ void adstar(const St7<T>& v, const St7<T>& mu, const Geo<T>& g, T out[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T acc = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      acc += dd(v, d, c, g) * mu.f[0][d];
+      acc += (mu.f[1 + 2 * d][c] * v.f[1 + 2 * d][d] - mu.f[2 + 2 * d][c] * v.f[2 + 2 * d][d]) * g.inv2h[d];
+    }
+    out[c] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(BX* BY)
+    k_epdiff_stage(Geo<T> g, const T* __restrict__ v, const T* __restrict__ mu, const T* mu0, T* mu_out, T dt,
+                   T a0, T a1) {
+  int i0, i1, i2;
+  if (!voxel(g, i0, i1, i2)) return;
+  const Nbr nb = neighbours(g, i0, i1, i2);
+  St7<T> V, Mu;
+  load7(V, v, nb, g.N);
+  load7(Mu, mu, nb, g.N);
+  T a[3];
+  adstar(V, Mu, g, a);
+  T out[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) out[c] = a1 * (Mu.f[0][c] - dt * a[c]);
+  if (a0 != T(0)) {
+    T m0[3];
+    load1(m0, mu0, nb.o[0], g.N);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c] += a0 * m0[c];
+  }
+  store1(mu_out, out, nb.o[0], g.N);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BX* BY)
+    k_tangent_stage(Geo<T> g, const T* __restrict__ X, const T* __restrict__ dmu, const T* __restrict__ W,
+                    const T* __restrict__ v, const T* __restrict__ mu, const T* X0, const T* dmu0, T* X_out,
+                    T* dmu_out, T dt, T a0, T a1) {
+  int i0, i1, i2;
+  if (!voxel(g, i0, i1, i2)) return;
+  const Nbr nb = neighbours(g, i0, i1, i2);
+  St7<T> Xs, Ws, Vs;
+  load7(Xs, X, nb, g.N);
+  load7(Ws, W, nb, g.N);
+  load7(Vs, v, nb, g.N);
+  T aX[3];
+  ad(Vs, Xs, g, aX);
+  T xo[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) xo[c] = a1 * (Xs.f[0][c] + dt * (Ws.f[0][c] + aX[c]));
+  St7<T> Ms, Ds;
+  load7(Ms, mu, nb, g.N);
+  load7(Ds, dmu, nb, g.N);
+  T t1[3], t2[3];
+  adstar(Ws, Ms, g, t1);
+  adstar(Vs, Ds, g, t2);
+  T mo[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) mo[c] = a1 * (Ds.f[0][c] - dt * (t1[c] + t2[c]));
+  if (a0 != T(0)) {
+    T x0v[3], m0v[3];
+    load1(x0v, X0, nb.o[0], g.N);
+    load1(m0v, dmu0, nb.o[0], g.N);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xo[c] += a0 * x0v[c];
+      mo[c] += a0 * m0v[c];
+    }
+  }
+  store1(X_out, xo, nb.o[0], g.N);
+  store1(dmu_out, mo, nb.o[0], g.N);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BX* BY)
+    k_adjoint_pre(Geo<T> g, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ mu,
+                  T* __restrict__ Z) {
+  int i0, i1, i2;
+  if (!voxel(g, i0, i1, i2)) return;
+  const Nbr nb = neighbours(g, i0, i1, i2);
+  St7<T> Ws, Ms;
+  load7(Ws, w, nb, g.N);
+  load7(Ms, mu, nb, g.N);
+  T a[3], u[3];
+  adstar(Ws, Ms, g, a);
+  load1(u, U, nb.o[0], g.N);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) a[c] += u[c];
+  store1(Z, a, nb.o[0], g.N);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BX* BY)
+    k_adjoint_post(Geo<T> g, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ KZ,
+                   const T* __restrict__ v, const T* U0, const T* w0, T* U_out, T* w_out, T dt, T a0, T a1) {
+  int i0, i1, i2;
+  if (!voxel(g, i0, i1, i2)) return;
+  const Nbr nb = neighbours(g, i0, i1, i2);
+  St7<T> Us, Ws, Vs;
+  load7(Us, U, nb, g.N);
+  load7(Vs, v, nb, g.N);
+  T aU[3];
+  adstar(Vs, Us, g, aU);
+  T uo[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) uo[c] = a1 * (Us.f[0][c] + dt * aU[c]);
+  load7(Ws, w, nb, g.N);
+  T aw[3], kz[3];
+  ad(Vs, Ws, g, aw);
+  load1(kz, KZ, nb.o[0], g.N);
+  T wo[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) wo[c] = a1 * (Ws.f[0][c] + dt * (kz[c] - aw[c]));
+  if (a0 != T(0)) {
+    T u0[3], ww0[3];
+    load1(u0, U0, nb.o[0], g.N);
+    load1(ww0, w0, nb.o[0], g.N);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      uo[c] += a0 * u0[c];
+      wo[c] += a0 * ww0[c];
+    }
+  }
+  store1(U_out, uo, nb.o[0], g.N);
+  store1(w_out, wo, nb.o[0], g.N);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BX* BY)
+    k_residual_grad(Geo<T> g, const T* __restrict__ J1, const T* __restrict__ I1, T* __restrict__ r,
+                    T* __restrict__ G) {
+  int i0, i1, i2;
+  if (!voxel(g, i0, i1, i2)) return;
+  const Nbr nb = neighbours(g, i0, i1, i2);
+  r[nb.o[0]] = J1[nb.o[0]] - I1[nb.o[0]];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) G[d * g.N + nb.o[0]] = (J1[nb.o[1 + 2 * d]] - J1[nb.o[2 + 2 * d]]) * g.inv2h[d];
+}
+
+template <typename T>
+__global__ void k_scalar_times_vec(long long N, const T* __restrict__ s, const T* __restrict__ G, T c,
+                                   T* __restrict__ U) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    const T f = c * s[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) U[d * N + i] = f * G[d * N + i];
+  }
+}
+
+template <typename T>
+__global__ void k_gn_final(long long N, const T* __restrict__ G, const T* __restrict__ X, T c, T* __restrict__ U) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    const T g0 = G[i], g1 = G[N + i], g2 = G[2 * N + i];
+    const T f = c * (g0 * X[i] + g1 * X[N + i] + g2 * X[2 * N + i]);
+    U[i] = f * g0;
+    U[N + i] = f * g1;
+    U[2 * N + i] = f * g2;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BX* BY) k_jacobian_det(Geo<T> g, const T* __restrict__ u, T* __restrict__ det) {
+  int i0, i1, i2;
+  if (!voxel(g, i0, i1, i2)) return;
+  const Nbr nb = neighbours(g, i0, i1, i2);
+  T J[3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      J[c][d] = (u[c * g.N + nb.o[1 + 2 * d]] - u[c * g.N + nb.o[2 + 2 * d]]) * g.inv2h[d] + (c == d ? T(1) : T(0));
+  det[nb.o[0]] = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+unsigned flat_blocks(long long N) {
+  long long b = (N + 255) / 256;
+  return (unsigned)(b < 8192 ? b : 8192);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_epdiff_stage(const Grid& g, const T* v, const T* mu, const T* mu0, T* mu_out, double dt, double a0,
+                         double a1, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "epdiff_stage", st);
+  k_epdiff_stage<T><<<field_grid(g), dim3(BX, BY), 0, st>>>(make_geo<T>(g), v, mu, mu0 ? mu0 : mu, mu_out, T(dt),
+                                                            T(a0), T(a1));
+}
+
+template <typename T>
+void launch_tangent_stage(const Grid& g, const T* X, const T* dmu, const T* W, const T* v, const T* mu,
+                          const T* X0, const T* dmu0, T* X_out, T* dmu_out, double dt, double a0, double a1,
+                          hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "tangent_stage", st);
+  k_tangent_stage<T><<<field_grid(g), dim3(BX, BY), 0, st>>>(make_geo<T>(g), X, dmu, W, v, mu, X0 ? X0 : X,
+                                                             dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt), T(a0), T(a1));
+}
+
+template <typename T>
+void launch_adjoint_pre(const Grid& g, const T* U, const T* w, const T* mu, T* Z, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "adjoint_pre", st);
+  k_adjoint_pre<T><<<field_grid(g), dim3(BX, BY), 0, st>>>(make_geo<T>(g), U, w, mu, Z);
+}
+
+template <typename T>
+void launch_adjoint_post(const Grid& g, const T* U, const T* w, const T* KZ, const T* v, const T* U0, const T* w0,
+                         T* U_out, T* w_out, double dt, double a0, double a1, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "adjoint_post", st);
+  k_adjoint_post<T><<<field_grid(g), dim3(BX, BY), 0, st>>>(make_geo<T>(g), U, w, KZ, v, U0 ? U0 : U, w0 ? w0 : w,
+                                                            U_out, w_out, T(dt), T(a0), T(a1));
+}
+
+template <typename T>
+void launch_residual_grad(const Grid& g, const T* J1, const T* I1, T* r, T* G, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "residual_grad", st);
+  k_residual_grad<T><<<field_grid(g), dim3(BX, BY), 0, st>>>(make_geo<T>(g), J1, I1, r, G);
+}
+
+template <typename T>
+void launch_scalar_times_vec(const Grid& g, const T* s, const T* G, double c, T* U, hipStream_t st,
+                             Profiler* prof) {
+  KernelTimer t(prof, "final_condition", st);
+  k_scalar_times_vec<T><<<flat_blocks(g.N), 256, 0, st>>>(g.N, s, G, T(c), U);
+}
+
+template <typename T>
+void launch_gn_final(const Grid& g, const T* G, const T* X, double c, T* U, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "gn_final_condition", st);
+  k_gn_final<T><<<flat_blocks(g.N), 256, 0, st>>>(g.N, G, X, T(c), U);
+}
+
+template <typename T>
+void launch_jacobian_det(const Grid& g, const T* u, T* det, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "jacobian_det", st);
+  k_jacobian_det<T><<<field_grid(g), dim3(BX, BY), 0, st>>>(make_geo<T>(g), u, det);
+}
+
+#define LDDMM_INST(T)                                                                                            \
+  template void launch_epdiff_stage<T>(const Grid&, const T*, const T*, const T*, T*, double, double, double,    \
+                                       hipStream_t, Profiler*);                                                  \
+  template void launch_tangent_stage<T>(const Grid&, const T*, const T*, const T*, const T*, const T*, const T*, \
+                                        const T*, T*, T*, double, double, double, hipStream_t, Profiler*);       \
+  template void launch_adjoint_pre<T>(const Grid&, const T*, const T*, const T*, T*, hipStream_t, Profiler*);   \
+  template void launch_adjoint_post<T>(const Grid&, const T*, const T*, const T*, const T*, const T*, const T*,  \
+                                       T*, T*, double, double, double, hipStream_t, Profiler*);                  \
+  template void launch_residual_grad<T>(const Grid&, const T*, const T*, T*, T*, hipStream_t, Profiler*);       \
+  template void launch_scalar_times_vec<T>(const Grid&, const T*, const T*, double, T*, hipStream_t, Profiler*); \
+  template void launch_gn_final<T>(const Grid&, const T*, const T*, double, T*, hipStream_t, Profiler*);        \
+  template void launch_jacobian_det<T>(const Grid&, const T*, T*, hipStream_t, Profiler*);
+
+LDDMM_INST(float)
+LDDMM_INST(double)
+
+}  // namespace lddmm

@@ -1,0 +1,63 @@
+// Host-side run of the FFT stage code of fft_core.h (the code the GPU kernels
+// execute per butterfly), for CPU tests against numpy.fft.  A stage has no
+// intra-stage hazards, so running its butterflies in order on one thread gives
+// the same result as the parallel run.
+#include <cmath>
+#include <vector>
+
+#include "fft_core.h"
+
+using namespace lddmm;
+
+namespace {
+
+template <bool INV>
+void run(cplx<double>* buf, const FftPlan& pl, const cplx<double>* tw) {
+  const int n = pl.n;
+  for (int i = 0; i < pl.nf; ++i) {
+    const int st = INV ? pl.nf - 1 - i : i;
+    const int r = pl.radix[st];
+    const int L = stage_length(pl, st);
+    for (int b = 0; b < n / r; ++b) {
+      switch (r) {
+        case 8: fft_stage_item<double, 8, INV, false>(buf, b, n, L, 1, 1, n, tw); break;
+        case 4: fft_stage_item<double, 4, INV, false>(buf, b, n, L, 1, 1, n, tw); break;
+        case 2: fft_stage_item<double, 2, INV, false>(buf, b, n, L, 1, 1, n, tw); break;
+        case 3: fft_stage_item<double, 3, INV, false>(buf, b, n, L, 1, 1, n, tw); break;
+        case 5: fft_stage_item<double, 5, INV, false>(buf, b, n, L, 1, 1, n, tw); break;
+        case 7: fft_stage_item<double, 7, INV, false>(buf, b, n, L, 1, 1, n, tw); break;
+        default: break;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+// In-place transform of n complex values (interleaved re, im).  inverse = 0:
+// DIF forward (output digit-reversed); 1: DIT inverse (input digit-reversed,
+// unnormalised).  Returns the number of stages, or -1 if n does not factor.
+int fftcore_transform(int n, double* data, int inverse) {
+  FftPlan pl;
+  if (!make_plan(n, pl)) return -1;
+  std::vector<cplx<double>> tw(n);
+  for (int m = 0; m < n; ++m) tw[m] = {std::cos(-2.0 * M_PI * m / n), std::sin(-2.0 * M_PI * m / n)};
+  auto* buf = reinterpret_cast<cplx<double>*>(data);
+  if (inverse)
+    run<true>(buf, pl, tw.data());
+  else
+    run<false>(buf, pl, tw.data());
+  return pl.nf;
+}
+
+// perm[p] = frequency held by DIF output slot p.
+int fftcore_digit_reverse(int n, int* perm) {
+  FftPlan pl;
+  if (!make_plan(n, pl)) return -1;
+  for (int p = 0; p < n; ++p) perm[p] = digit_reverse(pl, p);
+  return 0;
+}
+
+}
