@@ -1,0 +1,336 @@
+#!/usr/bin/env python3
+"""Benchmark of the LDDMM hot path on one MI355X.
+
+Workload (pair128): one template/target pair on a 128^3 periodic grid, nt = 10
+Heun steps, L = (Id - 0.0025 Laplacian)^2, sigma^2 = 1, FP32 fields with FP64
+reductions.  Template = seeded phantom (24 blobs, sigmas 4-12 voxels, tissue
+classes 0.2/0.5/0.8, ellipsoidal shell); target = template shot by a seeded
+band-limited v0 (max |v0| = 6 voxels) on the GPU in FP64, plus N(0, 0.01^2)
+noise.  Synthetic data stand in for the paper's brain volumes.
+
+One timed step = one full inexact Gauss-Newton-Krylov solve from v0 = 0 (10
+outer iterations, <= 20 CG iterations each, Armijo line search), i.e. every
+stage of the hot path: shooting with trajectory store, final conditions, the
+adjoint sweep, Hessian-vector products inside CG in V, line-search shoots.
+``value`` = solves per minute.  The same run also reports Hessian-vector
+products/s and gradients/s (HIP events on the library stream), the plain FP64
+path, the roofline of the dominant kernel and the CPU oracle on the host.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+# Algorithmic bytes per launch (each distinct operand read once, each result
+# written once) as a function of the grid; V = vector field, S = scalar field,
+# C = one component's half spectrum (N0 N1 (N2/2+1) complex).  The spectral
+# kernels always process the three components of a vector field here.
+def kernel_bytes(n, esize):
+    n0, n1, n2 = n
+    N = n0 * n1 * n2
+    S = N * esize
+    V = 3 * S
+    C = n0 * n1 * (n2 // 2 + 1) * 2 * esize
+    return {
+        "fft_plane_fwd": 3 * (S + C),
+        "fft_pencil_symbol": 3 * 2 * C,
+        "fft_plane_inv": 3 * (C + S),
+        "fft_rows_fwd": 3 * (S + C),
+        "fft_pencil_x1_fwd": 3 * 2 * C,
+        "fft_pencil_x1_inv": 3 * 2 * C,
+        "fft_rows_inv": 3 * (C + S),
+        "tangent_stage_pred": 7 * V,
+        "tangent_stage_corr": 9 * V,
+        "adjoint_pre": 4 * V,
+        "adjoint_post_pred": 6 * V,
+        "adjoint_post_corr": 8 * V,
+        "epdiff_stage_pred": 3 * V,
+        "epdiff_stage_corr": 4 * V,
+        "sl_step": 4 * V,
+        "compose": 2 * S + V,
+        "residual_grad": 3 * S + V,
+        "gn_final_condition": 3 * V,
+        "final_condition": S + 2 * V,
+    }
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_pair(spec, dtype, dev, torch, Registration, synth):
+    I0 = synth.phantom(spec.n, spec.n_blobs, spec.sigma_range, spec.classes, 1000, shells=spec.shells)
+    v0t = synth.random_velocity(spec.n, 2000, spec.disp_vox)
+    nz = synth.noise(spec.n, 3000, spec.noise_sd)
+    # target: FP64 GPU shoot of the seeded v0, plus noise
+    R = Registration(spec.n, spec.nt, spec.alpha, spec.s, spec.sigma2, dtype=torch.float64, device=dev)
+    t0 = torch.tensor(I0, dtype=torch.float64, device=dev)
+    R.set_images(t0, t0)
+    J1 = R.shoot(torch.tensor(v0t, dtype=torch.float64, device=dev), want=("J1",))["J1"]
+    I1 = (J1 + torch.tensor(nz, dtype=torch.float64, device=dev)).cpu().numpy()
+    R.close()
+    return I0, I1, v0t
+
+
+def time_events(torch, fn, reps):
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(reps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / reps  # ms
+
+
+def cpu_baseline(spec, I0, I1, v0t, solve_over_hv):
+    """Time the FP64 oracle's Hessian-vector product on the host, on a bounded
+    sample: the same 128^3 pair and operators over 2 of the nt time steps (the
+    sweep cost is linear in nt).  Scaled to nt steps, then to one solve by the
+    GPU's solve-time / Hv-time ratio."""
+    import numpy as np
+
+    import oracle as O
+    from synth import random_field
+
+    nt_s = 2
+    p = O.Params(spec.n, spec.alpha, spec.s, nt_s, spec.sigma2)
+    lin = O.linearize(0.5 * np.asarray(v0t), I0, I1, p)
+    dv = random_field(spec.n, 7)
+    t = time.perf_counter()
+    O.hessvec(dv, lin, p)
+    dt = time.perf_counter() - t
+    hv_full = dt * spec.nt / nt_s
+    per_solve = hv_full * solve_over_hv
+    return {
+        "value": round(60.0 / per_solve, 5),
+        "unit": "GN solves/min",
+        "cores": os.cpu_count(),
+        "kind": "oracle",
+        "sample": (
+            f"one FP64 oracle Hessian-vector product at {spec.n[0]}x{spec.n[1]}x{spec.n[2]} over {nt_s} of "
+            f"{spec.nt} time steps ({dt:.1f} s; scipy.fft on {os.cpu_count()} threads, numpy elementwise on one), "
+            f"scaled x{spec.nt / nt_s:g} to nt={spec.nt} ({hv_full:.1f} s per Hv) and x{solve_over_hv:.1f} "
+            "(GPU solve/Hv time ratio) to a solve"
+        ),
+        "hv_per_s": round(1.0 / hv_full, 5),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="pair128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--hv-reps", type=int, default=20)
+    ap.add_argument(
+        "--profile-hv",
+        type=int,
+        default=0,
+        metavar="K",
+        help="profiling mode: K Hessian-vector products at the workload's linearization, then "
+        "4 plain copies of 256 MiB (counter calibration), and exit",
+    )
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(
+            "bench.py measures one GPU only: the hot path runs on one MI355X per registration "
+            "problem; run it with --gpus 1",
+            file=sys.stderr,
+        )
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1807_04638_amd import Registration
+
+    spec = synth.WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"[bench] workload {spec.name} n={spec.n} nt={spec.nt}: building inputs")
+    I0, I1, v0t = make_pair(spec, torch.float64, dev, torch, Registration, synth)
+
+    def context(dtype):
+        R = Registration(spec.n, spec.nt, spec.alpha, spec.s, spec.sigma2, dtype=dtype, device=dev)
+        R.set_images(torch.tensor(I0, dtype=dtype, device=dev), torch.tensor(I1, dtype=dtype, device=dev))
+        return R
+
+    def solve(R, dtype):
+        v = torch.zeros((3,) + spec.n, dtype=dtype, device=dev)
+        return R.gn_solve(v, gn_iters=spec.gn_iters, cg_iters=spec.cg_iters)
+
+    R = context(torch.float32)
+    if args.profile_hv:
+        vlin = torch.tensor(0.5 * v0t, dtype=torch.float32, device=dev)
+        dv = torch.randn((3,) + spec.n, device=dev, generator=torch.Generator(device=dev).manual_seed(7))
+        hv = torch.empty_like(dv)
+        R.linearize(vlin)
+        for i in range(args.profile_hv):
+            R.hessvec(dv, out=hv)
+            torch.cuda.synchronize()
+            log(f"[bench] profile hessvec {i + 1}/{args.profile_hv}")
+        src = torch.ones(64 * 2**20, dtype=torch.float32, device=dev)  # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_hv": args.profile_hv, "copy_bytes_each_way": src.numel() * 4}), flush=True)
+        return
+    log(f"[bench] warmup {args.warmup} solve(s)")
+    for _ in range(args.warmup):
+        solve(R, torch.float32)
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} solve(s)")
+    t0 = time.perf_counter()
+    traces = []
+    for _ in range(args.steps):
+        traces.append(solve(R, torch.float32))
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    rep = traces[-1].report
+    ms_per_step = 1e3 * T / args.steps
+    log(f"[bench] {ms_per_step:.1f} ms per solve, report {rep}")
+
+    # Hessian-vector products and gradients (HIP events on the library stream)
+    vlin = torch.tensor(0.5 * v0t, dtype=torch.float32, device=dev)
+    dv = torch.randn((3,) + spec.n, device=dev, generator=torch.Generator(device=dev).manual_seed(7))
+    hv = torch.empty_like(dv)
+    g = torch.empty_like(dv)
+    R.linearize(vlin)
+    R.hessvec(dv, out=hv)
+    hv_ms = time_events(torch, lambda: R.hessvec(dv, out=hv), args.hv_reps)
+    grad_ms = time_events(torch, lambda: R.gradient(vlin, out=g), 5)
+    shoot_ms = time_events(torch, lambda: R.shoot(vlin, want=("J1",)), 5)
+    log(f"[bench] hessvec {hv_ms:.3f} ms, gradient {grad_ms:.3f} ms, shoot {shoot_ms:.3f} ms")
+
+    # per-kernel HIP-event timing over Hessian-vector products -> roofline
+    R.linearize(vlin)
+    R.profile_enable(True)
+    for _ in range(5):
+        R.hessvec(dv, out=hv)
+    prof = R.profile_read()
+    R.profile_enable(False)
+    nbytes = kernel_bytes(spec.n, 4)
+    kernels = {}
+    for name, (cnt, ms) in prof.items():
+        avg_us = 1e3 * ms / max(cnt, 1)
+        kb = nbytes.get(name)
+        kernels[name] = {
+            "launches_per_hv": cnt / 5,
+            "avg_us": round(avg_us, 2),
+            "share": round(ms / sum(v[1] for v in prof.values()), 4),
+            "GBps": round(kb / (avg_us * 1e-6) / 1e9, 1) if kb else None,
+        }
+    dom = max((k for k in kernels if k in nbytes), key=lambda k: prof[k][1])
+    dom_bytes = nbytes[dom]
+    dom_avg_s = kernels[dom]["avg_us"] * 1e-6
+    achieved = dom_bytes / dom_avg_s / 1e9
+    hv_bytes = sum(nbytes[k] * kernels[k]["launches_per_hv"] for k in kernels if k in nbytes)
+    log(f"[bench] dominant kernel {dom}: {kernels[dom]}")
+
+    # plain FP64 path
+    fp64 = None
+    if not args.no_fp64:
+        del R
+        torch.cuda.empty_cache()
+        R64 = context(torch.float64)
+        v64 = torch.tensor(0.5 * v0t, dtype=torch.float64, device=dev)
+        d64 = dv.double()
+        R64.hessvec(d64, v0=v64)
+        hv64_ms = time_events(torch, lambda: R64.hessvec(d64), max(5, args.hv_reps // 4))
+        t1 = time.perf_counter()
+        tr64 = solve(R64, torch.float64)
+        torch.cuda.synchronize()
+        s64 = time.perf_counter() - t1
+        fp64 = {
+            "gn_solves_per_min": round(60.0 / s64, 3),
+            "ms_per_solve": round(1e3 * s64, 1),
+            "hv_per_s": round(1e3 / hv64_ms, 2),
+            "mse_rel_final": tr64.report["mse_rel_final"],
+            "E_final": tr64.report["E_final"],
+            "hessvecs": tr64.report["hessvecs"],
+        }
+        log(f"[bench] fp64 {fp64}")
+        del R64
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline(spec, I0, I1, v0t, ms_per_step / hv_ms)
+
+    value = 60.0 * args.steps / T
+    out = {
+        "metric": "Hessian-vector products/s & GN solves/min at 128^3 vs FP64 path; % HBM peak",
+        "value": round(value, 3),
+        "unit": "GN solves/min",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{spec.name}: {spec.n[0]}x{spec.n[1]}x{spec.n[2]} pair, nt={spec.nt}, alpha={spec.alpha}, "
+            f"s={spec.s}, sigma2={spec.sigma2}, GN<= {spec.gn_iters}, CG<= {spec.cg_iters}, FP32 fields + FP64 reductions",
+            "global_batch": 1,
+            "grid": list(spec.n),
+            "parallelism": "single GPU",
+        },
+        "hv_per_s": round(1e3 / hv_ms, 2),
+        "ms_per_hv": round(hv_ms, 3),
+        "gradients_per_s": round(1e3 / grad_ms, 2),
+        "shoots_per_s": round(1e3 / shoot_ms, 2),
+        "solve": {
+            "iters": rep["iters"],
+            "hessvecs": rep["hessvecs"],
+            "gradients": rep["gradients"],
+            "line_search_shoots": rep["shoots"],
+            "mse_rel_final": rep["mse_rel_final"],
+            "E_first": rep["E_first"],
+            "E_final": rep["E_final"],
+        },
+        "fp64": fp64,
+        "fp32_speedup_vs_fp64": round(fp64["ms_per_solve"] / ms_per_step, 3) if fp64 else None,
+        "hv_algorithmic_GBps": round(hv_bytes / (hv_ms * 1e-3) / 1e9, 1),
+        "hv_algorithmic_bytes": int(hv_bytes),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "bytes_per_launch": int(dom_bytes),
+            "avg_launch_us": kernels[dom]["avg_us"],
+        },
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -311,7 +311,7 @@ unsigned flat_blocks(long long N) {
 template <typename T>
 void launch_epdiff_stage(const Grid& g, const T* v, const T* mu, const T* mu0, T* mu_out, double dt, double a0,
                          double a1, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, "epdiff_stage", st);
+  KernelTimer t(prof, a0 != 0.0 ? "epdiff_stage_corr" : "epdiff_stage_pred", st);
   k_epdiff_stage<T><<<field_grid(g), dim3(BX, BY), 0, st>>>(make_geo<T>(g), v, mu, mu0 ? mu0 : mu, mu_out, T(dt),
                                                             T(a0), T(a1));
 }
@@ -320,7 +320,7 @@ template <typename T>
 void launch_tangent_stage(const Grid& g, const T* X, const T* dmu, const T* W, const T* v, const T* mu,
                           const T* X0, const T* dmu0, T* X_out, T* dmu_out, double dt, double a0, double a1,
                           hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, "tangent_stage", st);
+  KernelTimer t(prof, a0 != 0.0 ? "tangent_stage_corr" : "tangent_stage_pred", st);
   k_tangent_stage<T><<<field_grid(g), dim3(BX, BY), 0, st>>>(make_geo<T>(g), X, dmu, W, v, mu, X0 ? X0 : X,
                                                              dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt), T(a0), T(a1));
 }
@@ -334,7 +334,7 @@ void launch_adjoint_pre(const Grid& g, const T* U, const T* w, const T* mu, T* Z
 template <typename T>
 void launch_adjoint_post(const Grid& g, const T* U, const T* w, const T* KZ, const T* v, const T* U0, const T* w0,
                          T* U_out, T* w_out, double dt, double a0, double a1, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, "adjoint_post", st);
+  KernelTimer t(prof, a0 != 0.0 ? "adjoint_post_corr" : "adjoint_post_pred", st);
   k_adjoint_post<T><<<field_grid(g), dim3(BX, BY), 0, st>>>(make_geo<T>(g), U, w, KZ, v, U0 ? U0 : U, w0 ? w0 : w,
                                                             U_out, w_out, T(dt), T(a0), T(a1));
 }

@@ -1,0 +1,374 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Inputs are seeded synthetic phantoms / band-limited fields from ``synth``; the
+same arrays feed both sides.  Tolerances (relative L2):
+  FP64 fields: 1e-11 (operators 1e-12) - both sides are FP64 with different
+                summation orders;
+  FP32 fields: shooting outputs 1e-5, gradient and Hessian-vector product 1e-4
+                (the stated FP32 targets), operators 2e-6.
+Sizes span several FFT stages, mixed radices (2, 3, 5, 8) and non-cubic grids,
+including one that takes the split (non-fused) transform path.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import phantom, random_field, random_velocity
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    a = np.asarray(a.detach().cpu() if torch.is_tensor(a) else a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def T(x, dtype):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+TOL = {
+    torch.float64: dict(op=1e-12, shoot=1e-11, grad=1e-11, hv=1e-11),
+    torch.float32: dict(op=2e-6, shoot=1e-5, grad=1e-4, hv=1e-4),
+}
+
+
+def l_tol(p, f, Lf, dtype):
+    """Bound for applying L: transform roundoff (relative eps per mode) is
+    multiplied by the symbol, so the relative error of L f is about
+    eps * rms(L^) * ||f|| / ||L f||; K^ <= 1 has no such growth."""
+    eps = 1.1e-16 if dtype == torch.float64 else 6e-8
+    lam = O.symbol_L(p)
+    amp = math.sqrt(float(np.mean(lam * lam))) * np.linalg.norm(f) / np.linalg.norm(Lf)
+    return max(TOL[dtype]["op"], 16 * eps * amp)
+
+
+def rounded(x, dtype):
+    """The values the device actually receives for x."""
+    return T(x, dtype).double().cpu().numpy()
+
+
+def make(n, dtype, nt=6, alpha=0.01, s=2, sigma2=1.0):
+    from paper_1807_04638_amd import Registration
+
+    say(f"[case] n={n} dtype={dtype} nt={nt} alpha={alpha} s={s} sigma2={sigma2}")
+    return Registration(n, nt, alpha, s, sigma2, dtype=dtype), O.Params(tuple(n), alpha, s, nt, sigma2)
+
+
+def images(n, seed=0):
+    I0 = phantom(n, 4, (1.5, 3.0), False, 1000 + seed)
+    I1 = phantom(n, 4, (1.5, 3.0), False, 1100 + seed)
+    return I0, I1
+
+
+DTYPES = [torch.float64, torch.float32]
+SMALL = [(16, 12, 20), (32, 32, 32), (24, 20, 30)]
+
+
+# ------------------------------------------------------------------ a1: K / L
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", SMALL + [(8, 10, 6)])
+def test_operator_parity(n, dtype):
+    R, p = make(n, dtype)
+    f = rounded(random_field(n, 1, kc=max(n) / 4), dtype)
+    Lf = O.apply_L(f, p)
+    for op, ref, tol in (("K", O.apply_K(f, p), TOL[dtype]["op"]), ("L", Lf, l_tol(p, f, Lf, dtype))):
+        got = R.apply_K(T(f, dtype)) if op == "K" else R.apply_L(T(f, dtype))
+        e = rel(got, ref)
+        say(f"  {op} rel {e:.3e} (tol {tol:.1e})")
+        assert e <= tol
+    # scalar fields, and in-place use
+    s = T(f[0], dtype)
+    R.apply_K(s, out=s)
+    assert rel(s, O.apply_K(f[0], p)) <= TOL[dtype]["op"]
+
+
+def test_operator_split_path_fp64():
+    """(x1, x2) half-plane of 256 x 129 complex doubles exceeds LDS: split passes."""
+    n = (6, 256, 256)
+    R, p = make(n, torch.float64, alpha=0.002)
+    f = random_field(n, 2, kc=20.0)
+    assert rel(R.apply_K(T(f, torch.float64)), O.apply_K(f, p)) <= 1e-12
+    assert rel(R.apply_L(T(f, torch.float64)), O.apply_L(f, p)) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_operator_single_modes_closed_form(dtype):
+    n = (16, 24, 20)
+    R, p = make(n, dtype, alpha=0.03, s=3)
+    x = O.grid_coords(p)
+    # L amplifies the rounding of the input in the highest modes by up to
+    # max(L^) / L^(k) relative to the mode itself
+    lam_max = (1.0 + p.alpha * sum((N // 2) ** 2 for N in n)) ** p.s
+    eps = 1e-16 if dtype == torch.float64 else 6e-8
+    for k in [(0, 0, 0), (1, 2, 3), (8, -5, 10), (3, 12, 1)]:
+        f = np.cos(k[0] * x[0] + k[1] * x[1] + k[2] * x[2] + 0.4)
+        lam = (1.0 + p.alpha * (k[0] ** 2 + k[1] ** 2 + k[2] ** 2)) ** p.s
+        assert rel(R.apply_L(T(f, dtype)), lam * f) <= TOL[dtype]["op"] + 2 * eps * lam_max / lam
+        assert rel(R.apply_K(T(f, dtype)), f / lam) <= TOL[dtype]["op"]
+
+
+# ------------------------------------------------------------------ FP64 dots
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_dot_parity(dtype):
+    n = (16, 12, 20)
+    R, p = make(n, dtype)
+    a, b = random_field(n, 3), random_field(n, 4)
+    ta, tb = T(a, dtype), T(b, dtype)
+    ref = O.inner(ta.double().cpu().numpy(), tb.double().cpu().numpy(), p)
+    assert R.dot(ta, tb) == pytest.approx(ref, rel=1e-13)
+    assert R.dot(ta[0].contiguous(), tb[0].contiguous()) == pytest.approx(
+        O.inner(ta[0].double().cpu().numpy(), tb[0].double().cpu().numpy(), p), rel=1e-13
+    )
+
+
+# ------------------------------------------------------------------ a2, a3: shooting
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", SMALL)
+def test_shoot_parity(n, dtype):
+    R, p = make(n, dtype)
+    I0, I1 = images(n)
+    R.set_images(T(I0, dtype), T(I1, dtype))
+    v0 = random_velocity(n, 2000, 1.5, kc=2.0)
+    out = R.shoot(T(v0, dtype), energy=True)
+    tr = O.shoot(v0, p, I0)
+    errs = dict(v1=rel(out["v1"], tr.v[-1]), u1=rel(out["u1"], tr.u), J1=rel(out["J1"], tr.J1))
+    say("  shoot", errs)
+    for k, e in errs.items():
+        assert e <= TOL[dtype]["shoot"], k
+    assert out["energy"] == pytest.approx(O.energy(v0, I0, I1, p), rel=TOL[dtype]["shoot"])
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_shoot_zero_velocity_is_identity(dtype):
+    n = (16, 12, 20)
+    R, p = make(n, dtype)
+    I0, I1 = images(n)
+    tI0 = T(I0, dtype)
+    R.set_images(tI0, T(I1, dtype))
+    out = R.shoot(torch.zeros((3,) + n, dtype=dtype, device=DEV))
+    assert torch.equal(out["J1"], tI0)
+    assert torch.count_nonzero(out["u1"]) == 0 and torch.count_nonzero(out["v1"]) == 0
+
+
+# ------------------------------------------------------------------ a4, a5: gradient
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", SMALL)
+def test_gradient_parity(n, dtype):
+    R, p = make(n, dtype, sigma2=0.05)
+    I0, I1 = images(n)
+    R.set_images(T(I0, dtype), T(I1, dtype))
+    v0 = random_velocity(n, 2001, 1.5, kc=2.0)
+    g, E = R.gradient(T(v0, dtype))
+    go, lin = O.gradient(v0, I0, I1, p)
+    e = rel(g, go)
+    say(f"  gradient rel {e:.3e}  E {E} vs {lin.E}")
+    assert e <= TOL[dtype]["grad"]
+    assert E == pytest.approx(lin.E, rel=TOL[dtype]["shoot"])
+
+
+# ------------------------------------------------------------------ a6, a7: Hv
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", SMALL)
+def test_hessvec_parity(n, dtype):
+    R, p = make(n, dtype, sigma2=0.05)
+    I0, I1 = images(n)
+    R.set_images(T(I0, dtype), T(I1, dtype))
+    v0 = random_velocity(n, 2002, 1.5, kc=2.0)
+    dv = random_field(n, 5, kc=3.0)
+    hv = R.hessvec(T(dv, dtype), v0=T(v0, dtype))
+    lin = O.linearize(v0, I0, I1, p)
+    ho = O.hessvec(dv, lin, p)
+    e = rel(hv, ho)
+    say(f"  hessvec rel {e:.3e}")
+    assert e <= TOL[dtype]["hv"]
+    # the current linearization is reused when v0 is omitted, bit for bit
+    hv2 = R.hessvec(T(dv, dtype))
+    assert torch.equal(hv, hv2)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_vjp_parity(dtype):
+    n = (16, 12, 20)
+    R, p = make(n, dtype)
+    I0, I1 = images(n)
+    R.set_images(T(I0, dtype), T(I1, dtype))
+    v0 = random_velocity(n, 2003, 1.5, kc=2.0)
+    gbar = random_field(n, 6, components=1)[0]
+    R.linearize(T(v0, dtype))
+    got = R.vjp(T(gbar, dtype))
+    lin = O.linearize(v0, I0, I1, p)
+    assert rel(got, O.vjp_J1(gbar, lin, p)) <= TOL[dtype]["grad"]
+
+
+# ------------------------------------------------------------------ a8: CG in V
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_cg_parity(dtype):
+    n = (16, 12, 20)
+    R, p = make(n, dtype, sigma2=0.05)
+    I0, I1 = images(n)
+    R.set_images(T(I0, dtype), T(I1, dtype))
+    v0 = random_velocity(n, 2004, 1.0, kc=2.0)
+    g, _ = R.gradient(T(v0, dtype))
+    go, lin = O.gradient(v0, I0, I1, p)
+    x, its = R.cg_solve(g, 0.05, 6)
+    xo, its_o = O.cg_v(lambda d: O.hessvec(d, lin, p), g.double().cpu().numpy(), p, 0.05, 6)
+    say(f"  cg its {its} vs {its_o}  rel {rel(x, xo):.3e}")
+    assert its == its_o
+    assert rel(x, xo) <= (1e-10 if dtype == torch.float64 else 1e-4)
+
+
+# ------------------------------------------------------------------ a9: GN loop
+def test_gn_solve_parity_fp64():
+    n = (16, 16, 16)
+    R, p = make(n, torch.float64, nt=5, sigma2=0.02)
+    I0 = phantom(n, 4, (1.5, 3.0), False, 1000)
+    vt = random_velocity(n, 2100, 1.0, kc=2.0)
+    I1 = O.shoot(vt, p, I0).J1
+    R.set_images(T(I0, torch.float64), T(I1, torch.float64))
+    v = torch.zeros((3,) + n, dtype=torch.float64, device=DEV)
+    tr = R.gn_solve(v, gn_iters=3, cg_iters=6)
+    vo, log, lin = O.gn_solve(I0, I1, p, gn_iters=3, cg_iters=6)
+    say("  gpu", tr.report, "\n  oracle", [(it.E, it.cg_iters, it.tau) for it in log])
+    assert len(tr.log) == len(log)
+    for a, b in zip(tr.log, log):
+        assert a["cg_iters"] == b.cg_iters and a["tau"] == b.tau
+        assert a["E"] == pytest.approx(b.E, rel=1e-10)
+        assert a["mse_rel"] == pytest.approx(b.mse_rel, rel=1e-9)
+        assert a["g_inf_rel"] == pytest.approx(b.g_inf_rel, rel=1e-9)
+    assert tr.report["E_final"] == pytest.approx(lin.E, rel=1e-10)
+    assert rel(v, vo) <= 1e-9
+
+
+def test_gn_solve_fp32_reaches_fp64_energy():
+    n = (16, 16, 16)
+    I0 = phantom(n, 4, (1.5, 3.0), False, 1000)
+    p = O.Params(n, 0.01, 2, 5, 0.02)
+    I1 = O.shoot(random_velocity(n, 2100, 1.0, kc=2.0), p, I0).J1
+    out = {}
+    for dtype in DTYPES:
+        R, _ = make(n, dtype, nt=5, sigma2=0.02)
+        R.set_images(T(I0, dtype), T(I1, dtype))
+        v = torch.zeros((3,) + n, dtype=dtype, device=DEV)
+        out[dtype] = R.gn_solve(v, gn_iters=4, cg_iters=6).report
+    a, b = out[torch.float32], out[torch.float64]
+    assert a["E_final"] == pytest.approx(b["E_final"], rel=1e-3)
+    assert a["E_final"] < a["E_first"]
+
+
+# ------------------------------------------------------------------ metrics / errors
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_jacobian_det_parity(dtype):
+    n = (16, 12, 20)
+    R, p = make(n, dtype)
+    u = 0.1 * random_field(n, 7, kc=2.0)
+    det, mn, mx = R.jacobian_det(T(u, dtype))
+    ref = O.jacobian_det(u, p)
+    assert rel(det, ref) <= (1e-13 if dtype == torch.float64 else 1e-6)
+    assert mn == pytest.approx(ref.min(), rel=1e-5) and mx == pytest.approx(ref.max(), rel=1e-5)
+
+
+def test_error_paths():
+    from paper_1807_04638_amd import LddmmError, Registration
+
+    n = (16, 12, 20)
+    R, p = make(n, torch.float32)
+    v = torch.zeros((3,) + n, device=DEV)
+    with pytest.raises(LddmmError) as e:
+        R.hessvec(v)  # no linearization yet
+    assert e.value.status == -6
+    I0, I1 = images(n)
+    R.set_images(T(I0, torch.float32), T(I1, torch.float32))
+    bad = v.clone()
+    bad[1, 3, 4, 5] = float("nan")
+    with pytest.raises(LddmmError) as e:
+        R.gradient(bad)
+    assert e.value.status == -5
+    with pytest.raises(LddmmError) as e:
+        Registration((16, 22, 20), 4, 0.01)
+    assert e.value.status == -2
+    with pytest.raises(ValueError):
+        R.gradient(torch.zeros((3, 16, 12, 21), device=DEV))
+
+
+# ------------------------------------------------------------------ full size (128^3, nt = 10)
+FULL = (128, 128, 128)
+
+
+def full_case(dtype):
+    R, p = make(FULL, dtype, nt=10, alpha=0.0025, s=2, sigma2=1.0)
+    I0 = phantom(FULL, 24, (4.0, 12.0), True, 1000)
+    I1 = phantom(FULL, 24, (4.0, 12.0), True, 1001)
+    R.set_images(T(I0, dtype), T(I1, dtype))
+    return R, p, I0, I1
+
+
+def test_full_size_operator_parity():
+    R, p, _, _ = full_case(torch.float32)
+    f = rounded(random_field(FULL, 8), torch.float32)
+    Lf = O.apply_L(f, p)
+    eK, eL = rel(R.apply_K(T(f, torch.float32)), O.apply_K(f, p)), rel(R.apply_L(T(f, torch.float32)), Lf)
+    say(f"  K rel {eK:.3e}  L rel {eL:.3e} (tol {l_tol(p, f, Lf, torch.float32):.1e})")
+    assert eK <= 2e-6
+    assert eL <= l_tol(p, f, Lf, torch.float32)
+
+
+def test_full_size_v0_zero_closed_forms():
+    """At v0 = 0: g = -(2/s2) K((I0 - I1) grad I0), H dv = 2 dv + (2/s2) K[(grad I0 . dv) grad I0]."""
+    R, p, I0, I1 = full_case(torch.float32)
+    z = torch.zeros((3,) + FULL, device=DEV)
+    g, _ = R.gradient(z)
+    gI0 = O.grad(I0, p)
+    ref_g = -(2.0 / p.sigma2) * O.apply_K((I0 - I1)[None] * gI0, p)
+    assert rel(g, ref_g) <= 1e-4
+    dv = random_field(FULL, 9)
+    hv = R.hessvec(T(dv, torch.float32))
+    ref_h = 2 * dv + (2.0 / p.sigma2) * O.apply_K(np.sum(gI0 * dv, axis=0)[None] * gI0, p)
+    assert rel(hv, ref_h) <= 1e-4
+
+
+def test_full_size_fp32_vs_fp64_and_hessian_properties():
+    v0 = random_velocity(FULL, 2000, 6.0)
+    a, b = random_field(FULL, 10), random_field(FULL, 11)
+    res = {}
+    for dtype in DTYPES:
+        R, p, _, _ = full_case(dtype)
+        tv = T(v0, dtype)
+        sh = R.shoot(tv)
+        g, E = R.gradient(tv)
+        ta, tb = T(a, dtype), T(b, dtype)
+        Ha, Hb = R.hessvec(ta), R.hessvec(tb)
+        La, Lb = R.apply_L(ta), R.apply_L(tb)
+        res[dtype] = dict(J1=sh["J1"].double().cpu(), v1=sh["v1"].double().cpu(), g=g.double().cpu(),
+                          Ha=Ha.double().cpu(), E=E, aHb=R.dot(La, Hb), Hab=R.dot(Ha, Lb),
+                          aHa=R.dot(La, Ha), aa=R.dot(La, ta))
+        say(f"  {dtype} symmetry {res[dtype]['aHb']} {res[dtype]['Hab']} rayleigh {res[dtype]['aHa'] / res[dtype]['aa']}")
+        sym_tol = 1e-11 if dtype == torch.float64 else 1e-4
+        assert abs(res[dtype]["aHb"] - res[dtype]["Hab"]) <= sym_tol * abs(res[dtype]["aHb"])
+        assert res[dtype]["aHa"] >= 2.0 * res[dtype]["aa"] * (1 - sym_tol)
+        del R
+        torch.cuda.empty_cache()
+    f32, f64 = res[torch.float32], res[torch.float64]
+    errs = {k: rel(f32[k].numpy(), f64[k].numpy()) for k in ("J1", "v1", "g", "Ha")}
+    say("  fp32 vs fp64", errs)
+    assert errs["J1"] <= 1e-5 and errs["v1"] <= 1e-5
+    assert errs["g"] <= 1e-4 and errs["Ha"] <= 1e-4
+    assert f32["E"] == pytest.approx(f64["E"], rel=1e-5)
+
+
+def test_deterministic_repeat():
+    R, p, _, _ = full_case(torch.float32)
+    dv = T(random_field(FULL, 12), torch.float32)
+    R.linearize(T(random_velocity(FULL, 2000, 6.0), torch.float32))
+    assert torch.equal(R.hessvec(dv), R.hessvec(dv))
