@@ -45,7 +45,7 @@ extern "C" {
 
 #define LDDMM_OK 0
 #define LDDMM_EINVAL (-1)       /* bad argument (NULL pointer, size, dtype)            */
-#define LDDMM_EUNSUPPORTED (-2) /* grid size with a prime factor > 7, odd N2, N_d < 4  */
+#define LDDMM_EUNSUPPORTED (-2) /* grid size: prime factor > 7, odd N2, N_d < 4, 3N >= 2^31 */
 #define LDDMM_ENOMEM (-3)       /* device allocation failed                            */
 #define LDDMM_EHIP (-4)         /* a HIP runtime call failed                           */
 #define LDDMM_ENONFINITE (-5)   /* an input field holds NaN or Inf                     */
@@ -60,7 +60,8 @@ extern "C" {
 
 typedef struct lddmm_ctx lddmm_ctx;
 
-/* Model and grid.  n[d] = N_d (each a product of 2, 3, 5, 7; N2 even; N_d >= 4),
+/* Model and grid.  n[d] = N_d (each a product of 2, 3, 5, 7; N2 even; N_d >= 4;
+ * 3 N0 N1 N2 < 2^31),
  * nt >= 1 Heun steps on [0, 1], s >= 1 and alpha > 0 of L, sigma2 > 0 the
  * image-noise variance of the data term (Section 3 energy).
  * mem_budget_bytes and checkpoint_every are reserved (0). */
@@ -179,6 +180,21 @@ int lddmm_jacobian_det(lddmm_ctx* ctx, const void* u, void* det, double* det_min
  * returns the number of kernel kinds (synchronises). */
 int lddmm_profile_enable(lddmm_ctx* ctx, int enable);
 int lddmm_profile_read(lddmm_ctx* ctx, const char** names, int64_t* counts, double* total_ms, int cap);
+
+/* Launch-shape options of the context's kernels (tuning; results do not change
+ * beyond rounding).  Keys:
+ *   "fft.plane_threads"   256 | 512 | 1024  threads of an (x1, x2) plane workgroup
+ *   "fft.pencil_threads"  256 | 512         threads of a pencil workgroup
+ *   "fft.pencil_tb"       1..128            contiguous pencils per workgroup
+ *   "fft.rows_rb"         1..64             rows per workgroup (split path)
+ *   "fft.force_split"     0 | 1             split transform path even where a plane fits
+ *   "fft.static"          0 | 1             compile-time kernels for power-of-two lengths
+ *   "fft.fused"           read-only: 1 if the fused plane path is in use
+ *   "fft.static_kernels"  read-only: number of passes using compile-time kernels
+ * LDDMM_EINVAL for an unknown key or a value out of range, LDDMM_EUNSUPPORTED if
+ * the tiles would not fit the LDS of a workgroup (the previous setting stays). */
+int lddmm_set_option(lddmm_ctx* ctx, const char* key, int64_t value);
+int lddmm_get_option(lddmm_ctx* ctx, const char* key, int64_t* value);
 
 /* Bytes of device memory held by the context. */
 int lddmm_memory_bytes(lddmm_ctx* ctx, int64_t* bytes);

@@ -59,14 +59,16 @@ __device__ void lds_fft(cplx<T>* buf, const FftPlan& pl, int count, int es, int 
 }
 
 // Rows of H complex pairs at A[r * M + j]: forward transform then split into the
-// N2/2 + 1 real-signal frequencies X[k]; X[k] lands in column slot2[k].
+// N2/2 + 1 real-signal frequencies X[k]; X[k] lands in column slot2[k].  Lanes
+// walk consecutive rows (stride M = H + 1 complex, an odd number of 8- or
+// 16-byte words), which keeps a wavefront's LDS accesses on distinct banks.
 template <typename T>
 __device__ void rows_r2c(cplx<T>* A, int count, int H, int M, const FftPlan& p2, const cplx<T>* tw2,
                          const cplx<T>* twr, const int* slot2) {
-  lds_fft<T, false, false>(A, p2, count, 1, M, tw2);
+  lds_fft<T, false, true>(A, p2, count, 1, M, tw2);
   const int per = H / 2 + 1;
   for (int idx = threadIdx.x; idx < count * per; idx += blockDim.x) {
-    const int r = idx / per, k = idx - r * per;
+    const int k = idx / count, r = idx - k * count;
     cplx<T>* row = A + r * M;
     if (k == 0) {
       const cplx<T> z = row[0];
@@ -94,7 +96,7 @@ __device__ void rows_c2r(cplx<T>* A, int count, int H, int M, const FftPlan& p2,
                          const cplx<T>* twr, const int* slot2) {
   const int per = H / 2 + 1;
   for (int idx = threadIdx.x; idx < count * per; idx += blockDim.x) {
-    const int r = idx / per, k = idx - r * per;
+    const int k = idx / count, r = idx - k * count;
     cplx<T>* row = A + r * M;
     if (k == 0) {
       const cplx<T> a = row[0], b = row[H];
@@ -112,7 +114,7 @@ __device__ void rows_c2r(cplx<T>* A, int count, int H, int M, const FftPlan& p2,
     }
   }
   __syncthreads();
-  lds_fft<T, true, false>(A, p2, count, 1, M, tw2);
+  lds_fft<T, true, true>(A, p2, count, 1, M, tw2);
 }
 
 template <typename T>
@@ -164,8 +166,8 @@ __device__ PlaneLds<T> carve(unsigned char* smem, int rows, const PlaneArgs<T>& 
 }
 
 // One (x0, component) plane: real rows -> x2 spectrum -> x1 columns.
-template <typename T>
-__global__ void __launch_bounds__(512) k_plane_fwd(const T* __restrict__ in, cplx<T>* __restrict__ spec,
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_plane_fwd(const T* __restrict__ in, cplx<T>* __restrict__ spec,
                                                    PlaneArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int x0 = blockIdx.x, comp = blockIdx.y;
@@ -185,8 +187,8 @@ __global__ void __launch_bounds__(512) k_plane_fwd(const T* __restrict__ in, cpl
 }
 
 // One (x0, component) plane: x1 columns inverse -> x2 rows inverse -> real rows.
-template <typename T>
-__global__ void __launch_bounds__(512) k_plane_inv(const cplx<T>* __restrict__ spec, T* __restrict__ out,
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_plane_inv(const cplx<T>* __restrict__ spec, T* __restrict__ out,
                                                    PlaneArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int x0 = blockIdx.x, comp = blockIdx.y;
@@ -266,8 +268,8 @@ struct PencilArgs {
 };
 
 // MODE 0: forward only, 1: inverse only, 2: forward, symbol, inverse.
-template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_pencil(cplx<T>* __restrict__ spec, PencilArgs<T> a) {
+template <typename T, int MODE, int NT>
+__global__ void __launch_bounds__(NT) k_pencil(cplx<T>* __restrict__ spec, PencilArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = a.pl.n, tb = a.tb;
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
@@ -308,6 +310,244 @@ __global__ void __launch_bounds__(256) k_pencil(cplx<T>* __restrict__ spec, Penc
 }
 
 // --------------------------------------------------------------------------
+// Compile-time variants for power-of-two lengths (same algorithm, same LDS
+// layout and spectrum layout as the generic kernels above; every index is a
+// constant shift and the stage loops unroll).
+// --------------------------------------------------------------------------
+template <typename T, class P, bool INV, bool SEQ_FAST, int COUNT, int ES, int SS, int NT, int I = 0>
+__device__ __forceinline__ void lds_fft_static(cplx<T>* buf, const cplx<T>* tw) {
+  if constexpr (I < P::nf) {
+    constexpr int st = INV ? P::nf - 1 - I : I;
+    constexpr int total = COUNT * (P::length(0) / P::radix(st));
+#pragma unroll
+    for (int b0 = 0; b0 < total; b0 += NT) {
+      const int b = b0 + int(threadIdx.x);
+      if (total % NT == 0 || b < total) fft_stage_item_static<T, P, st, INV, SEQ_FAST, COUNT, ES, SS>(buf, b, tw);
+    }
+    __syncthreads();
+    lds_fft_static<T, P, INV, SEQ_FAST, COUNT, ES, SS, NT, I + 1>(buf, tw);
+  }
+}
+
+template <typename T, int H, int COUNT, int NT>
+__device__ __forceinline__ void rows_r2c_static(cplx<T>* A, const cplx<T>* tw2, const cplx<T>* twr, const int* slot2) {
+  constexpr int M = H + 1;
+  lds_fft_static<T, Pow2Plan<H>, false, true, COUNT, 1, M, NT>(A, tw2);
+  constexpr int total = COUNT * (H / 2 + 1);
+#pragma unroll
+  for (int i0 = 0; i0 < total; i0 += NT) {
+    const int idx = i0 + int(threadIdx.x);
+    if (total % NT != 0 && idx >= total) continue;
+    const int k = idx / COUNT, r = idx - k * COUNT;
+    cplx<T>* row = A + r * M;
+    if (k == 0) {
+      const cplx<T> z = row[0];
+      row[0] = {z.x + z.y, T(0)};
+      row[H] = {z.x - z.y, T(0)};
+    } else {
+      const int sk = slot2[k], sm = slot2[H - k];
+      const cplx<T> a = row[sk], b = row[sm];
+      const cplx<T> e = {T(0.5) * (a.x + b.x), T(0.5) * (a.y - b.y)};
+      const cplx<T> o = {T(0.5) * (a.x - b.x), T(0.5) * (a.y + b.y)};
+      const cplx<T> wo = c_mul(twr[k], o);
+      row[sk] = {e.x + wo.y, e.y - wo.x};
+      if (sm != sk) row[sm] = {e.x - wo.y, -e.y - wo.x};
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int H, int COUNT, int NT>
+__device__ __forceinline__ void rows_c2r_static(cplx<T>* A, const cplx<T>* tw2, const cplx<T>* twr, const int* slot2) {
+  constexpr int M = H + 1;
+  constexpr int total = COUNT * (H / 2 + 1);
+#pragma unroll
+  for (int i0 = 0; i0 < total; i0 += NT) {
+    const int idx = i0 + int(threadIdx.x);
+    if (total % NT != 0 && idx >= total) continue;
+    const int k = idx / COUNT, r = idx - k * COUNT;
+    cplx<T>* row = A + r * M;
+    if (k == 0) {
+      const cplx<T> a = row[0], b = row[H];
+      const cplx<T> p = {a.x + b.x, a.y - b.y};
+      const cplx<T> q = {a.x - b.x, a.y + b.y};
+      row[0] = {p.x - q.y, p.y + q.x};
+    } else {
+      const int sk = slot2[k], sm = slot2[H - k];
+      const cplx<T> a = row[sk], b = row[sm];
+      const cplx<T> p = {a.x + b.x, a.y - b.y};
+      const cplx<T> q = {a.x - b.x, a.y + b.y};
+      const cplx<T> t = c_mulc(q, twr[k]);
+      row[sk] = {p.x - t.y, p.y + t.x};
+      if (sm != sk) row[sm] = {p.x + t.y, -p.y + t.x};
+    }
+  }
+  __syncthreads();
+  lds_fft_static<T, Pow2Plan<H>, true, true, COUNT, 1, M, NT>(A, tw2);
+}
+
+template <typename T, int H, int N1>
+__device__ __forceinline__ PlaneLds<T> carve_static(unsigned char* smem, int rows, const PlaneArgs<T>& a,
+                                                    bool with_tw1) {
+  constexpr int M = H + 1;
+  PlaneLds<T> L;
+  L.A = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* p = L.A + rows * M;
+  L.tw1 = p;
+  if (with_tw1) p += N1;
+  L.tw2 = p;
+  p += H;
+  L.twr = p;
+  p += H / 2 + 1;
+  L.slot2 = reinterpret_cast<int*>(p);
+  for (int i = threadIdx.x; i < N1 && with_tw1; i += blockDim.x) L.tw1[i] = a.tw1[i];
+  for (int i = threadIdx.x; i < H; i += blockDim.x) L.tw2[i] = a.tw2[i];
+  for (int i = threadIdx.x; i <= H / 2; i += blockDim.x) L.twr[i] = a.twr[i];
+  for (int i = threadIdx.x; i <= H; i += blockDim.x) L.slot2[i] = a.slot2[i];
+  return L;
+}
+
+template <typename T, int H, int N1, int NT>
+__global__ void __launch_bounds__(NT) k_plane_fwd_s(const T* __restrict__ in, cplx<T>* __restrict__ spec,
+                                                    PlaneArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int M = H + 1;
+  const int x0 = blockIdx.x, comp = blockIdx.y;
+  PlaneLds<T> L = carve_static<T, H, N1>(smem, N1, a, true);
+  const cplx<T>* src = reinterpret_cast<const cplx<T>*>(in + comp * a.N + (long long)x0 * (N1 * 2 * H));
+#pragma unroll
+  for (int i0 = 0; i0 < N1 * H; i0 += NT) {
+    const int idx = i0 + int(threadIdx.x);
+    if ((N1 * H) % NT != 0 && idx >= N1 * H) continue;
+    const int j1 = idx / H;
+    L.A[j1 * M + (idx - j1 * H)] = src[idx];
+  }
+  __syncthreads();
+  rows_r2c_static<T, H, N1, NT>(L.A, L.tw2, L.twr, L.slot2);
+  lds_fft_static<T, Pow2Plan<N1>, false, true, M, M, 1, NT>(L.A, L.tw1);
+  cplx<T>* dst = spec + ((long long)comp * a.n0 + x0) * (N1 * M);
+  for (int idx = threadIdx.x; idx < N1 * M; idx += NT) dst[idx] = L.A[idx];
+}
+
+template <typename T, int H, int N1, int NT>
+__global__ void __launch_bounds__(NT) k_plane_inv_s(const cplx<T>* __restrict__ spec, T* __restrict__ out,
+                                                    PlaneArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int M = H + 1;
+  const int x0 = blockIdx.x, comp = blockIdx.y;
+  PlaneLds<T> L = carve_static<T, H, N1>(smem, N1, a, true);
+  const cplx<T>* src = spec + ((long long)comp * a.n0 + x0) * (N1 * M);
+  for (int idx = threadIdx.x; idx < N1 * M; idx += NT) L.A[idx] = src[idx];
+  __syncthreads();
+  lds_fft_static<T, Pow2Plan<N1>, true, true, M, M, 1, NT>(L.A, L.tw1);
+  rows_c2r_static<T, H, N1, NT>(L.A, L.tw2, L.twr, L.slot2);
+  cplx<T>* dst = reinterpret_cast<cplx<T>*>(out + comp * a.N + (long long)x0 * (N1 * 2 * H));
+#pragma unroll
+  for (int i0 = 0; i0 < N1 * H; i0 += NT) {
+    const int idx = i0 + int(threadIdx.x);
+    if ((N1 * H) % NT != 0 && idx >= N1 * H) continue;
+    const int j1 = idx / H;
+    dst[idx] = L.A[j1 * M + (idx - j1 * H)];
+  }
+}
+
+template <typename T, int H, int RB, int NT>
+__global__ void __launch_bounds__(NT) k_rows_fwd_s(const T* __restrict__ in, cplx<T>* __restrict__ spec,
+                                                   PlaneArgs<T> a, int) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int M = H + 1;
+  const int comp = blockIdx.y;
+  const long long rows = (long long)a.n0 * a.n1;  // a multiple of RB (checked on the host)
+  const long long r0 = (long long)blockIdx.x * RB;
+  PlaneLds<T> L = carve_static<T, H, 1>(smem, RB, a, false);
+  const cplx<T>* src = reinterpret_cast<const cplx<T>*>(in + comp * a.N) + r0 * H;
+#pragma unroll
+  for (int i0 = 0; i0 < RB * H; i0 += NT) {
+    const int idx = i0 + int(threadIdx.x);
+    if ((RB * H) % NT != 0 && idx >= RB * H) continue;
+    const int r = idx / H;
+    L.A[r * M + (idx - r * H)] = src[idx];
+  }
+  __syncthreads();
+  rows_r2c_static<T, H, RB, NT>(L.A, L.tw2, L.twr, L.slot2);
+  cplx<T>* dst = spec + ((long long)comp * rows + r0) * M;
+  for (int idx = threadIdx.x; idx < RB * M; idx += NT) dst[idx] = L.A[idx];
+}
+
+template <typename T, int H, int RB, int NT>
+__global__ void __launch_bounds__(NT) k_rows_inv_s(const cplx<T>* __restrict__ spec, T* __restrict__ out,
+                                                   PlaneArgs<T> a, int) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int M = H + 1;
+  const int comp = blockIdx.y;
+  const long long rows = (long long)a.n0 * a.n1;
+  const long long r0 = (long long)blockIdx.x * RB;
+  PlaneLds<T> L = carve_static<T, H, 1>(smem, RB, a, false);
+  const cplx<T>* src = spec + ((long long)comp * rows + r0) * M;
+  for (int idx = threadIdx.x; idx < RB * M; idx += NT) L.A[idx] = src[idx];
+  __syncthreads();
+  rows_c2r_static<T, H, RB, NT>(L.A, L.tw2, L.twr, L.slot2);
+  cplx<T>* dst = reinterpret_cast<cplx<T>*>(out + comp * a.N) + r0 * H;
+#pragma unroll
+  for (int i0 = 0; i0 < RB * H; i0 += NT) {
+    const int idx = i0 + int(threadIdx.x);
+    if ((RB * H) % NT != 0 && idx >= RB * H) continue;
+    const int r = idx / H;
+    dst[idx] = L.A[r * M + (idx - r * H)];
+  }
+}
+
+// Pencils along an axis of power-of-two length N, TB per workgroup; each thread
+// keeps one sequence t = tid % TB, so the symbol's (k1, k2) part is looked up
+// once per sequence.
+template <typename T, int MODE, int N, int TB, int NT>
+__global__ void __launch_bounds__(NT) k_pencil_s(cplx<T>* __restrict__ spec, PencilArgs<T> a) {
+  static_assert(NT % TB == 0, "threads must cover whole rows of the tile");
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* tw = A + N * TB;
+  T* ksq0 = reinterpret_cast<T*>(tw + N);
+  T* ksq12 = ksq0 + N;
+  for (int i = threadIdx.x; i < N; i += NT) tw[i] = a.tw[i];
+  const int q0 = blockIdx.x * TB;
+  const int cnt = (a.nin - q0) < TB ? (a.nin - q0) : TB;
+  if (MODE == 2) {
+    for (int i = threadIdx.x; i < N; i += NT) ksq0[i] = a.ksq0[i];
+    if (threadIdx.x < TB) {
+      const int q = q0 + int(threadIdx.x);
+      const int s1 = q / a.M, s2 = q - s1 * a.M;
+      ksq12[threadIdx.x] = q < a.nin ? a.ksq1[s1] + a.ksq2[s2] : T(0);
+    }
+  }
+  const int t = int(threadIdx.x) % TB;
+  const int j0 = int(threadIdx.x) / TB;
+  constexpr int JS = NT / TB;
+  cplx<T>* base = spec + blockIdx.y * a.outer_stride + q0;
+  const bool live = t < cnt;
+#pragma unroll
+  for (int j = j0; j < N; j += JS) A[j * TB + t] = live ? base[(long long)j * a.es + t] : cplx<T>{T(0), T(0)};
+  __syncthreads();
+  if (MODE != 1) lds_fft_static<T, Pow2Plan<N>, false, true, TB, TB, 1, NT>(A, tw);
+  if (MODE == 2) {
+    const T k12 = ksq12[t];
+#pragma unroll
+    for (int j = j0; j < N; j += JS) {
+      const T b = T(1) + a.alpha * (ksq0[j] + k12);
+      T pw = b;
+      for (int i = 1; i < a.s; ++i) pw *= b;
+      const T f = a.op == LDDMM_OP_K ? a.scale / pw : a.scale * pw;
+      A[j * TB + t] = c_scale(A[j * TB + t], f);
+    }
+    __syncthreads();
+  }
+  if (MODE != 0) lds_fft_static<T, Pow2Plan<N>, true, true, TB, TB, 1, NT>(A, tw);
+  if (live) {
+#pragma unroll
+    for (int j = j0; j < N; j += JS) base[(long long)j * a.es + t] = A[j * TB + t];
+  }
+}
+
+// --------------------------------------------------------------------------
 // Host side
 // --------------------------------------------------------------------------
 namespace {
@@ -335,7 +575,188 @@ int fold_sq(int k, int n) {
   return a * a;
 }
 
+bool allowed_threads(int t) { return t == 256 || t == 512 || t == 1024; }
+
+
+// Kernel entry points chosen per plan (compile-time variants where instantiated).
+template <typename T>
+using PlaneFwdFn = void (*)(const T*, cplx<T>*, PlaneArgs<T>);
+template <typename T>
+using PlaneInvFn = void (*)(const cplx<T>*, T*, PlaneArgs<T>);
+template <typename T>
+using RowsFwdFn = void (*)(const T*, cplx<T>*, PlaneArgs<T>, int);
+template <typename T>
+using RowsInvFn = void (*)(const cplx<T>*, T*, PlaneArgs<T>, int);
+template <typename T>
+using PencilFn = void (*)(cplx<T>*, PencilArgs<T>);
+
+enum { KF_PLANE_FWD, KF_PLANE_INV, KF_ROWS_FWD, KF_ROWS_INV, KF_PENCIL0, KF_PENCIL1F, KF_PENCIL1I };
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+template <typename T, int NT>
+void plane_static(int H, int N1, void*& f, void*& i) {
+#define LDDMM_PLANE_CASE(h, n1)                                        \
+  if (H == h && N1 == n1) {                                            \
+    f = (void*)(PlaneFwdFn<T>)k_plane_fwd_s<T, h, n1, NT>;             \
+    i = (void*)(PlaneInvFn<T>)k_plane_inv_s<T, h, n1, NT>;             \
+    return;                                                            \
+  }
+  LDDMM_PLANE_CASE(8, 16)
+  LDDMM_PLANE_CASE(16, 32)
+  LDDMM_PLANE_CASE(32, 64)
+  LDDMM_PLANE_CASE(64, 128)
+#undef LDDMM_PLANE_CASE
+  f = i = nullptr;
+}
+
+template <typename T, int MODE>
+void* pencil_static(int N, int TB) {
+#define LDDMM_PENCIL_N(n)                                                                \
+  if (N == n) {                                                                          \
+    if (TB == 8) return (void*)(PencilFn<T>)k_pencil_s<T, MODE, n, 8, 256>;              \
+    if (TB == 16) return (void*)(PencilFn<T>)k_pencil_s<T, MODE, n, 16, 256>;            \
+    if (TB == 32) return (void*)(PencilFn<T>)k_pencil_s<T, MODE, n, 32, 256>;            \
+  }
+  LDDMM_PENCIL_N(16)
+  LDDMM_PENCIL_N(32)
+  LDDMM_PENCIL_N(64)
+  LDDMM_PENCIL_N(128)
+  LDDMM_PENCIL_N(256)
+#undef LDDMM_PENCIL_N
+  return nullptr;
+}
+
+template <typename T>
+void rows_static(int H, int RB, void*& f, void*& i) {
+#define LDDMM_ROWS_CASE(h, rb)                                         \
+  if (H == h && RB == rb) {                                            \
+    f = (void*)(RowsFwdFn<T>)k_rows_fwd_s<T, h, rb, 256>;              \
+    i = (void*)(RowsInvFn<T>)k_rows_inv_s<T, h, rb, 256>;              \
+    return;                                                            \
+  }
+  LDDMM_ROWS_CASE(64, 16)
+  LDDMM_ROWS_CASE(64, 32)
+  LDDMM_ROWS_CASE(128, 16)
+  LDDMM_ROWS_CASE(128, 32)
+#undef LDDMM_ROWS_CASE
+  f = i = nullptr;
+}
+
+template <typename T>
+void* pencil_generic(int mode, int nt) {
+  if (nt == 512) return mode == 0 ? (void*)(PencilFn<T>)k_pencil<T, 0, 512>
+                      : mode == 1 ? (void*)(PencilFn<T>)k_pencil<T, 1, 512>
+                                  : (void*)(PencilFn<T>)k_pencil<T, 2, 512>;
+  return mode == 0 ? (void*)(PencilFn<T>)k_pencil<T, 0, 256>
+       : mode == 1 ? (void*)(PencilFn<T>)k_pencil<T, 1, 256>
+                   : (void*)(PencilFn<T>)k_pencil<T, 2, 256>;
+}
+
 }  // namespace
+
+template <typename T>
+int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& err) {
+  if (!allowed_threads(tune.plane_threads) || (tune.pencil_threads != 256 && tune.pencil_threads != 512) ||
+      tune.pencil_tb < 1 || tune.pencil_tb > 128 || tune.rows_rb < 1 || tune.rows_rb > 64) {
+    err = "invalid transform tuning";
+    return LDDMM_EINVAL;
+  }
+  const size_t cb = sizeof(cplx<T>);
+  const int n0 = sp.n0, n1 = sp.n1, H = sp.H, M = sp.M;
+  const int tb = tune.pencil_tb;
+  const size_t tables = size_t(H + H / 2 + 1) * cb + size_t(H + 1) * sizeof(int);
+  const size_t plane_lds = size_t(n1) * M * cb + size_t(n1) * cb + tables;
+  const bool fused = !tune.force_split && plane_lds <= sp.max_lds;
+  // the compile-time pencils also keep TB per-sequence symbol terms
+  const size_t p0 = (size_t(n0) * tb + n0) * cb + size_t(n0 + tb) * sizeof(T);
+  const size_t p1 = (size_t(n1) * tb + n1) * cb + size_t(n1 + tb) * sizeof(T);
+  const size_t rl = size_t(tune.rows_rb) * M * cb + tables;
+  if (p0 > sp.max_lds || (!fused && (p1 > sp.max_lds || rl > sp.max_lds))) {
+    err = "transform tiles exceed the LDS of a workgroup";
+    return LDDMM_EUNSUPPORTED;
+  }
+  void* k[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int nstatic = 0;
+  const bool use_static = tune.use_static != 0;
+  if (fused) {
+    if (use_static && is_pow2(H) && is_pow2(n1)) {
+      if (tune.plane_threads == 512) plane_static<T, 512>(H, n1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
+      if (tune.plane_threads == 1024) plane_static<T, 1024>(H, n1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
+    }
+    if (k[KF_PLANE_FWD]) {
+      nstatic++;
+    } else {
+      k[KF_PLANE_FWD] = tune.plane_threads == 256    ? (void*)(PlaneFwdFn<T>)k_plane_fwd<T, 256>
+                        : tune.plane_threads == 1024 ? (void*)(PlaneFwdFn<T>)k_plane_fwd<T, 1024>
+                                                     : (void*)(PlaneFwdFn<T>)k_plane_fwd<T, 512>;
+      k[KF_PLANE_INV] = tune.plane_threads == 256    ? (void*)(PlaneInvFn<T>)k_plane_inv<T, 256>
+                        : tune.plane_threads == 1024 ? (void*)(PlaneInvFn<T>)k_plane_inv<T, 1024>
+                                                     : (void*)(PlaneInvFn<T>)k_plane_inv<T, 512>;
+    }
+  } else {
+    const long long rows = (long long)n0 * n1;
+    if (use_static && rows % tune.rows_rb == 0) rows_static<T>(H, tune.rows_rb, k[KF_ROWS_FWD], k[KF_ROWS_INV]);
+    if (k[KF_ROWS_FWD]) {
+      nstatic++;
+    } else {
+      k[KF_ROWS_FWD] = (void*)(RowsFwdFn<T>)k_rows_fwd<T>;
+      k[KF_ROWS_INV] = (void*)(RowsInvFn<T>)k_rows_inv<T>;
+    }
+    if (use_static && tune.pencil_threads == 256) {
+      k[KF_PENCIL1F] = pencil_static<T, 0>(n1, tb);
+      k[KF_PENCIL1I] = pencil_static<T, 1>(n1, tb);
+    }
+    if (k[KF_PENCIL1F]) {
+      nstatic++;
+    } else {
+      k[KF_PENCIL1F] = pencil_generic<T>(0, tune.pencil_threads);
+      k[KF_PENCIL1I] = pencil_generic<T>(1, tune.pencil_threads);
+    }
+  }
+  if (use_static && tune.pencil_threads == 256) k[KF_PENCIL0] = pencil_static<T, 2>(n0, tb);
+  if (k[KF_PENCIL0])
+    nstatic++;
+  else
+    k[KF_PENCIL0] = pencil_generic<T>(2, tune.pencil_threads);
+  for (void* f : k)
+    if (f && hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, int(sp.max_lds)) !=
+                 hipSuccess) {
+      err = "hipFuncSetAttribute(MaxDynamicSharedMemorySize) failed";
+      return LDDMM_EHIP;
+    }
+  sp.tune = tune;
+  sp.fused = fused;
+  sp.plane_lds = plane_lds;
+  sp.pencil0_lds = p0;
+  sp.pencil1_lds = p1;
+  sp.rows_lds = rl;
+  sp.static_kernels = nstatic;
+  for (int i = 0; i < 7; ++i) sp.kfn[i] = k[i];
+  return 0;
+}
+
+template <typename T>
+FftTuning default_tuning(const SpectralPlan<T>& sp) {
+  FftTuning t;
+  const size_t cb = sizeof(cplx<T>);
+  // measured best on MI355X at 32^3 .. 256^3: 1024-thread plane workgroups,
+  // 256-thread pencil workgroups with 128-byte (FP32) / 128-byte (FP64) rows
+  t.plane_threads = 1024;
+  t.pencil_threads = 256;
+  int tb = int(128 / cb);
+  while (tb > 1 && ((size_t(sp.n0) * tb + sp.n0) * cb + sp.n0 * sizeof(T) > sp.max_lds ||
+                    (size_t(sp.n1) * tb + sp.n1) * cb > sp.max_lds))
+    tb /= 2;
+  t.pencil_tb = tb;
+  const size_t tables = size_t(sp.H + sp.H / 2 + 1) * cb + size_t(sp.H + 1) * sizeof(int);
+  int rb = 16;
+  while (rb > 1 && size_t(rb) * sp.M * cb + tables > sp.max_lds) rb /= 2;
+  t.rows_rb = rb;
+  t.force_split = 0;
+  t.use_static = 1;
+  return t;
+}
 
 template <typename T>
 int spectral_init(SpectralPlan<T>& sp, const int n[3], size_t max_lds, std::string& err) {
@@ -343,6 +764,7 @@ int spectral_init(SpectralPlan<T>& sp, const int n[3], size_t max_lds, std::stri
   sp.n0 = n[0];
   sp.n1 = n[1];
   sp.n2 = n[2];
+  sp.max_lds = max_lds;
   if (n[0] < 4 || n[1] < 4 || n[2] < 4 || (n[2] & 1)) {
     err = "grid sizes must be >= 4 and N2 even";
     return LDDMM_EUNSUPPORTED;
@@ -375,40 +797,13 @@ int spectral_init(SpectralPlan<T>& sp, const int n[3], size_t max_lds, std::stri
   if ((rc = upload(&sp.ksq0, k0, by))) return rc;
   if ((rc = upload(&sp.ksq1, k1, by))) return rc;
   if ((rc = upload(&sp.ksq2, k2, by))) return rc;
-  const size_t cb = sizeof(cplx<T>);
-  const size_t spec_bytes = size_t(3) * n[0] * n[1] * M * cb;
+  const size_t spec_bytes = size_t(3) * n[0] * n[1] * M * sizeof(cplx<T>);
   if (hipMalloc(reinterpret_cast<void**>(&sp.spec), spec_bytes) != hipSuccess) {
     err = "out of device memory (spectrum workspace)";
     return LDDMM_ENOMEM;
   }
   by += spec_bytes;
-
-  const size_t tables = size_t(H + H / 2 + 1) * cb + size_t(H + 1) * sizeof(int);
-  sp.plane_lds = size_t(n[1]) * M * cb + size_t(n[1]) * cb + tables;
-  sp.fused = sp.plane_lds <= max_lds;
-  // pencils: 256-byte rows of tb complex values
-  int tb = int(256 / cb);
-  while (tb > 1 && (size_t(n[0]) * tb + n[0]) * cb + n[0] * sizeof(T) > max_lds) tb /= 2;
-  while (tb > 1 && !sp.fused && (size_t(n[1]) * tb + n[1]) * cb > max_lds) tb /= 2;
-  sp.pencil_tb = tb;
-  sp.pencil0_lds = (size_t(n[0]) * tb + n[0]) * cb + n[0] * sizeof(T);
-  sp.pencil1_lds = (size_t(n[1]) * tb + n[1]) * cb;
-  int rb = 16;
-  while (rb > 1 && size_t(rb) * M * cb + tables > max_lds) rb /= 2;
-  sp.rows_rb = rb;
-  sp.rows_lds = size_t(rb) * M * cb + tables;
-  if (sp.pencil0_lds > max_lds || sp.rows_lds > max_lds || (!sp.fused && sp.pencil1_lds > max_lds)) {
-    err = "grid too large for the LDS-staged transforms";
-    return LDDMM_EUNSUPPORTED;
-  }
-  const void* fns[] = {(const void*)k_plane_fwd<T>,  (const void*)k_plane_inv<T>, (const void*)k_rows_fwd<T>,
-                       (const void*)k_rows_inv<T>,   (const void*)k_pencil<T, 0>, (const void*)k_pencil<T, 1>,
-                       (const void*)k_pencil<T, 2>};
-  for (const void* f : fns)
-    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(max_lds)) != hipSuccess) {
-      err = "hipFuncSetAttribute(MaxDynamicSharedMemorySize) failed";
-      return LDDMM_EHIP;
-    }
+  if ((rc = spectral_configure(sp, default_tuning(sp), err))) return rc;
   return 0;
 }
 
@@ -436,6 +831,7 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   pa.tw2 = sp.tw2;
   pa.twr = sp.twr;
   pa.slot2 = sp.slot2;
+  const FftTuning& tu = sp.tune;
 
   const int P = sp.n1 * sp.M;
   PencilArgs<T> k0;
@@ -443,7 +839,7 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   k0.es = P;
   k0.nin = P;
   k0.outer_stride = (long long)sp.n0 * P;
-  k0.tb = sp.pencil_tb;
+  k0.tb = tu.pencil_tb;
   k0.tw = sp.tw0;
   k0.M = sp.M;
   k0.alpha = T(alpha);
@@ -453,20 +849,22 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   k0.ksq0 = sp.ksq0;
   k0.ksq1 = sp.ksq1;
   k0.ksq2 = sp.ksq2;
-  const dim3 g0((P + sp.pencil_tb - 1) / sp.pencil_tb, ncomp);
+  const dim3 g0((P + tu.pencil_tb - 1) / tu.pencil_tb, ncomp);
+  const PencilFn<T> pencil0 = (PencilFn<T>)sp.kfn[KF_PENCIL0];
 
   if (sp.fused) {
+    const dim3 gp(sp.n0, ncomp);
     {
       KernelTimer t(prof, "fft_plane_fwd", st);
-      k_plane_fwd<T><<<dim3(sp.n0, ncomp), 512, sp.plane_lds, st>>>(in, sp.spec, pa);
+      ((PlaneFwdFn<T>)sp.kfn[KF_PLANE_FWD])<<<gp, tu.plane_threads, sp.plane_lds, st>>>(in, sp.spec, pa);
     }
     {
       KernelTimer t(prof, "fft_pencil_symbol", st);
-      k_pencil<T, 2><<<g0, 256, sp.pencil0_lds, st>>>(sp.spec, k0);
+      pencil0<<<g0, tu.pencil_threads, sp.pencil0_lds, st>>>(sp.spec, k0);
     }
     {
       KernelTimer t(prof, "fft_plane_inv", st);
-      k_plane_inv<T><<<dim3(sp.n0, ncomp), 512, sp.plane_lds, st>>>(sp.spec, out, pa);
+      ((PlaneInvFn<T>)sp.kfn[KF_PLANE_INV])<<<gp, tu.plane_threads, sp.plane_lds, st>>>(sp.spec, out, pa);
     }
     return;
   }
@@ -476,38 +874,40 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   k1.nin = sp.M;
   k1.outer_stride = (long long)sp.n1 * sp.M;
   k1.tw = sp.tw1;
-  const dim3 g1((sp.M + sp.pencil_tb - 1) / sp.pencil_tb, ncomp * sp.n0);
+  const dim3 g1((sp.M + tu.pencil_tb - 1) / tu.pencil_tb, ncomp * sp.n0);
   const long long rows = (long long)sp.n0 * sp.n1;
-  const dim3 gr((unsigned)((rows + sp.rows_rb - 1) / sp.rows_rb), ncomp);
+  const dim3 gr((unsigned)((rows + tu.rows_rb - 1) / tu.rows_rb), ncomp);
   {
     KernelTimer t(prof, "fft_rows_fwd", st);
-    k_rows_fwd<T><<<gr, 256, sp.rows_lds, st>>>(in, sp.spec, pa, sp.rows_rb);
+    ((RowsFwdFn<T>)sp.kfn[KF_ROWS_FWD])<<<gr, 256, sp.rows_lds, st>>>(in, sp.spec, pa, tu.rows_rb);
   }
   {
     KernelTimer t(prof, "fft_pencil_x1_fwd", st);
-    k_pencil<T, 0><<<g1, 256, sp.pencil1_lds, st>>>(sp.spec, k1);
+    ((PencilFn<T>)sp.kfn[KF_PENCIL1F])<<<g1, tu.pencil_threads, sp.pencil1_lds, st>>>(sp.spec, k1);
   }
   {
     KernelTimer t(prof, "fft_pencil_symbol", st);
-    k_pencil<T, 2><<<g0, 256, sp.pencil0_lds, st>>>(sp.spec, k0);
+    pencil0<<<g0, tu.pencil_threads, sp.pencil0_lds, st>>>(sp.spec, k0);
   }
   {
     KernelTimer t(prof, "fft_pencil_x1_inv", st);
-    k_pencil<T, 1><<<g1, 256, sp.pencil1_lds, st>>>(sp.spec, k1);
+    ((PencilFn<T>)sp.kfn[KF_PENCIL1I])<<<g1, tu.pencil_threads, sp.pencil1_lds, st>>>(sp.spec, k1);
   }
   {
     KernelTimer t(prof, "fft_rows_inv", st);
-    k_rows_inv<T><<<gr, 256, sp.rows_lds, st>>>(sp.spec, out, pa, sp.rows_rb);
+    ((RowsInvFn<T>)sp.kfn[KF_ROWS_INV])<<<gr, 256, sp.rows_lds, st>>>(sp.spec, out, pa, tu.rows_rb);
   }
 }
 
-template int spectral_init<float>(SpectralPlan<float>&, const int[3], size_t, std::string&);
-template int spectral_init<double>(SpectralPlan<double>&, const int[3], size_t, std::string&);
-template void spectral_free<float>(SpectralPlan<float>&);
-template void spectral_free<double>(SpectralPlan<double>&);
-template void spectral_apply<float>(const SpectralPlan<float>&, const float*, float*, int, double, int, int,
-                                    hipStream_t, Profiler*);
-template void spectral_apply<double>(const SpectralPlan<double>&, const double*, double*, int, double, int, int,
-                                     hipStream_t, Profiler*);
+#define LDDMM_SINST(T)                                                                                   \
+  template int spectral_init<T>(SpectralPlan<T>&, const int[3], size_t, std::string&);                  \
+  template int spectral_configure<T>(SpectralPlan<T>&, const FftTuning&, std::string&);                 \
+  template FftTuning default_tuning<T>(const SpectralPlan<T>&);                                          \
+  template void spectral_free<T>(SpectralPlan<T>&);                                                      \
+  template void spectral_apply<T>(const SpectralPlan<T>&, const T*, T*, int, double, int, int, hipStream_t, \
+                                  Profiler*);
+
+LDDMM_SINST(float)
+LDDMM_SINST(double)
 
 }  // namespace lddmm

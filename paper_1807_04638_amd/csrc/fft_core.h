@@ -257,3 +257,48 @@ inline __host__ __device__ int digit_reverse(const FftPlan& pl, int p) {
 }
 
 }  // namespace lddmm
+
+namespace lddmm {
+
+// ---------------------------------------------------------------------------
+// Compile-time plans.  For the power-of-two lengths of the common grids the
+// radices, sub-lengths, strides and sequence counts are template constants, so
+// every index of a butterfly is a shift or a constant multiply.  The radix
+// order is the one make_plan produces (8s first, then one 4 or 2), which keeps
+// the digit-reversed slot tables of the runtime plan valid.
+// ---------------------------------------------------------------------------
+template <int N>
+struct Pow2Plan {
+  static_assert(N >= 2 && (N & (N - 1)) == 0, "power of two");
+  static constexpr int rest = N >> (3 * (__builtin_ctz(N) / 3));  // 1, 2 or 4
+  static constexpr int nf = __builtin_ctz(N) / 3 + (rest > 1 ? 1 : 0);
+  static constexpr int radix(int i) { return i < __builtin_ctz(N) / 3 ? 8 : rest; }
+  static constexpr int length(int i) { return i == 0 ? N : length(i - 1) / radix(i - 1); }
+};
+
+// Butterfly b of DIF/DIT stage ST (plan P) over COUNT sequences; element e of
+// sequence s at buf[s * SS + e * ES].
+template <typename T, class P, int ST, bool INV, bool SEQ_FAST, int COUNT, int ES, int SS>
+LD_HD void fft_stage_item_static(cplx<T>* buf, int b, const cplx<T>* tw) {
+  constexpr int R = P::radix(ST);
+  constexpr int L = P::length(ST);
+  constexpr int stride = L / R;
+  constexpr int nbf = P::length(0) / R;
+  int s, u;
+  if (SEQ_FAST) {
+    u = b / COUNT;
+    s = b - u * COUNT;
+  } else {
+    s = b / nbf;
+    u = b - s * nbf;
+  }
+  const int blk = u / stride;
+  const int j = u - blk * stride;
+  const int base = s * SS + (blk * L + j) * ES;
+  if (INV)
+    dit_butterfly<T, R>(buf, base, stride * ES, j, P::length(0) / L, tw);
+  else
+    dif_butterfly<T, R>(buf, base, stride * ES, j, P::length(0) / L, tw);
+}
+
+}  // namespace lddmm

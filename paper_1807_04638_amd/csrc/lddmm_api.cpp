@@ -516,6 +516,54 @@ class Engine {
     return hip_status("set_images");
   }
 
+  int set_option(const char* key, int64_t value) {
+    FftTuning t = sp.tune;
+    const std::string k(key);
+    if (k == "fft.plane_threads")
+      t.plane_threads = int(value);
+    else if (k == "fft.pencil_threads")
+      t.pencil_threads = int(value);
+    else if (k == "fft.pencil_tb")
+      t.pencil_tb = int(value);
+    else if (k == "fft.rows_rb")
+      t.rows_rb = int(value);
+    else if (k == "fft.force_split")
+      t.force_split = value != 0;
+    else if (k == "fft.static")
+      t.use_static = value != 0;
+    else
+      return fail(LDDMM_EINVAL, "unknown or read-only option " + k);
+    if (value < 0 || value > (1 << 20)) return fail(LDDMM_EINVAL, "option value out of range");
+    (void)hipStreamSynchronize(st);
+    std::string msg;
+    if (int rc = spectral_configure(sp, t, msg)) return fail(rc, msg);
+    return 0;
+  }
+
+  int get_option(const char* key, int64_t* value) {
+    const std::string k(key);
+    const FftTuning& t = sp.tune;
+    if (k == "fft.plane_threads")
+      *value = t.plane_threads;
+    else if (k == "fft.pencil_threads")
+      *value = t.pencil_threads;
+    else if (k == "fft.pencil_tb")
+      *value = t.pencil_tb;
+    else if (k == "fft.rows_rb")
+      *value = t.rows_rb;
+    else if (k == "fft.force_split")
+      *value = t.force_split;
+    else if (k == "fft.fused")
+      *value = sp.fused ? 1 : 0;
+    else if (k == "fft.static")
+      *value = t.use_static;
+    else if (k == "fft.static_kernels")
+      *value = sp.static_kernels;
+    else
+      return fail(LDDMM_EINVAL, "unknown option " + k);
+    return 0;
+  }
+
   int jacobian(const T* uin, T* det, double* mn, double* mx) {
     T* out = det ? det : tmpS;
     launch_jacobian_det<T>(g, uin, out, st, &prof);
@@ -574,6 +622,8 @@ int lddmm_create(const lddmm_params* params, void* hip_stream, lddmm_ctx** out) 
   for (int d = 0; d < 3; ++d)
     if (!good_size(p.n[d])) return LDDMM_EUNSUPPORTED;
   if (p.n[2] & 1) return LDDMM_EUNSUPPORTED;
+  // field kernels index the three components of a vector field with 32-bit offsets
+  if (3LL * p.n[0] * p.n[1] * p.n[2] >= (1LL << 31)) return LDDMM_EUNSUPPORTED;
   auto* c = new lddmm_ctx();
   c->dtype = p.dtype;
   int rc;
@@ -667,6 +717,16 @@ int lddmm_profile_enable(lddmm_ctx* ctx, int enable) {
 int lddmm_profile_read(lddmm_ctx* ctx, const char** names, int64_t* counts, double* total_ms, int cap) {
   if (cap < 0) return LDDMM_EINVAL;
   LDDMM_DISPATCH(ctx, E.prof.read(names, counts, total_ms, cap));
+}
+
+int lddmm_set_option(lddmm_ctx* ctx, const char* key, int64_t value) {
+  if (!key) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.set_option(key, value));
+}
+
+int lddmm_get_option(lddmm_ctx* ctx, const char* key, int64_t* value) {
+  if (!key || !value) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.get_option(key, value));
 }
 
 int lddmm_memory_bytes(lddmm_ctx* ctx, int64_t* bytes) {

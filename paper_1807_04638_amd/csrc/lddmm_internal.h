@@ -52,13 +52,58 @@ struct KernelTimer {
 // ---------------------------------------------------------------------------
 struct Grid {
   int n0, n1, n2;
-  long long N;           // n0 * n1 * n2
+  long long N;           // n0 * n1 * n2 (3 N < 2^31 is checked at creation)
   double h0, h1, h2;     // 2 pi / N_d
 };
+
+// Voxel tiling of the field kernels: a block covers BX x BY voxels of one x0
+// plane (BX spans a whole x2 row when N2 <= 256, so x2 halos stay inside the
+// tile).  With XCD-aware mapping the 8 XCDs (which take blocks round-robin)
+// each own a contiguous slab of x1 rows for every x0, so x1 halos and the
+// neighbouring x0 planes a block needs were loaded into the same L2.
+struct FieldTiling {
+  int BX, BY;      // block shape (threads)
+  int TX, TY;      // tiles along x2 and x1
+  int slab;        // tile rows of x1 per XCD (0: plain linear order)
+  unsigned blocks; // TX * TY * N0
+};
+FieldTiling make_field_tiling(const Grid& g);
+
+// Voxel (i0, i1, i2) of the calling thread under tiling t; false outside the grid.
+__device__ __forceinline__ bool tile_voxel(const FieldTiling& t, int n1, int n2, int& i0, int& i1, int& i2) {
+  const int b = blockIdx.x;
+  int bx, by;
+  if (t.slab) {
+    const int x = b & 7, k = b >> 3;
+    const int r = k / t.TX;
+    bx = k - r * t.TX;
+    const int rz = r / t.slab;
+    by = x * t.slab + (r - rz * t.slab);
+    i0 = rz;
+  } else {
+    const int r = b / t.TX;
+    bx = b - r * t.TX;
+    i0 = r / t.TY;
+    by = r - i0 * t.TY;
+  }
+  i2 = bx * t.BX + threadIdx.x;
+  i1 = by * t.BY + threadIdx.y;
+  return i2 < n2 && i1 < n1;
+}
 
 // ---------------------------------------------------------------------------
 // Spectral operator: 3D real FFT, symbol (1 + alpha |k|^2)^(+-s), inverse.
 // ---------------------------------------------------------------------------
+// Launch shapes of the transform kernels (see fft.hip); chosen per grid and dtype.
+struct FftTuning {
+  int plane_threads = 512;   // 256, 512 or 1024 threads per (x1, x2) plane workgroup
+  int pencil_threads = 256;  // 256 or 512 threads per pencil workgroup
+  int pencil_tb = 32;        // contiguous pencils per workgroup
+  int rows_rb = 16;          // rows per workgroup on the split path
+  int force_split = 0;       // 1: use the split path even where the plane fits the LDS
+  int use_static = 1;        // 1: compile-time kernels where instantiated (power-of-two lengths)
+};
+
 template <typename T>
 struct SpectralPlan {
   int n0 = 0, n1 = 0, n2 = 0, H = 0, M = 0;  // H = n2 / 2, M = H + 1 spectrum columns
@@ -74,7 +119,10 @@ struct SpectralPlan {
   cplx<T>* spec = nullptr;                   // workspace: 3 * n0 * n1 * M complex
   bool fused = false;                        // (x2, x1) plane fits one workgroup's LDS
   size_t plane_lds = 0, pencil0_lds = 0, pencil1_lds = 0, rows_lds = 0;
-  int pencil_tb = 0, rows_rb = 0;
+  size_t max_lds = 0;                        // LDS bytes available to one workgroup
+  FftTuning tune{};
+  void* kfn[7] = {};                         // kernel entry points chosen by spectral_configure
+  int static_kernels = 0;                    // how many of them are compile-time variants
   size_t bytes = 0;                          // device memory held
 };
 
@@ -83,6 +131,11 @@ template <typename T>
 int spectral_init(SpectralPlan<T>& sp, const int n[3], size_t max_lds, std::string& err);
 template <typename T>
 void spectral_free(SpectralPlan<T>& sp);
+// Apply new launch shapes; LDDMM_EINVAL / LDDMM_EUNSUPPORTED if they do not fit.
+template <typename T>
+int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& err);
+template <typename T>
+FftTuning default_tuning(const SpectralPlan<T>& sp);
 // out = K in (op = 0) or L in (op = 1) for ncomp components; in == out allowed.
 template <typename T>
 void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, double alpha, int s, int op,

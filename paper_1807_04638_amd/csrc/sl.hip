@@ -15,13 +15,12 @@ namespace lddmm {
 
 namespace {
 
-constexpr int BX = 64, BY = 4;
-
 template <typename T>
 struct SlGeo {
   int n0, n1, n2;
-  long long N;
+  int N;
   T invh[3];
+  FieldTiling ft;
 };
 
 template <typename T>
@@ -34,6 +33,7 @@ SlGeo<T> make_sl_geo(const Grid& g) {
   o.invh[0] = T(1.0 / g.h0);
   o.invh[1] = T(1.0 / g.h1);
   o.invh[2] = T(1.0 / g.h2);
+  o.ft = make_field_tiling(g);
   return o;
 }
 
@@ -46,7 +46,7 @@ __device__ __forceinline__ int wrap(int j, int n) {
 // displaced by (d0, d1, d2) voxels.
 template <typename T>
 struct Tri {
-  long long o[8];
+  int o[8];
   T w[8];
 };
 
@@ -64,12 +64,13 @@ __device__ __forceinline__ Tri<T> tri_setup(const SlGeo<T>& g, int i0, int i1, i
   const int b0 = a0 + 1 == g.n0 ? 0 : a0 + 1;
   const int b1 = a1 + 1 == g.n1 ? 0 : a1 + 1;
   const int b2 = a2 + 1 == g.n2 ? 0 : a2 + 1;
-  const long long s0 = (long long)g.n1 * g.n2;
-  const long long r0[2] = {a0 * s0, b0 * s0};
-  const long long r1[2] = {(long long)a1 * g.n2, (long long)b1 * g.n2};
+  const int s0 = g.n1 * g.n2;
+  const int r0[2] = {a0 * s0, b0 * s0};
+  const int r1[2] = {a1 * g.n2, b1 * g.n2};
   const int r2[2] = {a2, b2};
   const T w0[2] = {T(1) - t0, t0}, w1[2] = {T(1) - t1, t1}, w2[2] = {T(1) - t2, t2};
   Tri<T> tr;
+  // offsets fit in int: 3 N < 2^31
 #pragma unroll
   for (int c0 = 0; c0 < 2; ++c0)
 #pragma unroll
@@ -92,12 +93,12 @@ __device__ __forceinline__ T tri_eval(const Tri<T>& tr, const T* __restrict__ f)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(BX* BY)
+__global__ void __launch_bounds__(256)
     k_sl_step(SlGeo<T> g, const T* __restrict__ u_old, const T* __restrict__ v_old, const T* __restrict__ v_new,
               T* __restrict__ u_new, T dt) {
-  const int i2 = blockIdx.x * BX + threadIdx.x, i1 = blockIdx.y * BY + threadIdx.y, i0 = blockIdx.z;
-  if (i2 >= g.n2 || i1 >= g.n1) return;
-  const long long o = ((long long)i0 * g.n1 + i1) * g.n2 + i2;
+  int i0, i1, i2;
+  if (!tile_voxel(g.ft, g.n1, g.n2, i0, i1, i2)) return;
+  const int o = (i0 * g.n1 + i1) * g.n2 + i2;
   T vn[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) vn[c] = v_new[c * g.N + o];
@@ -111,11 +112,11 @@ __global__ void __launch_bounds__(BX* BY)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(BX* BY)
+__global__ void __launch_bounds__(256)
     k_compose(SlGeo<T> g, const T* __restrict__ I, const T* __restrict__ u, T* __restrict__ J) {
-  const int i2 = blockIdx.x * BX + threadIdx.x, i1 = blockIdx.y * BY + threadIdx.y, i0 = blockIdx.z;
-  if (i2 >= g.n2 || i1 >= g.n1) return;
-  const long long o = ((long long)i0 * g.n1 + i1) * g.n2 + i2;
+  int i0, i1, i2;
+  if (!tile_voxel(g.ft, g.n1, g.n2, i0, i1, i2)) return;
+  const int o = (i0 * g.n1 + i1) * g.n2 + i2;
   const Tri<T> t = tri_setup(g, i0, i1, i2, u[o] * g.invh[0], u[g.N + o] * g.invh[1], u[2 * g.N + o] * g.invh[2]);
   J[o] = tri_eval(t, I);
 }
@@ -126,15 +127,15 @@ template <typename T>
 void launch_sl_step(const Grid& g, const T* u_old, const T* v_old, const T* v_new, T* u_new, double dt,
                     hipStream_t st, Profiler* prof) {
   KernelTimer t(prof, "sl_step", st);
-  const dim3 grid((g.n2 + BX - 1) / BX, (g.n1 + BY - 1) / BY, g.n0);
-  k_sl_step<T><<<grid, dim3(BX, BY), 0, st>>>(make_sl_geo<T>(g), u_old, v_old, v_new, u_new, T(dt));
+  const FieldTiling ft = make_field_tiling(g);
+  k_sl_step<T><<<ft.blocks, dim3(ft.BX, ft.BY), 0, st>>>(make_sl_geo<T>(g), u_old, v_old, v_new, u_new, T(dt));
 }
 
 template <typename T>
 void launch_compose(const Grid& g, const T* I, const T* u, T* J, hipStream_t st, Profiler* prof) {
   KernelTimer t(prof, "compose", st);
-  const dim3 grid((g.n2 + BX - 1) / BX, (g.n1 + BY - 1) / BY, g.n0);
-  k_compose<T><<<grid, dim3(BX, BY), 0, st>>>(make_sl_geo<T>(g), I, u, J);
+  const FieldTiling ft = make_field_tiling(g);
+  k_compose<T><<<ft.blocks, dim3(ft.BX, ft.BY), 0, st>>>(make_sl_geo<T>(g), I, u, J);
 }
 
 template void launch_sl_step<float>(const Grid&, const float*, const float*, const float*, float*, double,

@@ -16,15 +16,27 @@
 
 namespace lddmm {
 
-namespace {
+FieldTiling make_field_tiling(const Grid& g) {
+  FieldTiling t;
+  int bx = (g.n2 + 31) / 32 * 32;
+  if (bx > 256) bx = 256;
+  t.BX = bx;
+  t.BY = 256 / bx > 0 ? 256 / bx : 1;
+  t.TX = (g.n2 + t.BX - 1) / t.BX;
+  t.TY = (g.n1 + t.BY - 1) / t.BY;
+  t.slab = (t.TY % 8 == 0) ? t.TY / 8 : 0;
+  t.blocks = unsigned(t.TX) * unsigned(t.TY) * unsigned(g.n0);
+  return t;
+}
 
-constexpr int BX = 64, BY = 4;
+namespace {
 
 template <typename T>
 struct Geo {
   int n0, n1, n2;
-  long long N;
+  int N;  // voxels per component
   T inv2h[3];
+  FieldTiling ft;
 };
 
 template <typename T>
@@ -33,27 +45,23 @@ Geo<T> make_geo(const Grid& g) {
   o.n0 = g.n0;
   o.n1 = g.n1;
   o.n2 = g.n2;
-  o.N = g.N;
+  o.N = int(g.N);
   o.inv2h[0] = T(0.5 / g.h0);
   o.inv2h[1] = T(0.5 / g.h1);
   o.inv2h[2] = T(0.5 / g.h2);
+  o.ft = make_field_tiling(g);
   return o;
 }
-
-dim3 field_grid(const Grid& g) { return dim3((g.n2 + BX - 1) / BX, (g.n1 + BY - 1) / BY, g.n0); }
 
 // Linear offsets of the voxel and its six periodic neighbours:
 // 0 centre, 1 +x0, 2 -x0, 3 +x1, 4 -x1, 5 +x2, 6 -x2.
 struct Nbr {
-  long long o[7];
+  int o[7];
 };
 
 template <typename T>
 __device__ __forceinline__ bool voxel(const Geo<T>& g, int& i0, int& i1, int& i2) {
-  i2 = blockIdx.x * BX + threadIdx.x;
-  i1 = blockIdx.y * BY + threadIdx.y;
-  i0 = blockIdx.z;
-  return i2 < g.n2 && i1 < g.n1;
+  return tile_voxel(g.ft, g.n1, g.n2, i0, i1, i2);
 }
 
 template <typename T>
@@ -61,15 +69,15 @@ __device__ __forceinline__ Nbr neighbours(const Geo<T>& g, int i0, int i1, int i
   const int p0 = i0 + 1 == g.n0 ? 0 : i0 + 1, m0 = i0 == 0 ? g.n0 - 1 : i0 - 1;
   const int p1 = i1 + 1 == g.n1 ? 0 : i1 + 1, m1 = i1 == 0 ? g.n1 - 1 : i1 - 1;
   const int p2 = i2 + 1 == g.n2 ? 0 : i2 + 1, m2 = i2 == 0 ? g.n2 - 1 : i2 - 1;
-  const long long s0 = (long long)g.n1 * g.n2;
-  const long long r0 = i0 * s0, rp0 = p0 * s0, rm0 = m0 * s0;
-  const long long r1 = (long long)i1 * g.n2;
+  const int s0 = g.n1 * g.n2;
+  const int r0 = i0 * s0, rp0 = p0 * s0, rm0 = m0 * s0;
+  const int r1 = i1 * g.n2;
   Nbr n;
   n.o[0] = r0 + r1 + i2;
   n.o[1] = rp0 + r1 + i2;
   n.o[2] = rm0 + r1 + i2;
-  n.o[3] = r0 + (long long)p1 * g.n2 + i2;
-  n.o[4] = r0 + (long long)m1 * g.n2 + i2;
+  n.o[3] = r0 + p1 * g.n2 + i2;
+  n.o[4] = r0 + m1 * g.n2 + i2;
   n.o[5] = r0 + r1 + p2;
   n.o[6] = r0 + r1 + m2;
   return n;
@@ -82,7 +90,7 @@ struct St7 {
 };
 
 template <typename T>
-__device__ __forceinline__ void load7(St7<T>& s, const T* __restrict__ p, const Nbr& nb, long long N) {
+__device__ __forceinline__ void load7(St7<T>& s, const T* __restrict__ p, const Nbr& nb, int N) {
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -90,13 +98,13 @@ __device__ __forceinline__ void load7(St7<T>& s, const T* __restrict__ p, const 
 }
 
 template <typename T>
-__device__ __forceinline__ void load1(T out[3], const T* __restrict__ p, long long o, long long N) {
+__device__ __forceinline__ void load1(T out[3], const T* __restrict__ p, int o, int N) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) out[c] = p[c * N + o];
 }
 
 template <typename T>
-__device__ __forceinline__ void store1(T* __restrict__ p, const T v[3], long long o, long long N) {
+__device__ __forceinline__ void store1(T* __restrict__ p, const T v[3], int o, int N) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) p[c * N + o] = v[c];
 }
@@ -136,7 +144,7 @@ __device__ __forceinline__ void adstar(const St7<T>& v, const St7<T>& mu, const 
 
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(BX* BY)
+__global__ void __launch_bounds__(256)
     k_epdiff_stage(Geo<T> g, const T* __restrict__ v, const T* __restrict__ mu, const T* mu0, T* mu_out, T dt,
                    T a0, T a1) {
   int i0, i1, i2;
@@ -160,7 +168,7 @@ __global__ void __launch_bounds__(BX* BY)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(BX* BY)
+__global__ void __launch_bounds__(256)
     k_tangent_stage(Geo<T> g, const T* __restrict__ X, const T* __restrict__ dmu, const T* __restrict__ W,
                     const T* __restrict__ v, const T* __restrict__ mu, const T* X0, const T* dmu0, T* X_out,
                     T* dmu_out, T dt, T a0, T a1) {
@@ -200,7 +208,7 @@ __global__ void __launch_bounds__(BX* BY)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(BX* BY)
+__global__ void __launch_bounds__(256)
     k_adjoint_pre(Geo<T> g, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ mu,
                   T* __restrict__ Z) {
   int i0, i1, i2;
@@ -218,7 +226,7 @@ __global__ void __launch_bounds__(BX* BY)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(BX* BY)
+__global__ void __launch_bounds__(256)
     k_adjoint_post(Geo<T> g, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ KZ,
                    const T* __restrict__ v, const T* U0, const T* w0, T* U_out, T* w_out, T dt, T a0, T a1) {
   int i0, i1, i2;
@@ -254,7 +262,7 @@ __global__ void __launch_bounds__(BX* BY)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(BX* BY)
+__global__ void __launch_bounds__(256)
     k_residual_grad(Geo<T> g, const T* __restrict__ J1, const T* __restrict__ I1, T* __restrict__ r,
                     T* __restrict__ G) {
   int i0, i1, i2;
@@ -287,7 +295,7 @@ __global__ void k_gn_final(long long N, const T* __restrict__ G, const T* __rest
 }
 
 template <typename T>
-__global__ void __launch_bounds__(BX* BY) k_jacobian_det(Geo<T> g, const T* __restrict__ u, T* __restrict__ det) {
+__global__ void __launch_bounds__(256) k_jacobian_det(Geo<T> g, const T* __restrict__ u, T* __restrict__ det) {
   int i0, i1, i2;
   if (!voxel(g, i0, i1, i2)) return;
   const Nbr nb = neighbours(g, i0, i1, i2);
@@ -301,6 +309,12 @@ __global__ void __launch_bounds__(BX* BY) k_jacobian_det(Geo<T> g, const T* __re
                  J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
 }
 
+dim3 ft_grid(const Grid& g) { return dim3(make_field_tiling(g).blocks); }
+dim3 ft_block(const Grid& g) {
+  const FieldTiling t = make_field_tiling(g);
+  return dim3(t.BX, t.BY);
+}
+
 unsigned flat_blocks(long long N) {
   long long b = (N + 255) / 256;
   return (unsigned)(b < 8192 ? b : 8192);
@@ -312,7 +326,7 @@ template <typename T>
 void launch_epdiff_stage(const Grid& g, const T* v, const T* mu, const T* mu0, T* mu_out, double dt, double a0,
                          double a1, hipStream_t st, Profiler* prof) {
   KernelTimer t(prof, a0 != 0.0 ? "epdiff_stage_corr" : "epdiff_stage_pred", st);
-  k_epdiff_stage<T><<<field_grid(g), dim3(BX, BY), 0, st>>>(make_geo<T>(g), v, mu, mu0 ? mu0 : mu, mu_out, T(dt),
+  k_epdiff_stage<T><<<ft_grid(g), ft_block(g), 0, st>>>(make_geo<T>(g), v, mu, mu0 ? mu0 : mu, mu_out, T(dt),
                                                             T(a0), T(a1));
 }
 
@@ -321,28 +335,28 @@ void launch_tangent_stage(const Grid& g, const T* X, const T* dmu, const T* W, c
                           const T* X0, const T* dmu0, T* X_out, T* dmu_out, double dt, double a0, double a1,
                           hipStream_t st, Profiler* prof) {
   KernelTimer t(prof, a0 != 0.0 ? "tangent_stage_corr" : "tangent_stage_pred", st);
-  k_tangent_stage<T><<<field_grid(g), dim3(BX, BY), 0, st>>>(make_geo<T>(g), X, dmu, W, v, mu, X0 ? X0 : X,
+  k_tangent_stage<T><<<ft_grid(g), ft_block(g), 0, st>>>(make_geo<T>(g), X, dmu, W, v, mu, X0 ? X0 : X,
                                                              dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt), T(a0), T(a1));
 }
 
 template <typename T>
 void launch_adjoint_pre(const Grid& g, const T* U, const T* w, const T* mu, T* Z, hipStream_t st, Profiler* prof) {
   KernelTimer t(prof, "adjoint_pre", st);
-  k_adjoint_pre<T><<<field_grid(g), dim3(BX, BY), 0, st>>>(make_geo<T>(g), U, w, mu, Z);
+  k_adjoint_pre<T><<<ft_grid(g), ft_block(g), 0, st>>>(make_geo<T>(g), U, w, mu, Z);
 }
 
 template <typename T>
 void launch_adjoint_post(const Grid& g, const T* U, const T* w, const T* KZ, const T* v, const T* U0, const T* w0,
                          T* U_out, T* w_out, double dt, double a0, double a1, hipStream_t st, Profiler* prof) {
   KernelTimer t(prof, a0 != 0.0 ? "adjoint_post_corr" : "adjoint_post_pred", st);
-  k_adjoint_post<T><<<field_grid(g), dim3(BX, BY), 0, st>>>(make_geo<T>(g), U, w, KZ, v, U0 ? U0 : U, w0 ? w0 : w,
+  k_adjoint_post<T><<<ft_grid(g), ft_block(g), 0, st>>>(make_geo<T>(g), U, w, KZ, v, U0 ? U0 : U, w0 ? w0 : w,
                                                             U_out, w_out, T(dt), T(a0), T(a1));
 }
 
 template <typename T>
 void launch_residual_grad(const Grid& g, const T* J1, const T* I1, T* r, T* G, hipStream_t st, Profiler* prof) {
   KernelTimer t(prof, "residual_grad", st);
-  k_residual_grad<T><<<field_grid(g), dim3(BX, BY), 0, st>>>(make_geo<T>(g), J1, I1, r, G);
+  k_residual_grad<T><<<ft_grid(g), ft_block(g), 0, st>>>(make_geo<T>(g), J1, I1, r, G);
 }
 
 template <typename T>
@@ -361,7 +375,7 @@ void launch_gn_final(const Grid& g, const T* G, const T* X, double c, T* U, hipS
 template <typename T>
 void launch_jacobian_det(const Grid& g, const T* u, T* det, hipStream_t st, Profiler* prof) {
   KernelTimer t(prof, "jacobian_det", st);
-  k_jacobian_det<T><<<field_grid(g), dim3(BX, BY), 0, st>>>(make_geo<T>(g), u, det);
+  k_jacobian_det<T><<<ft_grid(g), ft_block(g), 0, st>>>(make_geo<T>(g), u, det);
 }
 
 #define LDDMM_INST(T)                                                                                            \

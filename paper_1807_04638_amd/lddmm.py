@@ -107,6 +107,8 @@ SIGNATURES = {
         ctypes.c_int,
         [_vp, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int64), _c_double_p, ctypes.c_int],
     ),
+    "lddmm_set_option": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int64]),
+    "lddmm_get_option": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]),
     "lddmm_memory_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64)]),
     "lddmm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "lddmm_last_error": (ctypes.c_char_p, [_vp]),
@@ -326,6 +328,14 @@ class Registration:
         if k < 0:
             self._check(k, "profile_read")
         return {names[i].decode(): (counts[i], ms[i]) for i in range(min(k, cap))}
+
+    def set_option(self, key, value):
+        self._check(self.lib.lddmm_set_option(self._ctx, key.encode(), int(value)), f"set_option({key})")
+
+    def get_option(self, key):
+        v = ctypes.c_int64()
+        self._check(self.lib.lddmm_get_option(self._ctx, key.encode(), ctypes.byref(v)), f"get_option({key})")
+        return v.value
 
     def memory_bytes(self):
         b = ctypes.c_int64()

@@ -94,6 +94,23 @@ def test_operator_parity(n, dtype):
     assert rel(s, O.apply_K(f[0], p)) <= TOL[dtype]["op"]
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [(32, 32, 32), (64, 64, 64), (16, 32, 64)])
+@pytest.mark.parametrize("opts", [{"fft.static": 0}, {"fft.static": 1}, {"fft.force_split": 1},
+                                  {"fft.force_split": 1, "fft.static": 0}, {"fft.plane_threads": 256, "fft.pencil_tb": 32}])
+def test_operator_transform_variants(n, dtype, opts):
+    """Every transform path (compile-time / generic kernels, fused / split passes,
+    launch shapes) against the oracle on the same input."""
+    R, p = make(n, dtype, alpha=0.005)
+    for k, v in opts.items():
+        R.set_option(k, v)
+    say(f"  options {opts} fused={R.get_option('fft.fused')} static_kernels={R.get_option('fft.static_kernels')}")
+    f = rounded(random_field(n, 3, kc=max(n) / 3), dtype)
+    Lf = O.apply_L(f, p)
+    assert rel(R.apply_K(T(f, dtype)), O.apply_K(f, p)) <= TOL[dtype]["op"]
+    assert rel(R.apply_L(T(f, dtype)), Lf) <= l_tol(p, f, Lf, dtype)
+
+
 def test_operator_split_path_fp64():
     """(x1, x2) half-plane of 256 x 129 complex doubles exceeds LDS: split passes."""
     n = (6, 256, 256)
