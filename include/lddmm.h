@@ -61,10 +61,21 @@ extern "C" {
 typedef struct lddmm_ctx lddmm_ctx;
 
 /* Model and grid.  n[d] = N_d (each a product of 2, 3, 5, 7; N2 even; N_d >= 4;
- * 3 N0 N1 N2 < 2^31),
- * nt >= 1 Heun steps on [0, 1], s >= 1 and alpha > 0 of L, sigma2 > 0 the
- * image-noise variance of the data term (Section 3 energy).
- * mem_budget_bytes and checkpoint_every are reserved (0). */
+ * 3 N0 N1 N2 < 2^31), nt >= 1 Heun steps on [0, 1], s >= 1 and alpha > 0 of L,
+ * sigma2 > 0 the image-noise variance of the data term (Section 3 energy).
+ *
+ * Trajectory memory (the paper's Section 5 names the memory load of the
+ * stored geodesic as the method's main drawback):
+ *   checkpoint_every > 0   keep the momentum every c steps; each sweep
+ *                          recomputes one c-step segment at a time
+ *                          (ceil(nt/c) + 4c + 1 vector fields, 2 extra K
+ *                          applications per step and sweep)
+ *   checkpoint_every < 0   keep mu_0 only and replay (7 vector fields,
+ *                          O(nt^2) steps in the adjoint sweep)
+ *   checkpoint_every == 0  store every step (4 nt + 2 vector fields), unless
+ *                          mem_budget_bytes > 0 and the whole context would not
+ *                          fit it: then the largest c that fits, else replay.
+ * Every policy gives bitwise the same gradients and Hessian-vector products. */
 typedef struct {
   int32_t n[3];
   int32_t nt;
@@ -138,8 +149,9 @@ int lddmm_dot(lddmm_ctx* ctx, int ncomp, const void* a, const void* b, double* o
 int lddmm_shoot(lddmm_ctx* ctx, const void* v0, void* J1, void* u1, void* v1, double* energy);
 
 /* Shoot with trajectory store and form the final conditions at v0: residual
- * J_1 - I_1, energy, G = grad_h J_1.  Becomes the current linearization. */
-int lddmm_linearize(lddmm_ctx* ctx, const void* v0, double* energy);
+ * J_1 - I_1, energy, G = grad_h J_1.  Becomes the current linearization (its
+ * counter "lin.epoch" increases).  J1 (scalar field) and energy may be NULL. */
+int lddmm_linearize(lddmm_ctx* ctx, const void* v0, void* J1, double* energy);
 
 /* V-gradient g = 2 v0 + w_0 (Section 3: gradient at t = 1, lambda(1) grad J_1,
  * carried to t = 0 by the reduced adjoint Jacobi equations of Section 2.2).
@@ -191,6 +203,10 @@ int lddmm_profile_read(lddmm_ctx* ctx, const char** names, int64_t* counts, doub
  *   "fft.static"          0 | 1             compile-time kernels for power-of-two lengths
  *   "fft.fused"           read-only: 1 if the fused plane path is in use
  *   "fft.static_kernels"  read-only: number of passes using compile-time kernels
+ *   "traj.policy"         read-only: 0 store-all, 1 checkpoint, 2 recompute
+ *   "traj.every"          read-only: checkpoint interval c
+ *   "traj.bytes"          read-only: device bytes of the trajectory storage
+ *   "lin.epoch"           read-only: number of linearizations made so far
  * LDDMM_EINVAL for an unknown key or a value out of range, LDDMM_EUNSUPPORTED if
  * the tiles would not fit the LDS of a workgroup (the previous setting stays). */
 int lddmm_set_option(lddmm_ctx* ctx, const char* key, int64_t value);

@@ -116,6 +116,19 @@ class Engine {
   T *I0 = nullptr, *I1 = nullptr, *J1 = nullptr, *Jtmp = nullptr, *res = nullptr, *G = nullptr, *lin_v0 = nullptr;
   // trajectory store: mu_n, v_n (n <= nt), Heun predictors mu*_n, v*_n (n < nt)
   std::vector<T*> tmu, tv, tmus, tvs;
+  // trajectory memory policy: store every step, keep mu every c steps and
+  // re-materialise one segment at a time, or keep mu_0 only and replay
+  enum { TRAJ_STORE_ALL = 0, TRAJ_CHECKPOINT = 1, TRAJ_RECOMPUTE = 2 };
+  int traj_policy = TRAJ_STORE_ALL, traj_every = 0;
+  size_t traj_bytes = 0;
+  std::vector<T*> ck;                                 // mu_{k c} (checkpoint) or mu_0 (recompute)
+  std::vector<T*> seg_mu_buf, seg_v_buf, seg_mus, seg_vs;  // one materialised segment
+  std::vector<const T*> seg_mu, seg_v;                // views into ck / lin_v0 / seg_*_buf
+  int seg_loaded = -1;
+  T *rb_mu[2] = {nullptr, nullptr}, *rb_v[2] = {nullptr, nullptr}, *rb_mus = nullptr, *rb_vs = nullptr;
+  const T *rc_mu = nullptr, *rc_v = nullptr;
+  int rc_m = -1;
+  bool rc_star = false;
   // shooting scratch (no store) and displacement ping-pong
   T *sm[2] = {nullptr, nullptr}, *sv[2] = {nullptr, nullptr}, *sms = nullptr, *svs = nullptr;
   T *u[2] = {nullptr, nullptr};
@@ -130,6 +143,7 @@ class Engine {
   double* hres = nullptr;  // pinned host mirror of dres
 
   bool have_images = false, linearized = false;
+  int64_t lin_epoch = 0;
   double E = 0, Ereg = 0, Edata = 0, base_sq = 0;
 
   ~Engine() {
@@ -182,13 +196,7 @@ class Engine {
     T** scal[] = {&I0, &I1, &J1, &Jtmp, &res, &tmpS};
     for (T** q : scal)
       if (alloc(q, N)) return fail(LDDMM_ENOMEM, "out of device memory (images)");
-    tmu.resize(p.nt + 1);
-    tv.resize(p.nt + 1);
-    tmus.resize(p.nt);
-    tvs.resize(p.nt);
-    for (auto* vec : {&tmu, &tv, &tmus, &tvs})
-      for (T*& q : *vec)
-        if (alloc(&q, V)) return fail(LDDMM_ENOMEM, "out of device memory (trajectory store)");
+    if (int rc2 = alloc_trajectory(p, size_t(V) * sizeof(T))) return rc2;
     void* q = nullptr;
     if (hipMalloc(&q, sizeof(double) * 2 * kReduceBlocks) != hipSuccess) return fail(LDDMM_ENOMEM, "partials");
     allocs.push_back(q);
@@ -199,6 +207,156 @@ class Engine {
     if (hipHostMalloc(reinterpret_cast<void**>(&hres), sizeof(double) * 8, hipHostMallocDefault) != hipSuccess)
       return fail(LDDMM_ENOMEM, "pinned results");
     return 0;
+  }
+
+
+  // ---- trajectory memory ----------------------------------------------------
+  // Fields held per policy (V = one vector field):
+  //   store-all   4 nt + 2             (mu_n, v_n for n <= nt; mu*_n, v*_n for n < nt)
+  //   checkpoint  ceil(nt/c) + 4 c + 1 (mu every c steps; one segment: mu, v, mu*, v*)
+  //   recompute   7                    (mu_0; rolling mu, v pairs; mu*, v*)
+  static size_t traj_fields(int policy, int nt, int c) {
+    if (policy == TRAJ_STORE_ALL) return size_t(4) * nt + 2;
+    if (policy == TRAJ_CHECKPOINT) return size_t((nt + c - 1) / c) + size_t(4) * c + 1;
+    return 7;
+  }
+
+  int alloc_trajectory(const lddmm_params& p, size_t vbytes) {
+    const int nt = p.nt;
+    int policy = TRAJ_STORE_ALL, c = 0;
+    if (p.checkpoint_every > 0) {
+      policy = TRAJ_CHECKPOINT;
+      c = std::min(p.checkpoint_every, nt);
+    } else if (p.checkpoint_every < 0) {
+      policy = TRAJ_RECOMPUTE;
+    } else if (p.mem_budget_bytes > 0) {
+      // automatic: the cheapest policy in recomputation whose total fits the budget
+      const size_t fixed = bytes;  // workspace allocated so far
+      const size_t budget = size_t(p.mem_budget_bytes);
+      if (fixed + traj_fields(TRAJ_STORE_ALL, nt, 0) * vbytes <= budget) {
+        policy = TRAJ_STORE_ALL;
+      } else {
+        policy = TRAJ_RECOMPUTE;
+        for (int cc = nt; cc >= 1; --cc)
+          if (fixed + traj_fields(TRAJ_CHECKPOINT, nt, cc) * vbytes <= budget) {
+            policy = TRAJ_CHECKPOINT;
+            c = cc;
+            break;
+          }
+      }
+    }
+    traj_policy = policy;
+    traj_every = c;
+    const size_t before = bytes;
+    const long long V = 3 * N;
+    auto grab = [&](std::vector<T*>& vec, size_t n) {
+      vec.assign(n, nullptr);
+      for (T*& q : vec)
+        if (alloc(&q, V)) return false;
+      return true;
+    };
+    bool ok = true;
+    if (policy == TRAJ_STORE_ALL) {
+      ok = grab(tmu, nt + 1) && grab(tv, nt + 1) && grab(tmus, nt) && grab(tvs, nt);
+    } else if (policy == TRAJ_CHECKPOINT) {
+      ok = grab(ck, (nt + c - 1) / c) && grab(seg_mu_buf, c) && grab(seg_v_buf, c) && grab(seg_mus, c) &&
+           grab(seg_vs, c);
+      seg_mu.assign(c, nullptr);
+      seg_v.assign(c, nullptr);
+    } else {
+      ok = grab(ck, 1) && alloc(&rb_mu[0], V) == 0 && alloc(&rb_mu[1], V) == 0 && alloc(&rb_v[0], V) == 0 &&
+           alloc(&rb_v[1], V) == 0 && alloc(&rb_mus, V) == 0 && alloc(&rb_vs, V) == 0;
+    }
+    if (!ok) return fail(LDDMM_ENOMEM, "out of device memory (trajectory)");
+    traj_bytes = bytes - before;
+    return 0;
+  }
+
+  // Where shoot_core puts mu_{n} (n >= 1) when storing: the trajectory for
+  // store-all, a checkpoint slot at multiples of c, else scratch (nullptr).
+  T* store_slot_mu(int n) {
+    if (traj_policy == TRAJ_STORE_ALL) return tmu[n];
+    if (traj_policy == TRAJ_CHECKPOINT && n < P.nt && n % traj_every == 0) return ck[n / traj_every];
+    return nullptr;
+  }
+  T* store_slot_mu0() { return traj_policy == TRAJ_STORE_ALL ? tmu[0] : ck[0]; }
+
+  struct Step {
+    const T *mu, *v, *mus, *vs;
+  };
+
+  // One Heun step of the shooting from (mu, v): mus, vs always; next mu/v if asked.
+  void heun_step(const T* mu, const T* v, T* mus, T* vs, T* mu_next, T* v_next) {
+    launch_epdiff_stage<T>(g, v, mu, nullptr, mus, dt, 0.0, 1.0, st, &prof);
+    applyK(mus, vs);
+    if (mu_next) {
+      launch_epdiff_stage<T>(g, vs, mus, mu, mu_next, dt, 0.5, 0.5, st, &prof);
+      applyK(mu_next, v_next);
+    }
+  }
+
+  // Segment k of the checkpointed trajectory: steps [k c, min((k+1) c, nt)),
+  // recomputed from mu_{k c} with the shooting kernels (bitwise the stored run).
+  void materialize(int k) {
+    const int c = traj_every;
+    const int n0 = k * c;
+    const int len = std::min(c, P.nt - n0);
+    seg_mu[0] = ck[k];
+    if (k == 0) {
+      seg_v[0] = lin_v0;
+    } else {
+      applyK(ck[k], seg_v_buf[0]);
+      seg_v[0] = seg_v_buf[0];
+    }
+    for (int i = 0; i < len; ++i) {
+      const bool more = i + 1 < len;
+      heun_step(seg_mu[i], seg_v[i], seg_mus[i], seg_vs[i], more ? seg_mu_buf[i + 1] : nullptr,
+                more ? seg_v_buf[i + 1] : nullptr);
+      if (more) {
+        seg_mu[i + 1] = seg_mu_buf[i + 1];
+        seg_v[i + 1] = seg_v_buf[i + 1];
+      }
+    }
+    seg_loaded = k;
+  }
+
+  // Coefficients of step n for the sweeps (valid until the next call).
+  Step traj_view(int n) {
+    if (traj_policy == TRAJ_STORE_ALL) return {tmu[n], tv[n], tmus[n], tvs[n]};
+    if (traj_policy == TRAJ_CHECKPOINT) {
+      const int k = n / traj_every;
+      if (k != seg_loaded) materialize(k);
+      const int i = n - k * traj_every;
+      return {seg_mu[i], seg_v[i], seg_mus[i], seg_vs[i]};
+    }
+    // recompute: advance the rolling state, restarting from mu_0 when going back
+    if (rc_m < 0 || rc_m > n) {
+      rc_m = 0;
+      rc_mu = ck[0];
+      rc_v = lin_v0;
+      rc_star = false;
+    }
+    while (true) {
+      if (!rc_star) {
+        heun_step(rc_mu, rc_v, rb_mus, rb_vs, nullptr, nullptr);
+        rc_star = true;
+      }
+      if (rc_m == n) break;
+      const int nx = (rc_mu == rb_mu[0]) ? 1 : 0;
+      launch_epdiff_stage<T>(g, rb_vs, rb_mus, rc_mu, rb_mu[nx], dt, 0.5, 0.5, st, &prof);
+      applyK(rb_mu[nx], rb_v[nx]);
+      rc_mu = rb_mu[nx];
+      rc_v = rb_v[nx];
+      ++rc_m;
+      rc_star = false;
+    }
+    return {rc_mu, rc_v, rb_mus, rb_vs};
+  }
+
+  void traj_invalidate() {
+    seg_loaded = -1;
+    rc_m = -1;
+    rc_star = false;
   }
 
   int hip_status(const char* where) {
@@ -251,21 +409,21 @@ class Engine {
   // final (mu, v).
   void shoot_core(const T* v0, bool store, bool with_sl, T* Jout, T** mu_last, T** v_last,
                   bool want_energy = false) {
-    T* mu_cur = store ? tmu[0] : sm[0];
-    T* v_cur = store ? tv[0] : sv[0];
+    const bool all = store && traj_policy == TRAJ_STORE_ALL;
+    T* mu_cur = store ? store_slot_mu0() : sm[0];
+    T* v_cur = all ? tv[0] : sv[0];
     applyL(v0, mu_cur);
     copy(v_cur, v0, 3 * N);
+    if (store) traj_invalidate();
     if (want_energy) dot_dev(mu_cur, v0, 3, 2);
     if (with_sl) launch_fill<T>(3 * N, T(0), u[0], st, &prof);
     for (int n = 0; n < P.nt; ++n) {
-      T* ms = store ? tmus[n] : sms;
-      T* vs = store ? tvs[n] : svs;
-      launch_epdiff_stage<T>(g, v_cur, mu_cur, nullptr, ms, dt, 0.0, 1.0, st, &prof);
-      applyK(ms, vs);
-      T* mu_next = store ? tmu[n + 1] : sm[(n + 1) & 1];
-      T* v_next = store ? tv[n + 1] : sv[(n + 1) & 1];
-      launch_epdiff_stage<T>(g, vs, ms, mu_cur, mu_next, dt, 0.5, 0.5, st, &prof);
-      applyK(mu_next, v_next);
+      T* ms = all ? tmus[n] : sms;
+      T* vs = all ? tvs[n] : svs;
+      T* mu_next = store ? store_slot_mu(n + 1) : nullptr;
+      if (!mu_next) mu_next = (mu_cur == sm[0]) ? sm[1] : sm[0];
+      T* v_next = all ? tv[n + 1] : ((v_cur == sv[0]) ? sv[1] : sv[0]);
+      heun_step(mu_cur, v_cur, ms, vs, mu_next, v_next);
       if (with_sl) launch_sl_step<T>(g, u[n & 1], v_cur, v_next, u[(n + 1) & 1], dt, st, &prof);
       mu_cur = mu_next;
       v_cur = v_next;
@@ -301,10 +459,11 @@ class Engine {
     return hip_status("shoot");
   }
 
-  int linearize(const T* v0, double* energy_out) {
+  int linearize(const T* v0, T* J1out, double* energy_out) {
     if (!have_images) return fail(LDDMM_ESTATE, "images not set");
     if (int rc = check_finite(v0, 3 * N, "v0")) return rc;
     linearize_nocheck(v0);
+    if (J1out) copy(J1out, J1, N);
     if (energy_out) *energy_out = E;
     return hip_status("linearize");
   }
@@ -313,10 +472,11 @@ class Engine {
     if (v0 != lin_v0) copy(lin_v0, v0, 3 * N);
     shoot_core(lin_v0, true, true, J1, nullptr, nullptr);
     launch_residual_grad<T>(g, J1, I1, res, G, st, &prof);
-    Ereg = dot(tmu[0], lin_v0);
+    Ereg = dot(store_slot_mu0(), lin_v0);
     Edata = dot(res, res, 1) / P.sigma2;
     E = Ereg + Edata;
     linearized = true;
+    ++lin_epoch;
   }
 
   // ---- adjoint Jacobi sweep (transposed Heun) ------------------------------
@@ -324,12 +484,13 @@ class Engine {
   void backward() {
     launch_fill<T>(3 * N, T(0), Wh, st, &prof);
     for (int n = P.nt - 1; n >= 0; --n) {
-      launch_adjoint_pre<T>(g, U, Wh, tmus[n], Z, st, &prof);
+      const Step c = traj_view(n);
+      launch_adjoint_pre<T>(g, U, Wh, c.mus, Z, st, &prof);
       applyK(Z, Z);
-      launch_adjoint_post<T>(g, U, Wh, Z, tvs[n], nullptr, nullptr, Us, Whs, dt, 0.0, 1.0, st, &prof);
-      launch_adjoint_pre<T>(g, Us, Whs, tmu[n], Z, st, &prof);
+      launch_adjoint_post<T>(g, U, Wh, Z, c.vs, nullptr, nullptr, Us, Whs, dt, 0.0, 1.0, st, &prof);
+      launch_adjoint_pre<T>(g, Us, Whs, c.mu, Z, st, &prof);
       applyK(Z, Z);
-      launch_adjoint_post<T>(g, Us, Whs, Z, tv[n], U, Wh, U, Wh, dt, 0.5, 0.5, st, &prof);
+      launch_adjoint_post<T>(g, Us, Whs, Z, c.v, U, Wh, U, Wh, dt, 0.5, 0.5, st, &prof);
     }
   }
 
@@ -338,10 +499,11 @@ class Engine {
     applyL(dv, Mu);
     launch_fill<T>(3 * N, T(0), X, st, &prof);
     for (int n = 0; n < P.nt; ++n) {
+      const Step c = traj_view(n);
       applyK(Mu, W);
-      launch_tangent_stage<T>(g, X, Mu, W, tv[n], tmu[n], nullptr, nullptr, Xs, Mus, dt, 0.0, 1.0, st, &prof);
+      launch_tangent_stage<T>(g, X, Mu, W, c.v, c.mu, nullptr, nullptr, Xs, Mus, dt, 0.0, 1.0, st, &prof);
       applyK(Mus, W);
-      launch_tangent_stage<T>(g, Xs, Mus, W, tvs[n], tmus[n], X, Mu, X, Mu, dt, 0.5, 0.5, st, &prof);
+      launch_tangent_stage<T>(g, Xs, Mus, W, c.vs, c.mus, X, Mu, X, Mu, dt, 0.5, 0.5, st, &prof);
     }
   }
 
@@ -352,7 +514,7 @@ class Engine {
   }
 
   int gradient(const T* v0, T* gout, double* energy_out) {
-    if (int rc = linearize(v0, energy_out)) return rc;
+    if (int rc = linearize(v0, nullptr, energy_out)) return rc;
     gradient_core(gout);
     return hip_status("gradient");
   }
@@ -366,7 +528,7 @@ class Engine {
 
   int hessvec(const T* v0, const T* dv, T* hv) {
     if (v0) {
-      if (int rc = linearize(v0, nullptr)) return rc;
+      if (int rc = linearize(v0, nullptr, nullptr)) return rc;
     } else if (!linearized) {
       return fail(LDDMM_ESTATE, "hessvec without a linearization");
     }
@@ -559,6 +721,14 @@ class Engine {
       *value = t.use_static;
     else if (k == "fft.static_kernels")
       *value = sp.static_kernels;
+    else if (k == "traj.policy")
+      *value = traj_policy;
+    else if (k == "traj.every")
+      *value = traj_every;
+    else if (k == "traj.bytes")
+      *value = int64_t(traj_bytes);
+    else if (k == "lin.epoch")
+      *value = lin_epoch;
     else
       return fail(LDDMM_EINVAL, "unknown option " + k);
     return 0;
@@ -674,9 +844,9 @@ int lddmm_shoot(lddmm_ctx* ctx, const void* v0, void* J1, void* u1, void* v1, do
                               static_cast<T*>(v1), energy));
 }
 
-int lddmm_linearize(lddmm_ctx* ctx, const void* v0, double* energy) {
+int lddmm_linearize(lddmm_ctx* ctx, const void* v0, void* J1, double* energy) {
   if (!v0) return LDDMM_EINVAL;
-  LDDMM_DISPATCH(ctx, E.linearize(static_cast<const T*>(v0), energy));
+  LDDMM_DISPATCH(ctx, E.linearize(static_cast<const T*>(v0), static_cast<T*>(J1), energy));
 }
 
 int lddmm_gradient(lddmm_ctx* ctx, const void* v0, void* g, double* energy) {

@@ -92,7 +92,7 @@ SIGNATURES = {
     "lddmm_apply_operator": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp]),
     "lddmm_dot": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _c_double_p]),
     "lddmm_shoot": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _c_double_p]),
-    "lddmm_linearize": (ctypes.c_int, [_vp, _vp, _c_double_p]),
+    "lddmm_linearize": (ctypes.c_int, [_vp, _vp, _vp, _c_double_p]),
     "lddmm_gradient": (ctypes.c_int, [_vp, _vp, _vp, _c_double_p]),
     "lddmm_hessvec": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "lddmm_vjp": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -158,7 +158,8 @@ class Registration:
     sigma2 the data-term variance, dtype torch.float32 or torch.float64.
     """
 
-    def __init__(self, n, nt, alpha, s=2, sigma2=1.0, dtype=torch.float32, device="cuda:0"):
+    def __init__(self, n, nt, alpha, s=2, sigma2=1.0, dtype=torch.float32, device="cuda:0", checkpoint_every=0,
+                 mem_budget_bytes=0):
         self.lib = load_library()
         self.n = tuple(int(x) for x in n)
         self.nt, self.alpha, self.s, self.sigma2 = int(nt), float(alpha), int(s), float(sigma2)
@@ -175,6 +176,7 @@ class Registration:
         p.nt, p.s = self.nt, self.s
         p.dtype = F32 if dtype == torch.float32 else F64
         p.alpha, p.sigma2 = self.alpha, self.sigma2
+        p.checkpoint_every, p.mem_budget_bytes = int(checkpoint_every), int(mem_budget_bytes)
         self._ctx = ctypes.c_void_p()
         rc = self.lib.lddmm_create(ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._ctx))
         if rc != OK:
@@ -259,9 +261,12 @@ class Registration:
             out["energy"] = e.value
         return out
 
-    def linearize(self, v0):
+    def linearize(self, v0, J1_out=None):
         e = ctypes.c_double()
-        self._check(self.lib.lddmm_linearize(self._ctx, _ptr(self._field(v0, 3, "v0")), ctypes.byref(e)), "linearize")
+        J1p = None if J1_out is None else _ptr(self._field(J1_out, 1, "J1"))
+        self._check(
+            self.lib.lddmm_linearize(self._ctx, _ptr(self._field(v0, 3, "v0")), J1p, ctypes.byref(e)), "linearize"
+        )
         return e.value
 
     def gradient(self, v0, out=None):
