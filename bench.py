@@ -129,6 +129,77 @@ def cpu_baseline(spec, I0, I1, v0t, solve_over_hv):
     }
 
 
+def batch_bench(args, torch, synth, Batch, Registration):
+    """16 pairs of uneven sizes N in {64, 80, 96, 112, 128} (drawn with seed
+    4000), phantom recipe scaled by N/128, FP32, nt = 10: aggregate Hv/s and
+    solves/min for concurrent pairs (own streams, one host thread each, graph
+    replay) against the same batch run one pair after the other."""
+    import numpy as np
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(4000)
+    sizes = [int(x) for x in rng.choice([64, 80, 96, 112, 128], size=16)]
+    specs, data = [], []
+    for i, N in enumerate(sizes):
+        f = N / 128.0
+        n = (N, N, N)
+        I0 = synth.phantom(n, 24, (4.0 * f, 12.0 * f), True, 1000 + i)
+        v0 = synth.random_velocity(n, 2000 + i, 6.0 * f)
+        R = Registration(n, 10, 0.0025, 2, 1.0, dtype=torch.float64, device=dev)
+        t0 = torch.tensor(I0, dtype=torch.float64, device=dev)
+        R.set_images(t0, t0)
+        J1 = R.shoot(torch.tensor(v0, dtype=torch.float64, device=dev), want=("J1",))["J1"]
+        I1 = (J1 + torch.tensor(synth.noise(n, 3000 + i, 0.01), device=dev)).float()
+        R.close()
+        specs.append(dict(n=n, nt=10, alpha=0.0025, s=2, sigma2=1.0))
+        data.append((torch.tensor(I0, dtype=torch.float32, device=dev), I1))
+        log(f"[bench] pair {i}: {N}^3")
+    B = Batch(specs, dtype=torch.float32, device=dev)
+    for i, (I0, I1) in enumerate(data):
+        B.contexts[i].set_images(I0, I1)
+    B.autotune(reps=3)
+    out = {}
+    for mode, conc in (("sequential", False), ("concurrent", True)):
+        vs = [torch.zeros((3,) + sp["n"], device=dev) for sp in specs]
+        B.gn_solve(vs, concurrent=conc, gn_iters=2, cg_iters=5)  # warm-up (graph capture, caches)
+        vs = [torch.zeros((3,) + sp["n"], device=dev) for sp in specs]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = B.gn_solve(vs, concurrent=conc)
+        T = time.perf_counter() - t
+        hv = sum(r["hessvecs"] for r in reps)
+        dvs = [torch.randn((3,) + sp["n"], device=dev) for sp in specs]
+        hvs = [torch.empty_like(d) for d in dvs]
+        B.hessvec(dvs, hvs, reps=1, concurrent=conc)
+        t = time.perf_counter()
+        B.hessvec(dvs, hvs, reps=args.hv_reps, concurrent=conc)
+        Th = time.perf_counter() - t
+        out[mode] = {
+            "gn_solves_per_min": round(60.0 * len(specs) / T, 3),
+            "s_per_batch": round(T, 3),
+            "hessvecs_in_solves": hv,
+            "hv_per_s": round(len(specs) * args.hv_reps / Th, 2),
+            "mse_rel_final_mean": round(float(np.mean([r["mse_rel_final"] for r in reps])), 4),
+        }
+        log(f"[bench] {mode}: {out[mode]}")
+    line = {
+        "metric": "aggregate Hessian-vector products/s & GN solves/min, 16 uneven pairs",
+        "value": out["concurrent"]["hv_per_s"],
+        "unit": "Hv/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batch16: 16 pairs, N drawn from {64,80,96,112,128} with seed 4000, nt=10, "
+                               "alpha=0.0025, s=2, sigma2=1, GN<=10, CG<=20", "sizes": sizes},
+        "concurrent": out["concurrent"],
+        "sequential": out["sequential"],
+        "speedup_hv": round(out["concurrent"]["hv_per_s"] / out["sequential"]["hv_per_s"], 3),
+        "speedup_solves": round(out["concurrent"]["gn_solves_per_min"] / out["sequential"]["gn_solves_per_min"], 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +209,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--hv-reps", type=int, default=20)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default transform launch shapes")
+    ap.add_argument("--no-graph", action="store_true", help="launch Hessian-vector products kernel by kernel")
     ap.add_argument(
         "--profile-hv",
         type=int,
@@ -160,17 +233,28 @@ def main():
     import torch
 
     import synth
-    from paper_1807_04638_amd import Registration
+    from paper_1807_04638_amd import Batch, Registration
 
-    spec = synth.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "batch16":
+        batch_bench(args, torch, synth, Batch, Registration)
+        return
+    spec = synth.WORKLOADS[args.workload]
+    # everything runs on a dedicated stream so the contexts can replay graphs
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
     log(f"[bench] workload {spec.name} n={spec.n} nt={spec.nt}: building inputs")
     I0, I1, v0t = make_pair(spec, torch.float64, dev, torch, Registration, synth)
 
     def context(dtype):
         R = Registration(spec.n, spec.nt, spec.alpha, spec.s, spec.sigma2, dtype=dtype, device=dev)
         R.set_images(torch.tensor(I0, dtype=dtype, device=dev), torch.tensor(I1, dtype=dtype, device=dev))
+        if not args.no_tune:
+            tried, ms = R.autotune(reps=5)
+            log(f"[bench] autotune {dtype}: {tried} variants, K application {1e3 * ms:.1f} us")
+        if not args.no_graph:
+            R.set_option("exec.graph", 1)
         return R
 
     def solve(R, dtype):

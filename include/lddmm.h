@@ -207,13 +207,48 @@ int lddmm_profile_read(lddmm_ctx* ctx, const char** names, int64_t* counts, doub
  *   "traj.every"          read-only: checkpoint interval c
  *   "traj.bytes"          read-only: device bytes of the trajectory storage
  *   "lin.epoch"           read-only: number of linearizations made so far
+ *   "exec.graph"          0 | 1             replay Hessian-vector products from a captured
+ *                                           hipGraph (store-all trajectories; needs a
+ *                                           non-default stream)
  * LDDMM_EINVAL for an unknown key or a value out of range, LDDMM_EUNSUPPORTED if
  * the tiles would not fit the LDS of a workgroup (the previous setting stays). */
 int lddmm_set_option(lddmm_ctx* ctx, const char* key, int64_t value);
 int lddmm_get_option(lddmm_ctx* ctx, const char* key, int64_t* value);
 
+/* Autotuner: time the transform variants (plane workgroup size, pencil tile,
+ * compile-time vs generic kernels) on this context's grid with HIP events
+ * (reps applications each) and keep the fastest.  *tried = variants timed,
+ * *ms_per_apply = best time of one K application of a vector field (either
+ * may be NULL).  Synchronises. */
+int lddmm_autotune(lddmm_ctx* ctx, int reps, int* tried, double* ms_per_apply);
+
+/* Wait for all work of the context's stream. */
+int lddmm_sync(lddmm_ctx* ctx);
+
 /* Bytes of device memory held by the context. */
 int lddmm_memory_bytes(lddmm_ctx* ctx, int64_t* bytes);
+
+/* Batches of independent registrations (e.g. many template/target pairs of
+ * different sizes).  Each pair gets its own context on its own stream, created
+ * by the library (non-blocking, default priority), with graph replay of the
+ * Hessian-vector product enabled.  The contexts are used with the functions
+ * above (lddmm_batch_get); their calls are ordered on their own streams, so a
+ * caller working on another stream synchronises before handing buffers over.
+ * lddmm_batch_gn_solve / _hessvec run the pairs concurrently on one host
+ * thread per pair (concurrent != 0) or one after the other, and return after
+ * every pair has finished; the first failing status is returned. */
+typedef struct lddmm_batch lddmm_batch;
+int lddmm_batch_create(const lddmm_params* per_pair, int npairs, lddmm_batch** out);
+int lddmm_batch_destroy(lddmm_batch* batch);
+int lddmm_batch_get(lddmm_batch* batch, int i, lddmm_ctx** ctx);
+int lddmm_batch_sync(lddmm_batch* batch);
+/* v0_inout[i]: device vector field of pair i (solved in place); reports may be NULL. */
+int lddmm_batch_gn_solve(lddmm_batch* batch, void* const* v0_inout, const lddmm_solve_opts* opts,
+                         lddmm_solve_report* reports, int concurrent);
+/* reps Hessian-vector products per pair at each pair's current linearization. */
+int lddmm_batch_hessvec(lddmm_batch* batch, void* const* dv, void* const* hv, int reps, int concurrent);
+/* lddmm_autotune on every context. */
+int lddmm_batch_autotune(lddmm_batch* batch, int reps);
 
 const char* lddmm_strerror(int status);
 const char* lddmm_last_error(lddmm_ctx* ctx);

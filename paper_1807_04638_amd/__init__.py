@@ -8,4 +8,4 @@ The compute lives in the HIP library ``liblddmm.so`` (C ABI in include/lddmm.h);
 ``lddmm.Registration`` is its ctypes binding.
 """
 
-from .lddmm import LddmmError, Registration, load_library  # noqa: F401
+from .lddmm import Batch, LddmmError, Registration, load_library  # noqa: F401

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -106,7 +107,13 @@ class Engine {
   long long N = 0;
   double cell = 0.0, dt = 0.0;
   hipStream_t st = nullptr;
+  bool own_stream = false;  // created by a batch; destroyed with the engine
   std::string* err = nullptr;
+  // Hessian-vector product replayed from a captured hipGraph (exec.graph = 1)
+  bool use_graph = false;
+  hipGraphExec_t hv_exec = nullptr;
+  const T* graph_dv = nullptr;
+  T* graph_hv = nullptr;
   Profiler prof;
   SpectralPlan<T> sp;
   std::vector<void*> allocs;
@@ -147,6 +154,9 @@ class Engine {
   double E = 0, Ereg = 0, Edata = 0, base_sq = 0;
 
   ~Engine() {
+    if (st) (void)hipStreamSynchronize(st);
+    drop_graph();
+    if (own_stream && st) (void)hipStreamDestroy(st);
     spectral_free(sp);
     for (void* p : allocs) (void)hipFree(p);
     if (hres) (void)hipHostFree(hres);
@@ -519,12 +529,104 @@ class Engine {
     return hip_status("gradient");
   }
 
-  void hessvec_core(const T* dv, T* hv) {
+  void hessvec_kernels(const T* dv, T* hv) {
     tangent(dv);
     launch_gn_final<T>(g, G, X, 2.0 / P.sigma2, U, st, &prof);
     backward();
     launch_axpbyz<T>(3 * N, 2.0, dv, 1.0, Wh, hv, st, &prof);
   }
+
+  void drop_graph() {
+    if (hv_exec) (void)hipGraphExecDestroy(hv_exec);
+    hv_exec = nullptr;
+    graph_dv = nullptr;
+    graph_hv = nullptr;
+  }
+
+  // The Hv at a fixed linearization is a fixed sequence of launches on fixed
+  // buffers (the trajectory, G and the work fields), so it is captured once per
+  // (dv, hv) pair and replayed; the linearization's data change, not its
+  // addresses.  Store-all trajectories only (the segment bookkeeping of the
+  // other policies lives on the host), and never while profiling.
+  void hessvec_core(const T* dv, T* hv) {
+    if (!use_graph || traj_policy != TRAJ_STORE_ALL || prof.enabled || !st) {
+      hessvec_kernels(dv, hv);
+      return;
+    }
+    if (!hv_exec || graph_dv != dv || graph_hv != hv) {
+      drop_graph();
+      hipGraph_t graph = nullptr;
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        hessvec_kernels(dv, hv);
+        return;
+      }
+      hessvec_kernels(dv, hv);
+      if (hipStreamEndCapture(st, &graph) != hipSuccess || !graph) {
+        (void)hipGetLastError();
+        hessvec_kernels(dv, hv);
+        return;
+      }
+      const hipError_t e = hipGraphInstantiate(&hv_exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        hv_exec = nullptr;
+        (void)hipGetLastError();
+        hessvec_kernels(dv, hv);
+        return;
+      }
+      graph_dv = dv;
+      graph_hv = hv;
+    }
+    (void)hipGraphLaunch(hv_exec, st);
+  }
+
+  // ---- autotuner: time the transform variants on this grid, keep the fastest
+  int autotune(int reps, int* tried) {
+    if (reps <= 0) reps = 5;
+    (void)hipStreamSynchronize(st);
+    const FftTuning start = sp.tune;
+    FftTuning best = start;
+    float best_ms = -1.f;
+    int count = 0;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return fail(LDDMM_EHIP, "events");
+    const bool was = prof.enabled;
+    prof.enabled = false;
+    // operand: any vector work field (contents do not matter for timing)
+    for (int pt : {512, 1024})
+      for (int tb : {8, 16, 32})
+        for (int stc : {1, 0}) {
+          FftTuning t = start;
+          t.plane_threads = pt;
+          t.pencil_tb = tb;
+          t.pencil_threads = 256;
+          t.use_static = stc;
+          std::string msg;
+          if (spectral_configure(sp, t, msg) != 0) continue;
+          applyK(W, Z);
+          (void)hipEventRecord(a, st);
+          for (int r = 0; r < reps; ++r) applyK(W, Z);
+          (void)hipEventRecord(b, st);
+          (void)hipEventSynchronize(b);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, a, b);
+          ++count;
+          if (best_ms < 0.f || ms < best_ms) {
+            best_ms = ms;
+            best = t;
+          }
+        }
+    prof.enabled = was;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    std::string msg;
+    if (int rc = spectral_configure(sp, best, msg)) return fail(rc, msg);
+    drop_graph();
+    autotune_ms = best_ms / reps;
+    if (tried) *tried = count;
+    return hip_status("autotune");
+  }
+  float autotune_ms = 0.f;
 
   int hessvec(const T* v0, const T* dv, T* hv) {
     if (v0) {
@@ -693,12 +795,19 @@ class Engine {
       t.force_split = value != 0;
     else if (k == "fft.static")
       t.use_static = value != 0;
-    else
+    else if (k == "exec.graph") {
+      if (value != 0 && !st) return fail(LDDMM_EINVAL, "exec.graph needs a non-default stream");
+      (void)hipStreamSynchronize(st);
+      use_graph = value != 0;
+      drop_graph();
+      return 0;
+    } else
       return fail(LDDMM_EINVAL, "unknown or read-only option " + k);
     if (value < 0 || value > (1 << 20)) return fail(LDDMM_EINVAL, "option value out of range");
     (void)hipStreamSynchronize(st);
     std::string msg;
     if (int rc = spectral_configure(sp, t, msg)) return fail(rc, msg);
+    drop_graph();
     return 0;
   }
 
@@ -729,6 +838,8 @@ class Engine {
       *value = int64_t(traj_bytes);
     else if (k == "lin.epoch")
       *value = lin_epoch;
+    else if (k == "exec.graph")
+      *value = use_graph ? 1 : 0;
     else
       return fail(LDDMM_EINVAL, "unknown option " + k);
     return 0;
@@ -899,6 +1010,18 @@ int lddmm_get_option(lddmm_ctx* ctx, const char* key, int64_t* value) {
   LDDMM_DISPATCH(ctx, E.get_option(key, value));
 }
 
+int lddmm_autotune(lddmm_ctx* ctx, int reps, int* tried, double* ms_per_apply) {
+  LDDMM_DISPATCH(ctx, ([&]() {
+                   const int rc = E.autotune(reps, tried);
+                   if (ms_per_apply) *ms_per_apply = E.autotune_ms;
+                   return rc;
+                 }()));
+}
+
+int lddmm_sync(lddmm_ctx* ctx) {
+  LDDMM_DISPATCH(ctx, (hipStreamSynchronize(E.st) == hipSuccess ? LDDMM_OK : LDDMM_EHIP));
+}
+
 int lddmm_memory_bytes(lddmm_ctx* ctx, int64_t* bytes) {
   if (!bytes) return LDDMM_EINVAL;
   LDDMM_DISPATCH(ctx, (*bytes = int64_t(E.bytes), 0));
@@ -919,5 +1042,123 @@ const char* lddmm_strerror(int status) {
 }
 
 const char* lddmm_last_error(lddmm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+struct lddmm_batch {
+  std::vector<lddmm_ctx*> ctx;
+  int device = 0;
+};
+
+namespace {
+
+hipStream_t ctx_stream(lddmm_ctx* c) { return c->dtype == LDDMM_F32 ? c->f->st : c->d->st; }
+
+// Run fn(i) for every pair, on one host thread per pair (concurrent) or in order.
+template <class F>
+int for_pairs(lddmm_batch* b, int concurrent, F fn) {
+  const int n = int(b->ctx.size());
+  std::vector<int> rc(n, 0);
+  if (concurrent) {
+    std::vector<std::thread> th;
+    th.reserve(n);
+    for (int i = 0; i < n; ++i)
+      th.emplace_back([&, i]() {
+        (void)hipSetDevice(b->device);
+        rc[i] = fn(i);
+      });
+    for (auto& t : th) t.join();
+  } else {
+    for (int i = 0; i < n; ++i) rc[i] = fn(i);
+  }
+  for (int i = 0; i < n; ++i)
+    if (rc[i]) return rc[i];
+  return LDDMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lddmm_batch_create(const lddmm_params* per_pair, int npairs, lddmm_batch** out) {
+  if (!per_pair || npairs < 1 || !out) return LDDMM_EINVAL;
+  *out = nullptr;
+  auto* b = new lddmm_batch();
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return LDDMM_EHIP;
+  }
+  for (int i = 0; i < npairs; ++i) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      lddmm_batch_destroy(b);
+      return LDDMM_EHIP;
+    }
+    lddmm_ctx* c = nullptr;
+    const int rc = lddmm_create(&per_pair[i], s, &c);
+    if (rc) {
+      (void)hipStreamDestroy(s);
+      lddmm_batch_destroy(b);
+      return rc;
+    }
+    if (c->dtype == LDDMM_F32) {
+      c->f->own_stream = true;
+      c->f->use_graph = true;
+    } else {
+      c->d->own_stream = true;
+      c->d->use_graph = true;
+    }
+    b->ctx.push_back(c);
+  }
+  *out = b;
+  return LDDMM_OK;
+}
+
+int lddmm_batch_destroy(lddmm_batch* b) {
+  if (!b) return LDDMM_EINVAL;
+  for (lddmm_ctx* c : b->ctx) lddmm_destroy(c);
+  delete b;
+  return LDDMM_OK;
+}
+
+int lddmm_batch_get(lddmm_batch* b, int i, lddmm_ctx** out) {
+  if (!b || !out || i < 0 || i >= int(b->ctx.size())) return LDDMM_EINVAL;
+  *out = b->ctx[i];
+  return LDDMM_OK;
+}
+
+int lddmm_batch_sync(lddmm_batch* b) {
+  if (!b) return LDDMM_EINVAL;
+  for (lddmm_ctx* c : b->ctx)
+    if (hipStreamSynchronize(ctx_stream(c)) != hipSuccess) return LDDMM_EHIP;
+  return LDDMM_OK;
+}
+
+int lddmm_batch_gn_solve(lddmm_batch* b, void* const* v0_inout, const lddmm_solve_opts* opts,
+                         lddmm_solve_report* reports, int concurrent) {
+  if (!b || !v0_inout) return LDDMM_EINVAL;
+  return for_pairs(b, concurrent, [&](int i) {
+    return lddmm_gn_solve(b->ctx[i], v0_inout[i], opts, reports ? &reports[i] : nullptr, nullptr, 0);
+  });
+}
+
+int lddmm_batch_hessvec(lddmm_batch* b, void* const* dv, void* const* hv, int reps, int concurrent) {
+  if (!b || !dv || !hv || reps < 1) return LDDMM_EINVAL;
+  return for_pairs(b, concurrent, [&](int i) {
+    for (int r = 0; r < reps; ++r) {
+      const int rc = lddmm_hessvec(b->ctx[i], nullptr, dv[i], hv[i]);
+      if (rc) return rc;
+    }
+    return hipStreamSynchronize(ctx_stream(b->ctx[i])) == hipSuccess ? LDDMM_OK : LDDMM_EHIP;
+  });
+}
+
+int lddmm_batch_autotune(lddmm_batch* b, int reps) {
+  if (!b) return LDDMM_EINVAL;
+  return for_pairs(b, 0, [&](int i) { return lddmm_autotune(b->ctx[i], reps, nullptr, nullptr); });
+}
 
 }  // extern "C"

@@ -109,7 +109,19 @@ SIGNATURES = {
     ),
     "lddmm_set_option": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int64]),
     "lddmm_get_option": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]),
+    "lddmm_autotune": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _c_double_p]),
+    "lddmm_sync": (ctypes.c_int, [_vp]),
     "lddmm_memory_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64)]),
+    "lddmm_batch_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(_vp)]),
+    "lddmm_batch_destroy": (ctypes.c_int, [_vp]),
+    "lddmm_batch_get": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "lddmm_batch_sync": (ctypes.c_int, [_vp]),
+    "lddmm_batch_gn_solve": (
+        ctypes.c_int,
+        [_vp, ctypes.POINTER(_vp), ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveReport), ctypes.c_int],
+    ),
+    "lddmm_batch_hessvec": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int]),
+    "lddmm_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lddmm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "lddmm_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -159,8 +171,9 @@ class Registration:
     """
 
     def __init__(self, n, nt, alpha, s=2, sigma2=1.0, dtype=torch.float32, device="cuda:0", checkpoint_every=0,
-                 mem_budget_bytes=0):
+                 mem_budget_bytes=0, _handle=None):
         self.lib = load_library()
+        self._owned = _handle is None
         self.n = tuple(int(x) for x in n)
         self.nt, self.alpha, self.s, self.sigma2 = int(nt), float(alpha), int(s), float(sigma2)
         self.dtype = dtype
@@ -170,6 +183,11 @@ class Registration:
         if self.device.type != "cuda":
             raise ValueError("the library runs on a HIP device only")
         torch.cuda.set_device(self.device)
+        if _handle is not None:
+            # a batch context: its work runs on a library-owned stream
+            self.stream = None
+            self._ctx = ctypes.c_void_p(_handle)
+            return
         self.stream = torch.cuda.current_stream(self.device)
         p = Params()
         p.n = (ctypes.c_int32 * 3)(*self.n)
@@ -184,7 +202,7 @@ class Registration:
 
     # ---- helpers ----------------------------------------------------------
     def close(self):
-        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+        if getattr(self, "_owned", False) and getattr(self, "_ctx", None) is not None and self._ctx.value:
             self.lib.lddmm_destroy(self._ctx)
             self._ctx = ctypes.c_void_p()
 
@@ -195,11 +213,17 @@ class Registration:
             pass
 
     def _check(self, rc, what):
+        if self.stream is None and rc == OK:
+            # batch context: make its results visible to torch's stream
+            rc = self.lib.lddmm_sync(self._ctx)
         if rc != OK:
             msg = self.lib.lddmm_last_error(self._ctx) or b""
             raise LddmmError(rc, f"{what}: {self.lib.lddmm_strerror(rc).decode()}: {msg.decode()}")
 
     def _field(self, t, ncomp, name):
+        if self.stream is None:
+            # batch context on its own stream: inputs must be complete first
+            torch.cuda.current_stream(self.device).synchronize()
         shape = (ncomp,) + self.n if ncomp == 3 else self.n
         if t is None:
             raise ValueError(f"{name} is required")
@@ -342,7 +366,87 @@ class Registration:
         self._check(self.lib.lddmm_get_option(self._ctx, key.encode(), ctypes.byref(v)), f"get_option({key})")
         return v.value
 
+    def autotune(self, reps=5):
+        """Time the transform variants on this grid and keep the fastest;
+        returns (variants tried, ms per K application of a vector field)."""
+        tried, ms = ctypes.c_int(), ctypes.c_double()
+        self._check(self.lib.lddmm_autotune(self._ctx, int(reps), ctypes.byref(tried), ctypes.byref(ms)), "autotune")
+        return tried.value, ms.value
+
+    def sync(self):
+        self._check(self.lib.lddmm_sync(self._ctx), "sync")
+
     def memory_bytes(self):
         b = ctypes.c_int64()
         self._check(self.lib.lddmm_memory_bytes(self._ctx, ctypes.byref(b)), "memory_bytes")
         return b.value
+
+
+class Batch:
+    """Independent registrations, one context per pair on its own stream.
+
+    specs: list of dicts with keys n, nt, alpha, s, sigma2 (dtype shared).
+    ``contexts[i]`` is a Registration view of pair i; gn_solve / hessvec run all
+    pairs concurrently (one host thread each) or in order.
+    """
+
+    def __init__(self, specs, dtype=torch.float32, device="cuda:0"):
+        self.lib = load_library()
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        arr = (Params * len(specs))()
+        for i, sp in enumerate(specs):
+            p = arr[i]
+            p.n = (ctypes.c_int32 * 3)(*[int(x) for x in sp["n"]])
+            p.nt, p.s = int(sp["nt"]), int(sp.get("s", 2))
+            p.dtype = F32 if dtype == torch.float32 else F64
+            p.alpha, p.sigma2 = float(sp["alpha"]), float(sp.get("sigma2", 1.0))
+        self._b = ctypes.c_void_p()
+        rc = self.lib.lddmm_batch_create(arr, len(specs), ctypes.byref(self._b))
+        if rc != OK:
+            raise LddmmError(rc, "lddmm_batch_create: " + self.lib.lddmm_strerror(rc).decode())
+        self.contexts = []
+        for i, sp in enumerate(specs):
+            h = ctypes.c_void_p()
+            self.lib.lddmm_batch_get(self._b, i, ctypes.byref(h))
+            self.contexts.append(
+                Registration(sp["n"], sp["nt"], sp["alpha"], sp.get("s", 2), sp.get("sigma2", 1.0), dtype=dtype,
+                             device=device, _handle=h.value)
+            )
+
+    def __len__(self):
+        return len(self.contexts)
+
+    def _rc(self, rc, what):
+        if rc != OK:
+            raise LddmmError(rc, f"{what}: {self.lib.lddmm_strerror(rc).decode()}")
+
+    def gn_solve(self, v0s, concurrent=True, gn_iters=10, cg_iters=20, max_halvings=10, c1=1e-4, gtol=1e-3,
+                 eta_max=0.5):
+        torch.cuda.current_stream(self.device).synchronize()
+        ptrs = (_vp * len(v0s))(*[t.data_ptr() for t in v0s])
+        o = SolveOpts(gn_iters, cg_iters, max_halvings, 0, c1, gtol, eta_max)
+        reps = (SolveReport * len(v0s))()
+        self._rc(self.lib.lddmm_batch_gn_solve(self._b, ptrs, ctypes.byref(o), reps, 1 if concurrent else 0),
+                 "batch_gn_solve")
+        return [{k: getattr(r, k) for k, _ in SolveReport._fields_} for r in reps]
+
+    def hessvec(self, dvs, hvs, reps=1, concurrent=True):
+        torch.cuda.current_stream(self.device).synchronize()
+        a = (_vp * len(dvs))(*[t.data_ptr() for t in dvs])
+        b = (_vp * len(hvs))(*[t.data_ptr() for t in hvs])
+        self._rc(self.lib.lddmm_batch_hessvec(self._b, a, b, int(reps), 1 if concurrent else 0), "batch_hessvec")
+
+    def autotune(self, reps=5):
+        self._rc(self.lib.lddmm_batch_autotune(self._b, int(reps)), "batch_autotune")
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            self.lib.lddmm_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

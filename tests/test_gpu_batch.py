@@ -1,0 +1,124 @@
+"""Batched form: autotuner, hipGraph replay of the Hessian-vector product, and
+batches of pairs of uneven sizes solved concurrently on their own streams.
+
+Every check compares with the plain single-context path or the oracle on the
+same inputs; graph replays are compared with eager results on every replay,
+with eager work and synchronisations in between."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import phantom, random_field, random_velocity
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def T(x, dtype):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+def pair(n, seed):
+    I0 = phantom(n, 4, (1.5, 3.0), False, 1000 + seed)
+    p = O.Params(tuple(n), 0.01, 2, 4, 0.02)
+    I1 = O.shoot(random_velocity(n, 2000 + seed, 1.0, kc=2.0), p, I0).J1
+    return I0, I1
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_graph_replay_matches_eager(dtype):
+    from paper_1807_04638_amd import Registration
+
+    n = (32, 32, 32)
+    s = torch.cuda.Stream(device=DEV)
+    with torch.cuda.stream(s):
+        say(f"[case] graph replay {dtype}")
+        R = Registration(n, 5, 0.01, 2, 0.05, dtype=dtype)
+        I0, I1 = pair(n, 0)
+        R.set_images(T(I0, dtype), T(I1, dtype))
+        R.linearize(T(random_velocity(n, 2100, 1.5, kc=2.0), dtype))
+        dv = T(random_field(n, 13, kc=3.0), dtype)
+        eager = R.hessvec(dv)
+        R.set_option("exec.graph", 1)
+        hv = torch.empty_like(dv)
+        for rep in range(4):
+            R.hessvec(dv, out=hv)
+            s.synchronize()
+            assert torch.equal(hv, eager), rep
+            other = R.apply_K(dv)  # eager work between replays
+            s.synchronize()
+            del other
+        # a new linearization changes the data behind the captured graph
+        R.linearize(T(random_velocity(n, 2101, 1.5, kc=2.0), dtype))
+        R.hessvec(dv, out=hv)
+        R.set_option("exec.graph", 0)
+        assert torch.equal(hv, R.hessvec(dv))
+        s.synchronize()
+
+
+def test_graph_needs_a_stream():
+    from paper_1807_04638_amd import LddmmError, Registration
+
+    R = Registration((16, 16, 16), 3, 0.01)
+    if R.stream.cuda_stream == 0:
+        with pytest.raises(LddmmError):
+            R.set_option("exec.graph", 1)
+
+
+@pytest.mark.parametrize("n", [(32, 32, 32), (24, 20, 30)])
+def test_autotune_keeps_parity(n):
+    from paper_1807_04638_amd import Registration
+
+    R = Registration(n, 4, 0.01, dtype=torch.float32)
+    tried, ms = R.autotune(reps=3)
+    say(f"[case] autotune {n}: {tried} variants, best {ms * 1e3:.1f} us per K application")
+    assert tried >= 2 and ms > 0
+    p = O.Params(n, 0.01, 2, 4, 1.0)
+    f = T(random_field(n, 4, kc=max(n) / 4), torch.float32)
+    ref = O.apply_K(f.double().cpu().numpy(), p)
+    got = R.apply_K(f).double().cpu().numpy()
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 2e-6
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batch_uneven_sizes_matches_single_contexts(dtype):
+    """Pairs of uneven sizes (radices 2, 3, 5, 7) solved concurrently by a batch
+    give bitwise the reports and velocities of one-at-a-time single contexts."""
+    from paper_1807_04638_amd import Batch, Registration
+
+    sizes = [(16, 16, 16), (20, 20, 20), (24, 24, 24), (28, 28, 28), (16, 24, 20)]
+    specs = [dict(n=n, nt=4, alpha=0.01, s=2, sigma2=0.02) for n in sizes]
+    data = [pair(n, i) for i, n in enumerate(sizes)]
+    B = Batch(specs, dtype=dtype)
+    for i, (I0, I1) in enumerate(data):
+        B.contexts[i].set_images(T(I0, dtype), T(I1, dtype))
+        assert B.contexts[i].get_option("exec.graph") == 1
+    v_batch = [torch.zeros((3,) + n, dtype=dtype, device=DEV) for n in sizes]
+    say(f"[case] batch of {len(sizes)} {dtype}")
+    reps = B.gn_solve(v_batch, concurrent=True, gn_iters=3, cg_iters=5)
+    for i, n in enumerate(sizes):
+        R = Registration(n, 4, 0.01, 2, 0.02, dtype=dtype)
+        R.set_images(T(data[i][0], dtype), T(data[i][1], dtype))
+        v = torch.zeros((3,) + n, dtype=dtype, device=DEV)
+        tr = R.gn_solve(v, gn_iters=3, cg_iters=5)
+        say(f"  pair {i} {n}: batch E {reps[i]['E_final']:.6g} single {tr.report['E_final']:.6g}")
+        assert reps[i] == tr.report
+        assert torch.equal(v_batch[i], v)
+    # sequential batch runs give the same as concurrent ones
+    v_seq = [torch.zeros((3,) + n, dtype=dtype, device=DEV) for n in sizes]
+    reps_seq = B.gn_solve(v_seq, concurrent=False, gn_iters=3, cg_iters=5)
+    assert reps_seq == reps
+    assert all(torch.equal(a, b) for a, b in zip(v_seq, v_batch))
+    # batched Hessian-vector products at each pair's final linearization
+    dvs = [T(random_field(n, 30 + i, kc=2.0), dtype) for i, n in enumerate(sizes)]
+    hvs = [torch.empty_like(d) for d in dvs]
+    B.hessvec(dvs, hvs, reps=2, concurrent=True)
+    for i in range(len(sizes)):
+        assert torch.equal(hvs[i], B.contexts[i].hessvec(dvs[i]))
+    B.close()
