@@ -332,7 +332,7 @@ __device__ __forceinline__ void lds_fft_static(cplx<T>* buf, const cplx<T>* tw) 
 template <typename T, int H, int COUNT, int NT>
 __device__ __forceinline__ void rows_r2c_static(cplx<T>* A, const cplx<T>* tw2, const cplx<T>* twr, const int* slot2) {
   constexpr int M = H + 1;
-  lds_fft_static<T, Pow2Plan<H>, false, true, COUNT, 1, M, NT>(A, tw2);
+  lds_fft_static<T, typename PlanOf<H>::type, false, true, COUNT, 1, M, NT>(A, tw2);
   constexpr int total = COUNT * (H / 2 + 1);
 #pragma unroll
   for (int i0 = 0; i0 < total; i0 += NT) {
@@ -383,7 +383,7 @@ __device__ __forceinline__ void rows_c2r_static(cplx<T>* A, const cplx<T>* tw2, 
     }
   }
   __syncthreads();
-  lds_fft_static<T, Pow2Plan<H>, true, true, COUNT, 1, M, NT>(A, tw2);
+  lds_fft_static<T, typename PlanOf<H>::type, true, true, COUNT, 1, M, NT>(A, tw2);
 }
 
 template <typename T, int H, int N1>
@@ -424,7 +424,7 @@ __global__ void __launch_bounds__(NT) k_plane_fwd_s(const T* __restrict__ in, cp
   }
   __syncthreads();
   rows_r2c_static<T, H, N1, NT>(L.A, L.tw2, L.twr, L.slot2);
-  lds_fft_static<T, Pow2Plan<N1>, false, true, M, M, 1, NT>(L.A, L.tw1);
+  lds_fft_static<T, typename PlanOf<N1>::type, false, true, M, M, 1, NT>(L.A, L.tw1);
   cplx<T>* dst = spec + ((long long)comp * a.n0 + x0) * (N1 * M);
   for (int idx = threadIdx.x; idx < N1 * M; idx += NT) dst[idx] = L.A[idx];
 }
@@ -439,7 +439,7 @@ __global__ void __launch_bounds__(NT) k_plane_inv_s(const cplx<T>* __restrict__ 
   const cplx<T>* src = spec + ((long long)comp * a.n0 + x0) * (N1 * M);
   for (int idx = threadIdx.x; idx < N1 * M; idx += NT) L.A[idx] = src[idx];
   __syncthreads();
-  lds_fft_static<T, Pow2Plan<N1>, true, true, M, M, 1, NT>(L.A, L.tw1);
+  lds_fft_static<T, typename PlanOf<N1>::type, true, true, M, M, 1, NT>(L.A, L.tw1);
   rows_c2r_static<T, H, N1, NT>(L.A, L.tw2, L.twr, L.slot2);
   cplx<T>* dst = reinterpret_cast<cplx<T>*>(out + comp * a.N + (long long)x0 * (N1 * 2 * H));
 #pragma unroll
@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(NT) k_pencil_s(cplx<T>* __restrict__ spec, Pen
 #pragma unroll
   for (int j = j0; j < N; j += JS) A[j * TB + t] = live ? base[(long long)j * a.es + t] : cplx<T>{T(0), T(0)};
   __syncthreads();
-  if (MODE != 1) lds_fft_static<T, Pow2Plan<N>, false, true, TB, TB, 1, NT>(A, tw);
+  if (MODE != 1) lds_fft_static<T, typename PlanOf<N>::type, false, true, TB, TB, 1, NT>(A, tw);
   if (MODE == 2) {
     const T k12 = ksq12[t];
 #pragma unroll
@@ -540,7 +540,7 @@ __global__ void __launch_bounds__(NT) k_pencil_s(cplx<T>* __restrict__ spec, Pen
     }
     __syncthreads();
   }
-  if (MODE != 0) lds_fft_static<T, Pow2Plan<N>, true, true, TB, TB, 1, NT>(A, tw);
+  if (MODE != 0) lds_fft_static<T, typename PlanOf<N>::type, true, true, TB, TB, 1, NT>(A, tw);
   if (live) {
 #pragma unroll
     for (int j = j0; j < N; j += JS) base[(long long)j * a.es + t] = A[j * TB + t];
@@ -592,28 +592,32 @@ using PencilFn = void (*)(cplx<T>*, PencilArgs<T>);
 
 enum { KF_PLANE_FWD, KF_PLANE_INV, KF_ROWS_FWD, KF_ROWS_INV, KF_PENCIL0, KF_PENCIL1F, KF_PENCIL1I };
 
-bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
-
 template <typename T, int NT>
-void plane_static(int H, int N1, void*& f, void*& i) {
-#define LDDMM_PLANE_CASE(h, n1)                                        \
-  if (H == h && N1 == n1) {                                            \
-    f = (void*)(PlaneFwdFn<T>)k_plane_fwd_s<T, h, n1, NT>;             \
-    i = (void*)(PlaneInvFn<T>)k_plane_inv_s<T, h, n1, NT>;             \
-    return;                                                            \
+void plane_static(const FftPlan& p2, const FftPlan& p1, void*& f, void*& i) {
+  const int H = p2.n, N1 = p1.n;
+#define LDDMM_PLANE_CASE(h, n1)                                                                   \
+  if (H == h && N1 == n1 && plan_matches<PlanOf<h>::type>(p2) && plan_matches<PlanOf<n1>::type>(p1)) { \
+    f = (void*)(PlaneFwdFn<T>)k_plane_fwd_s<T, h, n1, NT>;                                        \
+    i = (void*)(PlaneInvFn<T>)k_plane_inv_s<T, h, n1, NT>;                                        \
+    return;                                                                                       \
   }
   LDDMM_PLANE_CASE(8, 16)
   LDDMM_PLANE_CASE(16, 32)
   LDDMM_PLANE_CASE(32, 64)
   LDDMM_PLANE_CASE(64, 128)
+  LDDMM_PLANE_CASE(40, 80)
+  LDDMM_PLANE_CASE(48, 96)
+  LDDMM_PLANE_CASE(56, 112)
+  LDDMM_PLANE_CASE(90, 216)
 #undef LDDMM_PLANE_CASE
   f = i = nullptr;
 }
 
 template <typename T, int MODE>
-void* pencil_static(int N, int TB) {
+void* pencil_static(const FftPlan& pl, int TB) {
+  const int N = pl.n;
 #define LDDMM_PENCIL_N(n)                                                                \
-  if (N == n) {                                                                          \
+  if (N == n && plan_matches<PlanOf<n>::type>(pl)) {                                     \
     if (TB == 8) return (void*)(PencilFn<T>)k_pencil_s<T, MODE, n, 8, 256>;              \
     if (TB == 16) return (void*)(PencilFn<T>)k_pencil_s<T, MODE, n, 16, 256>;            \
     if (TB == 32) return (void*)(PencilFn<T>)k_pencil_s<T, MODE, n, 32, 256>;            \
@@ -623,14 +627,20 @@ void* pencil_static(int N, int TB) {
   LDDMM_PENCIL_N(64)
   LDDMM_PENCIL_N(128)
   LDDMM_PENCIL_N(256)
+  LDDMM_PENCIL_N(80)
+  LDDMM_PENCIL_N(96)
+  LDDMM_PENCIL_N(112)
+  LDDMM_PENCIL_N(180)
+  LDDMM_PENCIL_N(216)
 #undef LDDMM_PENCIL_N
   return nullptr;
 }
 
 template <typename T>
-void rows_static(int H, int RB, void*& f, void*& i) {
+void rows_static(const FftPlan& p2, int RB, void*& f, void*& i) {
+  const int H = p2.n;
 #define LDDMM_ROWS_CASE(h, rb)                                         \
-  if (H == h && RB == rb) {                                            \
+  if (H == h && RB == rb && plan_matches<PlanOf<h>::type>(p2)) {       \
     f = (void*)(RowsFwdFn<T>)k_rows_fwd_s<T, h, rb, 256>;              \
     i = (void*)(RowsInvFn<T>)k_rows_inv_s<T, h, rb, 256>;              \
     return;                                                            \
@@ -639,6 +649,8 @@ void rows_static(int H, int RB, void*& f, void*& i) {
   LDDMM_ROWS_CASE(64, 32)
   LDDMM_ROWS_CASE(128, 16)
   LDDMM_ROWS_CASE(128, 32)
+  LDDMM_ROWS_CASE(90, 16)
+  LDDMM_ROWS_CASE(90, 32)
 #undef LDDMM_ROWS_CASE
   f = i = nullptr;
 }
@@ -680,9 +692,9 @@ int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& 
   int nstatic = 0;
   const bool use_static = tune.use_static != 0;
   if (fused) {
-    if (use_static && is_pow2(H) && is_pow2(n1)) {
-      if (tune.plane_threads == 512) plane_static<T, 512>(H, n1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
-      if (tune.plane_threads == 1024) plane_static<T, 1024>(H, n1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
+    if (use_static) {
+      if (tune.plane_threads == 512) plane_static<T, 512>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
+      if (tune.plane_threads == 1024) plane_static<T, 1024>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
     }
     if (k[KF_PLANE_FWD]) {
       nstatic++;
@@ -696,7 +708,7 @@ int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& 
     }
   } else {
     const long long rows = (long long)n0 * n1;
-    if (use_static && rows % tune.rows_rb == 0) rows_static<T>(H, tune.rows_rb, k[KF_ROWS_FWD], k[KF_ROWS_INV]);
+    if (use_static && rows % tune.rows_rb == 0) rows_static<T>(sp.p2, tune.rows_rb, k[KF_ROWS_FWD], k[KF_ROWS_INV]);
     if (k[KF_ROWS_FWD]) {
       nstatic++;
     } else {
@@ -704,8 +716,8 @@ int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& 
       k[KF_ROWS_INV] = (void*)(RowsInvFn<T>)k_rows_inv<T>;
     }
     if (use_static && tune.pencil_threads == 256) {
-      k[KF_PENCIL1F] = pencil_static<T, 0>(n1, tb);
-      k[KF_PENCIL1I] = pencil_static<T, 1>(n1, tb);
+      k[KF_PENCIL1F] = pencil_static<T, 0>(sp.p1, tb);
+      k[KF_PENCIL1I] = pencil_static<T, 1>(sp.p1, tb);
     }
     if (k[KF_PENCIL1F]) {
       nstatic++;
@@ -714,7 +726,7 @@ int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& 
       k[KF_PENCIL1I] = pencil_generic<T>(1, tune.pencil_threads);
     }
   }
-  if (use_static && tune.pencil_threads == 256) k[KF_PENCIL0] = pencil_static<T, 2>(n0, tb);
+  if (use_static && tune.pencil_threads == 256) k[KF_PENCIL0] = pencil_static<T, 2>(sp.p0, tb);
   if (k[KF_PENCIL0])
     nstatic++;
   else

@@ -276,6 +276,42 @@ struct Pow2Plan {
   static constexpr int length(int i) { return i == 0 ? N : length(i - 1) / radix(i - 1); }
 };
 
+// Explicit radix list (in DIF stage order) for the other lengths in use.
+template <int N, int... Rs>
+struct RadixPlan {
+  static constexpr int nf = sizeof...(Rs);
+  static constexpr int rs[sizeof...(Rs)] = {Rs...};
+  static constexpr int radix(int i) { return rs[i]; }
+  static constexpr int length(int i) { return i == 0 ? N : length(i - 1) / radix(i - 1); }
+};
+
+// Compile-time plan of length N: powers of two by rule, the mixed lengths of
+// the supported grids listed (each equal to make_plan(N), checked on the host).
+template <int N>
+struct PlanOf {
+  using type = Pow2Plan<N>;
+};
+#define LDDMM_PLAN(n, ...)                       template <>                                    struct PlanOf<n> {                               using type = RadixPlan<n, __VA_ARGS__>;      };
+LDDMM_PLAN(40, 8, 5)
+LDDMM_PLAN(48, 8, 2, 3)
+LDDMM_PLAN(56, 8, 7)
+LDDMM_PLAN(80, 8, 2, 5)
+LDDMM_PLAN(90, 2, 3, 3, 5)
+LDDMM_PLAN(96, 8, 4, 3)
+LDDMM_PLAN(112, 8, 2, 7)
+LDDMM_PLAN(180, 4, 3, 3, 5)
+LDDMM_PLAN(216, 8, 3, 3, 3)
+#undef LDDMM_PLAN
+
+// True if the compile-time plan P has the runtime plan's radices.
+template <class P>
+inline bool plan_matches(const FftPlan& rt) {
+  if (rt.n != P::length(0) || rt.nf != P::nf) return false;
+  for (int i = 0; i < P::nf; ++i)
+    if (rt.radix[i] != P::radix(i)) return false;
+  return true;
+}
+
 // Butterfly b of DIF/DIT stage ST (plan P) over COUNT sequences; element e of
 // sequence s at buf[s * SS + e * ES].
 template <typename T, class P, int ST, bool INV, bool SEQ_FAST, int COUNT, int ES, int SS>

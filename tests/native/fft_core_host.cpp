@@ -61,3 +61,58 @@ int fftcore_digit_reverse(int n, int* perm) {
 }
 
 }
+
+namespace {
+
+template <class P, bool INV, int I = 0>
+void run_static(cplx<double>* buf, const cplx<double>* tw) {
+  if constexpr (I < P::nf) {
+    constexpr int st = INV ? P::nf - 1 - I : I;
+    constexpr int total = P::length(0) / P::radix(st);
+    for (int b = 0; b < total; ++b) fft_stage_item_static<double, P, st, INV, false, 1, 1, P::length(0)>(buf, b, tw);
+    run_static<P, INV, I + 1>(buf, tw);
+  }
+}
+
+template <int N>
+int static_case(double* data, int inverse) {
+  using P = typename PlanOf<N>::type;
+  FftPlan rt;
+  if (!make_plan(N, rt) || !plan_matches<P>(rt)) return -2;  // compile-time plan must equal make_plan
+  std::vector<cplx<double>> tw(N);
+  for (int m = 0; m < N; ++m) tw[m] = {std::cos(-2.0 * M_PI * m / N), std::sin(-2.0 * M_PI * m / N)};
+  auto* buf = reinterpret_cast<cplx<double>*>(data);
+  if (inverse)
+    run_static<P, true>(buf, tw.data());
+  else
+    run_static<P, false>(buf, tw.data());
+  return P::nf;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Same as fftcore_transform through the compile-time plan of length n
+// (the lengths instantiated by the GPU kernels); -1 if n has none.
+int fftcore_transform_static(int n, double* data, int inverse) {
+  switch (n) {
+    case 16: return static_case<16>(data, inverse);
+    case 32: return static_case<32>(data, inverse);
+    case 64: return static_case<64>(data, inverse);
+    case 128: return static_case<128>(data, inverse);
+    case 256: return static_case<256>(data, inverse);
+    case 40: return static_case<40>(data, inverse);
+    case 48: return static_case<48>(data, inverse);
+    case 56: return static_case<56>(data, inverse);
+    case 80: return static_case<80>(data, inverse);
+    case 90: return static_case<90>(data, inverse);
+    case 96: return static_case<96>(data, inverse);
+    case 112: return static_case<112>(data, inverse);
+    case 180: return static_case<180>(data, inverse);
+    case 216: return static_case<216>(data, inverse);
+    default: return -1;
+  }
+}
+
+}

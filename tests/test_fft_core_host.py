@@ -26,6 +26,7 @@ def lib(tmp_path_factory):
     L = ctypes.CDLL(out)
     L.fftcore_transform.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     L.fftcore_digit_reverse.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    L.fftcore_transform_static.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     return L
 
 
@@ -60,3 +61,20 @@ def test_dit_inverts_dif(lib, n):
 def test_unsupported_length(lib):
     buf = np.zeros(22, dtype=np.complex128)
     assert lib.fftcore_transform(11, buf.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0) == -1
+
+
+STATIC = [16, 32, 64, 128, 256, 40, 48, 56, 80, 90, 96, 112, 180, 216]
+
+
+@pytest.mark.parametrize("n", STATIC)
+def test_compile_time_plans_match_runtime_and_numpy(lib, n):
+    """The compile-time plans used by the specialised GPU kernels have the
+    runtime plan's radices and transform the same way."""
+    rng = np.random.default_rng(300 + n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    buf = x.copy()
+    p = buf.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.fftcore_transform_static(n, p, 0) >= 1
+    np.testing.assert_allclose(buf, np.fft.fft(x)[_perm(lib, n)], atol=1e-12 * n)
+    lib.fftcore_transform_static(n, p, 1)
+    np.testing.assert_allclose(buf / n, x, atol=1e-13 * n)

@@ -95,7 +95,7 @@ def test_operator_parity(n, dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("n", [(32, 32, 32), (64, 64, 64), (16, 32, 64)])
+@pytest.mark.parametrize("n", [(32, 32, 32), (64, 64, 64), (16, 32, 64), (80, 80, 80), (112, 112, 112)])
 @pytest.mark.parametrize("opts", [{"fft.static": 0}, {"fft.static": 1}, {"fft.force_split": 1},
                                   {"fft.force_split": 1, "fft.static": 0}, {"fft.plane_threads": 256, "fft.pencil_tb": 32}])
 def test_operator_transform_variants(n, dtype, opts):
@@ -106,6 +106,20 @@ def test_operator_transform_variants(n, dtype, opts):
         R.set_option(k, v)
     say(f"  options {opts} fused={R.get_option('fft.fused')} static_kernels={R.get_option('fft.static_kernels')}")
     f = rounded(random_field(n, 3, kc=max(n) / 3), dtype)
+    Lf = O.apply_L(f, p)
+    assert rel(R.apply_K(T(f, dtype)), O.apply_K(f, p)) <= TOL[dtype]["op"]
+    assert rel(R.apply_L(T(f, dtype)), Lf) <= l_tol(p, f, Lf, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_operator_head_grid_180x216x180(dtype):
+    """Brain-shaped grid (radices 2, 3, 4, 5, 8): fused compile-time planes in
+    FP32, the split path in FP64 (the half-plane exceeds the LDS)."""
+    n = (180, 216, 180)
+    R, p = make(n, dtype, alpha=0.0025)
+    say(f"  fused={R.get_option('fft.fused')} static_kernels={R.get_option('fft.static_kernels')}")
+    assert R.get_option("fft.static_kernels") >= 2
+    f = rounded(random_field(n, 14, kc=10.0), dtype)
     Lf = O.apply_L(f, p)
     assert rel(R.apply_K(T(f, dtype)), O.apply_K(f, p)) <= TOL[dtype]["op"]
     assert rel(R.apply_L(T(f, dtype)), Lf) <= l_tol(p, f, Lf, dtype)
