@@ -200,6 +200,80 @@ def batch_bench(args, torch, synth, Batch, Registration):
     print(json.dumps(line), flush=True)
 
 
+def precision_bench(args, torch, synth, Registration, spec):
+    """Precision policy on a brain-shaped grid: FP32 fields with FP64 reductions
+    against the plain FP64 path (the FP64 GPU path is the reference here; it
+    matches the FP64 oracle to ~1e-15 at the sizes the oracle finishes).
+    Reports relative-L2 differences of v0 after the GN solve, the warped image,
+    and the <mu, v> drift of the final geodesic, with solve/Hv timings."""
+    import numpy as np
+
+    dev = torch.device("cuda:0")
+    n = spec.n
+    I0 = synth.phantom(n, spec.n_blobs, spec.sigma_range, spec.classes, 1000, shells=spec.shells)
+    v0t = synth.random_velocity(n, 2000, spec.disp_vox)
+    res = {}
+    I1 = None
+    for dt in (torch.float64, torch.float32):
+        R = Registration(n, spec.nt, spec.alpha, spec.s, spec.sigma2, dtype=dt, device=dev)
+        t0 = torch.tensor(I0, dtype=dt, device=dev)
+        if I1 is None:
+            R.set_images(t0, t0)
+            J = R.shoot(torch.tensor(v0t, dtype=dt, device=dev), want=("J1",))["J1"]
+            I1 = (J + torch.tensor(synth.noise(n, 3000, spec.noise_sd), dtype=dt, device=dev)).cpu().numpy()
+        R.set_images(t0, torch.tensor(I1, dtype=dt, device=dev))
+        tried, ms = R.autotune(reps=3)
+        R.set_option("exec.graph", 1)
+        log(f"[bench] {dt}: autotune {tried} variants, K {1e3 * ms:.1f} us; {R.get_option('fft.static_kernels')} compile-time passes")
+        v = torch.zeros((3,) + n, dtype=dt, device=dev)
+        R.gn_solve(v, gn_iters=1, cg_iters=2)  # warm-up
+        v = torch.zeros((3,) + n, dtype=dt, device=dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        tr = R.gn_solve(v, gn_iters=spec.gn_iters, cg_iters=spec.cg_iters)
+        torch.cuda.synchronize()
+        Ts = time.perf_counter() - t
+        sh = R.shoot(v, want=("J1", "v1"))
+        mu0, mu1 = R.apply_L(v), R.apply_L(sh["v1"])
+        drift = R.dot(mu1, sh["v1"]) / R.dot(mu0, v) - 1.0
+        dv = torch.randn((3,) + n, dtype=dt, device=dev, generator=torch.Generator(device=dev).manual_seed(5))
+        R.hessvec(dv)
+        hv_ms = time_events(torch, lambda: R.hessvec(dv), 5)
+        res[dt] = dict(v=v.double().cpu().numpy(), J1=sh["J1"].double().cpu().numpy(), drift=drift, s=Ts,
+                       hv_ms=hv_ms, rep=tr.report)
+        log(f"[bench] {dt}: solve {Ts:.2f} s, Hv {hv_ms:.2f} ms, drift {drift:.3e}, report {tr.report}")
+        del R
+        torch.cuda.empty_cache()
+    a, b = res[torch.float32], res[torch.float64]
+
+    def rel(x, y):
+        return float(np.linalg.norm(x - y) / np.linalg.norm(y))
+
+    line = {
+        "metric": "FP32 vs FP64 relative-L2 error (v0 after GN, warped image, drift) and solve speed",
+        "value": round(60.0 / a["s"], 3),
+        "unit": "GN solves/min",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{spec.name}: {n[0]}x{n[1]}x{n[2]} head phantom (3 shells, {spec.n_blobs} blobs), "
+                               f"nt={spec.nt}, alpha={spec.alpha}, s={spec.s}, sigma2={spec.sigma2}, disp {spec.disp_vox} vox, "
+                               "noise 0.01, GN<=10, CG<=20"},
+        "rel_l2_v0": rel(a["v"], b["v"]),
+        "rel_l2_J1": rel(a["J1"], b["J1"]),
+        "drift_fp32": a["drift"],
+        "drift_fp64": b["drift"],
+        "mse_rel_final": {"fp32": a["rep"]["mse_rel_final"], "fp64": b["rep"]["mse_rel_final"]},
+        "E_final": {"fp32": a["rep"]["E_final"], "fp64": b["rep"]["E_final"]},
+        "solve_s": {"fp32": round(a["s"], 3), "fp64": round(b["s"], 3)},
+        "hv_ms": {"fp32": round(a["hv_ms"], 3), "fp64": round(b["hv_ms"], 3)},
+        "fp32_speedup_vs_fp64": round(b["s"] / a["s"], 3),
+        "reference": "FP64 GPU path (oracle-pinned at small sizes)",
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +318,9 @@ def main():
     # everything runs on a dedicated stream so the contexts can replay graphs
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.set_stream(stream)
+    if args.workload == "head180x216x180":
+        precision_bench(args, torch, synth, Registration, spec)
+        return
     log(f"[bench] workload {spec.name} n={spec.n} nt={spec.nt}: building inputs")
     I0, I1, v0t = make_pair(spec, torch.float64, dev, torch, Registration, synth)
 
@@ -330,6 +407,14 @@ def main():
     hv_bytes = sum(nbytes[k] * kernels[k]["launches_per_hv"] for k in kernels if k in nbytes)
     log(f"[bench] dominant kernel {dom}: {kernels[dom]}")
 
+    # practical HBM ceiling for reference: a plain 1 GiB device copy (read + write)
+    src = torch.ones(256 * 2**20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    copy_ms = time_events(torch, lambda: dst.copy_(src), 10)
+    copy_GBps = 2 * src.numel() * 4 / (copy_ms * 1e-3) / 1e9
+    del src, dst
+    log(f"[bench] device copy 1 GiB: {copy_ms:.3f} ms, {copy_GBps:.0f} GB/s (read + write)")
+
     # plain FP64 path
     fp64 = None
     if not args.no_fp64:
@@ -411,6 +496,7 @@ def main():
             "avg_launch_us": kernels[dom]["avg_us"],
         },
         "kernels": kernels,
+        "hbm_copy_GBps": round(copy_GBps, 1),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

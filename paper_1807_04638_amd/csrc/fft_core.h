@@ -165,6 +165,19 @@ struct Dft<T, 8, DIR> {
   }
 };
 
+// Twiddle powers w[q] = W^(j q), q = 1..R-1, from one table read W^j (the
+// rest by complex products in registers: fewer LDS reads, a few ulp of error).
+template <typename T, int R>
+LD_HD void twiddle_powers(cplx<T>* w, int j, int twstep, const cplx<T>* tw) {
+  w[1] = tw[j * twstep];
+  if (R > 2) w[2] = c_mul(w[1], w[1]);
+  if (R > 3) w[3] = c_mul(w[2], w[1]);
+  if (R > 4) w[4] = c_mul(w[2], w[2]);
+  if (R > 5) w[5] = c_mul(w[4], w[1]);
+  if (R > 6) w[6] = c_mul(w[4], w[2]);
+  if (R > 7) w[7] = c_mul(w[4], w[3]);
+}
+
 // One butterfly of DIF stage with sub-length L = R * stride.  Elements at
 // base + t * step (t < R); j = position inside the sub-block; tw[m] =
 // exp(-2 pi i m / n); twstep = n / L.
@@ -175,8 +188,10 @@ LD_HD void dif_butterfly(cplx<T>* buf, int base, int step, int j, int twstep, co
   for (int t = 0; t < R; ++t) a[t] = buf[base + t * step];
   Dft<T, R, -1>::run(a);
   buf[base] = a[0];
+  cplx<T> w[R];
+  twiddle_powers<T, R>(w, j, twstep, tw);
 #pragma unroll
-  for (int q = 1; q < R; ++q) buf[base + q * step] = c_mul(a[q], tw[j * q * twstep]);
+  for (int q = 1; q < R; ++q) buf[base + q * step] = c_mul(a[q], w[q]);
 }
 
 // Inverse of dif_butterfly up to the factor R (conjugate twiddle, then DFT).
@@ -184,8 +199,10 @@ template <typename T, int R>
 LD_HD void dit_butterfly(cplx<T>* buf, int base, int step, int j, int twstep, const cplx<T>* tw) {
   cplx<T> a[R];
   a[0] = buf[base];
+  cplx<T> w[R];
+  twiddle_powers<T, R>(w, j, twstep, tw);
 #pragma unroll
-  for (int q = 1; q < R; ++q) a[q] = c_mulc(buf[base + q * step], tw[j * q * twstep]);
+  for (int q = 1; q < R; ++q) a[q] = c_mulc(buf[base + q * step], w[q]);
   Dft<T, R, +1>::run(a);
 #pragma unroll
   for (int t = 0; t < R; ++t) buf[base + t * step] = a[t];
