@@ -70,6 +70,54 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Transform launch shape that the autotuner chose; HBM traffic is recorded per shape.
+TUNED_KEYS = ("fft.plane_threads", "fft.pencil_threads", "fft.pencil_tb", "fft.rows_rb", "fft.fused", "fft.static_kernels")
+KERNEL_SOURCES = {
+    "fft": ("paper_1807_04638_amd/csrc/fft.hip", "paper_1807_04638_amd/csrc/fft_core.h"),
+    "stencil": ("paper_1807_04638_amd/csrc/stencil.hip",),
+}
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_pair128_fp32.md")
+
+
+def source_digest(group):
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES[group]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel, tuned):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    record, or None when the record is missing, was taken with another launch
+    shape, or the kernel's sources changed since."""
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            text = f.read()
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    if rec.get("sources", {}).get(k["sources"]) != source_digest(k["sources"]):
+        return None
+    if any(rec.get("tuned", {}).get(key) != tuned.get(key) for key in shape_keys(kernel)):
+        return None
+    return int(k["fetch_bytes"] + k["write_bytes"])
+
+
+def shape_keys(kernel):
+    """Launch-shape options that change a kernel's memory traffic."""
+    if kernel.startswith("fft_pencil"):
+        return ("fft.pencil_tb", "fft.pencil_threads", "fft.fused", "fft.static_kernels")
+    if kernel.startswith("fft_"):
+        return ("fft.plane_threads", "fft.rows_rb", "fft.fused", "fft.static_kernels")
+    return ()
+
+
 def make_pair(spec, dtype, dev, torch, Registration, synth):
     I0 = synth.phantom(spec.n, spec.n_blobs, spec.sigma_range, spec.classes, 1000, shells=spec.shells)
     v0t = synth.random_velocity(spec.n, 2000, spec.disp_vox)
@@ -353,7 +401,14 @@ def main():
         for _ in range(4):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_hv": args.profile_hv, "copy_bytes_each_way": src.numel() * 4}), flush=True)
+        tuned = {k: R.get_option(k) for k in TUNED_KEYS}
+        digests = {g: source_digest(g) for g in KERNEL_SOURCES}
+        print(
+            json.dumps(
+                {"profile_hv": args.profile_hv, "copy_bytes_each_way": src.numel() * 4, "tuned": tuned, "sources": digests}
+            ),
+            flush=True,
+        )
         return
     log(f"[bench] warmup {args.warmup} solve(s)")
     for _ in range(args.warmup):
@@ -400,6 +455,9 @@ def main():
             "share": round(ms / sum(v[1] for v in prof.values()), 4),
             "GBps": round(kb / (avg_us * 1e-6) / 1e9, 1) if kb else None,
         }
+    tuned = {k: R.get_option(k) for k in TUNED_KEYS}
+    for name in kernels:
+        kernels[name]["traffic"] = recorded_traffic(name, tuned)
     dom = max((k for k in kernels if k in nbytes), key=lambda k: prof[k][1])
     dom_bytes = nbytes[dom]
     dom_avg_s = kernels[dom]["avg_us"] * 1e-6
@@ -491,10 +549,11 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": kernels[dom]["traffic"],
             "bytes_per_launch": int(dom_bytes),
             "avg_launch_us": kernels[dom]["avg_us"],
         },
+        "fft_launch_shape": tuned,
         "kernels": kernels,
         "hbm_copy_GBps": round(copy_GBps, 1),
         "cpu_baseline": cpu,

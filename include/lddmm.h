@@ -217,7 +217,9 @@ int lddmm_get_option(lddmm_ctx* ctx, const char* key, int64_t* value);
 
 /* Autotuner: time the transform variants (plane workgroup size, pencil tile,
  * compile-time vs generic kernels) on this context's grid with HIP events
- * (reps applications each) and keep the fastest.  *tried = variants timed,
+ * (reps applications each) and keep the fastest; the shape in place when the
+ * call starts is kept unless another is more than 3 % faster, so repeated
+ * calls settle on the same shape.  *tried = variants timed,
  * *ms_per_apply = best time of one K application of a vector field (either
  * may be NULL).  Synchronises. */
 int lddmm_autotune(lddmm_ctx* ctx, int reps, int* tried, double* ms_per_apply);

@@ -329,57 +329,76 @@ __device__ __forceinline__ void lds_fft_static(cplx<T>* buf, const cplx<T>* tw) 
   }
 }
 
-template <typename T, int H, int COUNT, int NT>
+// Row post-processing: item k in 1..H/2 splits the pair (k, H - k); the last
+// item also does k = 0, so a row takes H/2 items (whole rounds of the block
+// for the usual sizes).  PACK stores the two real frequencies X[0] and X[H] of
+// a row as one complex number X[0] + i X[H] in column 0 (column H is left
+// alone): the columns k2 = 0 and k2 = N2/2 are real sequences along x1, and
+// one complex transform of the packed column does both.
+template <typename T, int H, int COUNT, int NT, bool PACK>
 __device__ __forceinline__ void rows_r2c_static(cplx<T>* A, const cplx<T>* tw2, const cplx<T>* twr, const int* slot2) {
   constexpr int M = H + 1;
+  constexpr int KI = H / 2;
   lds_fft_static<T, typename PlanOf<H>::type, false, true, COUNT, 1, M, NT>(A, tw2);
-  constexpr int total = COUNT * (H / 2 + 1);
+  constexpr int total = COUNT * KI;
 #pragma unroll
   for (int i0 = 0; i0 < total; i0 += NT) {
     const int idx = i0 + int(threadIdx.x);
     if (total % NT != 0 && idx >= total) continue;
-    const int k = idx / COUNT, r = idx - k * COUNT;
+    const int k = 1 + idx / COUNT, r = idx - (k - 1) * COUNT;
     cplx<T>* row = A + r * M;
-    if (k == 0) {
+    const int sk = slot2[k], sm = slot2[H - k];
+    const cplx<T> a = row[sk], b = row[sm];
+    // even part e = (a + conj b) / 2, odd part o = (a - conj b) / 2
+    const cplx<T> e = {T(0.5) * (a.x + b.x), T(0.5) * (a.y - b.y)};
+    const cplx<T> o = {T(0.5) * (a.x - b.x), T(0.5) * (a.y + b.y)};
+    const cplx<T> wo = c_mul(twr[k], o);
+    // X[k] = e - i w o ;  X[H-k] = conj(e) - i conj(w o)
+    row[sk] = {e.x + wo.y, e.y - wo.x};
+    if (sm != sk) row[sm] = {e.x - wo.y, -e.y - wo.x};
+    if (k == KI) {
       const cplx<T> z = row[0];
-      row[0] = {z.x + z.y, T(0)};
-      row[H] = {z.x - z.y, T(0)};
-    } else {
-      const int sk = slot2[k], sm = slot2[H - k];
-      const cplx<T> a = row[sk], b = row[sm];
-      const cplx<T> e = {T(0.5) * (a.x + b.x), T(0.5) * (a.y - b.y)};
-      const cplx<T> o = {T(0.5) * (a.x - b.x), T(0.5) * (a.y + b.y)};
-      const cplx<T> wo = c_mul(twr[k], o);
-      row[sk] = {e.x + wo.y, e.y - wo.x};
-      if (sm != sk) row[sm] = {e.x - wo.y, -e.y - wo.x};
+      if (PACK) {
+        row[0] = {z.x + z.y, z.x - z.y};
+      } else {
+        row[0] = {z.x + z.y, T(0)};
+        row[H] = {z.x - z.y, T(0)};
+      }
     }
   }
   __syncthreads();
 }
 
-template <typename T, int H, int COUNT, int NT>
+// Inverse of rows_r2c_static (times N2).  PACK: column 0 holds X[0] + i X[H]
+// with X[0], X[H] real.
+template <typename T, int H, int COUNT, int NT, bool PACK>
 __device__ __forceinline__ void rows_c2r_static(cplx<T>* A, const cplx<T>* tw2, const cplx<T>* twr, const int* slot2) {
   constexpr int M = H + 1;
-  constexpr int total = COUNT * (H / 2 + 1);
+  constexpr int KI = H / 2;
+  constexpr int total = COUNT * KI;
 #pragma unroll
   for (int i0 = 0; i0 < total; i0 += NT) {
     const int idx = i0 + int(threadIdx.x);
     if (total % NT != 0 && idx >= total) continue;
-    const int k = idx / COUNT, r = idx - k * COUNT;
+    const int k = 1 + idx / COUNT, r = idx - (k - 1) * COUNT;
     cplx<T>* row = A + r * M;
-    if (k == 0) {
-      const cplx<T> a = row[0], b = row[H];
-      const cplx<T> p = {a.x + b.x, a.y - b.y};
-      const cplx<T> q = {a.x - b.x, a.y + b.y};
-      row[0] = {p.x - q.y, p.y + q.x};
-    } else {
-      const int sk = slot2[k], sm = slot2[H - k];
-      const cplx<T> a = row[sk], b = row[sm];
-      const cplx<T> p = {a.x + b.x, a.y - b.y};
-      const cplx<T> q = {a.x - b.x, a.y + b.y};
-      const cplx<T> t = c_mulc(q, twr[k]);
-      row[sk] = {p.x - t.y, p.y + t.x};
-      if (sm != sk) row[sm] = {p.x + t.y, -p.y + t.x};
+    const int sk = slot2[k], sm = slot2[H - k];
+    const cplx<T> a = row[sk], b = row[sm];
+    const cplx<T> p = {a.x + b.x, a.y - b.y};  // X[k] + conj X[H-k]
+    const cplx<T> q = {a.x - b.x, a.y + b.y};  // X[k] - conj X[H-k]
+    const cplx<T> t = c_mulc(q, twr[k]);       // conj(w) q
+    row[sk] = {p.x - t.y, p.y + t.x};          // p + i t
+    if (sm != sk) row[sm] = {p.x + t.y, -p.y + t.x};  // conj(p) + i conj(t)
+    if (k == KI) {
+      if (PACK) {
+        const cplx<T> z = row[0];
+        row[0] = {z.x + z.y, z.x - z.y};
+      } else {
+        const cplx<T> a0 = row[0], b0 = row[H];
+        const cplx<T> p0 = {a0.x + b0.x, a0.y - b0.y};
+        const cplx<T> q0 = {a0.x - b0.x, a0.y + b0.y};
+        row[0] = {p0.x - q0.y, p0.y + q0.x};
+      }
     }
   }
   __syncthreads();
@@ -407,9 +426,14 @@ __device__ __forceinline__ PlaneLds<T> carve_static(unsigned char* smem, int row
   return L;
 }
 
+// Fused plane kernels.  The k2 = 0 and k2 = N2/2 columns travel packed in
+// column 0 through the x1 transform (H columns instead of H + 1) and are split
+// apart before the store: with Z the transform of X[0] + i X[N2/2] along x1,
+// the two spectra are (Z[k] + conj Z[-k]) / 2 and (Z[k] - conj Z[-k]) / 2i.
 template <typename T, int H, int N1, int NT>
 __global__ void __launch_bounds__(NT) k_plane_fwd_s(const T* __restrict__ in, cplx<T>* __restrict__ spec,
                                                     PlaneArgs<T> a) {
+  using P1 = typename PlanOf<N1>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int M = H + 1;
   const int x0 = blockIdx.x, comp = blockIdx.y;
@@ -423,8 +447,19 @@ __global__ void __launch_bounds__(NT) k_plane_fwd_s(const T* __restrict__ in, cp
     L.A[j1 * M + (idx - j1 * H)] = src[idx];
   }
   __syncthreads();
-  rows_r2c_static<T, H, N1, NT>(L.A, L.tw2, L.twr, L.slot2);
-  lds_fft_static<T, typename PlanOf<N1>::type, false, true, M, M, 1, NT>(L.A, L.tw1);
+  rows_r2c_static<T, H, N1, NT, true>(L.A, L.tw2, L.twr, L.slot2);
+  lds_fft_static<T, P1, false, true, H, M, 1, NT>(L.A, L.tw1);
+  for (int k = threadIdx.x; k <= N1 / 2; k += NT) {
+    const int sk = slot_of<P1>(k), sm = slot_of<P1>(k == 0 ? 0 : N1 - k);
+    const cplx<T> zk = L.A[sk * M], zm = L.A[sm * M];
+    const cplx<T> lo = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+    const cplx<T> hi = {T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
+    L.A[sk * M] = lo;
+    L.A[sk * M + H] = hi;
+    L.A[sm * M] = c_conj(lo);
+    L.A[sm * M + H] = c_conj(hi);
+  }
+  __syncthreads();
   cplx<T>* dst = spec + ((long long)comp * a.n0 + x0) * (N1 * M);
   for (int idx = threadIdx.x; idx < N1 * M; idx += NT) dst[idx] = L.A[idx];
 }
@@ -437,10 +472,18 @@ __global__ void __launch_bounds__(NT) k_plane_inv_s(const cplx<T>* __restrict__ 
   const int x0 = blockIdx.x, comp = blockIdx.y;
   PlaneLds<T> L = carve_static<T, H, N1>(smem, N1, a, true);
   const cplx<T>* src = spec + ((long long)comp * a.n0 + x0) * (N1 * M);
-  for (int idx = threadIdx.x; idx < N1 * M; idx += NT) L.A[idx] = src[idx];
+  for (int idx = threadIdx.x; idx < N1 * M; idx += NT) {
+    const int j1 = idx / M, c = idx - j1 * M;
+    cplx<T> v = src[idx];
+    if (c == 0) {
+      const cplx<T> hi = src[idx + H];
+      v = {v.x - hi.y, v.y + hi.x};  // X[0] + i X[N2/2]
+    }
+    L.A[idx] = v;
+  }
   __syncthreads();
-  lds_fft_static<T, typename PlanOf<N1>::type, true, true, M, M, 1, NT>(L.A, L.tw1);
-  rows_c2r_static<T, H, N1, NT>(L.A, L.tw2, L.twr, L.slot2);
+  lds_fft_static<T, typename PlanOf<N1>::type, true, true, H, M, 1, NT>(L.A, L.tw1);
+  rows_c2r_static<T, H, N1, NT, true>(L.A, L.tw2, L.twr, L.slot2);
   cplx<T>* dst = reinterpret_cast<cplx<T>*>(out + comp * a.N + (long long)x0 * (N1 * 2 * H));
 #pragma unroll
   for (int i0 = 0; i0 < N1 * H; i0 += NT) {
@@ -469,7 +512,7 @@ __global__ void __launch_bounds__(NT) k_rows_fwd_s(const T* __restrict__ in, cpl
     L.A[r * M + (idx - r * H)] = src[idx];
   }
   __syncthreads();
-  rows_r2c_static<T, H, RB, NT>(L.A, L.tw2, L.twr, L.slot2);
+  rows_r2c_static<T, H, RB, NT, false>(L.A, L.tw2, L.twr, L.slot2);
   cplx<T>* dst = spec + ((long long)comp * rows + r0) * M;
   for (int idx = threadIdx.x; idx < RB * M; idx += NT) dst[idx] = L.A[idx];
 }
@@ -486,7 +529,7 @@ __global__ void __launch_bounds__(NT) k_rows_inv_s(const cplx<T>* __restrict__ s
   const cplx<T>* src = spec + ((long long)comp * rows + r0) * M;
   for (int idx = threadIdx.x; idx < RB * M; idx += NT) L.A[idx] = src[idx];
   __syncthreads();
-  rows_c2r_static<T, H, RB, NT>(L.A, L.tw2, L.twr, L.slot2);
+  rows_c2r_static<T, H, RB, NT, false>(L.A, L.tw2, L.twr, L.slot2);
   cplx<T>* dst = reinterpret_cast<cplx<T>*>(out + comp * a.N) + r0 * H;
 #pragma unroll
   for (int i0 = 0; i0 < RB * H; i0 += NT) {
@@ -867,16 +910,16 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   if (sp.fused) {
     const dim3 gp(sp.n0, ncomp);
     {
-      KernelTimer t(prof, "fft_plane_fwd", st);
-      ((PlaneFwdFn<T>)sp.kfn[KF_PLANE_FWD])<<<gp, tu.plane_threads, sp.plane_lds, st>>>(in, sp.spec, pa);
+      KernelTimer t(prof, "fft_plane_fwd");
+      LDDMM_LAUNCH(t.start, t.stop, ((PlaneFwdFn<T>)sp.kfn[KF_PLANE_FWD]), gp, tu.plane_threads, sp.plane_lds, st, in, sp.spec, pa);
     }
     {
-      KernelTimer t(prof, "fft_pencil_symbol", st);
-      pencil0<<<g0, tu.pencil_threads, sp.pencil0_lds, st>>>(sp.spec, k0);
+      KernelTimer t(prof, "fft_pencil_symbol");
+      LDDMM_LAUNCH(t.start, t.stop, pencil0, g0, tu.pencil_threads, sp.pencil0_lds, st, sp.spec, k0);
     }
     {
-      KernelTimer t(prof, "fft_plane_inv", st);
-      ((PlaneInvFn<T>)sp.kfn[KF_PLANE_INV])<<<gp, tu.plane_threads, sp.plane_lds, st>>>(sp.spec, out, pa);
+      KernelTimer t(prof, "fft_plane_inv");
+      LDDMM_LAUNCH(t.start, t.stop, ((PlaneInvFn<T>)sp.kfn[KF_PLANE_INV]), gp, tu.plane_threads, sp.plane_lds, st, sp.spec, out, pa);
     }
     return;
   }
@@ -890,24 +933,24 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   const long long rows = (long long)sp.n0 * sp.n1;
   const dim3 gr((unsigned)((rows + tu.rows_rb - 1) / tu.rows_rb), ncomp);
   {
-    KernelTimer t(prof, "fft_rows_fwd", st);
-    ((RowsFwdFn<T>)sp.kfn[KF_ROWS_FWD])<<<gr, 256, sp.rows_lds, st>>>(in, sp.spec, pa, tu.rows_rb);
+    KernelTimer t(prof, "fft_rows_fwd");
+    LDDMM_LAUNCH(t.start, t.stop, ((RowsFwdFn<T>)sp.kfn[KF_ROWS_FWD]), gr, 256, sp.rows_lds, st, in, sp.spec, pa, tu.rows_rb);
   }
   {
-    KernelTimer t(prof, "fft_pencil_x1_fwd", st);
-    ((PencilFn<T>)sp.kfn[KF_PENCIL1F])<<<g1, tu.pencil_threads, sp.pencil1_lds, st>>>(sp.spec, k1);
+    KernelTimer t(prof, "fft_pencil_x1_fwd");
+    LDDMM_LAUNCH(t.start, t.stop, ((PencilFn<T>)sp.kfn[KF_PENCIL1F]), g1, tu.pencil_threads, sp.pencil1_lds, st, sp.spec, k1);
   }
   {
-    KernelTimer t(prof, "fft_pencil_symbol", st);
-    pencil0<<<g0, tu.pencil_threads, sp.pencil0_lds, st>>>(sp.spec, k0);
+    KernelTimer t(prof, "fft_pencil_symbol");
+    LDDMM_LAUNCH(t.start, t.stop, pencil0, g0, tu.pencil_threads, sp.pencil0_lds, st, sp.spec, k0);
   }
   {
-    KernelTimer t(prof, "fft_pencil_x1_inv", st);
-    ((PencilFn<T>)sp.kfn[KF_PENCIL1I])<<<g1, tu.pencil_threads, sp.pencil1_lds, st>>>(sp.spec, k1);
+    KernelTimer t(prof, "fft_pencil_x1_inv");
+    LDDMM_LAUNCH(t.start, t.stop, ((PencilFn<T>)sp.kfn[KF_PENCIL1I]), g1, tu.pencil_threads, sp.pencil1_lds, st, sp.spec, k1);
   }
   {
-    KernelTimer t(prof, "fft_rows_inv", st);
-    ((RowsInvFn<T>)sp.kfn[KF_ROWS_INV])<<<gr, 256, sp.rows_lds, st>>>(sp.spec, out, pa, tu.rows_rb);
+    KernelTimer t(prof, "fft_rows_inv");
+    LDDMM_LAUNCH(t.start, t.stop, ((RowsInvFn<T>)sp.kfn[KF_ROWS_INV]), gr, 256, sp.rows_lds, st, sp.spec, out, pa, tu.rows_rb);
   }
 }
 

@@ -180,29 +180,40 @@ LD_HD void twiddle_powers(cplx<T>* w, int j, int twstep, const cplx<T>* tw) {
 
 // One butterfly of DIF stage with sub-length L = R * stride.  Elements at
 // base + t * step (t < R); j = position inside the sub-block; tw[m] =
-// exp(-2 pi i m / n); twstep = n / L.
-template <typename T, int R>
+// exp(-2 pi i m / n); twstep = n / L.  TW = false when the stride is 1 (the
+// last DIF stage), where every twiddle is W^0 = 1.
+template <typename T, int R, bool TW = true>
 LD_HD void dif_butterfly(cplx<T>* buf, int base, int step, int j, int twstep, const cplx<T>* tw) {
   cplx<T> a[R];
 #pragma unroll
   for (int t = 0; t < R; ++t) a[t] = buf[base + t * step];
   Dft<T, R, -1>::run(a);
-  buf[base] = a[0];
-  cplx<T> w[R];
-  twiddle_powers<T, R>(w, j, twstep, tw);
+  if constexpr (TW) {
+    buf[base] = a[0];
+    cplx<T> w[R];
+    twiddle_powers<T, R>(w, j, twstep, tw);
 #pragma unroll
-  for (int q = 1; q < R; ++q) buf[base + q * step] = c_mul(a[q], w[q]);
+    for (int q = 1; q < R; ++q) buf[base + q * step] = c_mul(a[q], w[q]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < R; ++q) buf[base + q * step] = a[q];
+  }
 }
 
 // Inverse of dif_butterfly up to the factor R (conjugate twiddle, then DFT).
-template <typename T, int R>
+template <typename T, int R, bool TW = true>
 LD_HD void dit_butterfly(cplx<T>* buf, int base, int step, int j, int twstep, const cplx<T>* tw) {
   cplx<T> a[R];
-  a[0] = buf[base];
-  cplx<T> w[R];
-  twiddle_powers<T, R>(w, j, twstep, tw);
+  if constexpr (TW) {
+    a[0] = buf[base];
+    cplx<T> w[R];
+    twiddle_powers<T, R>(w, j, twstep, tw);
 #pragma unroll
-  for (int q = 1; q < R; ++q) a[q] = c_mulc(buf[base + q * step], w[q]);
+    for (int q = 1; q < R; ++q) a[q] = c_mulc(buf[base + q * step], w[q]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < R; ++q) a[q] = buf[base + q * step];
+  }
   Dft<T, R, +1>::run(a);
 #pragma unroll
   for (int t = 0; t < R; ++t) buf[base + t * step] = a[t];
@@ -320,6 +331,21 @@ LDDMM_PLAN(180, 4, 3, 3, 5)
 LDDMM_PLAN(216, 8, 3, 3, 3)
 #undef LDDMM_PLAN
 
+// Slot (DIF output position) that holds frequency k: the inverse of
+// digit_reverse for the compile-time plan P.
+template <class P>
+LD_HD int slot_of(int k) {
+  int p = 0, span = P::length(0);
+#pragma unroll
+  for (int i = 0; i < P::nf; ++i) {
+    span /= P::radix(i);
+    const int d = k % P::radix(i);
+    k /= P::radix(i);
+    p += d * span;
+  }
+  return p;
+}
+
 // True if the compile-time plan P has the runtime plan's radices.
 template <class P>
 inline bool plan_matches(const FftPlan& rt) {
@@ -349,9 +375,9 @@ LD_HD void fft_stage_item_static(cplx<T>* buf, int b, const cplx<T>* tw) {
   const int j = u - blk * stride;
   const int base = s * SS + (blk * L + j) * ES;
   if (INV)
-    dit_butterfly<T, R>(buf, base, stride * ES, j, P::length(0) / L, tw);
+    dit_butterfly<T, R, (stride > 1)>(buf, base, stride * ES, j, P::length(0) / L, tw);
   else
-    dif_butterfly<T, R>(buf, base, stride * ES, j, P::length(0) / L, tw);
+    dif_butterfly<T, R, (stride > 1)>(buf, base, stride * ES, j, P::length(0) / L, tw);
 }
 
 }  // namespace lddmm

@@ -1,6 +1,7 @@
 // lddmm_internal.h - declarations shared by the HIP kernel files and the host engine.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -12,13 +13,15 @@
 namespace lddmm {
 
 // ---------------------------------------------------------------------------
-// Per-kernel timing with HIP events on the launch stream (enabled on request).
+// Per-kernel timing (enabled on request).  The events are handed to
+// hipExtLaunchKernel, so the dispatch packet itself stamps the start of the
+// kernel and its end: the elapsed time is the kernel's execution, without the
+// dispatch latency a pair of marker events around the launch would add.
 // ---------------------------------------------------------------------------
 class Profiler {
  public:
   bool enabled = false;
-  void begin(const char* name, hipStream_t st);
-  void end(hipStream_t st);
+  void begin(const char* name, hipEvent_t* start, hipEvent_t* stop);
   int read(const char** names, int64_t* counts, double* total_ms, int cap);
   void clear();
   ~Profiler();
@@ -31,21 +34,27 @@ class Profiler {
   std::vector<const char*> kinds_;
   std::vector<Rec> recs_;
   std::vector<hipEvent_t> pool_;
-  int open_ = -1;
   hipEvent_t take();
 };
 
-// RAII bracket around one launch: KernelTimer t(prof, "name", stream); launch(...);
+// Timer of one launch (or of a short chain: start from the first, stop from
+// the last): KernelTimer t(prof, "name"); LDDMM_LAUNCH(t.start, t.stop, ...).
+// Both events are null while the profiler is off.
 struct KernelTimer {
-  Profiler* p;
-  hipStream_t st;
-  KernelTimer(Profiler* prof, const char* name, hipStream_t s) : p(prof), st(s) {
-    if (p && p->enabled) p->begin(name, st);
-  }
-  ~KernelTimer() {
-    if (p && p->enabled) p->end(st);
+  hipEvent_t start = nullptr, stop = nullptr;
+  KernelTimer(Profiler* prof, const char* name) {
+    if (prof && prof->enabled) prof->begin(name, &start, &stop);
   }
 };
+
+// Launch `kern` on stream `st`; with timer events the dispatch records them.
+#define LDDMM_LAUNCH(ev0, ev1, kern, grid, block, shmem, st, ...)                             \
+  do {                                                                                         \
+    if ((ev0) != nullptr || (ev1) != nullptr)                                                  \
+      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), (shmem), (st), (ev0), (ev1), 0, __VA_ARGS__); \
+    else                                                                                       \
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(block), (shmem), (st), __VA_ARGS__);          \
+  } while (0)
 
 // ---------------------------------------------------------------------------
 // Grid geometry passed by value to the field kernels.

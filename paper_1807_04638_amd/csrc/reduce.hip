@@ -161,45 +161,45 @@ unsigned red_blocks(long long n) {
 template <typename T>
 void launch_dot(const T* a, const T* b, long long n, double* partials, double* out, hipStream_t st,
                 Profiler* prof) {
-  KernelTimer t(prof, "dot", st);
+  KernelTimer t(prof, "dot");
   const unsigned nb = red_blocks(n);
-  k_dot<T><<<nb, RT, 0, st>>>(a, b, n, partials);
-  k_finish<1><<<1, RT, 0, st>>>(partials, (int)nb, 0, 0, out);
+  LDDMM_LAUNCH(t.start, nullptr, k_dot<T>, nb, RT, 0, st, a, b, n, partials);
+  LDDMM_LAUNCH(nullptr, t.stop, k_finish<1>, 1, RT, 0, st, partials, (int)nb, 0, 0, out);
 }
 
 template <typename T>
 void launch_check(const T* a, long long n, double* partials, double* out, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, "check", st);
+  KernelTimer t(prof, "check");
   const unsigned nb = red_blocks(n);
-  k_check<T><<<nb, RT, 0, st>>>(a, n, partials);
-  k_finish<2><<<1, RT, 0, st>>>(partials, (int)nb, 0, 1, out);
+  LDDMM_LAUNCH(t.start, nullptr, k_check<T>, nb, RT, 0, st, a, n, partials);
+  LDDMM_LAUNCH(nullptr, t.stop, k_finish<2>, 1, RT, 0, st, partials, (int)nb, 0, 1, out);
 }
 
 template <typename T>
 void launch_minmax(const T* a, long long n, double* partials, double* out, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, "minmax", st);
+  KernelTimer t(prof, "minmax");
   const unsigned nb = red_blocks(n);
-  k_minmax<T><<<nb, RT, 0, st>>>(a, n, partials);
-  k_finish<2><<<1, RT, 0, st>>>(partials, (int)nb, 2, 1, out);
+  LDDMM_LAUNCH(t.start, nullptr, k_minmax<T>, nb, RT, 0, st, a, n, partials);
+  LDDMM_LAUNCH(nullptr, t.stop, k_finish<2>, 1, RT, 0, st, partials, (int)nb, 2, 1, out);
 }
 
 template <typename T>
 void launch_axpby(long long n, double alpha, const T* x, double beta, T* y, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, "axpby", st);
-  k_axpby<T><<<ew_blocks(n), 256, 0, st>>>(n, T(alpha), x, T(beta), y);
+  KernelTimer t(prof, "axpby");
+  LDDMM_LAUNCH(t.start, t.stop, k_axpby<T>, ew_blocks(n), 256, 0, st, n, T(alpha), x, T(beta), y);
 }
 
 template <typename T>
 void launch_axpbyz(long long n, double alpha, const T* x, double beta, const T* y, T* z, hipStream_t st,
                    Profiler* prof) {
-  KernelTimer t(prof, "axpby", st);
-  k_axpbyz<T><<<ew_blocks(n), 256, 0, st>>>(n, T(alpha), x, T(beta), y, z);
+  KernelTimer t(prof, "axpby");
+  LDDMM_LAUNCH(t.start, t.stop, k_axpbyz<T>, ew_blocks(n), 256, 0, st, n, T(alpha), x, T(beta), y, z);
 }
 
 template <typename T>
 void launch_fill(long long n, T value, T* y, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, "fill", st);
-  k_fill<T><<<ew_blocks(n), 256, 0, st>>>(n, value, y);
+  KernelTimer t(prof, "fill");
+  LDDMM_LAUNCH(t.start, t.stop, k_fill<T>, ew_blocks(n), 256, 0, st, n, value, y);
 }
 
 #define LDDMM_RINST(T)                                                                                       \

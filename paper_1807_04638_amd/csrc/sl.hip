@@ -126,16 +126,16 @@ __global__ void __launch_bounds__(256)
 template <typename T>
 void launch_sl_step(const Grid& g, const T* u_old, const T* v_old, const T* v_new, T* u_new, double dt,
                     hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, "sl_step", st);
+  KernelTimer t(prof, "sl_step");
   const FieldTiling ft = make_field_tiling(g);
-  k_sl_step<T><<<ft.blocks, dim3(ft.BX, ft.BY), 0, st>>>(make_sl_geo<T>(g), u_old, v_old, v_new, u_new, T(dt));
+  LDDMM_LAUNCH(t.start, t.stop, k_sl_step<T>, ft.blocks, dim3(ft.BX, ft.BY), 0, st, make_sl_geo<T>(g), u_old, v_old, v_new, u_new, T(dt));
 }
 
 template <typename T>
 void launch_compose(const Grid& g, const T* I, const T* u, T* J, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, "compose", st);
+  KernelTimer t(prof, "compose");
   const FieldTiling ft = make_field_tiling(g);
-  k_compose<T><<<ft.blocks, dim3(ft.BX, ft.BY), 0, st>>>(make_sl_geo<T>(g), I, u, J);
+  LDDMM_LAUNCH(t.start, t.stop, k_compose<T>, ft.blocks, dim3(ft.BX, ft.BY), 0, st, make_sl_geo<T>(g), I, u, J);
 }
 
 template void launch_sl_step<float>(const Grid&, const float*, const float*, const float*, float*, double,

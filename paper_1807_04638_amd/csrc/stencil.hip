@@ -325,57 +325,54 @@ unsigned flat_blocks(long long N) {
 template <typename T>
 void launch_epdiff_stage(const Grid& g, const T* v, const T* mu, const T* mu0, T* mu_out, double dt, double a0,
                          double a1, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, a0 != 0.0 ? "epdiff_stage_corr" : "epdiff_stage_pred", st);
-  k_epdiff_stage<T><<<ft_grid(g), ft_block(g), 0, st>>>(make_geo<T>(g), v, mu, mu0 ? mu0 : mu, mu_out, T(dt),
-                                                            T(a0), T(a1));
+  KernelTimer t(prof, a0 != 0.0 ? "epdiff_stage_corr" : "epdiff_stage_pred");
+  LDDMM_LAUNCH(t.start, t.stop, k_epdiff_stage<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), v, mu, mu0 ? mu0 : mu, mu_out, T(dt), T(a0), T(a1));
 }
 
 template <typename T>
 void launch_tangent_stage(const Grid& g, const T* X, const T* dmu, const T* W, const T* v, const T* mu,
                           const T* X0, const T* dmu0, T* X_out, T* dmu_out, double dt, double a0, double a1,
                           hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, a0 != 0.0 ? "tangent_stage_corr" : "tangent_stage_pred", st);
-  k_tangent_stage<T><<<ft_grid(g), ft_block(g), 0, st>>>(make_geo<T>(g), X, dmu, W, v, mu, X0 ? X0 : X,
-                                                             dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt), T(a0), T(a1));
+  KernelTimer t(prof, a0 != 0.0 ? "tangent_stage_corr" : "tangent_stage_pred");
+  LDDMM_LAUNCH(t.start, t.stop, k_tangent_stage<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), X, dmu, W, v, mu, X0 ? X0 : X, dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt), T(a0), T(a1));
 }
 
 template <typename T>
 void launch_adjoint_pre(const Grid& g, const T* U, const T* w, const T* mu, T* Z, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, "adjoint_pre", st);
-  k_adjoint_pre<T><<<ft_grid(g), ft_block(g), 0, st>>>(make_geo<T>(g), U, w, mu, Z);
+  KernelTimer t(prof, "adjoint_pre");
+  LDDMM_LAUNCH(t.start, t.stop, k_adjoint_pre<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), U, w, mu, Z);
 }
 
 template <typename T>
 void launch_adjoint_post(const Grid& g, const T* U, const T* w, const T* KZ, const T* v, const T* U0, const T* w0,
                          T* U_out, T* w_out, double dt, double a0, double a1, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, a0 != 0.0 ? "adjoint_post_corr" : "adjoint_post_pred", st);
-  k_adjoint_post<T><<<ft_grid(g), ft_block(g), 0, st>>>(make_geo<T>(g), U, w, KZ, v, U0 ? U0 : U, w0 ? w0 : w,
-                                                            U_out, w_out, T(dt), T(a0), T(a1));
+  KernelTimer t(prof, a0 != 0.0 ? "adjoint_post_corr" : "adjoint_post_pred");
+  LDDMM_LAUNCH(t.start, t.stop, k_adjoint_post<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), U, w, KZ, v, U0 ? U0 : U, w0 ? w0 : w, U_out, w_out, T(dt), T(a0), T(a1));
 }
 
 template <typename T>
 void launch_residual_grad(const Grid& g, const T* J1, const T* I1, T* r, T* G, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, "residual_grad", st);
-  k_residual_grad<T><<<ft_grid(g), ft_block(g), 0, st>>>(make_geo<T>(g), J1, I1, r, G);
+  KernelTimer t(prof, "residual_grad");
+  LDDMM_LAUNCH(t.start, t.stop, k_residual_grad<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), J1, I1, r, G);
 }
 
 template <typename T>
 void launch_scalar_times_vec(const Grid& g, const T* s, const T* G, double c, T* U, hipStream_t st,
                              Profiler* prof) {
-  KernelTimer t(prof, "final_condition", st);
-  k_scalar_times_vec<T><<<flat_blocks(g.N), 256, 0, st>>>(g.N, s, G, T(c), U);
+  KernelTimer t(prof, "final_condition");
+  LDDMM_LAUNCH(t.start, t.stop, k_scalar_times_vec<T>, flat_blocks(g.N), 256, 0, st, g.N, s, G, T(c), U);
 }
 
 template <typename T>
 void launch_gn_final(const Grid& g, const T* G, const T* X, double c, T* U, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, "gn_final_condition", st);
-  k_gn_final<T><<<flat_blocks(g.N), 256, 0, st>>>(g.N, G, X, T(c), U);
+  KernelTimer t(prof, "gn_final_condition");
+  LDDMM_LAUNCH(t.start, t.stop, k_gn_final<T>, flat_blocks(g.N), 256, 0, st, g.N, G, X, T(c), U);
 }
 
 template <typename T>
 void launch_jacobian_det(const Grid& g, const T* u, T* det, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, "jacobian_det", st);
-  k_jacobian_det<T><<<ft_grid(g), ft_block(g), 0, st>>>(make_geo<T>(g), u, det);
+  KernelTimer t(prof, "jacobian_det");
+  LDDMM_LAUNCH(t.start, t.stop, k_jacobian_det<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), u, det);
 }
 
 #define LDDMM_INST(T)                                                                                            \

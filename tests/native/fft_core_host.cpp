@@ -79,6 +79,8 @@ int static_case(double* data, int inverse) {
   using P = typename PlanOf<N>::type;
   FftPlan rt;
   if (!make_plan(N, rt) || !plan_matches<P>(rt)) return -2;  // compile-time plan must equal make_plan
+  for (int p = 0; p < N; ++p)
+    if (slot_of<P>(digit_reverse(rt, p)) != p) return -3;  // slot_of inverts digit_reverse
   std::vector<cplx<double>> tw(N);
   for (int m = 0; m < N; ++m) tw[m] = {std::cos(-2.0 * M_PI * m / N), std::sin(-2.0 * M_PI * m / N)};
   auto* buf = reinterpret_cast<cplx<double>*>(data);
