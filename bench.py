@@ -71,7 +71,15 @@ def log(*a):
 
 
 # Transform launch shape that the autotuner chose; HBM traffic is recorded per shape.
-TUNED_KEYS = ("fft.plane_threads", "fft.pencil_threads", "fft.pencil_tb", "fft.rows_rb", "fft.fused", "fft.static_kernels")
+TUNED_KEYS = (
+    "fft.plane_threads",
+    "fft.pencil_threads",
+    "fft.pencil_tb",
+    "fft.rows_rb",
+    "fft.fused",
+    "fft.static_kernels",
+    "stencil.rowvec",
+)
 KERNEL_SOURCES = {
     "fft": ("paper_1807_04638_amd/csrc/fft.hip", "paper_1807_04638_amd/csrc/fft_core.h"),
     "stencil": ("paper_1807_04638_amd/csrc/stencil.hip",),
@@ -115,7 +123,7 @@ def shape_keys(kernel):
         return ("fft.pencil_tb", "fft.pencil_threads", "fft.fused", "fft.static_kernels")
     if kernel.startswith("fft_"):
         return ("fft.plane_threads", "fft.rows_rb", "fft.fused", "fft.static_kernels")
-    return ()
+    return ("stencil.rowvec",)
 
 
 def make_pair(spec, dtype, dev, torch, Registration, synth):
@@ -553,7 +561,7 @@ def main():
             "bytes_per_launch": int(dom_bytes),
             "avg_launch_us": kernels[dom]["avg_us"],
         },
-        "fft_launch_shape": tuned,
+        "launch_shape": tuned,
         "kernels": kernels,
         "hbm_copy_GBps": round(copy_GBps, 1),
         "cpu_baseline": cpu,

@@ -210,13 +210,19 @@ int lddmm_profile_read(lddmm_ctx* ctx, const char** names, int64_t* counts, doub
  *   "exec.graph"          0 | 1             replay Hessian-vector products from a captured
  *                                           hipGraph (store-all trajectories; needs a
  *                                           non-default stream)
+ *   "stencil.rowvec"      0, 1, 2, 4        voxels per lane of the row-vectorised stencil
+ *                                           kernels (0: one voxel per thread); nonzero
+ *                                           values need N2 / value = 32 or 64.  Default:
+ *                                           the smallest valid width in FP64, 0 in FP32;
+ *                                           same operators, summed in another order
  * LDDMM_EINVAL for an unknown key or a value out of range, LDDMM_EUNSUPPORTED if
  * the tiles would not fit the LDS of a workgroup (the previous setting stays). */
 int lddmm_set_option(lddmm_ctx* ctx, const char* key, int64_t value);
 int lddmm_get_option(lddmm_ctx* ctx, const char* key, int64_t* value);
 
 /* Autotuner: time the transform variants (plane workgroup size, pencil tile,
- * compile-time vs generic kernels) on this context's grid with HIP events
+ * compile-time vs generic kernels) and the stencil widths ("stencil.rowvec",
+ * timed on the tangent stage) on this context's grid with HIP events
  * (reps applications each) and keep the fastest; the shape in place when the
  * call starts is kept unless another is more than 3 % faster, so repeated
  * calls settle on the same shape.  *tried = variants timed,

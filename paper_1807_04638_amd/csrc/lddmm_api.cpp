@@ -181,6 +181,16 @@ class Engine {
     g.h0 = 2.0 * M_PI / p.n[0];
     g.h1 = 2.0 * M_PI / p.n[1];
     g.h2 = 2.0 * M_PI / p.n[2];
+    // stencil kernels: FP64 rows of 32-256 voxels go row-vectorised by default
+    // (measured faster there); FP32 starts at one voxel per thread.  The
+    // autotuner times both.
+    g.rowvec = 0;
+    if (sizeof(T) == 8)
+      for (int vw : {1, 2, 4})
+        if (row_vector_valid(g.n2, vw)) {
+          g.rowvec = vw;
+          break;
+        }
     N = g.N;
     cell = g.h0 * g.h1 * g.h2;
     dt = 1.0 / p.nt;
@@ -619,6 +629,32 @@ class Engine {
       best = start;
       best_ms = start_ms;
     }
+    // Stencil kernels: one voxel per thread or VW voxels per lane, timed on the
+    // tangent stage (the largest of them); work fields only, contents irrelevant.
+    {
+      const int start_vw = g.rowvec;
+      int best_vw = start_vw;
+      float best_t = -1.f, start_t = -1.f;
+      for (int vw : {0, 1, 2, 4}) {
+        if (vw != 0 && !row_vector_valid(g.n2, vw)) continue;
+        g.rowvec = vw;
+        launch_tangent_stage<T>(g, X, Mu, W, Xs, Mus, X, Mu, Us, Whs, dt, 0.0, 1.0, st, nullptr);
+        (void)hipEventRecord(a, st);
+        for (int r = 0; r < reps; ++r)
+          launch_tangent_stage<T>(g, X, Mu, W, Xs, Mus, X, Mu, Us, Whs, dt, 0.0, 1.0, st, nullptr);
+        (void)hipEventRecord(b, st);
+        (void)hipEventSynchronize(b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        ++count;
+        if (best_t < 0.f || ms < best_t) {
+          best_t = ms;
+          best_vw = vw;
+        }
+        if (vw == start_vw) start_t = ms;
+      }
+      g.rowvec = (start_t > 0.f && start_t <= 1.03f * best_t) ? start_vw : best_vw;
+    }
     prof.enabled = was;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
@@ -804,6 +840,13 @@ class Engine {
       use_graph = value != 0;
       drop_graph();
       return 0;
+    } else if (k == "stencil.rowvec") {
+      if (value != 0 && !row_vector_valid(g.n2, int(value)))
+        return fail(LDDMM_EINVAL, "stencil.rowvec: N2 / value must be 32 or 64 with value 1, 2 or 4");
+      (void)hipStreamSynchronize(st);
+      g.rowvec = int(value);
+      drop_graph();
+      return 0;
     } else
       return fail(LDDMM_EINVAL, "unknown or read-only option " + k);
     if (value < 0 || value > (1 << 20)) return fail(LDDMM_EINVAL, "option value out of range");
@@ -843,6 +886,8 @@ class Engine {
       *value = lin_epoch;
     else if (k == "exec.graph")
       *value = use_graph ? 1 : 0;
+    else if (k == "stencil.rowvec")
+      *value = g.rowvec;
     else
       return fail(LDDMM_EINVAL, "unknown option " + k);
     return 0;

@@ -47,13 +47,15 @@ struct KernelTimer {
   }
 };
 
+#define LDDMM_COMMA ,
+
 // Launch `kern` on stream `st`; with timer events the dispatch records them.
 #define LDDMM_LAUNCH(ev0, ev1, kern, grid, block, shmem, st, ...)                             \
   do {                                                                                         \
     if ((ev0) != nullptr || (ev1) != nullptr)                                                  \
-      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), (shmem), (st), (ev0), (ev1), 0, __VA_ARGS__); \
+      hipExtLaunchKernelGGL((kern), dim3(grid), dim3(block), (shmem), (st), (ev0), (ev1), 0, __VA_ARGS__); \
     else                                                                                       \
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(block), (shmem), (st), __VA_ARGS__);          \
+      hipLaunchKernelGGL((kern), dim3(grid), dim3(block), (shmem), (st), __VA_ARGS__);          \
   } while (0)
 
 // ---------------------------------------------------------------------------
@@ -63,7 +65,12 @@ struct Grid {
   int n0, n1, n2;
   long long N;           // n0 * n1 * n2 (3 N < 2^31 is checked at creation)
   double h0, h1, h2;     // 2 pi / N_d
+  int rowvec = 0;        // voxels per lane of the row-vectorised stencil kernels (0: one per thread)
 };
+
+// True if the row-vectorised stencil kernels take vw voxels per lane on rows of
+// n2 voxels: vw in {1, 2, 4} and a row is 32 or 64 lanes.
+bool row_vector_valid(int n2, int vw);
 
 // Voxel tiling of the field kernels: a block covers BX x BY voxels of one x0
 // plane (BX spans a whole x2 row when N2 <= 256, so x2 halos stay inside the

@@ -16,6 +16,11 @@
 
 namespace lddmm {
 
+bool row_vector_valid(int n2, int vw) {
+  if (vw != 1 && vw != 2 && vw != 4) return false;
+  return n2 % vw == 0 && (n2 / vw == 32 || n2 / vw == 64);
+}
+
 FieldTiling make_field_tiling(const Grid& g) {
   FieldTiling t;
   int bx = (g.n2 + 31) / 32 * 32;
@@ -309,6 +314,303 @@ __global__ void __launch_bounds__(256) k_jacobian_det(Geo<T> g, const T* __restr
                  J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
 }
 
+// ---------------------------------------------------------------------------
+// Row-vectorised variants for N2 = VW * RW with RW = 32 or 64 lanes.  A lane
+// owns VW consecutive voxels of an x2 row and a row is RW consecutive lanes of
+// one wavefront, so every x0 or x1 neighbour is one VW-wide load and the x2
+// neighbours come from the two adjacent lanes (periodic inside the row).  Same
+// operators as the kernels above, accumulated one direction at a time; about a
+// third of their load instructions, which is what limits those kernels (the
+// texture address and data units, not HBM, saturate first).
+// ---------------------------------------------------------------------------
+template <int VW>
+struct VNbr {
+  int o;            // first voxel of the lane
+  int ox[4];        // the same voxel at +x0, -x0, +x1, -x1
+  int left, right;  // lanes holding the x2 neighbours
+};
+
+template <typename T, int VW>
+__device__ __forceinline__ bool vvoxel(const Geo<T>& g, int RW, VNbr<VW>& nb) {
+  int i0, i1, j;
+  if (!tile_voxel(g.ft, g.n1, g.n2 / VW, i0, i1, j)) return false;
+  const int i2 = j * VW;
+  const int p0 = i0 + 1 == g.n0 ? 0 : i0 + 1, m0 = i0 == 0 ? g.n0 - 1 : i0 - 1;
+  const int p1 = i1 + 1 == g.n1 ? 0 : i1 + 1, m1 = i1 == 0 ? g.n1 - 1 : i1 - 1;
+  const int s0 = g.n1 * g.n2;
+  const int r1 = i1 * g.n2 + i2;
+  nb.o = i0 * s0 + r1;
+  nb.ox[0] = p0 * s0 + r1;
+  nb.ox[1] = m0 * s0 + r1;
+  nb.ox[2] = i0 * s0 + p1 * g.n2 + i2;
+  nb.ox[3] = i0 * s0 + m1 * g.n2 + i2;
+  const int lane = int(threadIdx.x + threadIdx.y * blockDim.x) & 63;
+  const int base = lane & ~(RW - 1);
+  nb.left = base | ((lane - 1) & (RW - 1));
+  nb.right = base | ((lane + 1) & (RW - 1));
+  return true;
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void vld(T out[VW], const T* __restrict__ p) {
+  typedef T vec __attribute__((ext_vector_type(VW)));
+  const vec x = *reinterpret_cast<const vec*>(p);
+#pragma unroll
+  for (int k = 0; k < VW; ++k) out[k] = x[k];
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void vload3(T out[3][VW], const T* __restrict__ f, int o, int N) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) vld<T, VW>(out[c], f + c * N + o);
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void vstore3(T* __restrict__ f, const T in[3][VW], int o, int N) {
+  typedef T vec __attribute__((ext_vector_type(VW)));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    vec x;
+#pragma unroll
+    for (int k = 0; k < VW; ++k) x[k] = in[c][k];
+    *reinterpret_cast<vec*>(f + c * N + o) = x;
+  }
+}
+
+// A vector field at the +e and -e neighbours of the lane's VW voxels.
+template <typename T, int VW>
+struct VPair {
+  T p[3][VW], m[3][VW];
+};
+
+template <typename T, int VW>
+__device__ __forceinline__ void vpair_load(VPair<T, VW>& s, const T* __restrict__ f, const VNbr<VW>& nb, int e,
+                                           int N) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    vld<T, VW>(s.p[c], f + c * N + nb.ox[2 * e]);
+    vld<T, VW>(s.m[c], f + c * N + nb.ox[2 * e + 1]);
+  }
+}
+
+// x2 neighbours: the lane's own values shifted by one, the ends from the
+// adjacent lanes of the row.
+template <typename T, int VW>
+__device__ __forceinline__ void vpair_shift(VPair<T, VW>& s, const T c0[3][VW], const VNbr<VW>& nb) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T from_right = __shfl(c0[c][0], nb.right);
+    const T from_left = __shfl(c0[c][VW - 1], nb.left);
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+      s.p[c][k] = k + 1 < VW ? c0[c][k + 1] : from_right;
+      s.m[c][k] = k > 0 ? c0[c][k - 1] : from_left;
+    }
+  }
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void vpair(VPair<T, VW>& s, const T* __restrict__ f, const T c0[3][VW],
+                                      const VNbr<VW>& nb, int e, int N) {
+  if (e < 2)
+    vpair_load<T, VW>(s, f, nb, e, N);
+  else
+    vpair_shift<T, VW>(s, c0, nb);
+}
+
+// Direction-e share of ad_v w and of ad*_v mu at each of the lane's voxels.
+template <typename T, int VW>
+__device__ __forceinline__ void vad_dir(T out[3][VW], const VPair<T, VW>& v, const VPair<T, VW>& w,
+                                        const T v0[3][VW], const T w0[3][VW], int e, T inv2h) {
+#pragma unroll
+  for (int k = 0; k < VW; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      out[c][k] += ((v.p[c][k] - v.m[c][k]) * w0[e][k] - (w.p[c][k] - w.m[c][k]) * v0[e][k]) * inv2h;
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void vadstar_dir(T out[3][VW], const VPair<T, VW>& v, const VPair<T, VW>& mu,
+                                            const T mu0[3][VW], int e, T inv2h) {
+#pragma unroll
+  for (int k = 0; k < VW; ++k) {
+    T s = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s += (v.p[d][k] - v.m[d][k]) * mu0[d][k];
+    out[e][k] += s * inv2h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c][k] += (mu.p[c][k] * v.p[e][k] - mu.m[c][k] * v.m[e][k]) * inv2h;
+  }
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void vheun(T out[3][VW], const T* y0, T a0, int o, int N) {
+  if (a0 != T(0)) {
+    T z[3][VW];
+    vload3<T, VW>(z, y0, o, N);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int k = 0; k < VW; ++k) out[c][k] += a0 * z[c][k];
+  }
+}
+
+template <typename T, int VW>
+__global__ void __launch_bounds__(256)
+    k_epdiff_stage_v(Geo<T> g, int RW, const T* __restrict__ v, const T* __restrict__ mu, const T* mu0,
+                     T* mu_out, T dt, T a0, T a1) {
+  VNbr<VW> nb;
+  if (!vvoxel<T, VW>(g, RW, nb)) return;
+  T m[3][VW], vc[3][VW], a[3][VW] = {};
+  vload3<T, VW>(m, mu, nb.o, g.N);
+  vload3<T, VW>(vc, v, nb.o, g.N);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    VPair<T, VW> Vp, Mp;
+    vpair<T, VW>(Vp, v, vc, nb, e, g.N);
+    vpair<T, VW>(Mp, mu, m, nb, e, g.N);
+    vadstar_dir<T, VW>(a, Vp, Mp, m, e, g.inv2h[e]);
+  }
+  T out[3][VW];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int k = 0; k < VW; ++k) out[c][k] = a1 * (m[c][k] - dt * a[c][k]);
+  vheun<T, VW>(out, mu0, a0, nb.o, g.N);
+  vstore3<T, VW>(mu_out, out, nb.o, g.N);
+}
+
+template <typename T, int VW>
+__global__ void __launch_bounds__(256)
+    k_tangent_stage_v(Geo<T> g, int RW, const T* __restrict__ X, const T* __restrict__ dmu, const T* __restrict__ W,
+                      const T* __restrict__ v, const T* __restrict__ mu, const T* X0, const T* dmu0, T* X_out,
+                      T* dmu_out, T dt, T a0, T a1) {
+  VNbr<VW> nb;
+  if (!vvoxel<T, VW>(g, RW, nb)) return;
+  T x[3][VW], vc[3][VW], dm[3][VW];
+  vload3<T, VW>(x, X, nb.o, g.N);
+  vload3<T, VW>(vc, v, nb.o, g.N);
+  vload3<T, VW>(dm, dmu, nb.o, g.N);
+  T aX[3][VW] = {}, t1[3][VW] = {}, t2[3][VW] = {};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    VPair<T, VW> Vp, Xp, Dp;
+    vpair<T, VW>(Vp, v, vc, nb, e, g.N);
+    vpair<T, VW>(Xp, X, x, nb, e, g.N);
+    vpair<T, VW>(Dp, dmu, dm, nb, e, g.N);
+    vad_dir<T, VW>(aX, Vp, Xp, vc, x, e, g.inv2h[e]);   // ad_v X
+    vadstar_dir<T, VW>(t2, Vp, Dp, dm, e, g.inv2h[e]);  // ad*_v dmu
+  }
+  T w[3][VW], m[3][VW];
+  vload3<T, VW>(w, W, nb.o, g.N);
+  vload3<T, VW>(m, mu, nb.o, g.N);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    VPair<T, VW> Wp, Mp;
+    vpair<T, VW>(Wp, W, w, nb, e, g.N);
+    vpair<T, VW>(Mp, mu, m, nb, e, g.N);
+    vadstar_dir<T, VW>(t1, Wp, Mp, m, e, g.inv2h[e]);  // ad*_W mu
+  }
+  T xo[3][VW], mo[3][VW];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+      xo[c][k] = a1 * (x[c][k] + dt * (w[c][k] + aX[c][k]));
+      mo[c][k] = a1 * (dm[c][k] - dt * (t1[c][k] + t2[c][k]));
+    }
+  vheun<T, VW>(xo, X0, a0, nb.o, g.N);
+  vheun<T, VW>(mo, dmu0, a0, nb.o, g.N);
+  vstore3<T, VW>(X_out, xo, nb.o, g.N);
+  vstore3<T, VW>(dmu_out, mo, nb.o, g.N);
+}
+
+template <typename T, int VW>
+__global__ void __launch_bounds__(256)
+    k_adjoint_pre_v(Geo<T> g, int RW, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ mu,
+                    T* __restrict__ Z) {
+  VNbr<VW> nb;
+  if (!vvoxel<T, VW>(g, RW, nb)) return;
+  T wc[3][VW], m[3][VW], a[3][VW] = {};
+  vload3<T, VW>(wc, w, nb.o, g.N);
+  vload3<T, VW>(m, mu, nb.o, g.N);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    VPair<T, VW> Wp, Mp;
+    vpair<T, VW>(Wp, w, wc, nb, e, g.N);
+    vpair<T, VW>(Mp, mu, m, nb, e, g.N);
+    vadstar_dir<T, VW>(a, Wp, Mp, m, e, g.inv2h[e]);
+  }
+  T u[3][VW];
+  vload3<T, VW>(u, U, nb.o, g.N);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int k = 0; k < VW; ++k) a[c][k] += u[c][k];
+  vstore3<T, VW>(Z, a, nb.o, g.N);
+}
+
+template <typename T, int VW>
+__global__ void __launch_bounds__(256)
+    k_adjoint_post_v(Geo<T> g, int RW, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ KZ,
+                     const T* __restrict__ v, const T* U0, const T* w0, T* U_out, T* w_out, T dt, T a0, T a1) {
+  VNbr<VW> nb;
+  if (!vvoxel<T, VW>(g, RW, nb)) return;
+  T u[3][VW], vc[3][VW], wc[3][VW];
+  vload3<T, VW>(u, U, nb.o, g.N);
+  vload3<T, VW>(vc, v, nb.o, g.N);
+  vload3<T, VW>(wc, w, nb.o, g.N);
+  T aU[3][VW] = {}, aw[3][VW] = {};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    VPair<T, VW> Vp, Up, Wp;
+    vpair<T, VW>(Vp, v, vc, nb, e, g.N);
+    vpair<T, VW>(Up, U, u, nb, e, g.N);
+    vpair<T, VW>(Wp, w, wc, nb, e, g.N);
+    vadstar_dir<T, VW>(aU, Vp, Up, u, e, g.inv2h[e]);  // ad*_v U
+    vad_dir<T, VW>(aw, Vp, Wp, vc, wc, e, g.inv2h[e]);  // ad_v w
+  }
+  T kz[3][VW];
+  vload3<T, VW>(kz, KZ, nb.o, g.N);
+  T uo[3][VW], wo[3][VW];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+      uo[c][k] = a1 * (u[c][k] + dt * aU[c][k]);
+      wo[c][k] = a1 * (wc[c][k] + dt * (kz[c][k] - aw[c][k]));
+    }
+  vheun<T, VW>(uo, U0, a0, nb.o, g.N);
+  vheun<T, VW>(wo, w0, a0, nb.o, g.N);
+  vstore3<T, VW>(U_out, uo, nb.o, g.N);
+  vstore3<T, VW>(w_out, wo, nb.o, g.N);
+}
+
+// Lane width VW of the row-vectorised kernels for this grid (0: one voxel per thread).
+int row_vector_width(const Grid& g) { return row_vector_valid(g.n2, g.rowvec) ? g.rowvec : 0; }
+
+template <typename T>
+Geo<T> make_vgeo(const Grid& g, int VW) {
+  Geo<T> o = make_geo<T>(g);
+  Grid gv = g;
+  gv.n2 = g.n2 / VW;
+  o.ft = make_field_tiling(gv);
+  return o;
+}
+
+#define LDDMM_ROWVEC(kern, ...)                                                                              \
+  do {                                                                                                       \
+    const Geo<T> gv = make_vgeo<T>(g, VW);                                                                   \
+    const dim3 grid_(gv.ft.blocks), block_(gv.ft.BX, gv.ft.BY);                                              \
+    const int RW = g.n2 / VW;                                                                                \
+    if (VW == 1)                                                                                             \
+      LDDMM_LAUNCH(t.start, t.stop, kern<T LDDMM_COMMA 1>, grid_, block_, 0, st, gv, RW, __VA_ARGS__);       \
+    else if (VW == 2)                                                                                        \
+      LDDMM_LAUNCH(t.start, t.stop, kern<T LDDMM_COMMA 2>, grid_, block_, 0, st, gv, RW, __VA_ARGS__);       \
+    else                                                                                                     \
+      LDDMM_LAUNCH(t.start, t.stop, kern<T LDDMM_COMMA 4>, grid_, block_, 0, st, gv, RW, __VA_ARGS__);       \
+  } while (0)
+
 dim3 ft_grid(const Grid& g) { return dim3(make_field_tiling(g).blocks); }
 dim3 ft_block(const Grid& g) {
   const FieldTiling t = make_field_tiling(g);
@@ -326,6 +628,10 @@ template <typename T>
 void launch_epdiff_stage(const Grid& g, const T* v, const T* mu, const T* mu0, T* mu_out, double dt, double a0,
                          double a1, hipStream_t st, Profiler* prof) {
   KernelTimer t(prof, a0 != 0.0 ? "epdiff_stage_corr" : "epdiff_stage_pred");
+  if (const int VW = row_vector_width(g)) {
+    LDDMM_ROWVEC(k_epdiff_stage_v, v, mu, mu0 ? mu0 : mu, mu_out, T(dt), T(a0), T(a1));
+    return;
+  }
   LDDMM_LAUNCH(t.start, t.stop, k_epdiff_stage<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), v, mu, mu0 ? mu0 : mu, mu_out, T(dt), T(a0), T(a1));
 }
 
@@ -334,12 +640,21 @@ void launch_tangent_stage(const Grid& g, const T* X, const T* dmu, const T* W, c
                           const T* X0, const T* dmu0, T* X_out, T* dmu_out, double dt, double a0, double a1,
                           hipStream_t st, Profiler* prof) {
   KernelTimer t(prof, a0 != 0.0 ? "tangent_stage_corr" : "tangent_stage_pred");
+  if (const int VW = row_vector_width(g)) {
+    LDDMM_ROWVEC(k_tangent_stage_v, X, dmu, W, v, mu, X0 ? X0 : X, dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt), T(a0),
+                 T(a1));
+    return;
+  }
   LDDMM_LAUNCH(t.start, t.stop, k_tangent_stage<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), X, dmu, W, v, mu, X0 ? X0 : X, dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt), T(a0), T(a1));
 }
 
 template <typename T>
 void launch_adjoint_pre(const Grid& g, const T* U, const T* w, const T* mu, T* Z, hipStream_t st, Profiler* prof) {
   KernelTimer t(prof, "adjoint_pre");
+  if (const int VW = row_vector_width(g)) {
+    LDDMM_ROWVEC(k_adjoint_pre_v, U, w, mu, Z);
+    return;
+  }
   LDDMM_LAUNCH(t.start, t.stop, k_adjoint_pre<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), U, w, mu, Z);
 }
 
@@ -347,6 +662,10 @@ template <typename T>
 void launch_adjoint_post(const Grid& g, const T* U, const T* w, const T* KZ, const T* v, const T* U0, const T* w0,
                          T* U_out, T* w_out, double dt, double a0, double a1, hipStream_t st, Profiler* prof) {
   KernelTimer t(prof, a0 != 0.0 ? "adjoint_post_corr" : "adjoint_post_pred");
+  if (const int VW = row_vector_width(g)) {
+    LDDMM_ROWVEC(k_adjoint_post_v, U, w, KZ, v, U0 ? U0 : U, w0 ? w0 : w, U_out, w_out, T(dt), T(a0), T(a1));
+    return;
+  }
   LDDMM_LAUNCH(t.start, t.stop, k_adjoint_post<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), U, w, KZ, v, U0 ? U0 : U, w0 ? w0 : w, U_out, w_out, T(dt), T(a0), T(a1));
 }
 

@@ -230,6 +230,36 @@ def test_hessvec_parity(n, dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [(10, 6, 64), (8, 12, 128), (6, 8, 256)])
+def test_row_vectorised_stencils(n, dtype):
+    """Every stencil width a row of N2 = 64, 128, 256 allows: one voxel per
+    thread (stencil.rowvec = 0) and VW = 1, 2, 4 voxels per lane with x2
+    neighbours across lanes (N2 / VW = 32 or 64).  Each against the oracle on
+    shooting, the gradient and the Hessian-vector product."""
+    I0, I1 = images(n)
+    v0 = random_velocity(n, 2003, 0.5, kc=2.0)  # coarse x0/x1 axes: keep the flow well resolved
+    dv = random_field(n, 6, kc=3.0)
+    p = O.Params(tuple(n), 0.01, 2, 6, 0.05)
+    tr = O.shoot(v0, p, I0)
+    go, lin = O.gradient(v0, I0, I1, p)
+    ho = O.hessvec(dv, lin, p)
+    widths = [0] + [vw for vw in (1, 2, 4) if n[2] % vw == 0 and n[2] // vw in (32, 64)]
+    for rowvec in widths:
+        R, _ = make(n, dtype, sigma2=0.05)
+        R.set_option("stencil.rowvec", rowvec)
+        assert R.get_option("stencil.rowvec") == rowvec
+        R.set_images(T(I0, dtype), T(I1, dtype))
+        out = R.shoot(T(v0, dtype))
+        g, E = R.gradient(T(v0, dtype))
+        hv = R.hessvec(T(dv, dtype))
+        errs = dict(v1=rel(out["v1"], tr.v[-1]), J1=rel(out["J1"], tr.J1), grad=rel(g, go), hv=rel(hv, ho))
+        say(f"  rowvec={rowvec}", errs)
+        assert errs["v1"] <= TOL[dtype]["shoot"] and errs["J1"] <= TOL[dtype]["shoot"]
+        assert errs["grad"] <= TOL[dtype]["grad"] and errs["hv"] <= TOL[dtype]["hv"]
+        assert E == pytest.approx(lin.E, rel=TOL[dtype]["shoot"])
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_vjp_parity(dtype):
     n = (16, 12, 20)
     R, p = make(n, dtype)
@@ -379,6 +409,11 @@ def test_error_paths():
     assert e.value.status == -2
     with pytest.raises(ValueError):
         R.gradient(torch.zeros((3, 16, 12, 21), device=DEV))
+    for width in (1, 3):  # N2 = 20: no row-vectorised width; 3 is never one
+        with pytest.raises(LddmmError) as e:
+            R.set_option("stencil.rowvec", width)
+        assert e.value.status == -1
+    assert R.get_option("stencil.rowvec") == 0
 
 
 # ------------------------------------------------------------------ full size (128^3, nt = 10)
