@@ -34,6 +34,12 @@ A2  Incremental initial condition delta v(0) = the PCG direction (the printed
 A3  Gauss-Newton drops every term containing the first-order adjoint fields and
     lambda(1) grad(delta m(1)); the incremental adjoint sweep is then the adjoint
     Jacobi sweep with a new final condition, and H = 2 I + (2/sigma^2) F* F.
+A17 "GN, L2" (Section 3, last remark; Table 1): gradient L g_V and Hessian
+    L H_V in the L2 product, solved by PCG with preconditioner K; every norm of
+    that solve (CG stop, forcing term, outer stop) is the L2 norm.
+A18 Gradient descent in V (Section 2.2): v0 <- v0 - tau g_V, tau by Armijo
+    backtracking from tau0 = 1/2, the exact minimiser along -g of the
+    regularisation term (its V-Hessian is 2 I).
 """
 
 from __future__ import annotations
@@ -448,23 +454,68 @@ def cg_v(hess, g, p, eta, maxit):
     return x, it
 
 
+def pcg_l2(hess, g, p, eta, maxit, precond):
+    """Preconditioned CG in the L2 product for H x = -g (H symmetric in L2) with
+    preconditioner `precond`; stops at ||r||_L2 <= eta ||g||_L2 or on
+    non-positive curvature.  Returns (x, iterations)."""
+    g = np.asarray(g, dtype=np.float64)
+    x = np.zeros_like(g)
+    r = -g
+    z = precond(r)
+    d = z.copy()
+    rz = inner(r, z, p)
+    tol = eta * math.sqrt(inner(g, g, p))
+    it = 0
+    for it in range(1, maxit + 1):
+        q = hess(d)
+        dq = inner(d, q, p)
+        if dq <= 0.0:
+            it -= 1
+            break
+        a = rz / dq
+        x = x + a * d
+        r = r - a * q
+        if math.sqrt(inner(r, r, p)) <= tol:
+            break
+        z = precond(r)
+        rz_new = inner(r, z, p)
+        d = z + (rz_new / rz) * d
+        rz = rz_new
+    return x, it
+
+
+def gradient_l2(v0, I0, I1, p):
+    """L2-gradient of E (A17): L g_V, so that dE[d] = <g_L2, d>."""
+    g, lin = gradient(v0, I0, I1, p)
+    return apply_L(g, p), lin
+
+
+def hessvec_l2(dv, lin, p):
+    """Gauss-Newton Hessian in the L2 product (A17): L H_V dv."""
+    return apply_L(hessvec(dv, lin, p), p)
+
+
 @dataclass
 class IterLog:
     E: float
     E_reg: float
     E_data: float
     mse_rel: float
-    g_norm_V: float
+    g_norm: float  # norm of the gradient in the solve's space (V, or L2 for "GN, L2")
     g_inf_rel: float
     cg_iters: int
     eta: float
     tau: float
 
 
-def gn_solve(I0, I1, p, gn_iters=10, cg_iters=20, c1=1e-4, max_halvings=10, gtol=1e-3, v0=None):
-    """Inexact Gauss-Newton-Krylov in V (Section 3): per iteration linearize, gradient,
-    CG on H p = -g with forcing eta = min(0.5, sqrt(||g||_V / ||g_0||_V)), then Armijo
-    backtracking v0 <- v0 + tau p (A1).  Returns (v0, log, final Linearization)."""
+def gn_solve(I0, I1, p, gn_iters=10, cg_iters=20, c1=1e-4, max_halvings=10, gtol=1e-3, v0=None, space="V"):
+    """Inexact Gauss-Newton-Krylov (Section 3): per iteration linearize, gradient,
+    a Krylov solve of H p = -g with forcing eta = min(0.5, sqrt(||g|| / ||g_0||)),
+    then Armijo backtracking v0 <- v0 + tau p (A1).  space="V": CG in V (the primary
+    method); space="L2": gradient and Hessian in L2 and PCG with preconditioner K
+    (A17).  Returns (v0, log, final Linearization)."""
+    if space not in ("V", "L2"):
+        raise ValueError("space must be 'V' or 'L2'")
     I0 = np.asarray(I0, dtype=np.float64)
     I1 = np.asarray(I1, dtype=np.float64)
     v = np.zeros((3,) + tuple(p.n)) if v0 is None else np.array(v0, dtype=np.float64)
@@ -473,16 +524,24 @@ def gn_solve(I0, I1, p, gn_iters=10, cg_iters=20, c1=1e-4, max_halvings=10, gtol
     g0 = ginf0 = None
     lin = None
     for _ in range(gn_iters):
-        g, lin = gradient(v, I0, I1, p)
-        gn = math.sqrt(inner_V(g, g, p))
+        if space == "V":
+            g, lin = gradient(v, I0, I1, p)
+            gn = math.sqrt(inner_V(g, g, p))
+        else:
+            g, lin = gradient_l2(v, I0, I1, p)
+            gn = math.sqrt(inner(g, g, p))
         ginf = float(np.max(np.abs(g)))
         if g0 is None:
             g0, ginf0 = gn, ginf
         if g0 == 0.0 or gn / g0 <= gtol:
             break
         eta = min(0.5, math.sqrt(gn / g0))
-        step, its = cg_v(lambda d: hessvec(d, lin, p), g, p, eta, cg_iters)
-        gp = inner_V(g, step, p)
+        if space == "V":
+            step, its = cg_v(lambda d: hessvec(d, lin, p), g, p, eta, cg_iters)
+            gp = inner_V(g, step, p)
+        else:
+            step, its = pcg_l2(lambda d: hessvec_l2(d, lin, p), g, p, eta, cg_iters, lambda r: apply_K(r, p))
+            gp = inner(g, step, p)
         tau, accepted = 1.0, False
         for _ in range(max_halvings + 1):
             if energy(v + tau * step, I0, I1, p) <= lin.E + c1 * tau * gp:
@@ -494,6 +553,41 @@ def gn_solve(I0, I1, p, gn_iters=10, cg_iters=20, c1=1e-4, max_halvings=10, gtol
         if not accepted:
             break
         v = v + tau * step
+    lin = linearize(v, I0, I1, p)
+    return v, log, lin
+
+
+def gd_solve(I0, I1, p, iters=50, c1=1e-4, max_halvings=10, gtol=1e-3, tau0=0.5, v0=None):
+    """Gradient descent in V (Section 2.2, the EPDiff-LDDMM baseline): per iteration
+    the V-gradient from the adjoint Jacobi sweep, then v0 <- v0 - tau g with tau
+    from tau0 by Armijo halving (A18).  Same stop rules and log as gn_solve (no CG:
+    cg_iters = 0, eta = 0).  Returns (v0, log, final Linearization)."""
+    I0 = np.asarray(I0, dtype=np.float64)
+    I1 = np.asarray(I1, dtype=np.float64)
+    v = np.zeros((3,) + tuple(p.n)) if v0 is None else np.array(v0, dtype=np.float64)
+    base = inner(I0 - I1, I0 - I1, p)
+    log = []
+    g0 = ginf0 = None
+    for _ in range(iters):
+        g, lin = gradient(v, I0, I1, p)
+        gg = inner_V(g, g, p)
+        gn = math.sqrt(gg)
+        ginf = float(np.max(np.abs(g)))
+        if g0 is None:
+            g0, ginf0 = gn, ginf
+        if g0 == 0.0 or gn / g0 <= gtol:
+            break
+        tau, accepted = tau0, False
+        for _ in range(max_halvings + 1):
+            if energy(v - tau * g, I0, I1, p) <= lin.E - c1 * tau * gg:
+                accepted = True
+                break
+            tau *= 0.5
+        log.append(IterLog(lin.E, lin.E_reg, lin.E_data, 100.0 * inner(lin.residual, lin.residual, p) / base,
+                           gn, ginf / ginf0, 0, 0.0, tau if accepted else 0.0))
+        if not accepted:
+            break
+        v = v - tau * g
     lin = linearize(v, I0, I1, p)
     return v, log, lin
 

@@ -376,6 +376,102 @@ def test_gn_solve_decreases_energy():
     assert log[0].g_inf_rel == 1.0 and all(it.cg_iters >= 1 for it in log)
 
 
+# --------------------------------------------------------------------------- "GN, L2" and gradient descent
+def test_l2_gradient_at_zero_closed_form():
+    """At v0 = 0 the L2-gradient is -(2/sigma2) (I0 - I1) grad I0: no K (the V-gradient's K is undone by L)."""
+    p, I0, I1, _ = phantom_case()
+    g, _ = O.gradient_l2(np.zeros((3,) + p.n), I0, I1, p)
+    expect = -(2.0 / p.sigma2) * (I0 - I1)[None] * O.grad(I0, p)
+    np.testing.assert_allclose(g, expect, atol=1e-11 * np.abs(expect).max())
+
+
+def _l2_system(n=(4, 4, 6)):
+    p = P(n, alpha=0.05, nt=4, sigma2=0.002)
+    I0 = phantom(n, 3, (1.0, 2.0), False, 1000)
+    I1 = phantom(n, 3, (1.0, 2.0), False, 1001)
+    v0 = random_velocity(n, 2000, 0.5, kc=1.5)
+    lin = O.linearize(v0, I0, I1, p)
+    g, _ = O.gradient(v0, I0, I1, p, lin)
+    return p, lin, g
+
+
+def test_pcg_l2_iterates_equal_cg_v_and_dense_solve():
+    """PCG in L2 with preconditioner K and CG in V produce the same iterates (exact
+    arithmetic identity: r_L2 = L r_V, z = K r_L2 = r_V); with many iterations both
+    reach the dense solution of L H x = -L g."""
+    p, lin, g = _l2_system()
+    gl2 = O.apply_L(g, p)
+    hl2 = lambda d: O.hessvec_l2(d, lin, p)
+    K = lambda r: O.apply_K(r, p)
+    for k in range(1, 7):
+        x_pcg, it_p = O.pcg_l2(hl2, gl2, p, 0.0, k, K)
+        x_cg, it_c = O.cg_v(lambda d: O.hessvec(d, lin, p), g, p, 0.0, k)
+        assert it_p == it_c == k
+        assert np.linalg.norm(x_pcg - x_cg) <= 1e-10 * np.linalg.norm(x_cg)
+    H = _dense_hessian(lin, p)
+    Lm = _dense_L(p)
+    x_dense = np.linalg.solve(Lm @ H, -gl2.ravel())
+    x_pcg, _ = O.pcg_l2(hl2, gl2, p, 1e-13, 400, K)
+    np.testing.assert_allclose(x_pcg.ravel(), x_dense, atol=1e-8 * np.abs(x_dense).max())
+
+
+def test_pcg_l2_stops_on_the_l2_residual():
+    """The stop is the first iterate with ||-g_L2 - H_L2 x_k||_L2 <= eta ||g_L2||_L2,
+    the residual recomputed here from a dense H_L2 and the CG-in-V iterates."""
+    p, lin, g = _l2_system()
+    gl2 = O.apply_L(g, p)
+    HL2 = _dense_L(p) @ _dense_hessian(lin, p)
+    cell = float(np.prod(p.h))
+    gnorm = np.sqrt(cell * np.sum(gl2 * gl2))
+    for eta in (0.3, 0.05, 0.01):
+        _, m = O.pcg_l2(lambda d: O.hessvec_l2(d, lin, p), gl2, p, eta, 200, lambda r: O.apply_K(r, p))
+        res = []
+        for k in (m - 1, m):
+            xk = O.cg_v(lambda d: O.hessvec(d, lin, p), g, p, 0.0, k)[0] if k > 0 else np.zeros_like(g)
+            r = -gl2.ravel() - HL2 @ xk.ravel()
+            res.append(np.sqrt(cell * np.sum(r * r)))
+        assert res[1] <= eta * gnorm * (1 + 1e-9) and res[0] > eta * gnorm, (eta, m, res, gnorm)
+
+
+def test_gn_l2_solve_decreases_energy():
+    p, I0, _, _ = phantom_case(n=(12, 12, 12), nt=5)
+    I1 = O.shoot(random_velocity(p.n, 2100, 1.0, kc=2.0), p, I0).J1
+    v, log, lin = O.gn_solve(I0, I1, p, gn_iters=3, cg_iters=10, space="L2")
+    Es = [it.E for it in log] + [lin.E]
+    for k, it in enumerate(log):
+        assert (Es[k + 1] < Es[k]) if it.tau > 0 else (Es[k + 1] == Es[k]), Es
+    assert log[0].tau > 0 and Es[-1] < 0.95 * Es[0]
+    g0, _ = O.gradient_l2(np.zeros((3,) + p.n), I0, I1, p)
+    assert log[0].g_norm == pytest.approx(np.sqrt(O.inner(g0, g0, p)), rel=1e-12)
+
+
+def test_gd_step_minimises_the_regulariser():
+    """With a negligible data term E ~ <L v0, v0>, whose V-gradient is 2 v0: the
+    first trial step tau0 = 1/2 lands on v0 = 0 and is accepted."""
+    p, I0, I1, _ = phantom_case()
+    p.sigma2 = 1e12
+    v0 = random_velocity(p.n, 2200, 1.0, kc=2.0)
+    v, log, _ = O.gd_solve(I0, I1, p, iters=1, v0=v0)
+    assert log[0].tau == 0.5 and log[0].cg_iters == 0
+    assert np.abs(v).max() <= 1e-9 * np.abs(v0).max()
+
+
+def test_gd_first_step_from_zero_and_monotone():
+    p, I0, _, _ = phantom_case(n=(12, 12, 12), nt=5)
+    I1 = O.shoot(random_velocity(p.n, 2100, 1.0, kc=2.0), p, I0).J1
+    v1, log1, _ = O.gd_solve(I0, I1, p, iters=1)
+    g0 = -(2.0 / p.sigma2) * O.apply_K((I0 - I1)[None] * O.grad(I0, p), p)  # P-7 closed form
+    np.testing.assert_allclose(v1, -log1[0].tau * g0, atol=1e-12 * np.abs(v1).max())
+    # accepted steps decrease E strictly; near a minimum the adjoint gradient need not
+    # be a descent direction of the discrete energy (optimise-then-discretise), so a
+    # failed line search (tau = 0) keeping E is allowed, as for Gauss-Newton
+    _, log, lin = O.gd_solve(I0, I1, p, iters=4)
+    Es = [it.E for it in log] + [lin.E]
+    for k, it in enumerate(log):
+        assert (Es[k + 1] < Es[k]) if it.tau > 0 else (Es[k + 1] == Es[k]), Es
+    assert log[0].tau > 0 and Es[-1] < 0.95 * Es[0]
+
+
 # --------------------------------------------------------------------------- planted mistakes
 def _fails(check):
     try:
@@ -422,7 +518,26 @@ def test_planted_mistakes(monkeypatch):
         X = x + 0.5 * p.dt * (v_new + OM.interp(v_old, x + p.dt * v_new, p))
         return OM.interp(u, X, p) + (X - x)
 
+    def pcg_unpreconditioned_beta(hess, g, p, eta, maxit, precond):  # beta from <r, r>, not <r, K r>
+        x = np.zeros_like(g)
+        r = -g
+        z = precond(r)
+        d = z.copy()
+        rz = OM.inner(r, z, p)
+        for _ in range(maxit):
+            q = hess(d)
+            a = rz / OM.inner(d, q, p)
+            x = x + a * d
+            rr_old = OM.inner(r, r, p)
+            r = r - a * q
+            z = precond(r)
+            d = z + (OM.inner(r, r, p) / rr_old) * d
+            rz = OM.inner(r, z, p)
+        return x, maxit
+
+    orig["pcg_l2"] = OM.pcg_l2
     cases = [
+        ("pcg_l2", pcg_unpreconditioned_beta, [test_pcg_l2_iterates_equal_cg_v_and_dense_solve]),
         ("ad", ad_transposed, [test_ad_constant_velocity_closed_form]),
         ("ad_star", ad_star_sign, [test_ad_identities, test_dot_product_tangent_vs_backward]),
         ("backward_sweep", bw_wrong_order, [test_dot_product_tangent_vs_backward]),
