@@ -338,6 +338,7 @@ def main():
     ap.add_argument("--workload", default="pair128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the GN-L2 and gradient-descent solves")
     ap.add_argument("--hv-reps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true", help="keep the default transform launch shapes")
     ap.add_argument("--no-graph", action="store_true", help="launch Hessian-vector products kernel by kernel")
@@ -481,6 +482,33 @@ def main():
     del src, dst
     log(f"[bench] device copy 1 GiB: {copy_ms:.3f} ms, {copy_GBps:.0f} GB/s (read + write)")
 
+    # the other optimisers of the comparison on the same pair: Gauss-Newton with
+    # PCG in L2 (preconditioner K) and gradient descent in V (50 iterations)
+    variants = {}
+    if not args.no_variants:
+        for method in ("gn_l2", "gd"):
+            v = torch.zeros((3,) + spec.n, dtype=torch.float32, device=dev)
+            R.gn_solve(v, gn_iters=1, cg_iters=2, method=method)  # warm-up (graph capture)
+            v.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            trv = R.gn_solve(v, cg_iters=spec.cg_iters, method=method)
+            torch.cuda.synchronize()
+            sv = time.perf_counter() - t1
+            r = trv.report
+            variants[method] = {
+                "solves_per_min": round(60.0 / sv, 3),
+                "ms_per_solve": round(1e3 * sv, 1),
+                "iters": r["iters"],
+                "cg_total": r["cg_total"],
+                "gradients": r["gradients"],
+                "line_search_shoots": r["shoots"],
+                "mse_rel_final": r["mse_rel_final"],
+                "E_final": r["E_final"],
+                "g_rel_final": r["g_rel_final"],
+            }
+            log(f"[bench] {method}: {variants[method]}")
+
     # plain FP64 path
     fp64 = None
     if not args.no_fp64:
@@ -548,6 +576,7 @@ def main():
         },
         "fp64": fp64,
         "fp32_speedup_vs_fp64": round(fp64["ms_per_solve"] / ms_per_step, 3) if fp64 else None,
+        "variants": variants,
         "hv_algorithmic_GBps": round(hv_bytes / (hv_ms * 1e-3) / 1e9, 1),
         "hv_algorithmic_bytes": int(hv_bytes),
         "roofline": {

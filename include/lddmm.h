@@ -88,15 +88,26 @@ typedef struct {
   int32_t reserved;
 } lddmm_params;
 
-/* Inexact Gauss-Newton-Krylov settings (Section 3 update and PCG system).
- * Zero fields take the defaults in brackets. */
+/* Optimisation methods of lddmm_gn_solve (lddmm_solve_opts.method); the three
+ * rows of the paper's comparison that use this hot path (Table 1). */
+enum {
+  LDDMM_GN_V = 0,  /* inexact Gauss-Newton-Krylov, CG in V (Section 3)             */
+  LDDMM_GN_L2 = 1, /* Gauss-Newton with the L2 gradient L g and Hessian L H, PCG
+                      with preconditioner K, L2 norms in every stop (Section 3)   */
+  LDDMM_GD_V = 2   /* gradient descent in V, v0 <- v0 - tau g (Section 2.2); the
+                      Armijo search starts at tau = 1/2                            */
+};
+
+/* Optimisation settings (Section 3 update and PCG system).  Zero fields take the
+ * defaults in brackets.  "||g||" is the norm of the method's space: ||g||_V, or
+ * ||L g||_L2 for LDDMM_GN_L2. */
 typedef struct {
-  int32_t gn_iters;     /* outer iterations [10]                                  */
+  int32_t gn_iters;     /* outer iterations [10; 50 for LDDMM_GD_V]               */
   int32_t cg_iters;     /* CG iterations per outer iteration [20]                 */
   int32_t max_halvings; /* Armijo step halvings [10]                              */
-  int32_t reserved;
+  int32_t method;       /* LDDMM_GN_V, LDDMM_GN_L2 or LDDMM_GD_V [LDDMM_GN_V]     */
   double c1;            /* Armijo constant [1e-4]                                 */
-  double gtol;          /* stop when ||g||_V / ||g_0||_V <= gtol [1e-3]           */
+  double gtol;          /* stop when ||g|| / ||g_0|| <= gtol [1e-3]               */
   double eta_max;       /* forcing term eta = min(eta_max, sqrt(||g||/||g_0||)) [0.5] */
 } lddmm_solve_opts;
 
@@ -104,8 +115,8 @@ typedef struct {
 typedef struct {
   double E, E_reg, E_data; /* energy and its two terms                          */
   double mse_rel;          /* 100 ||J_1 - I_1||^2 / ||I_0 - I_1||^2 (percent)   */
-  double g_norm_V;         /* ||g||_V                                           */
-  double g_inf_rel;        /* ||g||_inf / ||g_0||_inf                           */
+  double g_norm;           /* ||g|| in the method's space                       */
+  double g_inf_rel;        /* ||g||_inf / ||g_0||_inf (the method's gradient)   */
   double eta;              /* CG forcing term                                   */
   double tau;              /* accepted Armijo step (0 = line search failed)     */
   int32_t cg_iters;        /* CG iterations (= Hessian-vector products)         */
@@ -121,7 +132,7 @@ typedef struct {
   int32_t stop_reason; /* 0 iteration cap, 1 gradient tolerance, 2 line search    */
   double E_first, E_final;
   double mse_rel_final;
-  double g_rel_final;  /* ||g||_V / ||g_0||_V at the last linearization            */
+  double g_rel_final;  /* ||g|| / ||g_0|| at the last linearization                */
 } lddmm_solve_report;
 
 /* Create a context: validates params, allocates the workspace and the trajectory
@@ -176,8 +187,10 @@ int lddmm_vjp(lddmm_ctx* ctx, const void* gbar_J1, void* gbar_v0);
  * ||r||_V <= eta ||g||_V or after maxit iterations; *iters = iterations done. */
 int lddmm_cg_solve(lddmm_ctx* ctx, const void* g, void* x, double eta, int maxit, int* iters);
 
-/* Inexact Gauss-Newton-Krylov solve from v0_inout (updated in place).
- * opts may be NULL (defaults); report and log (capacity log_cap) may be NULL. */
+/* Solve from v0_inout (updated in place) with opts->method: inexact
+ * Gauss-Newton-Krylov in V (default) or with PCG in L2, or gradient descent in V.
+ * opts may be NULL (defaults); report and log (capacity log_cap) may be NULL.
+ * LDDMM_EINVAL for an unknown method. */
 int lddmm_gn_solve(lddmm_ctx* ctx, void* v0_inout, const lddmm_solve_opts* opts,
                    lddmm_solve_report* report, lddmm_iter_log* log, int log_cap);
 

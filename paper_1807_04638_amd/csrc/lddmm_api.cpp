@@ -720,6 +720,40 @@ class Engine {
     return 0;
   }
 
+  // PCG in L2 for (L H) x = -g_L2 with preconditioner K (the "GN, L2" variant):
+  // r, z = K r, d, q = L H d in cr, cLr, cd, cHd; H d itself in cLd.  Stops at
+  // ||r||_L2 <= eta ||g_L2||_L2.
+  int pcg_l2(const T* gl2, T* x, double eta, int maxit, int* iters) {
+    const long long V = 3 * N;
+    launch_axpbyz<T>(V, -1.0, gl2, 0.0, gl2, cr, st, &prof);
+    applyK(cr, cLr);
+    copy(cd, cLr, V);
+    launch_fill<T>(V, T(0), x, st, &prof);
+    double rz = dot(cr, cLr);
+    const double tol = eta * std::sqrt(dot(gl2, gl2));
+    int it = 0;
+    for (it = 1; it <= maxit; ++it) {
+      hessvec_core(cd, cLd);
+      applyL(cLd, cHd);
+      const double dq = dot(cd, cHd);
+      if (!(dq > 0.0)) {
+        --it;
+        break;
+      }
+      const double a = rz / dq;
+      launch_axpby<T>(V, a, cd, 1.0, x, st, &prof);
+      launch_axpby<T>(V, -a, cHd, 1.0, cr, st, &prof);
+      if (std::sqrt(dot(cr, cr)) <= tol) break;
+      applyK(cr, cLr);
+      const double rz_new = dot(cr, cLr);
+      launch_axpby<T>(V, 1.0, cLr, rz_new / rz, cd, st, &prof);
+      rz = rz_new;
+    }
+    if (it > maxit) it = maxit;
+    if (iters) *iters = it;
+    return 0;
+  }
+
   int cg_solve(const T* gin, T* x, double eta, int maxit, int* iters) {
     if (!linearized) return fail(LDDMM_ESTATE, "cg_solve without a linearization");
     if (maxit < 0 || !(eta >= 0.0)) return fail(LDDMM_EINVAL, "bad CG settings");
@@ -733,7 +767,10 @@ class Engine {
     if (int rc = check_finite(v, 3 * N, "v0")) return rc;
     lddmm_solve_opts op{};
     if (o) op = *o;
-    if (op.gn_iters <= 0) op.gn_iters = 10;
+    const int method = op.method;
+    if (method != LDDMM_GN_V && method != LDDMM_GN_L2 && method != LDDMM_GD_V)
+      return fail(LDDMM_EINVAL, "unknown optimisation method");
+    if (op.gn_iters <= 0) op.gn_iters = method == LDDMM_GD_V ? 50 : 10;
     if (op.cg_iters <= 0) op.cg_iters = 20;
     if (op.max_halvings <= 0) op.max_halvings = 10;
     if (op.c1 <= 0) op.c1 = 1e-4;
@@ -748,8 +785,9 @@ class Engine {
       R.gradients++;
       if (k == 0) R.E_first = E;
       applyL(gv, Lg);
-      const double gn = std::sqrt(std::max(0.0, dot(Lg, gv)));
-      const double ginf = maxabs(gv, V);
+      // the method's gradient and norm: g_V with ||g||_V, or g_L2 = L g_V with ||.||_L2
+      const double gn = method == LDDMM_GN_L2 ? std::sqrt(dot(Lg, Lg)) : std::sqrt(std::max(0.0, dot(Lg, gv)));
+      const double ginf = maxabs(method == LDDMM_GN_L2 ? Lg : gv, V);
       if (k == 0) {
         g0 = gn;
         ginf0 = ginf;
@@ -759,17 +797,29 @@ class Engine {
         R.stop_reason = 1;
         break;
       }
-      const double eta = std::min(op.eta_max, std::sqrt(gn / g0));
+      // search direction p and the slope <g, p> of E along it (same value in V and L2)
+      double eta = 0.0, gp = 0.0, tau = 1.0, sign = 1.0;
+      const T* dir = cx;
       int its = 0;
-      cg(gv, cx, eta, op.cg_iters, &its);
-      R.cg_total += its;
-      R.hessvecs += its;
-      const double gp = dot(Lg, cx);
-      double tau = 1.0;
+      if (method == LDDMM_GD_V) {
+        dir = gv;
+        sign = -1.0;
+        gp = -gn * gn;
+        tau = 0.5;
+      } else {
+        eta = std::min(op.eta_max, std::sqrt(gn / g0));
+        if (method == LDDMM_GN_V)
+          cg(gv, cx, eta, op.cg_iters, &its);
+        else
+          pcg_l2(Lg, cx, eta, op.cg_iters, &its);
+        R.cg_total += its;
+        R.hessvecs += its;
+        gp = dot(Lg, cx);
+      }
       bool accepted = false;
       int trials = 0;
       for (int h = 0; h <= op.max_halvings; ++h) {
-        launch_axpbyz<T>(V, 1.0, v, tau, cx, trial, st, &prof);
+        launch_axpbyz<T>(V, 1.0, v, sign * tau, dir, trial, st, &prof);
         shoot_core(trial, false, true, Jtmp, nullptr, nullptr, true);
         const double et = fetch_energy();
         R.shoots++;
@@ -786,7 +836,7 @@ class Engine {
         L.E_reg = Ereg;
         L.E_data = Edata;
         L.mse_rel = base_sq > 0 ? 100.0 * Edata * P.sigma2 / base_sq : 0.0;
-        L.g_norm_V = gn;
+        L.g_norm = gn;
         L.g_inf_rel = ginf0 > 0 ? ginf / ginf0 : 0.0;
         L.eta = eta;
         L.tau = accepted ? tau : 0.0;

@@ -42,12 +42,16 @@ class Params(ctypes.Structure):
     ]
 
 
+# lddmm_solve_opts.method
+METHODS = {"gn_v": 0, "gn_l2": 1, "gd": 2}
+
+
 class SolveOpts(ctypes.Structure):
     _fields_ = [
         ("gn_iters", ctypes.c_int32),
         ("cg_iters", ctypes.c_int32),
         ("max_halvings", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("method", ctypes.c_int32),
         ("c1", ctypes.c_double),
         ("gtol", ctypes.c_double),
         ("eta_max", ctypes.c_double),
@@ -60,7 +64,7 @@ class IterLog(ctypes.Structure):
         ("E_reg", ctypes.c_double),
         ("E_data", ctypes.c_double),
         ("mse_rel", ctypes.c_double),
-        ("g_norm_V", ctypes.c_double),
+        ("g_norm", ctypes.c_double),
         ("g_inf_rel", ctypes.c_double),
         ("eta", ctypes.c_double),
         ("tau", ctypes.c_double),
@@ -322,10 +326,17 @@ class Registration:
         )
         return out, its.value
 
-    def gn_solve(self, v0, gn_iters=10, cg_iters=20, max_halvings=10, c1=1e-4, gtol=1e-3, eta_max=0.5):
-        """Solve from v0 (updated in place); returns a Trace."""
+    def gn_solve(self, v0, gn_iters=None, cg_iters=20, max_halvings=10, c1=1e-4, gtol=1e-3, eta_max=0.5,
+                 method="gn_v"):
+        """Solve from v0 (updated in place); returns a Trace.  method: "gn_v"
+        (Gauss-Newton, CG in V), "gn_l2" (Gauss-Newton, PCG in L2 with
+        preconditioner K) or "gd" (gradient descent in V).  gn_iters defaults to
+        10 (50 for "gd")."""
         self._field(v0, 3, "v0")
-        o = SolveOpts(gn_iters, cg_iters, max_halvings, 0, c1, gtol, eta_max)
+        m = METHODS[method]
+        if gn_iters is None:
+            gn_iters = 50 if method == "gd" else 10
+        o = SolveOpts(gn_iters, cg_iters, max_halvings, m, c1, gtol, eta_max)
         rep = SolveReport()
         cap = max(1, gn_iters)
         logs = (IterLog * cap)()
@@ -421,11 +432,13 @@ class Batch:
         if rc != OK:
             raise LddmmError(rc, f"{what}: {self.lib.lddmm_strerror(rc).decode()}")
 
-    def gn_solve(self, v0s, concurrent=True, gn_iters=10, cg_iters=20, max_halvings=10, c1=1e-4, gtol=1e-3,
-                 eta_max=0.5):
+    def gn_solve(self, v0s, concurrent=True, gn_iters=None, cg_iters=20, max_halvings=10, c1=1e-4, gtol=1e-3,
+                 eta_max=0.5, method="gn_v"):
         torch.cuda.current_stream(self.device).synchronize()
         ptrs = (_vp * len(v0s))(*[t.data_ptr() for t in v0s])
-        o = SolveOpts(gn_iters, cg_iters, max_halvings, 0, c1, gtol, eta_max)
+        if gn_iters is None:
+            gn_iters = 50 if method == "gd" else 10
+        o = SolveOpts(gn_iters, cg_iters, max_halvings, METHODS[method], c1, gtol, eta_max)
         reps = (SolveReport * len(v0s))()
         self._rc(self.lib.lddmm_batch_gn_solve(self._b, ptrs, ctypes.byref(o), reps, 1 if concurrent else 0),
                  "batch_gn_solve")

@@ -59,9 +59,11 @@ def test_struct_layouts_match_c(tmp_path):
     src = tmp_path / "sizes.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "lddmm.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(lddmm_params), sizeof(lddmm_solve_opts),"
-        " sizeof(lddmm_iter_log), sizeof(lddmm_solve_report), offsetof(lddmm_params, alpha),"
-        " offsetof(lddmm_params, mem_budget_bytes), offsetof(lddmm_solve_report, E_first)); return 0;}\n"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %d %d %d\\n\", sizeof(lddmm_params),"
+        " sizeof(lddmm_solve_opts), sizeof(lddmm_iter_log), sizeof(lddmm_solve_report), offsetof(lddmm_params, alpha),"
+        " offsetof(lddmm_params, mem_budget_bytes), offsetof(lddmm_solve_report, E_first),"
+        " offsetof(lddmm_solve_opts, method), offsetof(lddmm_iter_log, g_norm), LDDMM_GN_V, LDDMM_GN_L2, LDDMM_GD_V);"
+        " return 0;}\n"
     )
     exe = tmp_path / "sizes"
     gcc = shutil.which("gcc") or shutil.which("cc")
@@ -77,6 +79,11 @@ def test_struct_layouts_match_c(tmp_path):
         B.Params.alpha.offset,
         B.Params.mem_budget_bytes.offset,
         B.SolveReport.E_first.offset,
+        B.SolveOpts.method.offset,
+        B.IterLog.g_norm.offset,
+        B.METHODS["gn_v"],
+        B.METHODS["gn_l2"],
+        B.METHODS["gd"],
     ]
     assert got == expect
 

@@ -356,8 +356,62 @@ def test_gn_solve_parity_fp64():
         assert a["E"] == pytest.approx(b.E, rel=1e-10)
         assert a["mse_rel"] == pytest.approx(b.mse_rel, rel=1e-9)
         assert a["g_inf_rel"] == pytest.approx(b.g_inf_rel, rel=1e-9)
+        assert a["g_norm"] == pytest.approx(b.g_norm, rel=1e-9)
     assert tr.report["E_final"] == pytest.approx(lin.E, rel=1e-10)
     assert rel(v, vo) <= 1e-9
+
+
+def _variant_case():
+    n = (16, 16, 16)
+    p = O.Params(n, 0.01, 2, 5, 0.02)
+    I0 = phantom(n, 4, (1.5, 3.0), False, 1000)
+    I1 = O.shoot(random_velocity(n, 2100, 1.0, kc=2.0), p, I0).J1
+    return n, p, I0, I1
+
+
+@pytest.mark.parametrize("method", ["gn_l2", "gd"])
+def test_solver_variants_parity_fp64(method):
+    """Gauss-Newton with PCG in L2 (preconditioner K, L2 norms) and gradient descent
+    in V against the oracle's literal implementations, iteration by iteration."""
+    n, p, I0, I1 = _variant_case()
+    R, _ = make(n, torch.float64, nt=5, sigma2=0.02)
+    R.set_images(T(I0, torch.float64), T(I1, torch.float64))
+    v = torch.zeros((3,) + n, dtype=torch.float64, device=DEV)
+    if method == "gn_l2":
+        tr = R.gn_solve(v, gn_iters=3, cg_iters=6, method="gn_l2")
+        vo, log, lin = O.gn_solve(I0, I1, p, gn_iters=3, cg_iters=6, space="L2")
+    else:
+        tr = R.gn_solve(v, gn_iters=6, method="gd")
+        vo, log, lin = O.gd_solve(I0, I1, p, iters=6)
+    say(f"  {method} gpu", tr.report, "\n  oracle", [(it.E, it.cg_iters, it.tau) for it in log])
+    assert len(tr.log) == len(log) >= 2
+    for a, b in zip(tr.log, log):
+        assert a["cg_iters"] == b.cg_iters and a["tau"] == b.tau
+        assert a["E"] == pytest.approx(b.E, rel=1e-10)
+        assert a["mse_rel"] == pytest.approx(b.mse_rel, rel=1e-9)
+        assert a["g_norm"] == pytest.approx(b.g_norm, rel=1e-9)
+        assert a["g_inf_rel"] == pytest.approx(b.g_inf_rel, rel=1e-9)
+    assert tr.report["E_final"] == pytest.approx(lin.E, rel=1e-10)
+    assert rel(v, vo) <= 1e-9
+    if method == "gd":
+        assert tr.report["cg_total"] == 0 and tr.report["hessvecs"] == 0
+
+
+@pytest.mark.parametrize("method", ["gn_v", "gn_l2", "gd"])
+def test_solver_variants_fp32(method):
+    """FP32 fields with FP64 reductions: each method decreases the energy and ends
+    within 1e-3 of its FP64 run."""
+    n, p, I0, I1 = _variant_case()
+    out = {}
+    for dtype in DTYPES:
+        R, _ = make(n, dtype, nt=5, sigma2=0.02)
+        R.set_images(T(I0, dtype), T(I1, dtype))
+        v = torch.zeros((3,) + n, dtype=dtype, device=DEV)
+        out[dtype] = R.gn_solve(v, gn_iters=4 if method != "gd" else 8, cg_iters=6, method=method).report
+    a, b = out[torch.float32], out[torch.float64]
+    say(f"  {method}", a, b)
+    assert a["E_final"] < a["E_first"]
+    assert a["E_final"] == pytest.approx(b["E_final"], rel=1e-3)
 
 
 def test_gn_solve_fp32_reaches_fp64_energy():
@@ -409,6 +463,13 @@ def test_error_paths():
     assert e.value.status == -2
     with pytest.raises(ValueError):
         R.gradient(torch.zeros((3, 16, 12, 21), device=DEV))
+    from paper_1807_04638_amd.lddmm import SolveOpts
+
+    import ctypes
+
+    bad_opts = SolveOpts(2, 2, 2, 7, 1e-4, 1e-3, 0.5)  # unknown method
+    rc = R.lib.lddmm_gn_solve(R._ctx, ctypes.c_void_p(v.data_ptr()), ctypes.byref(bad_opts), None, None, 0)
+    assert rc == -1
     for width in (1, 3):  # N2 = 20: no row-vectorised width; 3 is never one
         with pytest.raises(LddmmError) as e:
             R.set_option("stencil.rowvec", width)
