@@ -343,6 +343,13 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default transform launch shapes")
     ap.add_argument("--no-graph", action="store_true", help="launch Hessian-vector products kernel by kernel")
     ap.add_argument(
+        "--shape",
+        default=None,
+        metavar="JSON",
+        help='launch shape to use instead of autotuning, e.g. the "launch_shape" of an earlier bench line '
+        "(read-only keys in it are checked, not set)",
+    )
+    ap.add_argument(
         "--profile-hv",
         type=int,
         default=0,
@@ -384,7 +391,16 @@ def main():
     def context(dtype):
         R = Registration(spec.n, spec.nt, spec.alpha, spec.s, spec.sigma2, dtype=dtype, device=dev)
         R.set_images(torch.tensor(I0, dtype=dtype, device=dev), torch.tensor(I1, dtype=dtype, device=dev))
-        if not args.no_tune:
+        if args.shape and dtype == torch.float32:
+            shape = json.loads(args.shape)
+            for key, val in shape.items():
+                if key in ("fft.fused", "fft.static_kernels"):
+                    if R.get_option(key) != val:
+                        raise SystemExit(f"bench.py: launch shape {key}={val} is not what this grid gives")
+                else:
+                    R.set_option(key, val)
+            log(f"[bench] launch shape set: {shape}")
+        elif not args.no_tune:
             tried, ms = R.autotune(reps=5)
             log(f"[bench] autotune {dtype}: {tried} variants, K application {1e3 * ms:.1f} us")
         if not args.no_graph:
