@@ -40,6 +40,11 @@ A17 "GN, L2" (Section 3, last remark; Table 1): gradient L g_V and Hessian
 A18 Gradient descent in V (Section 2.2): v0 <- v0 - tau g_V, tau by Armijo
     backtracking from tau0 = 1/2, the exact minimiser along -g of the
     regularisation term (its V-Hessian is 2 I).
+A19 Full Newton (Section 3 before the Gauss-Newton drops): the incremental adjoint
+    sweep is the exact linearisation of the discrete adjoint sweep with respect to
+    the trajectory (tangent stage variations), plus lambda_1 grad(delta m_1) in its
+    final condition, delta m_1 in Jacobi form (R8).  CG meeting non-positive
+    curvature on its first direction returns -g (steepest descent).
 """
 
 from __future__ import annotations
@@ -412,6 +417,79 @@ def hessvec(dv, lin, p):
     return 2.0 * np.asarray(dv, dtype=np.float64) + w0
 
 
+# ---------------------------------------------------------------------------
+# Full Newton Hessian-vector product (Section 3: the incremental adjoint Jacobi
+# system with every term kept; A19)
+# ---------------------------------------------------------------------------
+
+
+def tangent_stages(dv, tr, p):
+    """Tangent sweep that also returns, for each step n, the variation of the two
+    trajectory points the Heun step visits: (delta mu_n, delta mu*_n).  Returns
+    (X_nt, [(delta mu_n, delta mu*_n) for n < nt])."""
+    dt = p.dt
+    dmu = apply_L(np.asarray(dv, dtype=np.float64), p)
+    X = np.zeros_like(dmu)
+    stages = []
+    for n in range(p.nt):
+        aX, am = _tangent_rhs(X, dmu, tr.v[n], tr.mu[n], p)
+        Xs, ms = X + dt * aX, dmu + dt * am
+        stages.append((dmu, ms))
+        bX, bm = _tangent_rhs(Xs, ms, tr.v_star[n], tr.mu_star[n], p)
+        X = 0.5 * X + 0.5 * (Xs + dt * bX)
+        dmu = 0.5 * dmu + 0.5 * (ms + dt * bm)
+    return X, stages
+
+
+def _adjoint_rhs_variation(U, w, dv, dmu, mu, p):
+    """Change of the adjoint right-hand side when the trajectory point moves by
+    (dv, dmu) = (K dmu, dmu) with the adjoint state (U^, w) held:
+    (ad*_{dv} U^,  K(ad*_w dmu) - ad_{dv} w) - the ad^dagger_{dv} U, ad^dagger_w dv
+    and -ad_{dv} w terms of the incremental adjoint Jacobi system (Section 3)."""
+    return ad_star(dv, U, p), apply_K(ad_star(w, dmu, p), p) - ad(dv, w, p)
+
+
+def newton_sweep(U_T, dU_T, stages, tr, p):
+    """Linearisation of backward_sweep(U_T, trajectory) when the trajectory varies by
+    `stages` (from tangent_stages) and the final condition by dU_T.  Carries the
+    first-order adjoint (U^, w) and its variation (dU^, dw) through the same
+    transposed Heun steps.  Returns dw_0."""
+    dt = p.dt
+    U = np.array(U_T, dtype=np.float64)
+    w = np.zeros_like(U)
+    dU = np.array(dU_T, dtype=np.float64)
+    dw = np.zeros_like(dU)
+    for n in reversed(range(p.nt)):
+        dmu_n, dmus_n = stages[n]
+        # stage at the predictor point (v*_n, mu*_n)
+        fU, fw = _adjoint_rhs(U, w, tr.v_star[n], tr.mu_star[n], p)
+        lU, lw = _adjoint_rhs(dU, dw, tr.v_star[n], tr.mu_star[n], p)
+        eU, ew = _adjoint_rhs_variation(U, w, apply_K(dmus_n, p), dmus_n, tr.mu_star[n], p)
+        Us, ws = U + dt * fU, w + dt * fw
+        dUs, dws = dU + dt * (lU + eU), dw + dt * (lw + ew)
+        # stage at (v_n, mu_n)
+        gU, gw = _adjoint_rhs(Us, ws, tr.v[n], tr.mu[n], p)
+        kU, kw = _adjoint_rhs(dUs, dws, tr.v[n], tr.mu[n], p)
+        e2U, e2w = _adjoint_rhs_variation(Us, ws, apply_K(dmu_n, p), dmu_n, tr.mu[n], p)
+        U, w = 0.5 * U + 0.5 * (Us + dt * gU), 0.5 * w + 0.5 * (ws + dt * gw)
+        dU = 0.5 * dU + 0.5 * (dUs + dt * (kU + e2U))
+        dw = 0.5 * dw + 0.5 * (dws + dt * (kw + e2w))
+    return dw
+
+
+def hessvec_newton(dv, lin, p):
+    """Newton Hessian-vector product in V (Section 3 with nothing dropped, A19):
+    2 dv + dw_0, where the final condition keeps lambda_1 grad(delta m_1),
+    dU^(1) = -(2/sigma^2) delta m_1 grad J_1 + lambda_1 grad_h(delta m_1), and the
+    sweep keeps the terms of the first-order adjoint (U^, w) of the gradient."""
+    X, stages = tangent_stages(dv, lin.tr, p)
+    dm1 = -np.sum(lin.G * X, axis=0)
+    lam = -(2.0 / p.sigma2) * lin.residual
+    U_T = lam[None] * lin.G
+    dU_T = (-(2.0 / p.sigma2) * dm1)[None] * lin.G + lam[None] * grad(dm1, p)
+    return 2.0 * np.asarray(dv, dtype=np.float64) + newton_sweep(U_T, dU_T, stages, lin.tr, p)
+
+
 def vjp_J1(gbar, lin, p):
     """Plain-array gradient of l(J_1) w.r.t. v0 given gbar = dl/dJ_1 (entrywise):
     L w_0 with U^(1) = -gbar grad J_1 (the h^3 factors of the pairing cancel)."""
@@ -429,7 +507,9 @@ def vjp_J1(gbar, lin, p):
 def cg_v(hess, g, p, eta, maxit):
     """Solve H x = -g by CG in the V inner product, stop at ||r||_V <= eta ||g||_V.
 
-    CG in V is PCG in L2 with preconditioner K.  Returns (x, iterations).
+    CG in V is PCG in L2 with preconditioner K.  On non-positive curvature it stops
+    with the current iterate, or with the steepest-descent direction -g if that
+    happens on the first direction (A19).  Returns (x, iterations).
     """
     x = np.zeros_like(g)
     r = -np.asarray(g, dtype=np.float64)
@@ -440,7 +520,9 @@ def cg_v(hess, g, p, eta, maxit):
     for it in range(1, maxit + 1):
         Hd = hess(d)
         dHd = inner_V(d, Hd, p)
-        if dHd <= 0.0:
+        if dHd <= 0.0:  # negative curvature (Newton Hessian far from a minimum)
+            if it == 1:
+                x = d.copy()  # steepest descent -g
             it -= 1
             break
         a = rr / dHd
@@ -508,14 +590,19 @@ class IterLog:
     tau: float
 
 
-def gn_solve(I0, I1, p, gn_iters=10, cg_iters=20, c1=1e-4, max_halvings=10, gtol=1e-3, v0=None, space="V"):
+def gn_solve(I0, I1, p, gn_iters=10, cg_iters=20, c1=1e-4, max_halvings=10, gtol=1e-3, v0=None, space="V",
+             hessian="gn"):
     """Inexact Gauss-Newton-Krylov (Section 3): per iteration linearize, gradient,
     a Krylov solve of H p = -g with forcing eta = min(0.5, sqrt(||g|| / ||g_0||)),
     then Armijo backtracking v0 <- v0 + tau p (A1).  space="V": CG in V (the primary
     method); space="L2": gradient and Hessian in L2 and PCG with preconditioner K
-    (A17).  Returns (v0, log, final Linearization)."""
+    (A17).  hessian="newton" (with space="V") uses the full Newton Hessian (A19).
+    Returns (v0, log, final Linearization)."""
     if space not in ("V", "L2"):
         raise ValueError("space must be 'V' or 'L2'")
+    if hessian not in ("gn", "newton") or (hessian == "newton" and space != "V"):
+        raise ValueError("hessian must be 'gn', or 'newton' with space 'V'")
+    hv = hessvec_newton if hessian == "newton" else hessvec
     I0 = np.asarray(I0, dtype=np.float64)
     I1 = np.asarray(I1, dtype=np.float64)
     v = np.zeros((3,) + tuple(p.n)) if v0 is None else np.array(v0, dtype=np.float64)
@@ -537,7 +624,7 @@ def gn_solve(I0, I1, p, gn_iters=10, cg_iters=20, c1=1e-4, max_halvings=10, gtol
             break
         eta = min(0.5, math.sqrt(gn / g0))
         if space == "V":
-            step, its = cg_v(lambda d: hessvec(d, lin, p), g, p, eta, cg_iters)
+            step, its = cg_v(lambda d: hv(d, lin, p), g, p, eta, cg_iters)
             gp = inner_V(g, step, p)
         else:
             step, its = pcg_l2(lambda d: hessvec_l2(d, lin, p), g, p, eta, cg_iters, lambda r: apply_K(r, p))

@@ -472,6 +472,85 @@ def test_gd_first_step_from_zero_and_monotone():
     assert log[0].tau > 0 and Es[-1] < 0.95 * Es[0]
 
 
+# --------------------------------------------------------------------------- full Newton Hessian
+def test_newton_equals_gauss_newton_at_zero_residual():
+    """With I1 = J1(v0) the multiplier lambda_1 and the first-order adjoint vanish, so
+    every term Gauss-Newton drops is zero."""
+    p, I0, _, v0 = phantom_case(n=(10, 12, 8), nt=5)
+    I1 = O.shoot(v0, p, I0).J1
+    lin = O.linearize(v0, I0, I1, p)
+    dv = random_field(p.n, 21, 2.0)
+    hn, hg = O.hessvec_newton(dv, lin, p), O.hessvec(dv, lin, p)
+    assert np.linalg.norm(hn - hg) <= 1e-13 * np.linalg.norm(hg)
+
+
+def test_newton_sweep_is_the_exact_linearisation():
+    """With the final condition held, the Newton sweep is the derivative of
+    v0 -> backward_sweep(U_T, shoot(v0)): central FD errors fall as eps^2."""
+    p, I0, I1, v0 = phantom_case(n=(12, 10, 14), nt=5)
+    lin = O.linearize(v0, I0, I1, p)
+    d = random_field(p.n, 5, 2.0)
+    U_T = random_field(p.n, 9, 2.0)
+    _, stages = O.tangent_stages(d, lin.tr, p)
+    an = O.newton_sweep(U_T, np.zeros_like(U_T), stages, lin.tr, p)
+    phi = lambda v: O.backward_sweep(U_T, O.shoot(v, p), p)[1]
+    errs = []
+    for eps in (1e-3, 1e-4):
+        fd = (phi(v0 + eps * d) - phi(v0 - eps * d)) / (2 * eps)
+        errs.append(np.linalg.norm(an - fd) / np.linalg.norm(fd))
+    assert errs[1] <= 1e-7 and errs[0] / errs[1] >= 50, errs
+
+
+def _smooth_newton_gaps(N):
+    n = (N, N, N)
+    p = P(n, alpha=0.05, nt=8, sigma2=0.5)
+    x = O.grid_coords(p)
+    I0 = 0.5 + 0.3 * np.sin(x[0]) * np.cos(2 * x[1]) + 0.2 * np.cos(x[2] + x[0])
+    I1 = 0.5 + 0.3 * np.sin(x[0] + 0.3) * np.cos(2 * x[1] - 0.2) + 0.2 * np.cos(x[2] + x[0] + 0.25)
+    v0 = 0.2 * np.stack([np.sin(x[1]), np.cos(x[2] + x[0]), np.sin(x[0] - x[1])])
+    d = np.stack([np.cos(x[2]), np.sin(x[0] + x[1]), np.cos(x[1])])
+    lin = O.linearize(v0, I0, I1, p)
+    g = lambda v: O.gradient(v, I0, I1, p)[0]
+    eps = 1e-4
+    fd = (g(v0 + eps * d) - g(v0 - eps * d)) / (2 * eps)
+    gap = lambda h: np.linalg.norm(h - fd) / np.linalg.norm(fd)
+    return gap(O.hessvec_newton(d, lin, p)), gap(O.hessvec(d, lin, p))
+
+
+def test_newton_hessian_is_the_derivative_of_the_gradient():
+    """Against central FD of the gradient map, the Newton Hv differs only by the
+    Jacobi-form incremental image (R8), a first-order discretisation gap that halves
+    from 16^3 to 32^3; the Gauss-Newton Hv keeps an O(residual) gap that does not."""
+    n16, g16 = _smooth_newton_gaps(16)
+    n32, g32 = _smooth_newton_gaps(32)
+    assert n16 <= 0.015 and n16 / n32 >= 1.6, (n16, n32)
+    assert g32 >= 4 * n32 and g32 >= 0.7 * g16, (g16, g32, n32)
+
+
+def test_cg_negative_curvature():
+    """Non-positive curvature on the first direction gives the steepest-descent
+    direction -g; met later, CG stops at its current iterate."""
+    p = P((4, 4, 6))
+    g = random_field(p.n, 3, 1.5)
+    x, it = O.cg_v(lambda d: -d, g, p, 1e-12, 10)
+    assert it == 0 and np.array_equal(x, -g)
+    # H = identity on the span of g's first mode, -identity beyond: the second direction is negative
+    e = g / math.sqrt(O.inner_V(g, g, p))
+    hess = lambda d: 2 * O.inner_V(e, d, p) * e - (d - O.inner_V(e, d, p) * e)
+    x2, it2 = O.cg_v(hess, g + 0.3 * random_field(p.n, 4, 1.5), p, 1e-12, 10)
+    assert it2 >= 1 and np.isfinite(x2).all() and np.abs(x2).max() > 0
+
+
+def test_newton_solve_decreases_energy():
+    p, I0, _, _ = phantom_case(n=(12, 12, 12), nt=5)
+    I1 = O.shoot(random_velocity(p.n, 2100, 1.0, kc=2.0), p, I0).J1
+    v, log, lin = O.gn_solve(I0, I1, p, gn_iters=3, cg_iters=10, hessian="newton")
+    Es = [it.E for it in log] + [lin.E]
+    for k, it in enumerate(log):
+        assert (Es[k + 1] < Es[k]) if it.tau > 0 else (Es[k + 1] == Es[k]), Es
+    assert log[0].tau > 0 and Es[-1] < 0.95 * Es[0]
+
+
 # --------------------------------------------------------------------------- planted mistakes
 def _fails(check):
     try:
@@ -487,7 +566,7 @@ def test_planted_mistakes(monkeypatch):
 
     def plant(name, fn):
         monkeypatch.setattr(OM, name, fn)
-        monkeypatch.setattr(O, name, fn)
+        monkeypatch.setattr(O, name, fn, raising=False)  # private helpers are not re-exported
 
     orig = {k: getattr(OM, k) for k in ("ad", "ad_star", "backward_sweep", "symbol_L", "sl_step")}
 
@@ -535,8 +614,14 @@ def test_planted_mistakes(monkeypatch):
             rz = OM.inner(r, z, p)
         return x, maxit
 
+    def variation_wrong_sign(U, w, dv, dmu, mu, p):  # +ad_{dv} w instead of -ad_{dv} w
+        a, b = orig["_adjoint_rhs_variation"](U, w, dv, dmu, mu, p)
+        return a, b + 2 * OM.ad(dv, w, p)
+
     orig["pcg_l2"] = OM.pcg_l2
+    orig["_adjoint_rhs_variation"] = OM._adjoint_rhs_variation
     cases = [
+        ("_adjoint_rhs_variation", variation_wrong_sign, [test_newton_sweep_is_the_exact_linearisation]),
         ("pcg_l2", pcg_unpreconditioned_beta, [test_pcg_l2_iterates_equal_cg_v_and_dense_solve]),
         ("ad", ad_transposed, [test_ad_constant_velocity_closed_form]),
         ("ad_star", ad_star_sign, [test_ad_identities, test_dot_product_tangent_vs_backward]),
