@@ -498,11 +498,15 @@ def main():
     del src, dst
     log(f"[bench] device copy 1 GiB: {copy_ms:.3f} ms, {copy_GBps:.0f} GB/s (read + write)")
 
-    # the other optimisers of the comparison on the same pair: Gauss-Newton with
-    # PCG in L2 (preconditioner K) and gradient descent in V (50 iterations)
+    # the other optimisers on the same pair: Gauss-Newton with PCG in L2
+    # (preconditioner K), gradient descent in V (50 iterations) and Newton-Krylov
+    # on the full Hessian
     variants = {}
+    vlin_newton = torch.tensor(0.5 * v0t, dtype=torch.float32, device=dev)
+    dvn = torch.randn((3,) + spec.n, device=dev, generator=torch.Generator(device=dev).manual_seed(8))
+    hvn = torch.empty_like(dvn)
     if not args.no_variants:
-        for method in ("gn_l2", "gd"):
+        for method in ("gn_l2", "gd", "newton"):
             v = torch.zeros((3,) + spec.n, dtype=torch.float32, device=dev)
             R.gn_solve(v, gn_iters=1, cg_iters=2, method=method)  # warm-up (graph capture)
             v.zero_()
@@ -512,6 +516,10 @@ def main():
             torch.cuda.synchronize()
             sv = time.perf_counter() - t1
             r = trv.report
+            if method == "newton":
+                R.linearize(vlin_newton)
+                R.hessvec(dvn, out=hvn, newton=True)
+                nms = time_events(torch, lambda: R.hessvec(dvn, out=hvn, newton=True), 5)
             variants[method] = {
                 "solves_per_min": round(60.0 / sv, 3),
                 "ms_per_solve": round(1e3 * sv, 1),
@@ -523,6 +531,8 @@ def main():
                 "E_final": r["E_final"],
                 "g_rel_final": r["g_rel_final"],
             }
+            if method == "newton":
+                variants[method]["hv_per_s"] = round(1e3 / nms, 2)
             log(f"[bench] {method}: {variants[method]}")
 
     # plain FP64 path

@@ -94,8 +94,11 @@ enum {
   LDDMM_GN_V = 0,  /* inexact Gauss-Newton-Krylov, CG in V (Section 3)             */
   LDDMM_GN_L2 = 1, /* Gauss-Newton with the L2 gradient L g and Hessian L H, PCG
                       with preconditioner K, L2 norms in every stop (Section 3)   */
-  LDDMM_GD_V = 2   /* gradient descent in V, v0 <- v0 - tau g (Section 2.2); the
+  LDDMM_GD_V = 2,  /* gradient descent in V, v0 <- v0 - tau g (Section 2.2); the
                       Armijo search starts at tau = 1/2                            */
+  LDDMM_NEWTON_V = 3 /* inexact Newton-Krylov, CG in V on the full Newton Hessian
+                      (lddmm_hessvec_newton); CG meeting non-positive curvature on
+                      its first direction returns -g                             */
 };
 
 /* Optimisation settings (Section 3 update and PCG system).  Zero fields take the
@@ -105,7 +108,7 @@ typedef struct {
   int32_t gn_iters;     /* outer iterations [10; 50 for LDDMM_GD_V]               */
   int32_t cg_iters;     /* CG iterations per outer iteration [20]                 */
   int32_t max_halvings; /* Armijo step halvings [10]                              */
-  int32_t method;       /* LDDMM_GN_V, LDDMM_GN_L2 or LDDMM_GD_V [LDDMM_GN_V]     */
+  int32_t method;       /* LDDMM_GN_V, LDDMM_GN_L2, LDDMM_GD_V, LDDMM_NEWTON_V [GN_V] */
   double c1;            /* Armijo constant [1e-4]                                 */
   double gtol;          /* stop when ||g|| / ||g_0|| <= gtol [1e-3]               */
   double eta_max;       /* forcing term eta = min(eta_max, sqrt(||g||/||g_0||)) [0.5] */
@@ -177,6 +180,17 @@ int lddmm_gradient(lddmm_ctx* ctx, const void* v0, void* g, double* energy);
  * Enqueue-only when v0 == NULL. */
 int lddmm_hessvec(lddmm_ctx* ctx, const void* v0, const void* dv, void* hv);
 
+/* Full Newton Hessian-vector product in V (Section 3 incremental adjoint Jacobi
+ * equations with nothing dropped): as lddmm_hessvec, plus the terms of the
+ * first-order adjoint (U, w) of the gradient in the incremental sweep
+ * (ad^dagger_dv U, -ad_dv w, ad^dagger_w dv) and lambda(1) grad(delta m(1)) in its
+ * final condition.  Not symmetric on the grid beyond discretisation error and
+ * indefinite far from a minimum.  The first call allocates 8 nt vector fields of
+ * stage history (LDDMM_ENOMEM if they do not fit); each new linearization costs one
+ * extra adjoint sweep to record (U, w).  v0 == NULL reuses the current
+ * linearization (LDDMM_ESTATE if there is none). */
+int lddmm_hessvec_newton(lddmm_ctx* ctx, const void* v0, const void* dv, void* hv);
+
 /* Backward of J_1 w.r.t. v0 at the current linearization for a plain-array
  * cotangent gbar = dl/dJ_1 (scalar field): gbar_v0 = L w_0 with
  * U^(1) = -gbar grad J_1 (the quadrature weights of the pairing cancel). */
@@ -188,7 +202,8 @@ int lddmm_vjp(lddmm_ctx* ctx, const void* gbar_J1, void* gbar_v0);
 int lddmm_cg_solve(lddmm_ctx* ctx, const void* g, void* x, double eta, int maxit, int* iters);
 
 /* Solve from v0_inout (updated in place) with opts->method: inexact
- * Gauss-Newton-Krylov in V (default) or with PCG in L2, or gradient descent in V.
+ * Gauss-Newton-Krylov in V (default) or with PCG in L2, gradient descent in V, or
+ * inexact Newton-Krylov in V.
  * opts may be NULL (defaults); report and log (capacity log_cap) may be NULL.
  * LDDMM_EINVAL for an unknown method. */
 int lddmm_gn_solve(lddmm_ctx* ctx, void* v0_inout, const lddmm_solve_opts* opts,

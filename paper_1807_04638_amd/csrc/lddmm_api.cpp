@@ -143,6 +143,13 @@ class Engine {
   double* dres = nullptr;
   double* hres = nullptr;  // pinned host mirror of dres
 
+  // full Newton Hessian: first-order adjoint (U^, w) at the two stage inputs of
+  // every backward step, and the tangent's trajectory variations (dmu, K dmu) at
+  // the two stage points of every forward step (allocated on first use)
+  std::vector<T*> nU1, nW1, nU2, nW2, tdmu, tdmuK, tdmus, tdmusK;
+  int64_t newton_epoch = -1;
+  bool use_newton = false;  // CG applies the Newton Hessian (solve method LDDMM_NEWTON_V)
+
   bool have_images = false, linearized = false;
   int64_t lin_epoch = 0;
   double E = 0, Ereg = 0, Edata = 0, base_sq = 0;
@@ -584,6 +591,98 @@ class Engine {
     (void)hipGraphLaunch(hv_exec, st);
   }
 
+  // ---- full Newton Hessian-vector product -----------------------------------
+  int ensure_newton() {
+    if (!nU1.empty()) return 0;
+    const long long V = 3 * N;
+    for (auto* vec : {&nU1, &nW1, &nU2, &nW2, &tdmu, &tdmuK, &tdmus, &tdmusK}) {
+      vec->assign(P.nt, nullptr);
+      for (int n = 0; n < P.nt; ++n)
+        if (alloc(&(*vec)[n], V)) {
+          for (auto* w : {&nU1, &nW1, &nU2, &nW2, &tdmu, &tdmuK, &tdmus, &tdmusK}) w->clear();
+          return fail(LDDMM_ENOMEM, "cannot allocate the Newton stage histories");
+        }
+    }
+    return 0;
+  }
+
+  // The gradient's adjoint sweep, keeping its state at each stage input.
+  void backward_record() {
+    const long long V = 3 * N;
+    launch_scalar_times_vec<T>(g, res, G, -2.0 / P.sigma2, U, st, &prof);
+    launch_fill<T>(V, T(0), Wh, st, &prof);
+    for (int n = P.nt - 1; n >= 0; --n) {
+      const Step c = traj_view(n);
+      copy(nU1[n], U, V);
+      copy(nW1[n], Wh, V);
+      launch_adjoint_pre<T>(g, U, Wh, c.mus, Z, st, &prof);
+      applyK(Z, Z);
+      launch_adjoint_post<T>(g, U, Wh, Z, c.vs, nullptr, nullptr, Us, Whs, dt, 0.0, 1.0, st, &prof);
+      copy(nU2[n], Us, V);
+      copy(nW2[n], Whs, V);
+      launch_adjoint_pre<T>(g, Us, Whs, c.mu, Z, st, &prof);
+      applyK(Z, Z);
+      launch_adjoint_post<T>(g, Us, Whs, Z, c.v, U, Wh, U, Wh, dt, 0.5, 0.5, st, &prof);
+    }
+  }
+
+  // The tangent sweep, keeping the trajectory variation at each stage point.
+  void tangent_record(const T* dv) {
+    const long long V = 3 * N;
+    applyL(dv, Mu);
+    launch_fill<T>(V, T(0), X, st, &prof);
+    for (int n = 0; n < P.nt; ++n) {
+      const Step c = traj_view(n);
+      copy(tdmu[n], Mu, V);
+      applyK(Mu, tdmuK[n]);
+      launch_tangent_stage<T>(g, X, Mu, tdmuK[n], c.v, c.mu, nullptr, nullptr, Xs, Mus, dt, 0.0, 1.0, st, &prof);
+      copy(tdmus[n], Mus, V);
+      applyK(Mus, tdmusK[n]);
+      launch_tangent_stage<T>(g, Xs, Mus, tdmusK[n], c.vs, c.mus, X, Mu, X, Mu, dt, 0.5, 0.5, st, &prof);
+    }
+  }
+
+  // 2 dv + dw_0 of the linearised adjoint sweep (dU, dw in U, Wh; stage in Us, Whs).
+  void newton_core(const T* dv, T* hv) {
+    if (newton_epoch != lin_epoch) {
+      backward_record();
+      newton_epoch = lin_epoch;
+    }
+    tangent_record(dv);
+    launch_newton_final<T>(g, G, X, res, -2.0 / P.sigma2, tmpS, U, st, &prof);
+    launch_fill<T>(3 * N, T(0), Wh, st, &prof);
+    for (int n = P.nt - 1; n >= 0; --n) {
+      const Step c = traj_view(n);
+      launch_newton_pre<T>(g, U, Wh, c.mus, nW1[n], tdmus[n], Z, st, &prof);
+      applyK(Z, Z);
+      launch_newton_post<T>(g, U, Wh, Z, c.vs, tdmusK[n], nU1[n], nW1[n], nullptr, nullptr, Us, Whs, dt, 0.0, 1.0, st,
+                            &prof);
+      launch_newton_pre<T>(g, Us, Whs, c.mu, nW2[n], tdmu[n], Z, st, &prof);
+      applyK(Z, Z);
+      launch_newton_post<T>(g, Us, Whs, Z, c.v, tdmuK[n], nU2[n], nW2[n], U, Wh, U, Wh, dt, 0.5, 0.5, st, &prof);
+    }
+    launch_axpbyz<T>(3 * N, 2.0, dv, 1.0, Wh, hv, st, &prof);
+  }
+
+  int hessvec_newton(const T* v0, const T* dv, T* hv) {
+    if (v0) {
+      if (int rc = linearize(v0, nullptr, nullptr)) return rc;
+    } else if (!linearized) {
+      return fail(LDDMM_ESTATE, "hessvec_newton without a linearization");
+    }
+    if (int rc = ensure_newton()) return rc;
+    newton_core(dv, hv);
+    return hip_status("hessvec_newton");
+  }
+
+  // Hessian applied inside CG.
+  void apply_hessian(const T* dv, T* hv) {
+    if (use_newton)
+      newton_core(dv, hv);
+    else
+      hessvec_core(dv, hv);
+  }
+
   // ---- autotuner: time the transform variants on this grid, keep the fastest
   int autotune(int reps, int* tried) {
     if (reps <= 0) reps = 5;
@@ -698,9 +797,10 @@ class Engine {
     const double tol = eta * std::sqrt(rr);
     int it = 0;
     for (it = 1; it <= maxit; ++it) {
-      hessvec_core(cd, cHd);
+      apply_hessian(cd, cHd);
       const double dHd = dot(cLd, cHd);
-      if (!(dHd > 0.0)) {
+      if (!(dHd > 0.0)) {  // non-positive curvature: keep x, or take -g on the first direction
+        if (it == 1) copy(x, cd, V);
         --it;
         break;
       }
@@ -768,8 +868,15 @@ class Engine {
     lddmm_solve_opts op{};
     if (o) op = *o;
     const int method = op.method;
-    if (method != LDDMM_GN_V && method != LDDMM_GN_L2 && method != LDDMM_GD_V)
+    if (method != LDDMM_GN_V && method != LDDMM_GN_L2 && method != LDDMM_GD_V && method != LDDMM_NEWTON_V)
       return fail(LDDMM_EINVAL, "unknown optimisation method");
+    if (method == LDDMM_NEWTON_V)
+      if (int rc = ensure_newton()) return rc;
+    struct NewtonScope {  // CG applies the Newton Hessian for this solve only
+      bool& flag;
+      NewtonScope(bool& f, bool on) : flag(f) { flag = on; }
+      ~NewtonScope() { flag = false; }
+    } newton_scope(use_newton, method == LDDMM_NEWTON_V);
     if (op.gn_iters <= 0) op.gn_iters = method == LDDMM_GD_V ? 50 : 10;
     if (op.cg_iters <= 0) op.cg_iters = 20;
     if (op.max_halvings <= 0) op.max_halvings = 10;
@@ -808,7 +915,7 @@ class Engine {
         tau = 0.5;
       } else {
         eta = std::min(op.eta_max, std::sqrt(gn / g0));
-        if (method == LDDMM_GN_V)
+        if (method == LDDMM_GN_V || method == LDDMM_NEWTON_V)
           cg(gv, cx, eta, op.cg_iters, &its);
         else
           pcg_l2(Lg, cx, eta, op.cg_iters, &its);
@@ -1066,6 +1173,11 @@ int lddmm_gradient(lddmm_ctx* ctx, const void* v0, void* g, double* energy) {
 int lddmm_hessvec(lddmm_ctx* ctx, const void* v0, const void* dv, void* hv) {
   if (!dv || !hv) return LDDMM_EINVAL;
   LDDMM_DISPATCH(ctx, E.hessvec(static_cast<const T*>(v0), static_cast<const T*>(dv), static_cast<T*>(hv)));
+}
+
+int lddmm_hessvec_newton(lddmm_ctx* ctx, const void* v0, const void* dv, void* hv) {
+  if (!dv || !hv) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.hessvec_newton(static_cast<const T*>(v0), static_cast<const T*>(dv), static_cast<T*>(hv)));
 }
 
 int lddmm_vjp(lddmm_ctx* ctx, const void* gbar_J1, void* gbar_v0) {

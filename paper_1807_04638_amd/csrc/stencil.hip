@@ -266,6 +266,120 @@ __global__ void __launch_bounds__(256)
   store1(w_out, wo, nb.o[0], g.N);
 }
 
+// ---------------------------------------------------------------------------
+// Full Newton Hessian (Section 3 incremental adjoint Jacobi system with the
+// first-order adjoint terms kept).  The sweep carries (dU, dw); (U1, w1) is the
+// first-order adjoint at the same stage and (W, dmu) = (K dmu, dmu) the
+// variation of the trajectory point.
+// ---------------------------------------------------------------------------
+// Z = dU + ad*_{dw} mu + ad*_{w1} dmu   (argument of K)
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_newton_pre(Geo<T> g, const T* __restrict__ dU, const T* __restrict__ dw, const T* __restrict__ mu,
+                 const T* __restrict__ w1, const T* __restrict__ dmu, T* __restrict__ Z) {
+  int i0, i1, i2;
+  if (!voxel(g, i0, i1, i2)) return;
+  const Nbr nb = neighbours(g, i0, i1, i2);
+  T a[3], b[3], u[3];
+  {
+    St7<T> Dw, M;
+    load7(Dw, dw, nb, g.N);
+    load7(M, mu, nb, g.N);
+    adstar(Dw, M, g, a);
+  }
+  {
+    St7<T> W1, Dm;
+    load7(W1, w1, nb, g.N);
+    load7(Dm, dmu, nb, g.N);
+    adstar(W1, Dm, g, b);
+  }
+  load1(u, dU, nb.o[0], g.N);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) a[c] += b[c] + u[c];
+  store1(Z, a, nb.o[0], g.N);
+}
+
+// f = (ad*_v dU + ad*_W U1,  KZ - ad_v dw - ad_W w1);  out = a1 (y + dt f) + a0 y0
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_newton_post(Geo<T> g, const T* __restrict__ dU, const T* __restrict__ dw, const T* __restrict__ KZ,
+                  const T* __restrict__ v, const T* __restrict__ Wv, const T* __restrict__ U1,
+                  const T* __restrict__ w1, const T* dU0, const T* dw0, T* dU_out, T* dw_out, T dt, T a0, T a1) {
+  int i0, i1, i2;
+  if (!voxel(g, i0, i1, i2)) return;
+  const Nbr nb = neighbours(g, i0, i1, i2);
+  T aU[3], aw[3], t[3], du[3], dwc[3];
+  {
+    St7<T> V, D;
+    load7(V, v, nb, g.N);
+    load7(D, dU, nb, g.N);
+    adstar(V, D, g, aU);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) du[c] = D.f[0][c];
+    St7<T> E;
+    load7(E, dw, nb, g.N);
+    ad(V, E, g, aw);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dwc[c] = E.f[0][c];
+  }
+  {
+    St7<T> Wk, A;
+    load7(Wk, Wv, nb, g.N);
+    load7(A, U1, nb, g.N);
+    adstar(Wk, A, g, t);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) aU[c] += t[c];
+    St7<T> B;
+    load7(B, w1, nb, g.N);
+    ad(Wk, B, g, t);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) aw[c] += t[c];
+  }
+  T kz[3];
+  load1(kz, KZ, nb.o[0], g.N);
+  T uo[3], wo[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    uo[c] = a1 * (du[c] + dt * aU[c]);
+    wo[c] = a1 * (dwc[c] + dt * (kz[c] - aw[c]));
+  }
+  if (a0 != T(0)) {
+    T u0[3], ww0[3];
+    load1(u0, dU0, nb.o[0], g.N);
+    load1(ww0, dw0, nb.o[0], g.N);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      uo[c] += a0 * u0[c];
+      wo[c] += a0 * ww0[c];
+    }
+  }
+  store1(dU_out, uo, nb.o[0], g.N);
+  store1(dw_out, wo, nb.o[0], g.N);
+}
+
+// delta m_1 = -grad J_1 . X (pointwise)
+template <typename T>
+__global__ void k_dm1(long long N, const T* __restrict__ G, const T* __restrict__ X, T* __restrict__ s) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x)
+    s[i] = -(G[i] * X[i] + G[N + i] * X[N + i] + G[2 * N + i] * X[2 * N + i]);
+}
+
+// Newton final condition: U = c s grad J_1 + c r grad_h s  (c = -2/sigma^2:
+// delta lambda_1 grad J_1 + lambda_1 grad(delta m_1) with lambda_1 = c r)
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_newton_final(Geo<T> g, const T* __restrict__ s, const T* __restrict__ r, const T* __restrict__ G, T c,
+                   T* __restrict__ U) {
+  int i0, i1, i2;
+  if (!voxel(g, i0, i1, i2)) return;
+  const Nbr nb = neighbours(g, i0, i1, i2);
+  const T s0 = s[nb.o[0]], r0 = r[nb.o[0]];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    U[d * g.N + nb.o[0]] =
+        c * s0 * G[d * g.N + nb.o[0]] + c * r0 * (s[nb.o[1 + 2 * d]] - s[nb.o[2 + 2 * d]]) * g.inv2h[d];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_residual_grad(Geo<T> g, const T* __restrict__ J1, const T* __restrict__ I1, T* __restrict__ r,
@@ -689,6 +803,31 @@ void launch_gn_final(const Grid& g, const T* G, const T* X, double c, T* U, hipS
 }
 
 template <typename T>
+void launch_newton_pre(const Grid& g, const T* dU, const T* dw, const T* mu, const T* w1, const T* dmu, T* Z,
+                       hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "newton_pre");
+  LDDMM_LAUNCH(t.start, t.stop, k_newton_pre<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), dU, dw, mu, w1, dmu,
+               Z);
+}
+
+template <typename T>
+void launch_newton_post(const Grid& g, const T* dU, const T* dw, const T* KZ, const T* v, const T* Wv, const T* U1,
+                        const T* w1, const T* dU0, const T* dw0, T* dU_out, T* dw_out, double dt, double a0,
+                        double a1, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, a0 != 0.0 ? "newton_post_corr" : "newton_post_pred");
+  LDDMM_LAUNCH(t.start, t.stop, k_newton_post<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), dU, dw, KZ, v, Wv, U1,
+               w1, dU0 ? dU0 : dU, dw0 ? dw0 : dw, dU_out, dw_out, T(dt), T(a0), T(a1));
+}
+
+template <typename T>
+void launch_newton_final(const Grid& g, const T* G, const T* X, const T* r, double c, T* s, T* U, hipStream_t st,
+                         Profiler* prof) {
+  KernelTimer t(prof, "newton_final_condition");
+  LDDMM_LAUNCH(t.start, nullptr, k_dm1<T>, flat_blocks(g.N), 256, 0, st, g.N, G, X, s);
+  LDDMM_LAUNCH(nullptr, t.stop, k_newton_final<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), s, r, G, T(c), U);
+}
+
+template <typename T>
 void launch_jacobian_det(const Grid& g, const T* u, T* det, hipStream_t st, Profiler* prof) {
   KernelTimer t(prof, "jacobian_det");
   LDDMM_LAUNCH(t.start, t.stop, k_jacobian_det<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), u, det);
@@ -705,7 +844,14 @@ void launch_jacobian_det(const Grid& g, const T* u, T* det, hipStream_t st, Prof
   template void launch_residual_grad<T>(const Grid&, const T*, const T*, T*, T*, hipStream_t, Profiler*);       \
   template void launch_scalar_times_vec<T>(const Grid&, const T*, const T*, double, T*, hipStream_t, Profiler*); \
   template void launch_gn_final<T>(const Grid&, const T*, const T*, double, T*, hipStream_t, Profiler*);        \
-  template void launch_jacobian_det<T>(const Grid&, const T*, T*, hipStream_t, Profiler*);
+  template void launch_jacobian_det<T>(const Grid&, const T*, T*, hipStream_t, Profiler*);                      \
+  template void launch_newton_pre<T>(const Grid&, const T*, const T*, const T*, const T*, const T*, T*,          \
+                                     hipStream_t, Profiler*);                                                    \
+  template void launch_newton_post<T>(const Grid&, const T*, const T*, const T*, const T*, const T*, const T*,   \
+                                      const T*, const T*, const T*, T*, T*, double, double, double, hipStream_t, \
+                                      Profiler*);                                                                \
+  template void launch_newton_final<T>(const Grid&, const T*, const T*, const T*, double, T*, T*, hipStream_t,    \
+                                       Profiler*);
 
 LDDMM_INST(float)
 LDDMM_INST(double)

@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
 
 
 # lddmm_solve_opts.method
-METHODS = {"gn_v": 0, "gn_l2": 1, "gd": 2}
+METHODS = {"gn_v": 0, "gn_l2": 1, "gd": 2, "newton": 3}
 
 
 class SolveOpts(ctypes.Structure):
@@ -99,6 +99,7 @@ SIGNATURES = {
     "lddmm_linearize": (ctypes.c_int, [_vp, _vp, _vp, _c_double_p]),
     "lddmm_gradient": (ctypes.c_int, [_vp, _vp, _vp, _c_double_p]),
     "lddmm_hessvec": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "lddmm_hessvec_newton": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "lddmm_vjp": (ctypes.c_int, [_vp, _vp, _vp]),
     "lddmm_cg_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "lddmm_gn_solve": (
@@ -305,10 +306,12 @@ class Registration:
         )
         return out, e.value
 
-    def hessvec(self, dv, v0=None, out=None):
+    def hessvec(self, dv, v0=None, out=None, newton=False):
+        """Gauss-Newton Hessian-vector product in V (newton=True: the full Newton Hessian)."""
         out = self.empty_vector() if out is None else self._field(out, 3, "hv")
         v0p = None if v0 is None else _ptr(self._field(v0, 3, "v0"))
-        self._check(self.lib.lddmm_hessvec(self._ctx, v0p, _ptr(self._field(dv, 3, "dv")), _ptr(out)), "hessvec")
+        fn = self.lib.lddmm_hessvec_newton if newton else self.lib.lddmm_hessvec
+        self._check(fn(self._ctx, v0p, _ptr(self._field(dv, 3, "dv")), _ptr(out)), "hessvec")
         return out
 
     def vjp(self, gbar_J1, out=None):
@@ -330,8 +333,8 @@ class Registration:
                  method="gn_v"):
         """Solve from v0 (updated in place); returns a Trace.  method: "gn_v"
         (Gauss-Newton, CG in V), "gn_l2" (Gauss-Newton, PCG in L2 with
-        preconditioner K) or "gd" (gradient descent in V).  gn_iters defaults to
-        10 (50 for "gd")."""
+        preconditioner K), "gd" (gradient descent in V) or "newton" (Newton-Krylov
+        in V on the full Hessian).  gn_iters defaults to 10 (50 for "gd")."""
         self._field(v0, 3, "v0")
         m = METHODS[method]
         if gn_iters is None:

@@ -59,10 +59,11 @@ def test_struct_layouts_match_c(tmp_path):
     src = tmp_path / "sizes.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "lddmm.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %d %d %d\\n\", sizeof(lddmm_params),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %d %d %d %d\\n\", sizeof(lddmm_params),"
         " sizeof(lddmm_solve_opts), sizeof(lddmm_iter_log), sizeof(lddmm_solve_report), offsetof(lddmm_params, alpha),"
         " offsetof(lddmm_params, mem_budget_bytes), offsetof(lddmm_solve_report, E_first),"
-        " offsetof(lddmm_solve_opts, method), offsetof(lddmm_iter_log, g_norm), LDDMM_GN_V, LDDMM_GN_L2, LDDMM_GD_V);"
+        " offsetof(lddmm_solve_opts, method), offsetof(lddmm_iter_log, g_norm), LDDMM_GN_V, LDDMM_GN_L2, LDDMM_GD_V,"
+        " LDDMM_NEWTON_V);"
         " return 0;}\n"
     )
     exe = tmp_path / "sizes"
@@ -84,6 +85,7 @@ def test_struct_layouts_match_c(tmp_path):
         B.METHODS["gn_v"],
         B.METHODS["gn_l2"],
         B.METHODS["gd"],
+        B.METHODS["newton"],
     ]
     assert got == expect
 
@@ -122,6 +124,7 @@ def test_null_arguments_are_rejected(lib):
     assert lib.lddmm_destroy(None) == -1
     assert lib.lddmm_shoot(None, None, None, None, None, None) == -1
     assert lib.lddmm_hessvec(None, None, None, None) == -1
+    assert lib.lddmm_hessvec_newton(None, None, None, None) == -1
     assert lib.lddmm_gn_solve(None, None, None, None, None, 0) == -1
 
 

@@ -259,6 +259,42 @@ def test_row_vectorised_stencils(n, dtype):
         assert E == pytest.approx(lin.E, rel=TOL[dtype]["shoot"])
 
 
+# ------------------------------------------------------------------ full Newton Hessian
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", SMALL)
+def test_hessvec_newton_parity(n, dtype):
+    R, p = make(n, dtype, sigma2=0.05)
+    I0, I1 = images(n)
+    R.set_images(T(I0, dtype), T(I1, dtype))
+    v0 = random_velocity(n, 2002, 1.5, kc=2.0)
+    dv = random_field(n, 5, kc=3.0)
+    hv = R.hessvec(T(dv, dtype), v0=T(v0, dtype), newton=True)
+    lin = O.linearize(v0, I0, I1, p)
+    ho = O.hessvec_newton(dv, lin, p)
+    e = rel(hv, ho)
+    say(f"  newton hessvec rel {e:.3e}; differs from Gauss-Newton by {rel(ho, O.hessvec(dv, lin, p)):.3f}")
+    assert e <= TOL[dtype]["hv"]
+    # the recorded first-order adjoint is reused at the same linearization, bit for bit,
+    # and the Gauss-Newton product is unaffected
+    assert torch.equal(hv, R.hessvec(T(dv, dtype), newton=True))
+    assert rel(R.hessvec(T(dv, dtype)), O.hessvec(dv, lin, p)) <= TOL[dtype]["hv"]
+
+
+def test_hessvec_newton_zero_residual_is_gauss_newton():
+    """I1 = J1(v0) on the device: lambda_1 and the first-order adjoint vanish."""
+    n = (16, 12, 20)
+    R, p = make(n, torch.float64, sigma2=0.05)
+    I0, _ = images(n)
+    v0 = T(random_velocity(n, 2002, 1.5, kc=2.0), torch.float64)
+    dv = T(random_field(n, 5, kc=3.0), torch.float64)
+    R.set_images(T(I0, torch.float64), T(I0, torch.float64))
+    J1 = R.shoot(v0, want=("J1",))["J1"]
+    R.set_images(T(I0, torch.float64), J1)
+    hn = R.hessvec(dv, v0=v0, newton=True)
+    hg = R.hessvec(dv)
+    assert rel(hn, hg.cpu().numpy()) <= 1e-13
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_vjp_parity(dtype):
     n = (16, 12, 20)
@@ -297,11 +333,13 @@ def test_trajectory_policies_are_bitwise_store_all(dtype, every):
         hv = R.hessvec(dv)
         hv2 = R.hessvec(dv)
         vj = R.vjp(gbar)
-        out[ce] = (g, E, hv, hv2, vj, R.get_option("traj.bytes"))
+        hn = R.hessvec(dv, newton=True)
+        out[ce] = (g, E, hv, hv2, vj, R.get_option("traj.bytes"), hn)
     a, b = out[0], out[every]
     assert torch.equal(a[0], b[0]) and a[1] == b[1]
     assert torch.equal(a[2], b[2]) and torch.equal(b[2], b[3])
     assert torch.equal(a[4], b[4])
+    assert torch.equal(a[6], b[6])
     assert b[5] < a[5]
 
 
@@ -369,7 +407,7 @@ def _variant_case():
     return n, p, I0, I1
 
 
-@pytest.mark.parametrize("method", ["gn_l2", "gd"])
+@pytest.mark.parametrize("method", ["gn_l2", "gd", "newton"])
 def test_solver_variants_parity_fp64(method):
     """Gauss-Newton with PCG in L2 (preconditioner K, L2 norms) and gradient descent
     in V against the oracle's literal implementations, iteration by iteration."""
@@ -380,6 +418,9 @@ def test_solver_variants_parity_fp64(method):
     if method == "gn_l2":
         tr = R.gn_solve(v, gn_iters=3, cg_iters=6, method="gn_l2")
         vo, log, lin = O.gn_solve(I0, I1, p, gn_iters=3, cg_iters=6, space="L2")
+    elif method == "newton":
+        tr = R.gn_solve(v, gn_iters=3, cg_iters=6, method="newton")
+        vo, log, lin = O.gn_solve(I0, I1, p, gn_iters=3, cg_iters=6, hessian="newton")
     else:
         tr = R.gn_solve(v, gn_iters=6, method="gd")
         vo, log, lin = O.gd_solve(I0, I1, p, iters=6)
@@ -397,7 +438,7 @@ def test_solver_variants_parity_fp64(method):
         assert tr.report["cg_total"] == 0 and tr.report["hessvecs"] == 0
 
 
-@pytest.mark.parametrize("method", ["gn_v", "gn_l2", "gd"])
+@pytest.mark.parametrize("method", ["gn_v", "gn_l2", "gd", "newton"])
 def test_solver_variants_fp32(method):
     """FP32 fields with FP64 reductions: each method decreases the energy and ends
     within 1e-3 of its FP64 run."""
