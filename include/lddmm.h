@@ -131,7 +131,9 @@ typedef struct {
   int32_t cg_total;    /* sum of CG iterations                                    */
   int32_t hessvecs;    /* Hessian-vector products                                 */
   int32_t gradients;   /* gradients (each = shoot with store + backward sweep)    */
-  int32_t shoots;      /* line-search shoots without store                        */
+  int32_t shoots;      /* line-search trials; each is a linearization (trajectory
+                          store, residual, energy) and an accepted trial is reused
+                          as the next iteration's linearization                    */
   int32_t stop_reason; /* 0 iteration cap, 1 gradient tolerance, 2 line search    */
   double E_first, E_final;
   double mse_rel_final;

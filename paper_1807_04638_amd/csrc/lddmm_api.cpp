@@ -886,8 +886,14 @@ class Engine {
     lddmm_solve_report R{};
     const long long V = 3 * N;
     double g0 = 0, ginf0 = 0;
+    // Each line-search trial is a full linearization (trajectory store, residual,
+    // grad J_1, energy): the store costs the same writes as the scratch buffers
+    // of a plain shoot, and an accepted trial is then already the next
+    // iteration's linearization.
+    bool at_v = false;  // the current linearization is at v
     for (int k = 0; k < op.gn_iters; ++k) {
-      linearize_nocheck(v);
+      if (!at_v) linearize_nocheck(v);
+      at_v = true;
       gradient_core(gv);
       R.gradients++;
       if (k == 0) R.E_first = E;
@@ -923,15 +929,16 @@ class Engine {
         R.hessvecs += its;
         gp = dot(Lg, cx);
       }
+      const double E0 = E, Er0 = Ereg, Ed0 = Edata;
       bool accepted = false;
       int trials = 0;
       for (int h = 0; h <= op.max_halvings; ++h) {
         launch_axpbyz<T>(V, 1.0, v, sign * tau, dir, trial, st, &prof);
-        shoot_core(trial, false, true, Jtmp, nullptr, nullptr, true);
-        const double et = fetch_energy();
+        linearize_nocheck(trial);
+        at_v = false;
         R.shoots++;
         trials++;
-        if (et <= E + op.c1 * tau * gp) {
+        if (E <= E0 + op.c1 * tau * gp) {
           accepted = true;
           break;
         }
@@ -939,10 +946,10 @@ class Engine {
       }
       if (log && k < log_cap) {
         lddmm_iter_log& L = log[k];
-        L.E = E;
-        L.E_reg = Ereg;
-        L.E_data = Edata;
-        L.mse_rel = base_sq > 0 ? 100.0 * Edata * P.sigma2 / base_sq : 0.0;
+        L.E = E0;
+        L.E_reg = Er0;
+        L.E_data = Ed0;
+        L.mse_rel = base_sq > 0 ? 100.0 * Ed0 * P.sigma2 / base_sq : 0.0;
         L.g_norm = gn;
         L.g_inf_rel = ginf0 > 0 ? ginf / ginf0 : 0.0;
         L.eta = eta;
@@ -956,8 +963,9 @@ class Engine {
         break;
       }
       copy(v, trial, V);
+      at_v = true;  // the accepted trial's linearization is the one at the new v
     }
-    linearize_nocheck(v);
+    if (!at_v) linearize_nocheck(v);
     R.E_final = E;
     R.mse_rel_final = base_sq > 0 ? 100.0 * Edata * P.sigma2 / base_sq : 0.0;
     if (rep) *rep = R;
