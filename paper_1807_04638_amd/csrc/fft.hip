@@ -314,9 +314,11 @@ __global__ void __launch_bounds__(NT) k_pencil(cplx<T>* __restrict__ spec, Penci
 // layout and spectrum layout as the generic kernels above; every index is a
 // constant shift and the stage loops unroll).
 // --------------------------------------------------------------------------
-template <typename T, class P, bool INV, bool SEQ_FAST, int COUNT, int ES, int SS, int NT, int I = 0>
+// Stages I .. END-1 of the transform (in DIF order forward, DIT order inverse).
+template <typename T, class P, bool INV, bool SEQ_FAST, int COUNT, int ES, int SS, int NT, int I = 0,
+          int END = P::nf>
 __device__ __forceinline__ void lds_fft_static(cplx<T>* buf, const cplx<T>* tw) {
-  if constexpr (I < P::nf) {
+  if constexpr (I < END) {
     constexpr int st = INV ? P::nf - 1 - I : I;
     constexpr int total = COUNT * (P::length(0) / P::radix(st));
 #pragma unroll
@@ -325,8 +327,54 @@ __device__ __forceinline__ void lds_fft_static(cplx<T>* buf, const cplx<T>* tw) 
       if (total % NT == 0 || b < total) fft_stage_item_static<T, P, st, INV, SEQ_FAST, COUNT, ES, SS>(buf, b, tw);
     }
     __syncthreads();
-    lds_fft_static<T, P, INV, SEQ_FAST, COUNT, ES, SS, NT, I + 1>(buf, tw);
+    lds_fft_static<T, P, INV, SEQ_FAST, COUNT, ES, SS, NT, I + 1, END>(buf, tw);
   }
+}
+
+template <typename T>
+__device__ __forceinline__ T symbol_recip(T x) {
+  return T(1) / x;
+}
+// FP32: the hardware reciprocal (1 ulp; the symbol's argument is >= 1)
+template <>
+__device__ __forceinline__ float symbol_recip<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+
+// The last DIF stage (stride 1, no twiddles), the K/L symbol and the first DIT
+// stage on the same R elements, in registers: between the forward and the
+// inverse transform the spectrum does not go back to LDS.  Sequences are
+// contiguous (SEQ_FAST, sequence stride 1, element stride ES); the calling
+// thread's sequences all have the symbol part k12; ksq0 holds |k0|^2 per slot.
+template <typename T, class P, int COUNT, int ES, int NT>
+__device__ __forceinline__ void fused_symbol_stage(cplx<T>* buf, const T* ksq0, T k12, T alpha, int s, T scale,
+                                                   bool inverse_op) {
+  constexpr int st = P::nf - 1;
+  constexpr int R = P::radix(st);
+  static_assert(P::length(st) == R, "the last stage has stride 1");
+  constexpr int total = COUNT * (P::length(0) / R);
+#pragma unroll
+  for (int b0 = 0; b0 < total; b0 += NT) {
+    const int b = b0 + int(threadIdx.x);
+    if (total % NT != 0 && b >= total) continue;
+    const int u = b / COUNT, sq = b - u * COUNT;
+    const int base = sq + u * R * ES;
+    cplx<T> a[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) a[q] = buf[base + q * ES];
+    Dft<T, R, -1>::run(a);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const T bq = T(1) + alpha * (ksq0[u * R + q] + k12);
+      T pw = bq;
+      for (int i = 1; i < s; ++i) pw *= bq;
+      a[q] = c_scale(a[q], inverse_op ? scale * symbol_recip<T>(pw) : scale * pw);
+    }
+    Dft<T, R, +1>::run(a);
+#pragma unroll
+    for (int q = 0; q < R; ++q) buf[base + q * ES] = a[q];
+  }
+  __syncthreads();
 }
 
 // Row post-processing: item k in 1..H/2 splits the pair (k, H - k); the last
@@ -448,20 +496,44 @@ __global__ void __launch_bounds__(NT) k_plane_fwd_s(const T* __restrict__ in, cp
   }
   __syncthreads();
   rows_r2c_static<T, H, N1, NT, true>(L.A, L.tw2, L.twr, L.slot2);
-  lds_fft_static<T, P1, false, true, H, M, 1, NT>(L.A, L.tw1);
+  lds_fft_static<T, P1, false, true, H, M, 1, NT, 0, P1::nf - 1>(L.A, L.tw1);
+  // Last column stage (stride 1, no twiddles) straight to the spectrum: consecutive
+  // threads take consecutive columns, so each store is contiguous.  The packed
+  // column 0 goes back to LDS for the split below.
+  cplx<T>* dst = spec + ((long long)comp * a.n0 + x0) * (N1 * M);
+  {
+    constexpr int R = P1::radix(P1::nf - 1);
+    constexpr int total = H * (N1 / R);
+#pragma unroll
+    for (int b0 = 0; b0 < total; b0 += NT) {
+      const int b = b0 + int(threadIdx.x);
+      if (total % NT != 0 && b >= total) continue;
+      const int u = b / H, col = b - u * H;
+      const int base = u * R * M + col;
+      cplx<T> v[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[q] = L.A[base + q * M];
+      Dft<T, R, -1>::run(v);
+      if (col == 0) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) L.A[base + q * M] = v[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < R; ++q) dst[base + q * M] = v[q];
+      }
+    }
+  }
+  __syncthreads();
   for (int k = threadIdx.x; k <= N1 / 2; k += NT) {
     const int sk = slot_of<P1>(k), sm = slot_of<P1>(k == 0 ? 0 : N1 - k);
     const cplx<T> zk = L.A[sk * M], zm = L.A[sm * M];
     const cplx<T> lo = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
     const cplx<T> hi = {T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
-    L.A[sk * M] = lo;
-    L.A[sk * M + H] = hi;
-    L.A[sm * M] = c_conj(lo);
-    L.A[sm * M + H] = c_conj(hi);
+    dst[sk * M] = lo;
+    dst[sk * M + H] = hi;
+    dst[sm * M] = c_conj(lo);
+    dst[sm * M + H] = c_conj(hi);
   }
-  __syncthreads();
-  cplx<T>* dst = spec + ((long long)comp * a.n0 + x0) * (N1 * M);
-  for (int idx = threadIdx.x; idx < N1 * M; idx += NT) dst[idx] = L.A[idx];
 }
 
 template <typename T, int H, int N1, int NT>
@@ -470,19 +542,38 @@ __global__ void __launch_bounds__(NT) k_plane_inv_s(const cplx<T>* __restrict__ 
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int M = H + 1;
   const int x0 = blockIdx.x, comp = blockIdx.y;
+  using P1 = typename PlanOf<N1>::type;
   PlaneLds<T> L = carve_static<T, H, N1>(smem, N1, a, true);
   const cplx<T>* src = spec + ((long long)comp * a.n0 + x0) * (N1 * M);
-  for (int idx = threadIdx.x; idx < N1 * M; idx += NT) {
-    const int j1 = idx / M, c = idx - j1 * M;
-    cplx<T> v = src[idx];
-    if (c == 0) {
-      const cplx<T> hi = src[idx + H];
-      v = {v.x - hi.y, v.y + hi.x};  // X[0] + i X[N2/2]
+  // First column stage (the last DIF stage: stride 1, no twiddles) straight from
+  // the spectrum, consecutive threads on consecutive columns; column 0 is packed
+  // with column N2/2 on the way in: X[0] + i X[N2/2].
+  {
+    constexpr int R = P1::radix(P1::nf - 1);
+    constexpr int total = H * (N1 / R);
+#pragma unroll
+    for (int b0 = 0; b0 < total; b0 += NT) {
+      const int b = b0 + int(threadIdx.x);
+      if (total % NT != 0 && b >= total) continue;
+      const int u = b / H, col = b - u * H;
+      const int base = u * R * M + col;
+      cplx<T> v[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[q] = src[base + q * M];
+      if (col == 0) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const cplx<T> hi = src[base + q * M + H];
+          v[q] = {v[q].x - hi.y, v[q].y + hi.x};
+        }
+      }
+      Dft<T, R, +1>::run(v);
+#pragma unroll
+      for (int q = 0; q < R; ++q) L.A[base + q * M] = v[q];
     }
-    L.A[idx] = v;
   }
   __syncthreads();
-  lds_fft_static<T, typename PlanOf<N1>::type, true, true, H, M, 1, NT>(L.A, L.tw1);
+  lds_fft_static<T, P1, true, true, H, M, 1, NT, 1>(L.A, L.tw1);
   rows_c2r_static<T, H, N1, NT, true>(L.A, L.tw2, L.twr, L.slot2);
   cplx<T>* dst = reinterpret_cast<cplx<T>*>(out + comp * a.N + (long long)x0 * (N1 * 2 * H));
 #pragma unroll
@@ -570,20 +661,16 @@ __global__ void __launch_bounds__(NT) k_pencil_s(cplx<T>* __restrict__ spec, Pen
 #pragma unroll
   for (int j = j0; j < N; j += JS) A[j * TB + t] = live ? base[(long long)j * a.es + t] : cplx<T>{T(0), T(0)};
   __syncthreads();
-  if (MODE != 1) lds_fft_static<T, typename PlanOf<N>::type, false, true, TB, TB, 1, NT>(A, tw);
+  using PN = typename PlanOf<N>::type;
   if (MODE == 2) {
-    const T k12 = ksq12[t];
-#pragma unroll
-    for (int j = j0; j < N; j += JS) {
-      const T b = T(1) + a.alpha * (ksq0[j] + k12);
-      T pw = b;
-      for (int i = 1; i < a.s; ++i) pw *= b;
-      const T f = a.op == LDDMM_OP_K ? a.scale / pw : a.scale * pw;
-      A[j * TB + t] = c_scale(A[j * TB + t], f);
-    }
-    __syncthreads();
+    lds_fft_static<T, PN, false, true, TB, TB, 1, NT, 0, PN::nf - 1>(A, tw);
+    fused_symbol_stage<T, PN, TB, TB, NT>(A, ksq0, ksq12[t], a.alpha, a.s, a.scale, a.op == LDDMM_OP_K);
+    lds_fft_static<T, PN, true, true, TB, TB, 1, NT, 1>(A, tw);
+  } else if (MODE == 0) {
+    lds_fft_static<T, PN, false, true, TB, TB, 1, NT>(A, tw);
+  } else {
+    lds_fft_static<T, PN, true, true, TB, TB, 1, NT>(A, tw);
   }
-  if (MODE != 0) lds_fft_static<T, typename PlanOf<N>::type, true, true, TB, TB, 1, NT>(A, tw);
   if (live) {
 #pragma unroll
     for (int j = j0; j < N; j += JS) base[(long long)j * a.es + t] = A[j * TB + t];
