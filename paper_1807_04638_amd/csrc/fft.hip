@@ -383,11 +383,11 @@ __device__ __forceinline__ void fused_symbol_stage(cplx<T>* buf, const T* ksq0, 
 // a row as one complex number X[0] + i X[H] in column 0 (column H is left
 // alone): the columns k2 = 0 and k2 = N2/2 are real sequences along x1, and
 // one complex transform of the packed column does both.
-template <typename T, int H, int COUNT, int NT, bool PACK>
+template <typename T, int H, int COUNT, int NT, bool PACK, int FIRST = 0>
 __device__ __forceinline__ void rows_r2c_static(cplx<T>* A, const cplx<T>* tw2, const cplx<T>* twr, const int* slot2) {
   constexpr int M = H + 1;
   constexpr int KI = H / 2;
-  lds_fft_static<T, typename PlanOf<H>::type, false, true, COUNT, 1, M, NT>(A, tw2);
+  lds_fft_static<T, typename PlanOf<H>::type, false, true, COUNT, 1, M, NT, FIRST>(A, tw2);
   constexpr int total = COUNT * KI;
 #pragma unroll
   for (int i0 = 0; i0 < total; i0 += NT) {
@@ -419,7 +419,7 @@ __device__ __forceinline__ void rows_r2c_static(cplx<T>* A, const cplx<T>* tw2, 
 
 // Inverse of rows_r2c_static (times N2).  PACK: column 0 holds X[0] + i X[H]
 // with X[0], X[H] real.
-template <typename T, int H, int COUNT, int NT, bool PACK>
+template <typename T, int H, int COUNT, int NT, bool PACK, int SKIP_LAST = 0>
 __device__ __forceinline__ void rows_c2r_static(cplx<T>* A, const cplx<T>* tw2, const cplx<T>* twr, const int* slot2) {
   constexpr int M = H + 1;
   constexpr int KI = H / 2;
@@ -450,7 +450,69 @@ __device__ __forceinline__ void rows_c2r_static(cplx<T>* A, const cplx<T>* tw2, 
     }
   }
   __syncthreads();
-  lds_fft_static<T, typename PlanOf<H>::type, true, true, COUNT, 1, M, NT>(A, tw2);
+  using P2 = typename PlanOf<H>::type;
+  lds_fft_static<T, P2, true, true, COUNT, 1, M, NT, 0, P2::nf - SKIP_LAST>(A, tw2);
+}
+
+// First DIF stage of COUNT rows of length H straight from global memory (row s
+// at src + s * H); lanes walk a row's butterflies first, so each load is a
+// contiguous run of H / R elements.  The result lands in LDS rows of stride H + 1.
+template <typename T, int H, int COUNT, int NT>
+__device__ __forceinline__ void rows_first_stage_global(cplx<T>* A, const cplx<T>* __restrict__ src,
+                                                        const cplx<T>* tw) {
+  using P2 = typename PlanOf<H>::type;
+  constexpr int R = P2::radix(0), S = H / R, M = H + 1;
+  constexpr int total = COUNT * S;
+#pragma unroll
+  for (int b0 = 0; b0 < total; b0 += NT) {
+    const int b = b0 + int(threadIdx.x);
+    if (total % NT != 0 && b >= total) continue;
+    const int r = b / S, j = b - r * S;
+    cplx<T> v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = src[r * H + j + q * S];
+    Dft<T, R, -1>::run(v);
+    A[r * M + j] = v[0];
+    if constexpr (S > 1) {
+      cplx<T> w[R];
+      twiddle_powers<T, R>(w, j, 1, tw);
+#pragma unroll
+      for (int q = 1; q < R; ++q) A[r * M + j + q * S] = c_mul(v[q], w[q]);
+    } else {
+#pragma unroll
+      for (int q = 1; q < R; ++q) A[r * M + j + q * S] = v[q];
+    }
+  }
+}
+
+// Last DIT stage of COUNT rows (the inverse of rows_first_stage_global) straight to
+// global memory (row s at dst + s * H).
+template <typename T, int H, int COUNT, int NT>
+__device__ __forceinline__ void rows_last_stage_global(const cplx<T>* A, cplx<T>* __restrict__ dst,
+                                                       const cplx<T>* tw) {
+  using P2 = typename PlanOf<H>::type;
+  constexpr int R = P2::radix(0), S = H / R, M = H + 1;
+  constexpr int total = COUNT * S;
+#pragma unroll
+  for (int b0 = 0; b0 < total; b0 += NT) {
+    const int b = b0 + int(threadIdx.x);
+    if (total % NT != 0 && b >= total) continue;
+    const int r = b / S, j = b - r * S;
+    cplx<T> v[R];
+    v[0] = A[r * M + j];
+    if constexpr (S > 1) {
+      cplx<T> w[R];
+      twiddle_powers<T, R>(w, j, 1, tw);
+#pragma unroll
+      for (int q = 1; q < R; ++q) v[q] = c_mulc(A[r * M + j + q * S], w[q]);
+    } else {
+#pragma unroll
+      for (int q = 1; q < R; ++q) v[q] = A[r * M + j + q * S];
+    }
+    Dft<T, R, +1>::run(v);
+#pragma unroll
+    for (int q = 0; q < R; ++q) dst[r * H + j + q * S] = v[q];
+  }
 }
 
 template <typename T, int H, int N1>
@@ -487,15 +549,11 @@ __global__ void __launch_bounds__(NT) k_plane_fwd_s(const T* __restrict__ in, cp
   const int x0 = blockIdx.x, comp = blockIdx.y;
   PlaneLds<T> L = carve_static<T, H, N1>(smem, N1, a, true);
   const cplx<T>* src = reinterpret_cast<const cplx<T>*>(in + comp * a.N + (long long)x0 * (N1 * 2 * H));
-#pragma unroll
-  for (int i0 = 0; i0 < N1 * H; i0 += NT) {
-    const int idx = i0 + int(threadIdx.x);
-    if ((N1 * H) % NT != 0 && idx >= N1 * H) continue;
-    const int j1 = idx / H;
-    L.A[j1 * M + (idx - j1 * H)] = src[idx];
-  }
+  // first row stage from global memory (twiddles read there too: the LDS copy is
+  // not complete before the barrier below)
+  rows_first_stage_global<T, H, N1, NT>(L.A, src, a.tw2);
   __syncthreads();
-  rows_r2c_static<T, H, N1, NT, true>(L.A, L.tw2, L.twr, L.slot2);
+  rows_r2c_static<T, H, N1, NT, true, 1>(L.A, L.tw2, L.twr, L.slot2);
   lds_fft_static<T, P1, false, true, H, M, 1, NT, 0, P1::nf - 1>(L.A, L.tw1);
   // Last column stage (stride 1, no twiddles) straight to the spectrum: consecutive
   // threads take consecutive columns, so each store is contiguous.  The packed
@@ -574,15 +632,9 @@ __global__ void __launch_bounds__(NT) k_plane_inv_s(const cplx<T>* __restrict__ 
   }
   __syncthreads();
   lds_fft_static<T, P1, true, true, H, M, 1, NT, 1>(L.A, L.tw1);
-  rows_c2r_static<T, H, N1, NT, true>(L.A, L.tw2, L.twr, L.slot2);
+  rows_c2r_static<T, H, N1, NT, true, 1>(L.A, L.tw2, L.twr, L.slot2);
   cplx<T>* dst = reinterpret_cast<cplx<T>*>(out + comp * a.N + (long long)x0 * (N1 * 2 * H));
-#pragma unroll
-  for (int i0 = 0; i0 < N1 * H; i0 += NT) {
-    const int idx = i0 + int(threadIdx.x);
-    if ((N1 * H) % NT != 0 && idx >= N1 * H) continue;
-    const int j1 = idx / H;
-    dst[idx] = L.A[j1 * M + (idx - j1 * H)];
-  }
+  rows_last_stage_global<T, H, N1, NT>(L.A, dst, L.tw2);
 }
 
 template <typename T, int H, int RB, int NT>
