@@ -689,6 +689,8 @@ __global__ void __launch_bounds__(NT) k_rows_inv_s(const cplx<T>* __restrict__ s
 template <typename T, int MODE, int N, int TB, int NT>
 __global__ void __launch_bounds__(NT) k_pencil_s(cplx<T>* __restrict__ spec, PencilArgs<T> a) {
   static_assert(NT % TB == 0, "threads must cover whole rows of the tile");
+  using PN = typename PlanOf<N>::type;
+  static_assert(PN::nf >= 2, "first and last stages are fused with different neighbours");
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = A + N * TB;
@@ -706,26 +708,72 @@ __global__ void __launch_bounds__(NT) k_pencil_s(cplx<T>* __restrict__ spec, Pen
     }
   }
   const int t = int(threadIdx.x) % TB;
-  const int j0 = int(threadIdx.x) / TB;
-  constexpr int JS = NT / TB;
   cplx<T>* base = spec + blockIdx.y * a.outer_stride + q0;
   const bool live = t < cnt;
+  constexpr int R0 = PN::radix(0), S0 = N / R0;  // first DIF / last DIT stage
+  constexpr int total0 = TB * S0;
+  if (MODE != 1) {
+    // first DIF stage straight from the spectrum: consecutive lanes take
+    // consecutive pencils (contiguous); twiddles from global memory (the LDS copy
+    // is complete only after the barrier)
 #pragma unroll
-  for (int j = j0; j < N; j += JS) A[j * TB + t] = live ? base[(long long)j * a.es + t] : cplx<T>{T(0), T(0)};
-  __syncthreads();
-  using PN = typename PlanOf<N>::type;
-  if (MODE == 2) {
-    lds_fft_static<T, PN, false, true, TB, TB, 1, NT, 0, PN::nf - 1>(A, tw);
-    fused_symbol_stage<T, PN, TB, TB, NT>(A, ksq0, ksq12[t], a.alpha, a.s, a.scale, a.op == LDDMM_OP_K);
-    lds_fft_static<T, PN, true, true, TB, TB, 1, NT, 1>(A, tw);
-  } else if (MODE == 0) {
-    lds_fft_static<T, PN, false, true, TB, TB, 1, NT>(A, tw);
+    for (int b0 = 0; b0 < total0; b0 += NT) {
+      const int b = b0 + int(threadIdx.x);
+      if (total0 % NT != 0 && b >= total0) continue;
+      const int j = b / TB;
+      cplx<T> v[R0];
+#pragma unroll
+      for (int q = 0; q < R0; ++q) v[q] = live ? base[(long long)(j + q * S0) * a.es + t] : cplx<T>{T(0), T(0)};
+      Dft<T, R0, -1>::run(v);
+      A[j * TB + t] = v[0];
+      cplx<T> w[R0];
+      twiddle_powers<T, R0>(w, j, 1, a.tw);
+#pragma unroll
+      for (int q = 1; q < R0; ++q) A[(j + q * S0) * TB + t] = c_mul(v[q], w[q]);
+    }
   } else {
-    lds_fft_static<T, PN, true, true, TB, TB, 1, NT>(A, tw);
-  }
-  if (live) {
 #pragma unroll
-    for (int j = j0; j < N; j += JS) base[(long long)j * a.es + t] = A[j * TB + t];
+    for (int b0 = 0; b0 < N * TB; b0 += NT) {
+      const int idx = b0 + int(threadIdx.x), j = idx / TB;
+      if ((N * TB) % NT != 0 && idx >= N * TB) continue;
+      A[idx] = live ? base[(long long)j * a.es + t] : cplx<T>{T(0), T(0)};
+    }
+  }
+  __syncthreads();
+  if (MODE == 2) {
+    lds_fft_static<T, PN, false, true, TB, TB, 1, NT, 1, PN::nf - 1>(A, tw);
+    fused_symbol_stage<T, PN, TB, TB, NT>(A, ksq0, ksq12[t], a.alpha, a.s, a.scale, a.op == LDDMM_OP_K);
+    lds_fft_static<T, PN, true, true, TB, TB, 1, NT, 1, PN::nf - 1>(A, tw);
+  } else if (MODE == 0) {
+    lds_fft_static<T, PN, false, true, TB, TB, 1, NT, 1>(A, tw);
+  } else {
+    lds_fft_static<T, PN, true, true, TB, TB, 1, NT, 0, PN::nf - 1>(A, tw);
+  }
+  if (MODE != 0) {
+    // last DIT stage straight to the spectrum
+#pragma unroll
+    for (int b0 = 0; b0 < total0; b0 += NT) {
+      const int b = b0 + int(threadIdx.x);
+      if (total0 % NT != 0 && b >= total0) continue;
+      const int j = b / TB;
+      cplx<T> v[R0], w[R0];
+      twiddle_powers<T, R0>(w, j, 1, tw);
+      v[0] = A[j * TB + t];
+#pragma unroll
+      for (int q = 1; q < R0; ++q) v[q] = c_mulc(A[(j + q * S0) * TB + t], w[q]);
+      Dft<T, R0, +1>::run(v);
+      if (live) {
+#pragma unroll
+        for (int q = 0; q < R0; ++q) base[(long long)(j + q * S0) * a.es + t] = v[q];
+      }
+    }
+  } else if (live) {
+#pragma unroll
+    for (int b0 = 0; b0 < N * TB; b0 += NT) {
+      const int idx = b0 + int(threadIdx.x), j = idx / TB;
+      if ((N * TB) % NT != 0 && idx >= N * TB) continue;
+      base[(long long)j * a.es + t] = A[idx];
+    }
   }
 }
 
