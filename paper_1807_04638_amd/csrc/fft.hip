@@ -45,6 +45,7 @@ __device__ void lds_fft(cplx<T>* buf, const FftPlan& pl, int count, int es, int 
     const int L = stage_length(pl, st);
     const int total = count * (n / r);
     switch (r) {
+      LDDMM_FFT_STAGE(16)
       LDDMM_FFT_STAGE(8)
       LDDMM_FFT_STAGE(4)
       LDDMM_FFT_STAGE(2)

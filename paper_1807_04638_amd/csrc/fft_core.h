@@ -165,6 +165,44 @@ struct Dft<T, 8, DIR> {
   }
 };
 
+// 16 = 4 x 4: DFT4 over the four stride-4 groups, twiddles W16^(n2 k1), DFT4 over
+// the groups again (Cooley-Tukey; W = exp(DIR 2 pi i / 16)).
+template <typename T, int DIR>
+struct Dft<T, 16, DIR> {
+  // x * (re + DIR im i) for the constant root (re, im)
+  static LD_HD cplx<T> rot(cplx<T> x, T re, T im) {
+    const T si = T(DIR) * im;
+    return {x.x * re - x.y * si, x.x * si + x.y * re};
+  }
+  static LD_HD void run(cplx<T>* a) {
+    const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173), r = T(0.70710678118654752440);
+    cplx<T> y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      cplx<T> g[4] = {a[n2], a[4 + n2], a[8 + n2], a[12 + n2]};
+      Dft<T, 4, DIR>::run(g);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = g[k1];
+    }
+    y[1][1] = rot(y[1][1], c1, s1);    // W^1
+    y[1][2] = cplx<T>{r * (y[1][2].x - T(DIR) * y[1][2].y), r * (y[1][2].y + T(DIR) * y[1][2].x)};  // W^2
+    y[1][3] = rot(y[1][3], s1, c1);    // W^3
+    y[2][1] = cplx<T>{r * (y[2][1].x - T(DIR) * y[2][1].y), r * (y[2][1].y + T(DIR) * y[2][1].x)};  // W^2
+    y[2][2] = c_mul_i<DIR>(y[2][2]);   // W^4
+    y[2][3] = cplx<T>{-r * (y[2][3].x + T(DIR) * y[2][3].y), r * (T(DIR) * y[2][3].x - y[2][3].y)};  // W^6
+    y[3][1] = rot(y[3][1], s1, c1);    // W^3
+    y[3][2] = cplx<T>{-r * (y[3][2].x + T(DIR) * y[3][2].y), r * (T(DIR) * y[3][2].x - y[3][2].y)};  // W^6
+    y[3][3] = rot(y[3][3], -c1, -s1);  // W^9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cplx<T> h[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+      Dft<T, 4, DIR>::run(h);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = h[k2];
+    }
+  }
+};
+
 // Twiddle powers w[q] = W^(j q), q = 1..R-1, from one table read W^j (the
 // rest by complex products in registers: fewer LDS reads, a few ulp of error).
 template <typename T, int R>
@@ -176,6 +214,11 @@ LD_HD void twiddle_powers(cplx<T>* w, int j, int twstep, const cplx<T>* tw) {
   if (R > 5) w[5] = c_mul(w[4], w[1]);
   if (R > 6) w[6] = c_mul(w[4], w[2]);
   if (R > 7) w[7] = c_mul(w[4], w[3]);
+  if (R > 8) {
+    w[8] = c_mul(w[4], w[4]);
+#pragma unroll
+    for (int q = 9; q < R; ++q) w[q] = c_mul(w[8], w[q - 8]);
+  }
 }
 
 // One butterfly of DIF stage with sub-length L = R * stride.  Elements at
@@ -252,8 +295,10 @@ LD_HD int stage_length(const FftPlan& pl, int st) {
   return L;
 }
 
-// Factor n into radices, largest power-of-two radices first (8, then one 4 or 2),
-// then 3, 5, 7.  False if another prime divides n.
+// Factor n into radices, largest power-of-two radices first (8s, then one 4 or
+// 2), then 3, 5, 7; with at least two 8s a trailing 8 x 2 becomes 16 and a
+// trailing 8 x 8 x 4 becomes 16 x 16 (one stage fewer).  False if another prime
+// divides n.
 inline bool make_plan(int n, FftPlan& pl) {
   pl.n = n;
   pl.nf = 0;
@@ -268,7 +313,21 @@ inline bool make_plan(int n, FftPlan& pl) {
     pl.radix[pl.nf++] = r;
     m /= r;
   }
-  return m == 1;
+  if (m != 1) return false;
+  int n8 = 0;
+  while (n8 < pl.nf && pl.radix[n8] == 8) ++n8;
+  const int rest = n8 < pl.nf ? pl.radix[n8] : 1;
+  if (n8 >= 2 && (rest == 2 || rest == 4)) {
+    int out[kMaxFactors], k = 0;
+    const int keep = rest == 2 ? n8 - 1 : n8 - 2;
+    for (int i = 0; i < keep; ++i) out[k++] = 8;
+    out[k++] = 16;
+    if (rest == 4) out[k++] = 16;
+    for (int i = n8 + 1; i < pl.nf; ++i) out[k++] = pl.radix[i];
+    for (int i = 0; i < kMaxFactors; ++i) pl.radix[i] = i < k ? out[i] : 0;
+    pl.nf = k;
+  }
+  return true;
 }
 
 // DIF output slot p holds frequency digit_reverse(p).
@@ -292,15 +351,20 @@ namespace lddmm {
 // Compile-time plans.  For the power-of-two lengths of the common grids the
 // radices, sub-lengths, strides and sequence counts are template constants, so
 // every index of a butterfly is a shift or a constant multiply.  The radix
-// order is the one make_plan produces (8s first, then one 4 or 2), which keeps
-// the digit-reversed slot tables of the runtime plan valid.
+// order is the one make_plan produces, which keeps the digit-reversed slot
+// tables of the runtime plan valid.
 // ---------------------------------------------------------------------------
 template <int N>
 struct Pow2Plan {
   static_assert(N >= 2 && (N & (N - 1)) == 0, "power of two");
-  static constexpr int rest = N >> (3 * (__builtin_ctz(N) / 3));  // 1, 2 or 4
-  static constexpr int nf = __builtin_ctz(N) / 3 + (rest > 1 ? 1 : 0);
-  static constexpr int radix(int i) { return i < __builtin_ctz(N) / 3 ? 8 : rest; }
+  static constexpr int n8 = __builtin_ctz(N) / 3;
+  static constexpr int rest = N >> (3 * n8);  // 1, 2 or 4
+  static constexpr bool g2 = rest == 2 && n8 >= 2;  // ... 8 x 2 -> 16
+  static constexpr bool g4 = rest == 4 && n8 >= 2;  // ... 8 x 8 x 4 -> 16 x 16
+  static constexpr int nf = (g2 || g4) ? n8 : n8 + (rest > 1 ? 1 : 0);
+  static constexpr int radix(int i) {
+    return g2 ? (i < n8 - 1 ? 8 : 16) : g4 ? (i < n8 - 2 ? 8 : 16) : (i < n8 ? 8 : rest);
+  }
   static constexpr int length(int i) { return i == 0 ? N : length(i - 1) / radix(i - 1); }
 };
 

@@ -20,6 +20,7 @@ void run(cplx<double>* buf, const FftPlan& pl, const cplx<double>* tw) {
     const int L = stage_length(pl, st);
     for (int b = 0; b < n / r; ++b) {
       switch (r) {
+        case 16: fft_stage_item<double, 16, INV, false>(buf, b, n, L, 1, 1, n, tw); break;
         case 8: fft_stage_item<double, 8, INV, false>(buf, b, n, L, 1, 1, n, tw); break;
         case 4: fft_stage_item<double, 4, INV, false>(buf, b, n, L, 1, 1, n, tw); break;
         case 2: fft_stage_item<double, 2, INV, false>(buf, b, n, L, 1, 1, n, tw); break;

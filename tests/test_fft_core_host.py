@@ -11,7 +11,7 @@ import pytest
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SIZES = [2, 3, 4, 5, 7, 8, 16, 30, 32, 40, 45, 48, 56, 64, 90, 105, 108, 128, 180, 216, 256]
+SIZES = [2, 3, 4, 5, 7, 8, 16, 30, 32, 40, 45, 48, 56, 64, 90, 105, 108, 128, 180, 216, 256, 384, 512, 1024, 2048]
 
 
 @pytest.fixture(scope="module")
@@ -78,3 +78,12 @@ def test_compile_time_plans_match_runtime_and_numpy(lib, n):
     np.testing.assert_allclose(buf, np.fft.fft(x)[_perm(lib, n)], atol=1e-12 * n)
     lib.fftcore_transform_static(n, p, 1)
     np.testing.assert_allclose(buf / n, x, atol=1e-13 * n)
+
+
+@pytest.mark.parametrize("n, stages", [(16, 2), (32, 2), (64, 2), (128, 2), (256, 2), (384, 3), (512, 3), (1024, 3),
+                                       (2048, 3), (80, 3), (96, 3)])
+def test_radix16_regrouping_stage_counts(lib, n, stages):
+    """With two or more radix-8 stages, a trailing 8 x 2 is one radix-16 stage and a
+    trailing 8 x 8 x 4 two radix-16 stages; short lengths keep their two stages."""
+    x = np.zeros(2 * n)
+    assert lib.fftcore_transform(n, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0) == stages
