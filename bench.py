@@ -73,6 +73,7 @@ def log(*a):
 # Transform launch shape that the autotuner chose; HBM traffic is recorded per shape.
 TUNED_KEYS = (
     "fft.plane_threads",
+    "fft.plane_grid",
     "fft.pencil_threads",
     "fft.pencil_tb",
     "fft.rows_rb",

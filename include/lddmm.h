@@ -231,6 +231,12 @@ int lddmm_profile_read(lddmm_ctx* ctx, const char** names, int64_t* counts, doub
  *   "fft.rows_rb"         1..64             rows per workgroup (split path)
  *   "fft.force_split"     0 | 1             split transform path even where a plane fits
  *   "fft.static"          0 | 1             compile-time kernels for power-of-two lengths
+ *   "fft.plane_grid"      0..65535          0: one (x1, x2) plane per workgroup; G > 0: G
+ *                                           workgroups walk the planes (g, g + G, ...), loading
+ *                                           the next plane while transforming the current one
+ *                                           (compile-time plane kernels; not with 1024 threads
+ *                                           in FP64)
+ *   "fft.plane_walk"      read-only: workgroups of the plane walk in use (0: none)
  *   "fft.fused"           read-only: 1 if the fused plane path is in use
  *   "fft.static_kernels"  read-only: number of passes using compile-time kernels
  *   "traj.policy"         read-only: 0 store-all, 1 checkpoint, 2 recompute
@@ -251,7 +257,8 @@ int lddmm_set_option(lddmm_ctx* ctx, const char* key, int64_t value);
 int lddmm_get_option(lddmm_ctx* ctx, const char* key, int64_t* value);
 
 /* Autotuner: time the transform variants (plane workgroup size, pencil tile,
- * compile-time vs generic kernels) and the stencil widths ("stencil.rowvec",
+ * compile-time vs generic kernels, plane walk over one workgroup per compute
+ * unit or two planes per workgroup) and the stencil widths ("stencil.rowvec",
  * timed on the tangent stage) on this context's grid with HIP events
  * (reps applications each) and keep the fastest; the shape in place when the
  * call starts is kept unless another is more than 3 % faster, so repeated

@@ -129,6 +129,7 @@ __device__ void load_table(cplx<T>* dst, const cplx<T>* src, int n) {
 template <typename T>
 struct PlaneArgs {
   int n0, n1, n2, H, M;
+  int planes;  // (x1, x2) planes of the call: components * n0
   long long N;
   FftPlan p1, p2;
   const cplx<T>* tw1;
@@ -456,22 +457,41 @@ __device__ __forceinline__ void rows_c2r_static(cplx<T>* A, const cplx<T>* tw2, 
 }
 
 // First DIF stage of COUNT rows of length H straight from global memory (row s
-// at src + s * H); lanes walk a row's butterflies first, so each load is a
-// contiguous run of H / R elements.  The result lands in LDS rows of stride H + 1.
+// at src + s * H), in two halves: rows_first_load brings a thread's inputs into
+// registers and rows_first_compute transforms them into LDS rows of stride H + 1,
+// so the loads of the next plane can be in flight while the current one is
+// transformed.  Lanes walk a row's butterflies first, so each load is a
+// contiguous run of H / R elements.
 template <typename T, int H, int COUNT, int NT>
-__device__ __forceinline__ void rows_first_stage_global(cplx<T>* A, const cplx<T>* __restrict__ src,
-                                                        const cplx<T>* tw) {
+struct RowStageIn {
   using P2 = typename PlanOf<H>::type;
-  constexpr int R = P2::radix(0), S = H / R, M = H + 1;
-  constexpr int total = COUNT * S;
+  static constexpr int R = P2::radix(0), S = H / R, total = COUNT * S, iters = (total + NT - 1) / NT;
+  cplx<T> v[iters][R];
+};
+
+template <typename T, int H, int COUNT, int NT>
+__device__ __forceinline__ void rows_first_load(RowStageIn<T, H, COUNT, NT>& in, const cplx<T>* __restrict__ src) {
+  using I = RowStageIn<T, H, COUNT, NT>;
 #pragma unroll
-  for (int b0 = 0; b0 < total; b0 += NT) {
-    const int b = b0 + int(threadIdx.x);
-    if (total % NT != 0 && b >= total) continue;
+  for (int it = 0; it < I::iters; ++it) {
+    const int b = it * NT + int(threadIdx.x);
+    if (I::total % NT != 0 && b >= I::total) continue;
+    const int r = b / I::S, j = b - r * I::S;
+#pragma unroll
+    for (int q = 0; q < I::R; ++q) in.v[it][q] = src[r * H + j + q * I::S];
+  }
+}
+
+template <typename T, int H, int COUNT, int NT>
+__device__ __forceinline__ void rows_first_compute(cplx<T>* A, RowStageIn<T, H, COUNT, NT>& in, const cplx<T>* tw) {
+  using I = RowStageIn<T, H, COUNT, NT>;
+  constexpr int R = I::R, S = I::S, M = H + 1;
+#pragma unroll
+  for (int it = 0; it < I::iters; ++it) {
+    const int b = it * NT + int(threadIdx.x);
+    if (I::total % NT != 0 && b >= I::total) continue;
     const int r = b / S, j = b - r * S;
-    cplx<T> v[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) v[q] = src[r * H + j + q * S];
+    cplx<T>* v = in.v[it];
     Dft<T, R, -1>::run(v);
     A[r * M + j] = v[0];
     if constexpr (S > 1) {
@@ -486,7 +506,7 @@ __device__ __forceinline__ void rows_first_stage_global(cplx<T>* A, const cplx<T
   }
 }
 
-// Last DIT stage of COUNT rows (the inverse of rows_first_stage_global) straight to
+// Last DIT stage of COUNT rows (the inverse of the first row stage) straight to
 // global memory (row s at dst + s * H).
 template <typename T, int H, int COUNT, int NT>
 __device__ __forceinline__ void rows_last_stage_global(const cplx<T>* A, cplx<T>* __restrict__ dst,
@@ -541,101 +561,190 @@ __device__ __forceinline__ PlaneLds<T> carve_static(unsigned char* smem, int row
 // column 0 through the x1 transform (H columns instead of H + 1) and are split
 // apart before the store: with Z the transform of X[0] + i X[N2/2] along x1,
 // the two spectra are (Z[k] + conj Z[-k]) / 2 and (Z[k] - conj Z[-k]) / 2i.
-template <typename T, int H, int N1, int NT>
+//
+// Plane p of a call is component p / n0 at x0 = p % n0.  WALK = false: one
+// plane per workgroup, grid (n0, components).  WALK = true: a 1D grid of G
+// workgroups, workgroup g taking planes g, g + G, g + 2G, ...; the inputs of the
+// next plane's first stage are loaded into registers while the current plane
+// is transformed and stored, so with fewer workgroups than planes the memory
+// phases of consecutive planes overlap inside one workgroup.
+template <typename T, int H, int N1, int NT, bool WALK>
 __global__ void __launch_bounds__(NT) k_plane_fwd_s(const T* __restrict__ in, cplx<T>* __restrict__ spec,
                                                     PlaneArgs<T> a) {
   using P1 = typename PlanOf<N1>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int M = H + 1;
-  const int x0 = blockIdx.x, comp = blockIdx.y;
   PlaneLds<T> L = carve_static<T, H, N1>(smem, N1, a, true);
-  const cplx<T>* src = reinterpret_cast<const cplx<T>*>(in + comp * a.N + (long long)x0 * (N1 * 2 * H));
-  // first row stage from global memory (twiddles read there too: the LDS copy is
-  // not complete before the barrier below)
-  rows_first_stage_global<T, H, N1, NT>(L.A, src, a.tw2);
-  __syncthreads();
-  rows_r2c_static<T, H, N1, NT, true, 1>(L.A, L.tw2, L.twr, L.slot2);
-  lds_fft_static<T, P1, false, true, H, M, 1, NT, 0, P1::nf - 1>(L.A, L.tw1);
-  // Last column stage (stride 1, no twiddles) straight to the spectrum: consecutive
-  // threads take consecutive columns, so each store is contiguous.  The packed
-  // column 0 goes back to LDS for the split below.
-  cplx<T>* dst = spec + ((long long)comp * a.n0 + x0) * (N1 * M);
-  {
-    constexpr int R = P1::radix(P1::nf - 1);
-    constexpr int total = H * (N1 / R);
+  const long long plane_len = (long long)N1 * 2 * H;
+  auto plane_src = [&](int q) {
+    const int comp = q / a.n0, x0 = q - comp * a.n0;
+    return reinterpret_cast<const cplx<T>*>(in + comp * a.N + x0 * plane_len);
+  };
+  int p = WALK ? int(blockIdx.x) : int(blockIdx.y) * a.n0 + int(blockIdx.x);
+  // the first plane's row twiddles come from global memory: the LDS copy is
+  // complete only after the first barrier
+  const cplx<T>* tw_first = a.tw2;
+  RowStageIn<T, H, N1, NT> rin;
+  rows_first_load<T, H, N1, NT>(rin, plane_src(p));
+  for (;;) {
+    rows_first_compute<T, H, N1, NT>(L.A, rin, tw_first);
+    __syncthreads();
+    const int pn = WALK ? p + int(gridDim.x) : a.planes;
+    if (WALK && pn < a.planes) rows_first_load<T, H, N1, NT>(rin, plane_src(pn));
+    rows_r2c_static<T, H, N1, NT, true, 1>(L.A, L.tw2, L.twr, L.slot2);
+    lds_fft_static<T, P1, false, true, H, M, 1, NT, 0, P1::nf - 1>(L.A, L.tw1);
+    // Last column stage (stride 1, no twiddles) straight to the spectrum:
+    // consecutive threads take consecutive columns, so each store is contiguous.
+    // The packed column 0 goes back to LDS for the split below.
+    cplx<T>* dst = spec + (long long)p * (N1 * M);
+    {
+      constexpr int R = P1::radix(P1::nf - 1);
+      constexpr int total = H * (N1 / R);
 #pragma unroll
-    for (int b0 = 0; b0 < total; b0 += NT) {
-      const int b = b0 + int(threadIdx.x);
-      if (total % NT != 0 && b >= total) continue;
-      const int u = b / H, col = b - u * H;
-      const int base = u * R * M + col;
-      cplx<T> v[R];
+      for (int b0 = 0; b0 < total; b0 += NT) {
+        const int b = b0 + int(threadIdx.x);
+        if (total % NT != 0 && b >= total) continue;
+        const int u = b / H, col = b - u * H;
+        const int base = u * R * M + col;
+        cplx<T> v[R];
 #pragma unroll
-      for (int q = 0; q < R; ++q) v[q] = L.A[base + q * M];
-      Dft<T, R, -1>::run(v);
-      if (col == 0) {
+        for (int q = 0; q < R; ++q) v[q] = L.A[base + q * M];
+        Dft<T, R, -1>::run(v);
+        if (col == 0) {
 #pragma unroll
-        for (int q = 0; q < R; ++q) L.A[base + q * M] = v[q];
-      } else {
+          for (int q = 0; q < R; ++q) L.A[base + q * M] = v[q];
+        } else {
 #pragma unroll
-        for (int q = 0; q < R; ++q) dst[base + q * M] = v[q];
+          for (int q = 0; q < R; ++q) dst[base + q * M] = v[q];
+        }
       }
     }
+    __syncthreads();
+    for (int k = threadIdx.x; k <= N1 / 2; k += NT) {
+      const int sk = slot_of<P1>(k), sm = slot_of<P1>(k == 0 ? 0 : N1 - k);
+      const cplx<T> zk = L.A[sk * M], zm = L.A[sm * M];
+      const cplx<T> lo = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+      const cplx<T> hi = {T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
+      dst[sk * M] = lo;
+      dst[sk * M + H] = hi;
+      dst[sm * M] = c_conj(lo);
+      dst[sm * M + H] = c_conj(hi);
+    }
+    if (!WALK || pn >= a.planes) break;
+    __syncthreads();  // column 0 is read above before the next plane overwrites the LDS
+    p = pn;
+    tw_first = L.tw2;
   }
-  __syncthreads();
-  for (int k = threadIdx.x; k <= N1 / 2; k += NT) {
-    const int sk = slot_of<P1>(k), sm = slot_of<P1>(k == 0 ? 0 : N1 - k);
-    const cplx<T> zk = L.A[sk * M], zm = L.A[sm * M];
-    const cplx<T> lo = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
-    const cplx<T> hi = {T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
-    dst[sk * M] = lo;
-    dst[sk * M + H] = hi;
-    dst[sm * M] = c_conj(lo);
-    dst[sm * M + H] = c_conj(hi);
+}
+
+// Inputs of the first inverse column stage (the last DIF stage of the x1 plan:
+// stride 1, no twiddles) in registers; column-0 butterflies also hold column H,
+// which is packed into column 0 as X[0] + i X[N2/2].
+template <typename T, int H, int N1, int NT>
+struct ColStageIn {
+  using P1 = typename PlanOf<N1>::type;
+  static constexpr int R = P1::radix(P1::nf - 1), total = H * (N1 / R), iters = (total + NT - 1) / NT;
+  cplx<T> v[iters][R];
+  cplx<T> hi[iters][R];
+};
+
+template <typename T, int H, int N1, int NT>
+__device__ __forceinline__ void cols_first_load(ColStageIn<T, H, N1, NT>& in, const cplx<T>* __restrict__ src) {
+  using I = ColStageIn<T, H, N1, NT>;
+  constexpr int R = I::R, M = H + 1;
+#pragma unroll
+  for (int it = 0; it < I::iters; ++it) {
+    const int b = it * NT + int(threadIdx.x);
+    if (I::total % NT != 0 && b >= I::total) continue;
+    const int u = b / H, col = b - u * H;
+    const int base = u * R * M + col;
+#pragma unroll
+    for (int q = 0; q < R; ++q) in.v[it][q] = src[base + q * M];
+    if (col == 0) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) in.hi[it][q] = src[base + q * M + H];
+    }
   }
 }
 
 template <typename T, int H, int N1, int NT>
+__device__ __forceinline__ void cols_first_compute(cplx<T>* A, ColStageIn<T, H, N1, NT>& in) {
+  using I = ColStageIn<T, H, N1, NT>;
+  constexpr int R = I::R, M = H + 1;
+#pragma unroll
+  for (int it = 0; it < I::iters; ++it) {
+    const int b = it * NT + int(threadIdx.x);
+    if (I::total % NT != 0 && b >= I::total) continue;
+    const int u = b / H, col = b - u * H;
+    const int base = u * R * M + col;
+    cplx<T>* v = in.v[it];
+    if (col == 0) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[q] = {v[q].x - in.hi[it][q].y, v[q].y + in.hi[it][q].x};
+    }
+    Dft<T, R, +1>::run(v);
+#pragma unroll
+    for (int q = 0; q < R; ++q) A[base + q * M] = v[q];
+  }
+}
+
+template <typename T, int H, int N1, int NT>
+__device__ __forceinline__ void cols_first_stage_global(cplx<T>* A, const cplx<T>* __restrict__ src) {
+  using I = ColStageIn<T, H, N1, NT>;
+  constexpr int R = I::R, M = H + 1;
+#pragma unroll
+  for (int it = 0; it < I::iters; ++it) {
+    const int b = it * NT + int(threadIdx.x);
+    if (I::total % NT != 0 && b >= I::total) continue;
+    const int u = b / H, col = b - u * H;
+    const int base = u * R * M + col;
+    cplx<T> v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = src[base + q * M];
+    if (col == 0) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const cplx<T> hi = src[base + q * M + H];
+        v[q] = {v[q].x - hi.y, v[q].y + hi.x};
+      }
+    }
+    Dft<T, R, +1>::run(v);
+#pragma unroll
+    for (int q = 0; q < R; ++q) A[base + q * M] = v[q];
+  }
+}
+
+template <typename T, int H, int N1, int NT, bool WALK>
 __global__ void __launch_bounds__(NT) k_plane_inv_s(const cplx<T>* __restrict__ spec, T* __restrict__ out,
                                                     PlaneArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int M = H + 1;
-  const int x0 = blockIdx.x, comp = blockIdx.y;
   using P1 = typename PlanOf<N1>::type;
   PlaneLds<T> L = carve_static<T, H, N1>(smem, N1, a, true);
-  const cplx<T>* src = spec + ((long long)comp * a.n0 + x0) * (N1 * M);
-  // First column stage (the last DIF stage: stride 1, no twiddles) straight from
-  // the spectrum, consecutive threads on consecutive columns; column 0 is packed
-  // with column N2/2 on the way in: X[0] + i X[N2/2].
-  {
-    constexpr int R = P1::radix(P1::nf - 1);
-    constexpr int total = H * (N1 / R);
-#pragma unroll
-    for (int b0 = 0; b0 < total; b0 += NT) {
-      const int b = b0 + int(threadIdx.x);
-      if (total % NT != 0 && b >= total) continue;
-      const int u = b / H, col = b - u * H;
-      const int base = u * R * M + col;
-      cplx<T> v[R];
-#pragma unroll
-      for (int q = 0; q < R; ++q) v[q] = src[base + q * M];
-      if (col == 0) {
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-          const cplx<T> hi = src[base + q * M + H];
-          v[q] = {v[q].x - hi.y, v[q].y + hi.x};
-        }
-      }
-      Dft<T, R, +1>::run(v);
-#pragma unroll
-      for (int q = 0; q < R; ++q) L.A[base + q * M] = v[q];
-    }
+  const long long plane_len = (long long)N1 * 2 * H;
+  int p = WALK ? int(blockIdx.x) : int(blockIdx.y) * a.n0 + int(blockIdx.x);
+  // first column stage straight from the spectrum, consecutive threads on
+  // consecutive columns; one plane per workgroup loads and transforms in one go
+  // (fewer live registers), the walk keeps the next plane's inputs in registers
+  ColStageIn<T, H, N1, NT> cin;
+  if (WALK) cols_first_load<T, H, N1, NT>(cin, spec + (long long)p * (N1 * M));
+  for (;;) {
+    if (WALK)
+      cols_first_compute<T, H, N1, NT>(L.A, cin);
+    else
+      cols_first_stage_global<T, H, N1, NT>(L.A, spec + (long long)p * (N1 * M));
+    __syncthreads();
+    const int pn = WALK ? p + int(gridDim.x) : a.planes;
+    if (WALK && pn < a.planes) cols_first_load<T, H, N1, NT>(cin, spec + (long long)pn * (N1 * M));
+    lds_fft_static<T, P1, true, true, H, M, 1, NT, 1>(L.A, L.tw1);
+    rows_c2r_static<T, H, N1, NT, true, 1>(L.A, L.tw2, L.twr, L.slot2);
+    const int comp = p / a.n0, x0 = p - comp * a.n0;
+    cplx<T>* dst = reinterpret_cast<cplx<T>*>(out + comp * a.N + x0 * plane_len);
+    rows_last_stage_global<T, H, N1, NT>(L.A, dst, L.tw2);
+    if (!WALK || pn >= a.planes) break;
+    __syncthreads();  // the last row stage reads the LDS the next plane overwrites
+    p = pn;
   }
-  __syncthreads();
-  lds_fft_static<T, P1, true, true, H, M, 1, NT, 1>(L.A, L.tw1);
-  rows_c2r_static<T, H, N1, NT, true, 1>(L.A, L.tw2, L.twr, L.slot2);
-  cplx<T>* dst = reinterpret_cast<cplx<T>*>(out + comp * a.N + (long long)x0 * (N1 * 2 * H));
-  rows_last_stage_global<T, H, N1, NT>(L.A, dst, L.tw2);
 }
 
 template <typename T, int H, int RB, int NT>
@@ -823,13 +932,13 @@ using PencilFn = void (*)(cplx<T>*, PencilArgs<T>);
 
 enum { KF_PLANE_FWD, KF_PLANE_INV, KF_ROWS_FWD, KF_ROWS_INV, KF_PENCIL0, KF_PENCIL1F, KF_PENCIL1I };
 
-template <typename T, int NT>
+template <typename T, int NT, bool WALK>
 void plane_static(const FftPlan& p2, const FftPlan& p1, void*& f, void*& i) {
   const int H = p2.n, N1 = p1.n;
 #define LDDMM_PLANE_CASE(h, n1)                                                                   \
   if (H == h && N1 == n1 && plan_matches<PlanOf<h>::type>(p2) && plan_matches<PlanOf<n1>::type>(p1)) { \
-    f = (void*)(PlaneFwdFn<T>)k_plane_fwd_s<T, h, n1, NT>;                                        \
-    i = (void*)(PlaneInvFn<T>)k_plane_inv_s<T, h, n1, NT>;                                        \
+    f = (void*)(PlaneFwdFn<T>)k_plane_fwd_s<T, h, n1, NT, WALK>;                                  \
+    i = (void*)(PlaneInvFn<T>)k_plane_inv_s<T, h, n1, NT, WALK>;                                  \
     return;                                                                                       \
   }
   LDDMM_PLANE_CASE(8, 16)
@@ -901,7 +1010,8 @@ void* pencil_generic(int mode, int nt) {
 template <typename T>
 int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& err) {
   if (!allowed_threads(tune.plane_threads) || (tune.pencil_threads != 256 && tune.pencil_threads != 512) ||
-      tune.pencil_tb < 1 || tune.pencil_tb > 128 || tune.rows_rb < 1 || tune.rows_rb > 64) {
+      tune.pencil_tb < 1 || tune.pencil_tb > 128 || tune.rows_rb < 1 || tune.rows_rb > 64 || tune.plane_grid < 0 ||
+      tune.plane_grid > 65535) {
     err = "invalid transform tuning";
     return LDDMM_EINVAL;
   }
@@ -922,13 +1032,22 @@ int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& 
   void* k[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int nstatic = 0;
   const bool use_static = tune.use_static != 0;
+  // plane walk: compile-time plane kernels only
+  const bool walk = tune.plane_grid > 0;
+  int plane_grid = 0;
   if (fused) {
     if (use_static) {
-      if (tune.plane_threads == 512) plane_static<T, 512>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
-      if (tune.plane_threads == 1024) plane_static<T, 1024>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
+      if (tune.plane_threads == 512 && walk) plane_static<T, 512, true>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
+      if (tune.plane_threads == 512 && !walk) plane_static<T, 512, false>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
+      // the walk's extra registers spill with 1024 threads in FP64: not offered there
+      if constexpr (sizeof(T) == 4)
+        if (tune.plane_threads == 1024 && walk) plane_static<T, 1024, true>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
+      if (tune.plane_threads == 1024 && (!walk || sizeof(T) != 4))
+        plane_static<T, 1024, false>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
     }
     if (k[KF_PLANE_FWD]) {
       nstatic++;
+      plane_grid = walk && (sizeof(T) == 4 || tune.plane_threads != 1024) ? tune.plane_grid : 0;
     } else {
       k[KF_PLANE_FWD] = tune.plane_threads == 256    ? (void*)(PlaneFwdFn<T>)k_plane_fwd<T, 256>
                         : tune.plane_threads == 1024 ? (void*)(PlaneFwdFn<T>)k_plane_fwd<T, 1024>
@@ -970,6 +1089,7 @@ int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& 
     }
   sp.tune = tune;
   sp.fused = fused;
+  sp.plane_grid = plane_grid;
   sp.plane_lds = plane_lds;
   sp.pencil0_lds = p0;
   sp.pencil1_lds = p1;
@@ -1067,6 +1187,7 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   pa.n2 = sp.n2;
   pa.H = sp.H;
   pa.M = sp.M;
+  pa.planes = ncomp * sp.n0;
   pa.N = (long long)sp.n0 * sp.n1 * sp.n2;
   pa.p1 = sp.p1;
   pa.p2 = sp.p2;
@@ -1096,7 +1217,9 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   const PencilFn<T> pencil0 = (PencilFn<T>)sp.kfn[KF_PENCIL0];
 
   if (sp.fused) {
-    const dim3 gp(sp.n0, ncomp);
+    // plane walk: at most plane_grid workgroups, never more than there are planes
+    const dim3 gp = sp.plane_grid > 0 ? dim3(unsigned(sp.plane_grid < pa.planes ? sp.plane_grid : pa.planes))
+                                      : dim3(sp.n0, ncomp);
     {
       KernelTimer t(prof, "fft_plane_fwd");
       LDDMM_LAUNCH(t.start, t.stop, ((PlaneFwdFn<T>)sp.kfn[KF_PLANE_FWD]), gp, tu.plane_threads, sp.plane_lds, st, in, sp.spec, pa);

@@ -105,6 +105,7 @@ class Engine {
   std::string* err = nullptr;
   // Hessian-vector product replayed from a captured hipGraph (exec.graph = 1)
   bool use_graph = false;
+  int cus = 0;  // compute units of the device (plane-walk candidates of the autotuner)
   hipGraphExec_t hv_exec = nullptr;
   const T* graph_dv = nullptr;
   T* graph_hv = nullptr;
@@ -203,7 +204,8 @@ class Engine {
     dt = 1.0 / p.nt;
     int dev = 0, lds = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return fail(LDDMM_EHIP, "cannot query the device");
     std::string msg;
     int rc = spectral_init(sp, p.n, size_t(lds), msg);
@@ -696,14 +698,21 @@ class Engine {
     const bool was = prof.enabled;
     prof.enabled = false;
     // operand: any vector work field (contents do not matter for timing)
+    // plane walk candidates: one plane per workgroup, one workgroup per compute
+    // unit, two planes per workgroup (vector fields: 3 n0 planes)
+    const int planes = 3 * g.n0;
+    const int grids[3] = {0, cus < planes ? cus : 0, planes > 1 ? (planes + 1) / 2 : 0};
     for (int pt : {512, 1024})
       for (int tb : {8, 16, 32})
-        for (int stc : {1, 0}) {
+        for (int stc : {1, 0})
+          for (int gi = 0; gi < 3; ++gi) {
+          if (gi > 0 && (grids[gi] == 0 || stc == 0 || grids[gi] == grids[gi - 1])) continue;
           FftTuning t = start;
           t.plane_threads = pt;
           t.pencil_tb = tb;
           t.pencil_threads = 256;
           t.use_static = stc;
+          t.plane_grid = grids[gi];
           std::string msg;
           if (spectral_configure(sp, t, msg) != 0) continue;
           applyK(W, Z);
@@ -719,7 +728,8 @@ class Engine {
             best = t;
           }
           if (t.plane_threads == start.plane_threads && t.pencil_tb == start.pencil_tb &&
-              t.pencil_threads == start.pencil_threads && t.use_static == start.use_static)
+              t.pencil_threads == start.pencil_threads && t.use_static == start.use_static &&
+              t.plane_grid == start.plane_grid)
             start_ms = ms;
         }
     // Keep the starting shape unless another one is clearly faster: variants
@@ -999,6 +1009,8 @@ class Engine {
       t.force_split = value != 0;
     else if (k == "fft.static")
       t.use_static = value != 0;
+    else if (k == "fft.plane_grid")
+      t.plane_grid = int(value);
     else if (k == "exec.graph") {
       if (value != 0 && !st) return fail(LDDMM_EINVAL, "exec.graph needs a non-default stream");
       (void)hipStreamSynchronize(st);
@@ -1041,6 +1053,10 @@ class Engine {
       *value = t.use_static;
     else if (k == "fft.static_kernels")
       *value = sp.static_kernels;
+    else if (k == "fft.plane_grid")
+      *value = t.plane_grid;
+    else if (k == "fft.plane_walk")
+      *value = sp.plane_grid;
     else if (k == "traj.policy")
       *value = traj_policy;
     else if (k == "traj.every")

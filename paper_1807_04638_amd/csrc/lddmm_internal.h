@@ -118,6 +118,7 @@ struct FftTuning {
   int rows_rb = 16;          // rows per workgroup on the split path
   int force_split = 0;       // 1: use the split path even where the plane fits the LDS
   int use_static = 1;        // 1: compile-time kernels where instantiated (power-of-two lengths)
+  int plane_grid = 0;        // 0: one (x1, x2) plane per workgroup; G > 0: G workgroups walk the planes
 };
 
 template <typename T>
@@ -139,6 +140,7 @@ struct SpectralPlan {
   FftTuning tune{};
   void* kfn[7] = {};                         // kernel entry points chosen by spectral_configure
   int static_kernels = 0;                    // how many of them are compile-time variants
+  int plane_grid = 0;                        // workgroups of the plane walk in use (0: one plane each)
   size_t bytes = 0;                          // device memory held
 };
 

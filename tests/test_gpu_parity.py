@@ -97,18 +97,47 @@ def test_operator_parity(n, dtype):
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("n", [(32, 32, 32), (64, 64, 64), (16, 32, 64), (80, 80, 80), (112, 112, 112)])
 @pytest.mark.parametrize("opts", [{"fft.static": 0}, {"fft.static": 1}, {"fft.force_split": 1},
-                                  {"fft.force_split": 1, "fft.static": 0}, {"fft.plane_threads": 256, "fft.pencil_tb": 32}])
+                                  {"fft.force_split": 1, "fft.static": 0}, {"fft.plane_threads": 256, "fft.pencil_tb": 32},
+                                  {"fft.plane_grid": 7}, {"fft.plane_grid": 2, "fft.plane_threads": 512}])
 def test_operator_transform_variants(n, dtype, opts):
     """Every transform path (compile-time / generic kernels, fused / split passes,
-    launch shapes) against the oracle on the same input."""
+    launch shapes, plane walks with a ragged last round) against the oracle on
+    the same input."""
     R, p = make(n, dtype, alpha=0.005)
     for k, v in opts.items():
         R.set_option(k, v)
-    say(f"  options {opts} fused={R.get_option('fft.fused')} static_kernels={R.get_option('fft.static_kernels')}")
+    say(f"  options {opts} fused={R.get_option('fft.fused')} static_kernels={R.get_option('fft.static_kernels')} "
+        f"plane_walk={R.get_option('fft.plane_walk')}")
     f = rounded(random_field(n, 3, kc=max(n) / 3), dtype)
     Lf = O.apply_L(f, p)
     assert rel(R.apply_K(T(f, dtype)), O.apply_K(f, p)) <= TOL[dtype]["op"]
     assert rel(R.apply_L(T(f, dtype)), Lf) <= l_tol(p, f, Lf, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("grid", [256, 192, 100, 1])
+def test_plane_walk_matches_one_plane_per_workgroup(dtype, grid):
+    """128^3: workgroups walking several (x1, x2) planes (next plane's inputs in
+    registers) give the transform of one plane per workgroup, for vector and
+    scalar fields, and stay within the oracle's tolerance."""
+    n = (128, 128, 128)
+    R, p = make(n, dtype, alpha=0.0025)
+    f = rounded(random_field(n, 21, kc=20.0), dtype)
+    ft = T(f, dtype)
+    R.set_option("fft.plane_grid", 0)
+    ref_K, ref_L = R.apply_K(ft).clone(), R.apply_L(ft).clone()
+    ref_s = R.apply_K(ft[1].contiguous()).clone()
+    threads = 1024 if dtype == torch.float32 else 512
+    R.set_option("fft.plane_threads", threads)
+    R.set_option("fft.plane_grid", grid)
+    walk = R.get_option("fft.plane_walk")
+    say(f"  plane_grid {grid} threads {threads}: walk {walk}")
+    assert walk == grid
+    for got, ref in ((R.apply_K(ft), ref_K), (R.apply_L(ft), ref_L), (R.apply_K(ft[1].contiguous()), ref_s)):
+        e = rel(got, ref.cpu())
+        say(f"  walk vs one plane per workgroup: rel {e:.2e}")
+        assert e <= (1e-6 if dtype == torch.float32 else 1e-14)
+    assert rel(R.apply_K(ft), O.apply_K(f, p)) <= TOL[dtype]["op"]
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
