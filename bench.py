@@ -80,6 +80,7 @@ TUNED_KEYS = (
     "fft.fused",
     "fft.static_kernels",
     "stencil.rowvec",
+    "stencil.pair_rows",
 )
 KERNEL_SOURCES = {
     "fft": ("paper_1807_04638_amd/csrc/fft.hip", "paper_1807_04638_amd/csrc/fft_core.h"),

@@ -251,6 +251,9 @@ int lddmm_profile_read(lddmm_ctx* ctx, const char** names, int64_t* counts, doub
  *                                           values need N2 / value = 32 or 64.  Default:
  *                                           the smallest valid width in FP64, 0 in FP32;
  *                                           same operators, summed in another order
+ *   "stencil.pair_rows"   0 | 1             with N2 / rowvec = 32 and N1 even a wave holds two
+ *                                           x1 rows; 1: the row each half needs from the other
+ *                                           comes by a lane swap instead of a load.  Default 1
  * LDDMM_EINVAL for an unknown key or a value out of range, LDDMM_EUNSUPPORTED if
  * the tiles would not fit the LDS of a workgroup (the previous setting stays). */
 int lddmm_set_option(lddmm_ctx* ctx, const char* key, int64_t value);
@@ -259,7 +262,7 @@ int lddmm_get_option(lddmm_ctx* ctx, const char* key, int64_t* value);
 /* Autotuner: time the transform variants (plane workgroup size, pencil tile,
  * compile-time vs generic kernels, plane walk over one workgroup per compute
  * unit or two planes per workgroup) and the stencil widths ("stencil.rowvec",
- * timed on the tangent stage) on this context's grid with HIP events
+ * "stencil.pair_rows", timed on the tangent stage) on this context's grid with HIP events
  * (reps applications each) and keep the fastest; the shape in place when the
  * call starts is kept unless another is more than 3 % faster, so repeated
  * calls settle on the same shape.  *tried = variants timed,

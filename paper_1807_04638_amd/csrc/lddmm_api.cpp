@@ -741,12 +741,15 @@ class Engine {
     // Stencil kernels: one voxel per thread or VW voxels per lane, timed on the
     // tangent stage (the largest of them); work fields only, contents irrelevant.
     {
-      const int start_vw = g.rowvec;
-      int best_vw = start_vw;
+      const int start_vw = g.rowvec, start_pair = g.pair_rows;
+      int best_vw = start_vw, best_pair = start_pair;
       float best_t = -1.f, start_t = -1.f;
-      for (int vw : {0, 1, 2, 4}) {
+      for (int vp : {0, 1, 2, 4, 0x11, 0x12, 0x14}) {
+        const int vw = vp & 0xf, pr = vp >> 4;
         if (vw != 0 && !row_vector_valid(g.n2, vw)) continue;
+        if (pr && (vw == 0 || g.n2 / vw != 32 || g.n1 % 2 != 0)) continue;  // pairing needs 32-lane rows
         g.rowvec = vw;
+        g.pair_rows = pr;
         launch_tangent_stage<T>(g, X, Mu, W, Xs, Mus, X, Mu, Us, Whs, dt, 0.0, 1.0, st, nullptr);
         (void)hipEventRecord(a, st);
         for (int r = 0; r < reps; ++r)
@@ -759,10 +762,13 @@ class Engine {
         if (best_t < 0.f || ms < best_t) {
           best_t = ms;
           best_vw = vw;
+          best_pair = pr;
         }
-        if (vw == start_vw) start_t = ms;
+        if (vw == start_vw && (pr == start_pair || vw == 0 || g.n2 / vw != 32)) start_t = ms;
       }
-      g.rowvec = (start_t > 0.f && start_t <= 1.03f * best_t) ? start_vw : best_vw;
+      const bool keep = start_t > 0.f && start_t <= 1.03f * best_t;
+      g.rowvec = keep ? start_vw : best_vw;
+      g.pair_rows = keep ? start_pair : best_pair;
     }
     prof.enabled = was;
     (void)hipEventDestroy(a);
@@ -1024,6 +1030,12 @@ class Engine {
       g.rowvec = int(value);
       drop_graph();
       return 0;
+    } else if (k == "stencil.pair_rows") {
+      if (value != 0 && value != 1) return fail(LDDMM_EINVAL, "stencil.pair_rows: 0 or 1");
+      (void)hipStreamSynchronize(st);
+      g.pair_rows = int(value);
+      drop_graph();
+      return 0;
     } else
       return fail(LDDMM_EINVAL, "unknown or read-only option " + k);
     if (value < 0 || value > (1 << 20)) return fail(LDDMM_EINVAL, "option value out of range");
@@ -1055,6 +1067,8 @@ class Engine {
       *value = sp.static_kernels;
     else if (k == "fft.plane_grid")
       *value = t.plane_grid;
+    else if (k == "stencil.pair_rows")
+      *value = g.pair_rows;
     else if (k == "fft.plane_walk")
       *value = sp.plane_grid;
     else if (k == "traj.policy")

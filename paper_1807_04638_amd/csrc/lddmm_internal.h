@@ -66,6 +66,7 @@ struct Grid {
   long long N;           // n0 * n1 * n2 (3 N < 2^31 is checked at creation)
   double h0, h1, h2;     // 2 pi / N_d
   int rowvec = 0;        // voxels per lane of the row-vectorised stencil kernels (0: one per thread)
+  int pair_rows = 1;     // row-vectorised stencils: x1 rows shared by the two halves of a wave
 };
 
 // True if the row-vectorised stencil kernels take vw voxels per lane on rows of

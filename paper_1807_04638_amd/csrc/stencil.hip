@@ -42,6 +42,7 @@ struct Geo {
   int N;  // voxels per component
   T inv2h[3];
   FieldTiling ft;
+  int pair;  // launch the PAIR row-vectorised kernels: a wave holds two x1 rows (see VNbr)
 };
 
 template <typename T>
@@ -55,6 +56,7 @@ Geo<T> make_geo(const Grid& g) {
   o.inv2h[1] = T(0.5 / g.h1);
   o.inv2h[2] = T(0.5 / g.h2);
   o.ft = make_field_tiling(g);
+  o.pair = 0;
   return o;
 }
 
@@ -437,11 +439,18 @@ __global__ void __launch_bounds__(256) k_jacobian_det(Geo<T> g, const T* __restr
 // third of their load instructions, which is what limits those kernels (the
 // texture address and data units, not HBM, saturate first).
 // ---------------------------------------------------------------------------
+// Row-vectorised neighbourhoods.  In the PAIR kernels the 64 lanes of a wave hold
+// two adjacent x1 rows: lanes 0-31 row i1 (i1 even), lanes 32-63 row i1 + 1.
+// The row each half needs from the other comes by a lane swap, and only the
+// outer row (i1 - 1 below, i1 + 2 above) is loaded: the x1 pair of a lane is
+// then (other half's row, outer row), which is (+x1, -x1) in the lower half and
+// (-x1, +x1) in the upper half, so the upper half takes -1/2h as its x1 factor.
 template <int VW>
 struct VNbr {
   int o;            // first voxel of the lane
   int ox[4];        // the same voxel at +x0, -x0, +x1, -x1
   int left, right;  // lanes holding the x2 neighbours
+  bool upper;       // lanes 32-63 of a paired wave
 };
 
 template <typename T, int VW>
@@ -462,7 +471,15 @@ __device__ __forceinline__ bool vvoxel(const Geo<T>& g, int RW, VNbr<VW>& nb) {
   const int base = lane & ~(RW - 1);
   nb.left = base | ((lane - 1) & (RW - 1));
   nb.right = base | ((lane + 1) & (RW - 1));
+  nb.upper = lane >= 32;
   return true;
+}
+
+// Factor 1/2h of direction e for the lane (sign-flipped for x1 in the upper
+// half of a paired wave).
+template <typename T, int VW, bool PAIR>
+__device__ __forceinline__ T vinv2h(const Geo<T>& g, const VNbr<VW>& nb, int e) {
+  return (PAIR && e == 1 && nb.upper) ? -g.inv2h[1] : g.inv2h[e];
 }
 
 template <typename T, int VW>
@@ -523,10 +540,25 @@ __device__ __forceinline__ void vpair_shift(VPair<T, VW>& s, const T c0[3][VW], 
   }
 }
 
+// x1 pair of a paired wave: (other half's row by lane swap, outer row loaded).
 template <typename T, int VW>
+__device__ __forceinline__ void vpair_swap(VPair<T, VW>& s, const T* __restrict__ f, const T c0[3][VW],
+                                           const VNbr<VW>& nb, int N) {
+  const int outer = nb.upper ? nb.ox[2] : nb.ox[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    vld<T, VW>(s.m[c], f + c * N + outer);
+#pragma unroll
+    for (int k = 0; k < VW; ++k) s.p[c][k] = __shfl_xor(c0[c][k], 32);
+  }
+}
+
+template <typename T, int VW, bool PAIR>
 __device__ __forceinline__ void vpair(VPair<T, VW>& s, const T* __restrict__ f, const T c0[3][VW],
                                       const VNbr<VW>& nb, int e, int N) {
-  if (e < 2)
+  if (PAIR && e == 1)
+    vpair_swap<T, VW>(s, f, c0, nb, N);
+  else if (e < 2)
     vpair_load<T, VW>(s, f, nb, e, N);
   else
     vpair_shift<T, VW>(s, c0, nb);
@@ -569,7 +601,7 @@ __device__ __forceinline__ void vheun(T out[3][VW], const T* y0, T a0, int o, in
   }
 }
 
-template <typename T, int VW>
+template <typename T, int VW, bool PAIR>
 __global__ void __launch_bounds__(256)
     k_epdiff_stage_v(Geo<T> g, int RW, const T* __restrict__ v, const T* __restrict__ mu, const T* mu0,
                      T* mu_out, T dt, T a0, T a1) {
@@ -581,9 +613,9 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     VPair<T, VW> Vp, Mp;
-    vpair<T, VW>(Vp, v, vc, nb, e, g.N);
-    vpair<T, VW>(Mp, mu, m, nb, e, g.N);
-    vadstar_dir<T, VW>(a, Vp, Mp, m, e, g.inv2h[e]);
+    vpair<T, VW, PAIR>(Vp, v, vc, nb, e, g.N);
+    vpair<T, VW, PAIR>(Mp, mu, m, nb, e, g.N);
+    vadstar_dir<T, VW>(a, Vp, Mp, m, e, vinv2h<T, VW, PAIR>(g, nb, e));
   }
   T out[3][VW];
 #pragma unroll
@@ -594,7 +626,7 @@ __global__ void __launch_bounds__(256)
   vstore3<T, VW>(mu_out, out, nb.o, g.N);
 }
 
-template <typename T, int VW>
+template <typename T, int VW, bool PAIR>
 __global__ void __launch_bounds__(256)
     k_tangent_stage_v(Geo<T> g, int RW, const T* __restrict__ X, const T* __restrict__ dmu, const T* __restrict__ W,
                       const T* __restrict__ v, const T* __restrict__ mu, const T* X0, const T* dmu0, T* X_out,
@@ -609,11 +641,11 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     VPair<T, VW> Vp, Xp, Dp;
-    vpair<T, VW>(Vp, v, vc, nb, e, g.N);
-    vpair<T, VW>(Xp, X, x, nb, e, g.N);
-    vpair<T, VW>(Dp, dmu, dm, nb, e, g.N);
-    vad_dir<T, VW>(aX, Vp, Xp, vc, x, e, g.inv2h[e]);   // ad_v X
-    vadstar_dir<T, VW>(t2, Vp, Dp, dm, e, g.inv2h[e]);  // ad*_v dmu
+    vpair<T, VW, PAIR>(Vp, v, vc, nb, e, g.N);
+    vpair<T, VW, PAIR>(Xp, X, x, nb, e, g.N);
+    vpair<T, VW, PAIR>(Dp, dmu, dm, nb, e, g.N);
+    vad_dir<T, VW>(aX, Vp, Xp, vc, x, e, vinv2h<T, VW, PAIR>(g, nb, e));   // ad_v X
+    vadstar_dir<T, VW>(t2, Vp, Dp, dm, e, vinv2h<T, VW, PAIR>(g, nb, e));  // ad*_v dmu
   }
   T w[3][VW], m[3][VW];
   vload3<T, VW>(w, W, nb.o, g.N);
@@ -621,9 +653,9 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     VPair<T, VW> Wp, Mp;
-    vpair<T, VW>(Wp, W, w, nb, e, g.N);
-    vpair<T, VW>(Mp, mu, m, nb, e, g.N);
-    vadstar_dir<T, VW>(t1, Wp, Mp, m, e, g.inv2h[e]);  // ad*_W mu
+    vpair<T, VW, PAIR>(Wp, W, w, nb, e, g.N);
+    vpair<T, VW, PAIR>(Mp, mu, m, nb, e, g.N);
+    vadstar_dir<T, VW>(t1, Wp, Mp, m, e, vinv2h<T, VW, PAIR>(g, nb, e));  // ad*_W mu
   }
   T xo[3][VW], mo[3][VW];
 #pragma unroll
@@ -639,7 +671,7 @@ __global__ void __launch_bounds__(256)
   vstore3<T, VW>(dmu_out, mo, nb.o, g.N);
 }
 
-template <typename T, int VW>
+template <typename T, int VW, bool PAIR>
 __global__ void __launch_bounds__(256)
     k_adjoint_pre_v(Geo<T> g, int RW, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ mu,
                     T* __restrict__ Z) {
@@ -651,9 +683,9 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     VPair<T, VW> Wp, Mp;
-    vpair<T, VW>(Wp, w, wc, nb, e, g.N);
-    vpair<T, VW>(Mp, mu, m, nb, e, g.N);
-    vadstar_dir<T, VW>(a, Wp, Mp, m, e, g.inv2h[e]);
+    vpair<T, VW, PAIR>(Wp, w, wc, nb, e, g.N);
+    vpair<T, VW, PAIR>(Mp, mu, m, nb, e, g.N);
+    vadstar_dir<T, VW>(a, Wp, Mp, m, e, vinv2h<T, VW, PAIR>(g, nb, e));
   }
   T u[3][VW];
   vload3<T, VW>(u, U, nb.o, g.N);
@@ -664,7 +696,7 @@ __global__ void __launch_bounds__(256)
   vstore3<T, VW>(Z, a, nb.o, g.N);
 }
 
-template <typename T, int VW>
+template <typename T, int VW, bool PAIR>
 __global__ void __launch_bounds__(256)
     k_adjoint_post_v(Geo<T> g, int RW, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ KZ,
                      const T* __restrict__ v, const T* U0, const T* w0, T* U_out, T* w_out, T dt, T a0, T a1) {
@@ -678,11 +710,11 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     VPair<T, VW> Vp, Up, Wp;
-    vpair<T, VW>(Vp, v, vc, nb, e, g.N);
-    vpair<T, VW>(Up, U, u, nb, e, g.N);
-    vpair<T, VW>(Wp, w, wc, nb, e, g.N);
-    vadstar_dir<T, VW>(aU, Vp, Up, u, e, g.inv2h[e]);  // ad*_v U
-    vad_dir<T, VW>(aw, Vp, Wp, vc, wc, e, g.inv2h[e]);  // ad_v w
+    vpair<T, VW, PAIR>(Vp, v, vc, nb, e, g.N);
+    vpair<T, VW, PAIR>(Up, U, u, nb, e, g.N);
+    vpair<T, VW, PAIR>(Wp, w, wc, nb, e, g.N);
+    vadstar_dir<T, VW>(aU, Vp, Up, u, e, vinv2h<T, VW, PAIR>(g, nb, e));  // ad*_v U
+    vad_dir<T, VW>(aw, Vp, Wp, vc, wc, e, vinv2h<T, VW, PAIR>(g, nb, e));  // ad_v w
   }
   T kz[3][VW];
   vload3<T, VW>(kz, KZ, nb.o, g.N);
@@ -709,20 +741,31 @@ Geo<T> make_vgeo(const Grid& g, int VW) {
   Grid gv = g;
   gv.n2 = g.n2 / VW;
   o.ft = make_field_tiling(gv);
+  // 32 lanes per row: a wave holds rows (i1, i1 + 1) with i1 even; with N1 even
+  // both rows of every wave exist
+  o.pair = (g.n2 / VW == 32 && o.ft.BX == 32 && o.ft.BY % 2 == 0 && g.n1 % 2 == 0 && g.pair_rows) ? 1 : 0;
   return o;
 }
 
-#define LDDMM_ROWVEC(kern, ...)                                                                              \
-  do {                                                                                                       \
-    const Geo<T> gv = make_vgeo<T>(g, VW);                                                                   \
-    const dim3 grid_(gv.ft.blocks), block_(gv.ft.BX, gv.ft.BY);                                              \
-    const int RW = g.n2 / VW;                                                                                \
-    if (VW == 1)                                                                                             \
-      LDDMM_LAUNCH(t.start, t.stop, kern<T LDDMM_COMMA 1>, grid_, block_, 0, st, gv, RW, __VA_ARGS__);       \
-    else if (VW == 2)                                                                                        \
-      LDDMM_LAUNCH(t.start, t.stop, kern<T LDDMM_COMMA 2>, grid_, block_, 0, st, gv, RW, __VA_ARGS__);       \
-    else                                                                                                     \
-      LDDMM_LAUNCH(t.start, t.stop, kern<T LDDMM_COMMA 4>, grid_, block_, 0, st, gv, RW, __VA_ARGS__);       \
+#define LDDMM_ROWVEC_AT(kern, vw, pr, ...) \
+  LDDMM_LAUNCH(t.start, t.stop, kern<T LDDMM_COMMA vw LDDMM_COMMA pr>, grid_, block_, 0, st, gv, RW, __VA_ARGS__)
+#define LDDMM_ROWVEC(kern, ...)                                        \
+  do {                                                                 \
+    const Geo<T> gv = make_vgeo<T>(g, VW);                             \
+    const dim3 grid_(gv.ft.blocks), block_(gv.ft.BX, gv.ft.BY);        \
+    const int RW = g.n2 / VW;                                          \
+    if (VW == 1 && gv.pair)                                            \
+      LDDMM_ROWVEC_AT(kern, 1, true, __VA_ARGS__);                     \
+    else if (VW == 1)                                                  \
+      LDDMM_ROWVEC_AT(kern, 1, false, __VA_ARGS__);                    \
+    else if (VW == 2 && gv.pair)                                       \
+      LDDMM_ROWVEC_AT(kern, 2, true, __VA_ARGS__);                     \
+    else if (VW == 2)                                                  \
+      LDDMM_ROWVEC_AT(kern, 2, false, __VA_ARGS__);                    \
+    else if (gv.pair)                                                  \
+      LDDMM_ROWVEC_AT(kern, 4, true, __VA_ARGS__);                     \
+    else                                                               \
+      LDDMM_ROWVEC_AT(kern, 4, false, __VA_ARGS__);                    \
   } while (0)
 
 dim3 ft_grid(const Grid& g) { return dim3(make_field_tiling(g).blocks); }

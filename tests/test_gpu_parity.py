@@ -259,12 +259,14 @@ def test_hessvec_parity(n, dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("n", [(10, 6, 64), (8, 12, 128), (6, 8, 256)])
+@pytest.mark.parametrize("n", [(10, 6, 64), (8, 12, 128), (6, 8, 256), (6, 7, 128)])
 def test_row_vectorised_stencils(n, dtype):
     """Every stencil width a row of N2 = 64, 128, 256 allows: one voxel per
     thread (stencil.rowvec = 0) and VW = 1, 2, 4 voxels per lane with x2
-    neighbours across lanes (N2 / VW = 32 or 64).  Each against the oracle on
-    shooting, the gradient and the Hessian-vector product."""
+    neighbours across lanes (N2 / VW = 32 or 64); with 32-lane rows both with
+    and without the x1 row shared by the two halves of a wave (N1 odd: the
+    pairing stays off).  Each against the oracle on shooting, the gradient and
+    the Hessian-vector product."""
     I0, I1 = images(n)
     v0 = random_velocity(n, 2003, 0.5, kc=2.0)  # coarse x0/x1 axes: keep the flow well resolved
     dv = random_field(n, 6, kc=3.0)
@@ -273,16 +275,18 @@ def test_row_vectorised_stencils(n, dtype):
     go, lin = O.gradient(v0, I0, I1, p)
     ho = O.hessvec(dv, lin, p)
     widths = [0] + [vw for vw in (1, 2, 4) if n[2] % vw == 0 and n[2] // vw in (32, 64)]
-    for rowvec in widths:
+    shapes = [(vw, pr) for vw in widths for pr in ((0, 1) if vw and n[2] // vw == 32 else (1,))]
+    for rowvec, pair in shapes:
         R, _ = make(n, dtype, sigma2=0.05)
         R.set_option("stencil.rowvec", rowvec)
-        assert R.get_option("stencil.rowvec") == rowvec
+        R.set_option("stencil.pair_rows", pair)
+        assert R.get_option("stencil.rowvec") == rowvec and R.get_option("stencil.pair_rows") == pair
         R.set_images(T(I0, dtype), T(I1, dtype))
         out = R.shoot(T(v0, dtype))
         g, E = R.gradient(T(v0, dtype))
         hv = R.hessvec(T(dv, dtype))
         errs = dict(v1=rel(out["v1"], tr.v[-1]), J1=rel(out["J1"], tr.J1), grad=rel(g, go), hv=rel(hv, ho))
-        say(f"  rowvec={rowvec}", errs)
+        say(f"  rowvec={rowvec} pair_rows={pair}", errs)
         assert errs["v1"] <= TOL[dtype]["shoot"] and errs["J1"] <= TOL[dtype]["shoot"]
         assert errs["grad"] <= TOL[dtype]["grad"] and errs["hv"] <= TOL[dtype]["hv"]
         assert E == pytest.approx(lin.E, rel=TOL[dtype]["shoot"])
@@ -545,6 +549,14 @@ def test_error_paths():
             R.set_option("stencil.rowvec", width)
         assert e.value.status == -1
     assert R.get_option("stencil.rowvec") == 0
+    for bad in (-1, 2):
+        with pytest.raises(LddmmError) as e:
+            R.set_option("stencil.pair_rows", bad)
+        assert e.value.status == -1
+    for bad in (-1, 70000):
+        with pytest.raises(LddmmError) as e:
+            R.set_option("fft.plane_grid", bad)
+        assert e.value.status == -1
 
 
 # ------------------------------------------------------------------ full size (128^3, nt = 10)
