@@ -42,12 +42,18 @@ __device__ __forceinline__ int wrap(int j, int n) {
   return j < 0 ? j + n : j;
 }
 
-// Corner offsets and weights of the trilinear stencil at voxel (i0, i1, i2)
-// displaced by (d0, d1, d2) voxels.
+// Corners and weights of the trilinear stencil at voxel (i0, i1, i2) displaced by
+// (d0, d1, d2) voxels.  The two x2 corners of each (x0, x1) pair are adjacent in
+// memory unless the lower one is the last of its row (periodic wrap), so a pair
+// is one two-element load: o[k] is the lower corner of pair k = 2 c0 + c1, wrap
+// says the upper corner is the first of the row (o[k] - (N2 - 1)).
 template <typename T>
 struct Tri {
-  int o[8];
-  T w[8];
+  int o[4];
+  int n2m1;
+  bool wrap;
+  T w01[4];   // (x0, x1) weight of pair k
+  T t2;       // x2 fraction: weights 1 - t2, t2 of the lower and upper corner
 };
 
 template <typename T>
@@ -63,32 +69,57 @@ __device__ __forceinline__ Tri<T> tri_setup(const SlGeo<T>& g, int i0, int i1, i
   const int a0 = wrap(i0 + int(f0), g.n0), a1 = wrap(i1 + int(f1), g.n1), a2 = wrap(i2 + int(f2), g.n2);
   const int b0 = a0 + 1 == g.n0 ? 0 : a0 + 1;
   const int b1 = a1 + 1 == g.n1 ? 0 : a1 + 1;
-  const int b2 = a2 + 1 == g.n2 ? 0 : a2 + 1;
   const int s0 = g.n1 * g.n2;
   const int r0[2] = {a0 * s0, b0 * s0};
   const int r1[2] = {a1 * g.n2, b1 * g.n2};
-  const int r2[2] = {a2, b2};
-  const T w0[2] = {T(1) - t0, t0}, w1[2] = {T(1) - t1, t1}, w2[2] = {T(1) - t2, t2};
+  const T w0[2] = {T(1) - t0, t0}, w1[2] = {T(1) - t1, t1};
   Tri<T> tr;
   // offsets fit in int: 3 N < 2^31
 #pragma unroll
   for (int c0 = 0; c0 < 2; ++c0)
 #pragma unroll
-    for (int c1 = 0; c1 < 2; ++c1)
-#pragma unroll
-      for (int c2 = 0; c2 < 2; ++c2) {
-        const int k = c0 * 4 + c1 * 2 + c2;
-        tr.o[k] = r0[c0] + r1[c1] + r2[c2];
-        tr.w[k] = w0[c0] * w1[c1] * w2[c2];
-      }
+    for (int c1 = 0; c1 < 2; ++c1) {
+      const int k = c0 * 2 + c1;
+      tr.o[k] = r0[c0] + r1[c1] + a2;
+      tr.w01[k] = w0[c0] * w1[c1];
+    }
+  tr.n2m1 = g.n2 - 1;
+  tr.wrap = a2 == g.n2 - 1;
+  tr.t2 = t2;
   return tr;
 }
 
+// Two consecutive elements f[o], f[o + 1] as one 8-byte load (4-byte aligned:
+// the hardware takes element-aligned vector loads from global memory).
+__device__ __forceinline__ void load_pair(const float* __restrict__ f, int o, float& lo, float& hi) {
+  typedef float vec2 __attribute__((ext_vector_type(2)));
+  vec2 v;
+  __builtin_memcpy(&v, f + o, sizeof(vec2));
+  lo = v.x;
+  hi = v.y;
+}
+
+// FP32 reads each x2 pair with one load (half the gathers); FP64 reads the
+// corners one by one (its 16-byte pairs measured slower than two loads).
 template <typename T>
 __device__ __forceinline__ T tri_eval(const Tri<T>& tr, const T* __restrict__ f) {
   T acc = T(0);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) acc += tr.w[k] * f[tr.o[k]];
+  for (int k = 0; k < 4; ++k) {
+    T lo, hi;
+    if constexpr (sizeof(T) == 4) {
+      if (!tr.wrap) {
+        load_pair(f, tr.o[k], lo, hi);
+      } else {
+        lo = f[tr.o[k]];
+        hi = f[tr.o[k] - tr.n2m1];
+      }
+    } else {
+      lo = f[tr.o[k]];
+      hi = f[tr.wrap ? tr.o[k] - tr.n2m1 : tr.o[k] + 1];
+    }
+    acc += tr.w01[k] * (lo + tr.t2 * (hi - lo));
+  }
   return acc;
 }
 
