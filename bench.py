@@ -47,15 +47,15 @@ def kernel_bytes(n, esize):
         "fft_plane_fwd": 3 * (S + C),
         "fft_pencil_symbol": 3 * 2 * C,
         "fft_plane_inv": 3 * (C + S),
+        "fft_plane_inv_add": 3 * (C + 2 * S),
         "fft_rows_fwd": 3 * (S + C),
         "fft_pencil_x1_fwd": 3 * 2 * C,
         "fft_pencil_x1_inv": 3 * 2 * C,
         "fft_rows_inv": 3 * (C + S),
         "tangent_stage_pred": 7 * V,
         "tangent_stage_corr": 9 * V,
-        "adjoint_pre": 4 * V,
-        "adjoint_post_pred": 6 * V,
-        "adjoint_post_corr": 8 * V,
+        "adjoint_stage_pred": 7 * V,
+        "adjoint_stage_corr": 9 * V,
         "epdiff_stage_pred": 3 * V,
         "epdiff_stage_corr": 4 * V,
         "sl_step": 4 * V,

@@ -136,6 +136,8 @@ struct PlaneArgs {
   const cplx<T>* tw2;
   const cplx<T>* twr;
   const int* slot2;
+  const T* add;  // inverse pass with an addend: out = add + add_scale * (transform)
+  T add_scale;
 };
 
 // LDS carve-up shared by the plane and row kernels: A | tw1 | tw2 | twr | slot2
@@ -507,10 +509,12 @@ __device__ __forceinline__ void rows_first_compute(cplx<T>* A, RowStageIn<T, H, 
 }
 
 // Last DIT stage of COUNT rows (the inverse of the first row stage) straight to
-// global memory (row s at dst + s * H).
-template <typename T, int H, int COUNT, int NT>
+// global memory (row s at dst + s * H).  ADD: dst = add + scale * (result), the
+// addend (same layout as dst) loaded before the butterfly so its latency overlaps.
+template <typename T, int H, int COUNT, int NT, bool ADD = false>
 __device__ __forceinline__ void rows_last_stage_global(const cplx<T>* A, cplx<T>* __restrict__ dst,
-                                                       const cplx<T>* tw) {
+                                                       const cplx<T>* tw, const cplx<T>* __restrict__ add = nullptr,
+                                                       T scale = T(0)) {
   using P2 = typename PlanOf<H>::type;
   constexpr int R = P2::radix(0), S = H / R, M = H + 1;
   constexpr int total = COUNT * S;
@@ -519,6 +523,11 @@ __device__ __forceinline__ void rows_last_stage_global(const cplx<T>* A, cplx<T>
     const int b = b0 + int(threadIdx.x);
     if (total % NT != 0 && b >= total) continue;
     const int r = b / S, j = b - r * S;
+    cplx<T> ad[ADD ? R : 1];
+    if constexpr (ADD) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) ad[q] = add[r * H + j + q * S];
+    }
     cplx<T> v[R];
     v[0] = A[r * M + j];
     if constexpr (S > 1) {
@@ -531,6 +540,10 @@ __device__ __forceinline__ void rows_last_stage_global(const cplx<T>* A, cplx<T>
       for (int q = 1; q < R; ++q) v[q] = A[r * M + j + q * S];
     }
     Dft<T, R, +1>::run(v);
+    if constexpr (ADD) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[q] = {ad[q].x + scale * v[q].x, ad[q].y + scale * v[q].y};
+    }
 #pragma unroll
     for (int q = 0; q < R; ++q) dst[r * H + j + q * S] = v[q];
   }
@@ -714,7 +727,7 @@ __device__ __forceinline__ void cols_first_stage_global(cplx<T>* A, const cplx<T
   }
 }
 
-template <typename T, int H, int N1, int NT, bool WALK>
+template <typename T, int H, int N1, int NT, bool WALK, bool ADD = false>
 __global__ void __launch_bounds__(NT) k_plane_inv_s(const cplx<T>* __restrict__ spec, T* __restrict__ out,
                                                     PlaneArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -740,7 +753,11 @@ __global__ void __launch_bounds__(NT) k_plane_inv_s(const cplx<T>* __restrict__ 
     rows_c2r_static<T, H, N1, NT, true, 1>(L.A, L.tw2, L.twr, L.slot2);
     const int comp = p / a.n0, x0 = p - comp * a.n0;
     cplx<T>* dst = reinterpret_cast<cplx<T>*>(out + comp * a.N + x0 * plane_len);
-    rows_last_stage_global<T, H, N1, NT>(L.A, dst, L.tw2);
+    if constexpr (ADD)
+      rows_last_stage_global<T, H, N1, NT, true>(
+          L.A, dst, L.tw2, reinterpret_cast<const cplx<T>*>(a.add + comp * a.N + x0 * plane_len), a.add_scale);
+    else
+      rows_last_stage_global<T, H, N1, NT>(L.A, dst, L.tw2);
     if (!WALK || pn >= a.planes) break;
     __syncthreads();  // the last row stage reads the LDS the next plane overwrites
     p = pn;
@@ -930,15 +947,16 @@ using RowsInvFn = void (*)(const cplx<T>*, T*, PlaneArgs<T>, int);
 template <typename T>
 using PencilFn = void (*)(cplx<T>*, PencilArgs<T>);
 
-enum { KF_PLANE_FWD, KF_PLANE_INV, KF_ROWS_FWD, KF_ROWS_INV, KF_PENCIL0, KF_PENCIL1F, KF_PENCIL1I };
+enum { KF_PLANE_FWD, KF_PLANE_INV, KF_ROWS_FWD, KF_ROWS_INV, KF_PENCIL0, KF_PENCIL1F, KF_PENCIL1I, KF_PLANE_INV_ADD };
 
 template <typename T, int NT, bool WALK>
-void plane_static(const FftPlan& p2, const FftPlan& p1, void*& f, void*& i) {
+void plane_static(const FftPlan& p2, const FftPlan& p1, void*& f, void*& i, void*& ia) {
   const int H = p2.n, N1 = p1.n;
 #define LDDMM_PLANE_CASE(h, n1)                                                                   \
   if (H == h && N1 == n1 && plan_matches<PlanOf<h>::type>(p2) && plan_matches<PlanOf<n1>::type>(p1)) { \
     f = (void*)(PlaneFwdFn<T>)k_plane_fwd_s<T, h, n1, NT, WALK>;                                  \
-    i = (void*)(PlaneInvFn<T>)k_plane_inv_s<T, h, n1, NT, WALK>;                                  \
+    i = (void*)(PlaneInvFn<T>)k_plane_inv_s<T, h, n1, NT, WALK, false>;                           \
+    ia = (void*)(PlaneInvFn<T>)k_plane_inv_s<T, h, n1, NT, WALK, true>;                           \
     return;                                                                                       \
   }
   LDDMM_PLANE_CASE(8, 16)
@@ -950,7 +968,7 @@ void plane_static(const FftPlan& p2, const FftPlan& p1, void*& f, void*& i) {
   LDDMM_PLANE_CASE(56, 112)
   LDDMM_PLANE_CASE(90, 216)
 #undef LDDMM_PLANE_CASE
-  f = i = nullptr;
+  f = i = ia = nullptr;
 }
 
 template <typename T, int MODE>
@@ -1029,7 +1047,7 @@ int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& 
     err = "transform tiles exceed the LDS of a workgroup";
     return LDDMM_EUNSUPPORTED;
   }
-  void* k[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  void* k[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int nstatic = 0;
   const bool use_static = tune.use_static != 0;
   // plane walk: compile-time plane kernels only
@@ -1037,13 +1055,13 @@ int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& 
   int plane_grid = 0;
   if (fused) {
     if (use_static) {
-      if (tune.plane_threads == 512 && walk) plane_static<T, 512, true>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
-      if (tune.plane_threads == 512 && !walk) plane_static<T, 512, false>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
+      if (tune.plane_threads == 512 && walk) plane_static<T, 512, true>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV], k[KF_PLANE_INV_ADD]);
+      if (tune.plane_threads == 512 && !walk) plane_static<T, 512, false>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV], k[KF_PLANE_INV_ADD]);
       // the walk's extra registers spill with 1024 threads in FP64: not offered there
       if constexpr (sizeof(T) == 4)
-        if (tune.plane_threads == 1024 && walk) plane_static<T, 1024, true>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
+        if (tune.plane_threads == 1024 && walk) plane_static<T, 1024, true>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV], k[KF_PLANE_INV_ADD]);
       if (tune.plane_threads == 1024 && (!walk || sizeof(T) != 4))
-        plane_static<T, 1024, false>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV]);
+        plane_static<T, 1024, false>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV], k[KF_PLANE_INV_ADD]);
     }
     if (k[KF_PLANE_FWD]) {
       nstatic++;
@@ -1095,7 +1113,7 @@ int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& 
   sp.pencil1_lds = p1;
   sp.rows_lds = rl;
   sp.static_kernels = nstatic;
-  for (int i = 0; i < 7; ++i) sp.kfn[i] = k[i];
+  for (int i = 0; i < 8; ++i) sp.kfn[i] = k[i];
   return 0;
 }
 
@@ -1180,7 +1198,7 @@ void spectral_free(SpectralPlan<T>& sp) {
 
 template <typename T>
 void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, double alpha, int s, int op,
-                    hipStream_t st, Profiler* prof) {
+                    hipStream_t st, Profiler* prof, const T* add, double add_scale) {
   PlaneArgs<T> pa;
   pa.n0 = sp.n0;
   pa.n1 = sp.n1;
@@ -1195,6 +1213,8 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   pa.tw2 = sp.tw2;
   pa.twr = sp.twr;
   pa.slot2 = sp.slot2;
+  pa.add = add;
+  pa.add_scale = T(add_scale);
   const FftTuning& tu = sp.tune;
 
   const int P = sp.n1 * sp.M;
@@ -1228,10 +1248,17 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
       KernelTimer t(prof, "fft_pencil_symbol");
       LDDMM_LAUNCH(t.start, t.stop, pencil0, g0, tu.pencil_threads, sp.pencil0_lds, st, sp.spec, k0);
     }
+    if (add && sp.kfn[KF_PLANE_INV_ADD]) {
+      // the addend rides on the inverse plane pass: out = add + add_scale * K in
+      KernelTimer t(prof, "fft_plane_inv_add");
+      LDDMM_LAUNCH(t.start, t.stop, ((PlaneInvFn<T>)sp.kfn[KF_PLANE_INV_ADD]), gp, tu.plane_threads, sp.plane_lds, st, sp.spec, out, pa);
+      return;
+    }
     {
       KernelTimer t(prof, "fft_plane_inv");
       LDDMM_LAUNCH(t.start, t.stop, ((PlaneInvFn<T>)sp.kfn[KF_PLANE_INV]), gp, tu.plane_threads, sp.plane_lds, st, sp.spec, out, pa);
     }
+    if (add) launch_axpbyz<T>((long long)ncomp * pa.N, 1.0, add, add_scale, out, out, st, prof);
     return;
   }
   PencilArgs<T> k1 = k0;
@@ -1263,6 +1290,7 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
     KernelTimer t(prof, "fft_rows_inv");
     LDDMM_LAUNCH(t.start, t.stop, ((RowsInvFn<T>)sp.kfn[KF_ROWS_INV]), gr, 256, sp.rows_lds, st, sp.spec, out, pa, tu.rows_rb);
   }
+  if (add) launch_axpbyz<T>((long long)ncomp * pa.N, 1.0, add, add_scale, out, out, st, prof);
 }
 
 #define LDDMM_SINST(T)                                                                                   \
@@ -1271,7 +1299,7 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   template FftTuning default_tuning<T>(const SpectralPlan<T>&);                                          \
   template void spectral_free<T>(SpectralPlan<T>&);                                                      \
   template void spectral_apply<T>(const SpectralPlan<T>&, const T*, T*, int, double, int, int, hipStream_t, \
-                                  Profiler*);
+                                  Profiler*, const T*, double);
 
 LDDMM_SINST(float)
 LDDMM_SINST(double)

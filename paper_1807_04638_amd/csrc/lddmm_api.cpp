@@ -134,9 +134,10 @@ class Engine {
   // shooting scratch (no store) and displacement ping-pong
   T *sm[2] = {nullptr, nullptr}, *sv[2] = {nullptr, nullptr}, *sms = nullptr, *svs = nullptr;
   T *u[2] = {nullptr, nullptr};
-  // tangent (X, dmu) and adjoint (U^, w) states, predictors and K-argument
+  // tangent (X, dmu) and adjoint (U^, w) states, predictors, K-argument and the
+  // adjoint stage's w-update part Qw (w_out = Qw + a1 dt K Z)
   T *X = nullptr, *Mu = nullptr, *Xs = nullptr, *Mus = nullptr, *W = nullptr;
-  T *U = nullptr, *Wh = nullptr, *Us = nullptr, *Whs = nullptr, *Z = nullptr;
+  T *U = nullptr, *Wh = nullptr, *Us = nullptr, *Whs = nullptr, *Z = nullptr, *Qw = nullptr;
   // CG and Gauss-Newton vectors
   T *cr = nullptr, *cd = nullptr, *cHd = nullptr, *cLr = nullptr, *cLd = nullptr, *cx = nullptr;
   T *gv = nullptr, *Lg = nullptr, *trial = nullptr, *tmpS = nullptr;
@@ -213,7 +214,7 @@ class Engine {
     bytes += sp.bytes;
     const long long V = 3 * N;
     T** vecs[] = {&G, &lin_v0, &sm[0], &sm[1], &sv[0], &sv[1], &sms, &svs, &u[0], &u[1], &X, &Mu, &Xs, &Mus, &W,
-                  &U, &Wh, &Us, &Whs, &Z, &cr, &cd, &cHd, &cLr, &cLd, &cx, &gv, &Lg, &trial};
+                  &U, &Wh, &Us, &Whs, &Z, &Qw, &cr, &cd, &cHd, &cLr, &cLd, &cx, &gv, &Lg, &trial};
     for (T** q : vecs)
       if (alloc(q, V)) return fail(LDDMM_ENOMEM, "out of device memory (workspace)");
     T** scal[] = {&I0, &I1, &J1, &Jtmp, &res, &tmpS};
@@ -395,6 +396,10 @@ class Engine {
   void applyL(const T* in, T* out, int ncomp = 3) {
     spectral_apply(sp, in, out, ncomp, P.alpha, P.s, LDDMM_OP_L, st, &prof);
   }
+  // out = add + scale K in (vector fields): the adjoint stage's w update
+  void applyK_add(const T* in, const T* add, double scale, T* out) {
+    spectral_apply(sp, in, out, 3, P.alpha, P.s, LDDMM_OP_K, st, &prof, add, scale);
+  }
   void copy(T* dst, const T* src, long long count) {
     (void)hipMemcpyAsync(dst, src, size_t(count) * sizeof(T), hipMemcpyDeviceToDevice, st);
   }
@@ -504,16 +509,22 @@ class Engine {
 
   // ---- adjoint Jacobi sweep (transposed Heun) ------------------------------
   // Input: U holds U^(1).  Output: Wh holds w_0 (U holds U^_0).
+  // Each stage is one stencil kernel (Z = U + ad*_w mu, the U update and the
+  // part Q of the w update) and one K application that adds a1 dt K Z to Q.
+  void adjoint_pred(const Step& c) {
+    launch_adjoint_stage<T>(g, U, Wh, c.mus, c.vs, nullptr, nullptr, Z, Qw, Us, dt, 0.0, 1.0, st, &prof);
+    applyK_add(Z, Qw, dt, Whs);
+  }
+  void adjoint_corr(const Step& c) {
+    launch_adjoint_stage<T>(g, Us, Whs, c.mu, c.v, U, Wh, Z, Qw, U, dt, 0.5, 0.5, st, &prof);
+    applyK_add(Z, Qw, 0.5 * dt, Wh);
+  }
   void backward() {
     launch_fill<T>(3 * N, T(0), Wh, st, &prof);
     for (int n = P.nt - 1; n >= 0; --n) {
       const Step c = traj_view(n);
-      launch_adjoint_pre<T>(g, U, Wh, c.mus, Z, st, &prof);
-      applyK(Z, Z);
-      launch_adjoint_post<T>(g, U, Wh, Z, c.vs, nullptr, nullptr, Us, Whs, dt, 0.0, 1.0, st, &prof);
-      launch_adjoint_pre<T>(g, Us, Whs, c.mu, Z, st, &prof);
-      applyK(Z, Z);
-      launch_adjoint_post<T>(g, Us, Whs, Z, c.v, U, Wh, U, Wh, dt, 0.5, 0.5, st, &prof);
+      adjoint_pred(c);
+      adjoint_corr(c);
     }
   }
 
@@ -617,14 +628,10 @@ class Engine {
       const Step c = traj_view(n);
       copy(nU1[n], U, V);
       copy(nW1[n], Wh, V);
-      launch_adjoint_pre<T>(g, U, Wh, c.mus, Z, st, &prof);
-      applyK(Z, Z);
-      launch_adjoint_post<T>(g, U, Wh, Z, c.vs, nullptr, nullptr, Us, Whs, dt, 0.0, 1.0, st, &prof);
+      adjoint_pred(c);
       copy(nU2[n], Us, V);
       copy(nW2[n], Whs, V);
-      launch_adjoint_pre<T>(g, Us, Whs, c.mu, Z, st, &prof);
-      applyK(Z, Z);
-      launch_adjoint_post<T>(g, Us, Whs, Z, c.v, U, Wh, U, Wh, dt, 0.5, 0.5, st, &prof);
+      adjoint_corr(c);
     }
   }
 

@@ -139,7 +139,7 @@ struct SpectralPlan {
   size_t plane_lds = 0, pencil0_lds = 0, pencil1_lds = 0, rows_lds = 0;
   size_t max_lds = 0;                        // LDS bytes available to one workgroup
   FftTuning tune{};
-  void* kfn[7] = {};                         // kernel entry points chosen by spectral_configure
+  void* kfn[8] = {};                         // kernel entry points chosen by spectral_configure
   int static_kernels = 0;                    // how many of them are compile-time variants
   int plane_grid = 0;                        // workgroups of the plane walk in use (0: one plane each)
   size_t bytes = 0;                          // device memory held
@@ -156,9 +156,10 @@ int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& 
 template <typename T>
 FftTuning default_tuning(const SpectralPlan<T>& sp);
 // out = K in (op = 0) or L in (op = 1) for ncomp components; in == out allowed.
+// With add != nullptr: out = add + add_scale * (K or L) in, add == out allowed.
 template <typename T>
 void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, double alpha, int s, int op,
-                    hipStream_t st, Profiler* prof);
+                    hipStream_t st, Profiler* prof, const T* add = nullptr, double add_scale = 0.0);
 
 // ---------------------------------------------------------------------------
 // Field kernels (stencils, Heun stages, final conditions) - stencil.hip
@@ -187,15 +188,13 @@ void launch_newton_post(const Grid& g, const T* dU, const T* dw, const T* KZ, co
 template <typename T>
 void launch_newton_final(const Grid& g, const T* G, const T* X, const T* r, double c, T* s, T* U, hipStream_t st,
                          Profiler* prof);
-// Z = U + ad*_w mu   (argument of K in the adjoint stage)
+// Adjoint stage at (v, mu) with the K application left out:
+//   Z     = U + ad*_w mu                        (argument of K)
+//   Q     = a0 w0 + a1 (w - dt ad_v w)          (then w_out = Q + a1 dt K Z)
+//   U_out = a0 U0 + a1 (U + dt ad*_v U)
 template <typename T>
-void launch_adjoint_pre(const Grid& g, const T* U, const T* w, const T* mu, T* Z, hipStream_t st, Profiler* prof);
-// Adjoint stage at v with KZ = K(U + ad*_w mu):
-//   U_out = a0 U0 + a1 (U + dt ad*_v U);  w_out = a0 w0 + a1 (w + dt (KZ - ad_v w))
-template <typename T>
-void launch_adjoint_post(const Grid& g, const T* U, const T* w, const T* KZ, const T* v, const T* U0,
-                         const T* w0, T* U_out, T* w_out, double dt, double a0, double a1, hipStream_t st,
-                         Profiler* prof);
+void launch_adjoint_stage(const Grid& g, const T* U, const T* w, const T* mu, const T* v, const T* U0, const T* w0,
+                          T* Z, T* Q, T* U_out, double dt, double a0, double a1, hipStream_t st, Profiler* prof);
 // r = J1 - I1, G = grad_h J1
 template <typename T>
 void launch_residual_grad(const Grid& g, const T* J1, const T* I1, T* r, T* G, hipStream_t st, Profiler* prof);

@@ -214,46 +214,42 @@ __global__ void __launch_bounds__(256)
   store1(dmu_out, mo, nb.o[0], g.N);
 }
 
+// Adjoint stage at (v, mu) except for K: Z = U + ad*_w mu is K's argument, and the
+// w update is split as w_out = Q + a1 dt K Z with Q = a0 w0 + a1 (w - dt ad_v w),
+// so the K pass adds a1 dt K Z to Q on its way out (the w stencil is read once).
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_adjoint_pre(Geo<T> g, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ mu,
-                  T* __restrict__ Z) {
+    k_adjoint_stage(Geo<T> g, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ mu,
+                    const T* __restrict__ v, const T* U0, const T* w0, T* __restrict__ Z, T* __restrict__ Q,
+                    T* U_out, T dt, T a0, T a1) {
   int i0, i1, i2;
   if (!voxel(g, i0, i1, i2)) return;
   const Nbr nb = neighbours(g, i0, i1, i2);
-  St7<T> Ws, Ms;
+  St7<T> Ws, Vs;
   load7(Ws, w, nb, g.N);
-  load7(Ms, mu, nb, g.N);
-  T a[3], u[3];
-  adstar(Ws, Ms, g, a);
-  load1(u, U, nb.o[0], g.N);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) a[c] += u[c];
-  store1(Z, a, nb.o[0], g.N);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256)
-    k_adjoint_post(Geo<T> g, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ KZ,
-                   const T* __restrict__ v, const T* U0, const T* w0, T* U_out, T* w_out, T dt, T a0, T a1) {
-  int i0, i1, i2;
-  if (!voxel(g, i0, i1, i2)) return;
-  const Nbr nb = neighbours(g, i0, i1, i2);
-  St7<T> Us, Ws, Vs;
-  load7(Us, U, nb, g.N);
   load7(Vs, v, nb, g.N);
-  T aU[3];
-  adstar(Vs, Us, g, aU);
-  T uo[3];
+  T z[3], aw[3], aU[3];
+  {
+    St7<T> Ms;
+    load7(Ms, mu, nb, g.N);
+    adstar(Ws, Ms, g, z);  // ad*_w mu
+  }
+  ad(Vs, Ws, g, aw);  // ad_v w
+  T u[3];
+  {
+    St7<T> Us;
+    load7(Us, U, nb, g.N);
+    adstar(Vs, Us, g, aU);  // ad*_v U
 #pragma unroll
-  for (int c = 0; c < 3; ++c) uo[c] = a1 * (Us.f[0][c] + dt * aU[c]);
-  load7(Ws, w, nb, g.N);
-  T aw[3], kz[3];
-  ad(Vs, Ws, g, aw);
-  load1(kz, KZ, nb.o[0], g.N);
-  T wo[3];
+    for (int c = 0; c < 3; ++c) u[c] = Us.f[0][c];
+  }
+  T q[3], uo[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) wo[c] = a1 * (Ws.f[0][c] + dt * (kz[c] - aw[c]));
+  for (int c = 0; c < 3; ++c) {
+    z[c] += u[c];
+    q[c] = a1 * (Ws.f[0][c] - dt * aw[c]);
+    uo[c] = a1 * (u[c] + dt * aU[c]);
+  }
   if (a0 != T(0)) {
     T u0[3], ww0[3];
     load1(u0, U0, nb.o[0], g.N);
@@ -261,11 +257,12 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       uo[c] += a0 * u0[c];
-      wo[c] += a0 * ww0[c];
+      q[c] += a0 * ww0[c];
     }
   }
+  store1(Z, z, nb.o[0], g.N);
+  store1(Q, q, nb.o[0], g.N);
   store1(U_out, uo, nb.o[0], g.N);
-  store1(w_out, wo, nb.o[0], g.N);
 }
 
 // ---------------------------------------------------------------------------
@@ -673,63 +670,49 @@ __global__ void __launch_bounds__(256)
 
 template <typename T, int VW, bool PAIR>
 __global__ void __launch_bounds__(256)
-    k_adjoint_pre_v(Geo<T> g, int RW, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ mu,
-                    T* __restrict__ Z) {
+    k_adjoint_stage_v(Geo<T> g, int RW, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ mu,
+                      const T* __restrict__ v, const T* U0, const T* w0, T* __restrict__ Z, T* __restrict__ Q,
+                      T* U_out, T dt, T a0, T a1) {
   VNbr<VW> nb;
   if (!vvoxel<T, VW>(g, RW, nb)) return;
-  T wc[3][VW], m[3][VW], a[3][VW] = {};
-  vload3<T, VW>(wc, w, nb.o, g.N);
-  vload3<T, VW>(m, mu, nb.o, g.N);
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    VPair<T, VW> Wp, Mp;
-    vpair<T, VW, PAIR>(Wp, w, wc, nb, e, g.N);
-    vpair<T, VW, PAIR>(Mp, mu, m, nb, e, g.N);
-    vadstar_dir<T, VW>(a, Wp, Mp, m, e, vinv2h<T, VW, PAIR>(g, nb, e));
-  }
-  T u[3][VW];
-  vload3<T, VW>(u, U, nb.o, g.N);
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int k = 0; k < VW; ++k) a[c][k] += u[c][k];
-  vstore3<T, VW>(Z, a, nb.o, g.N);
-}
-
-template <typename T, int VW, bool PAIR>
-__global__ void __launch_bounds__(256)
-    k_adjoint_post_v(Geo<T> g, int RW, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ KZ,
-                     const T* __restrict__ v, const T* U0, const T* w0, T* U_out, T* w_out, T dt, T a0, T a1) {
-  VNbr<VW> nb;
-  if (!vvoxel<T, VW>(g, RW, nb)) return;
-  T u[3][VW], vc[3][VW], wc[3][VW];
+  T u[3][VW], vc[3][VW], wc[3][VW], m[3][VW];
   vload3<T, VW>(u, U, nb.o, g.N);
   vload3<T, VW>(vc, v, nb.o, g.N);
   vload3<T, VW>(wc, w, nb.o, g.N);
-  T aU[3][VW] = {}, aw[3][VW] = {};
+  vload3<T, VW>(m, mu, nb.o, g.N);
+  T z[3][VW] = {}, aU[3][VW] = {}, aw[3][VW] = {};
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    VPair<T, VW> Vp, Up, Wp;
-    vpair<T, VW, PAIR>(Vp, v, vc, nb, e, g.N);
-    vpair<T, VW, PAIR>(Up, U, u, nb, e, g.N);
+    const T h = vinv2h<T, VW, PAIR>(g, nb, e);
+    VPair<T, VW> Wp, Vp;
     vpair<T, VW, PAIR>(Wp, w, wc, nb, e, g.N);
-    vadstar_dir<T, VW>(aU, Vp, Up, u, e, vinv2h<T, VW, PAIR>(g, nb, e));  // ad*_v U
-    vad_dir<T, VW>(aw, Vp, Wp, vc, wc, e, vinv2h<T, VW, PAIR>(g, nb, e));  // ad_v w
+    {
+      VPair<T, VW> Mp;
+      vpair<T, VW, PAIR>(Mp, mu, m, nb, e, g.N);
+      vadstar_dir<T, VW>(z, Wp, Mp, m, e, h);  // ad*_w mu
+    }
+    vpair<T, VW, PAIR>(Vp, v, vc, nb, e, g.N);
+    vad_dir<T, VW>(aw, Vp, Wp, vc, wc, e, h);  // ad_v w
+    {
+      VPair<T, VW> Up;
+      vpair<T, VW, PAIR>(Up, U, u, nb, e, g.N);
+      vadstar_dir<T, VW>(aU, Vp, Up, u, e, h);  // ad*_v U
+    }
   }
-  T kz[3][VW];
-  vload3<T, VW>(kz, KZ, nb.o, g.N);
-  T uo[3][VW], wo[3][VW];
+  T q[3][VW], uo[3][VW];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int k = 0; k < VW; ++k) {
+      z[c][k] += u[c][k];
+      q[c][k] = a1 * (wc[c][k] - dt * aw[c][k]);
       uo[c][k] = a1 * (u[c][k] + dt * aU[c][k]);
-      wo[c][k] = a1 * (wc[c][k] + dt * (kz[c][k] - aw[c][k]));
     }
+  vheun<T, VW>(q, w0, a0, nb.o, g.N);
   vheun<T, VW>(uo, U0, a0, nb.o, g.N);
-  vheun<T, VW>(wo, w0, a0, nb.o, g.N);
+  vstore3<T, VW>(Z, z, nb.o, g.N);
+  vstore3<T, VW>(Q, q, nb.o, g.N);
   vstore3<T, VW>(U_out, uo, nb.o, g.N);
-  vstore3<T, VW>(w_out, wo, nb.o, g.N);
 }
 
 // Lane width VW of the row-vectorised kernels for this grid (0: one voxel per thread).
@@ -806,24 +789,14 @@ void launch_tangent_stage(const Grid& g, const T* X, const T* dmu, const T* W, c
 }
 
 template <typename T>
-void launch_adjoint_pre(const Grid& g, const T* U, const T* w, const T* mu, T* Z, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, "adjoint_pre");
+void launch_adjoint_stage(const Grid& g, const T* U, const T* w, const T* mu, const T* v, const T* U0, const T* w0,
+                          T* Z, T* Q, T* U_out, double dt, double a0, double a1, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, a0 != 0.0 ? "adjoint_stage_corr" : "adjoint_stage_pred");
   if (const int VW = row_vector_width(g)) {
-    LDDMM_ROWVEC(k_adjoint_pre_v, U, w, mu, Z);
+    LDDMM_ROWVEC(k_adjoint_stage_v, U, w, mu, v, U0 ? U0 : U, w0 ? w0 : w, Z, Q, U_out, T(dt), T(a0), T(a1));
     return;
   }
-  LDDMM_LAUNCH(t.start, t.stop, k_adjoint_pre<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), U, w, mu, Z);
-}
-
-template <typename T>
-void launch_adjoint_post(const Grid& g, const T* U, const T* w, const T* KZ, const T* v, const T* U0, const T* w0,
-                         T* U_out, T* w_out, double dt, double a0, double a1, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, a0 != 0.0 ? "adjoint_post_corr" : "adjoint_post_pred");
-  if (const int VW = row_vector_width(g)) {
-    LDDMM_ROWVEC(k_adjoint_post_v, U, w, KZ, v, U0 ? U0 : U, w0 ? w0 : w, U_out, w_out, T(dt), T(a0), T(a1));
-    return;
-  }
-  LDDMM_LAUNCH(t.start, t.stop, k_adjoint_post<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), U, w, KZ, v, U0 ? U0 : U, w0 ? w0 : w, U_out, w_out, T(dt), T(a0), T(a1));
+  LDDMM_LAUNCH(t.start, t.stop, k_adjoint_stage<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), U, w, mu, v, U0 ? U0 : U, w0 ? w0 : w, Z, Q, U_out, T(dt), T(a0), T(a1));
 }
 
 template <typename T>
@@ -881,9 +854,8 @@ void launch_jacobian_det(const Grid& g, const T* u, T* det, hipStream_t st, Prof
                                        hipStream_t, Profiler*);                                                  \
   template void launch_tangent_stage<T>(const Grid&, const T*, const T*, const T*, const T*, const T*, const T*, \
                                         const T*, T*, T*, double, double, double, hipStream_t, Profiler*);       \
-  template void launch_adjoint_pre<T>(const Grid&, const T*, const T*, const T*, T*, hipStream_t, Profiler*);   \
-  template void launch_adjoint_post<T>(const Grid&, const T*, const T*, const T*, const T*, const T*, const T*,  \
-                                       T*, T*, double, double, double, hipStream_t, Profiler*);                  \
+  template void launch_adjoint_stage<T>(const Grid&, const T*, const T*, const T*, const T*, const T*, const T*, \
+                                        T*, T*, T*, double, double, double, hipStream_t, Profiler*);             \
   template void launch_residual_grad<T>(const Grid&, const T*, const T*, T*, T*, hipStream_t, Profiler*);       \
   template void launch_scalar_times_vec<T>(const Grid&, const T*, const T*, double, T*, hipStream_t, Profiler*); \
   template void launch_gn_final<T>(const Grid&, const T*, const T*, double, T*, hipStream_t, Profiler*);        \
