@@ -662,13 +662,12 @@ class Engine {
     launch_fill<T>(3 * N, T(0), Wh, st, &prof);
     for (int n = P.nt - 1; n >= 0; --n) {
       const Step c = traj_view(n);
-      launch_newton_pre<T>(g, U, Wh, c.mus, nW1[n], tdmus[n], Z, st, &prof);
-      applyK(Z, Z);
-      launch_newton_post<T>(g, U, Wh, Z, c.vs, tdmusK[n], nU1[n], nW1[n], nullptr, nullptr, Us, Whs, dt, 0.0, 1.0, st,
-                            &prof);
-      launch_newton_pre<T>(g, Us, Whs, c.mu, nW2[n], tdmu[n], Z, st, &prof);
-      applyK(Z, Z);
-      launch_newton_post<T>(g, Us, Whs, Z, c.v, tdmuK[n], nU2[n], nW2[n], U, Wh, U, Wh, dt, 0.5, 0.5, st, &prof);
+      launch_newton_stage<T>(g, U, Wh, c.mus, nW1[n], tdmus[n], c.vs, tdmusK[n], nU1[n], nullptr, nullptr, Z, Qw,
+                             Us, dt, 0.0, 1.0, st, &prof);
+      applyK_add(Z, Qw, dt, Whs);
+      launch_newton_stage<T>(g, Us, Whs, c.mu, nW2[n], tdmu[n], c.v, tdmuK[n], nU2[n], U, Wh, Z, Qw, U, dt, 0.5, 0.5,
+                             st, &prof);
+      applyK_add(Z, Qw, 0.5 * dt, Wh);
     }
     launch_axpbyz<T>(3 * N, 2.0, dv, 1.0, Wh, hv, st, &prof);
   }

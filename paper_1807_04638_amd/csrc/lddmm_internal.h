@@ -175,15 +175,14 @@ template <typename T>
 void launch_tangent_stage(const Grid& g, const T* X, const T* dmu, const T* W, const T* v, const T* mu,
                           const T* X0, const T* dmu0, T* X_out, T* dmu_out, double dt, double a0, double a1,
                           hipStream_t st, Profiler* prof);
-// Full Newton sweep (first-order adjoint terms kept): Z = dU + ad*_dw mu + ad*_w1 dmu;
-// then f = (ad*_v dU + ad*_W U1, KZ - ad_v dw - ad_W w1), out = a1 (y + dt f) + a0 y0.
+// Full Newton sweep (first-order adjoint terms kept).
+// Fused Newton stage with the K application left out (W = K dmu):
+//   Z = dU + ad*_dw mu + ad*_w1 dmu;  Q = a0 dw0 + a1 (dw - dt (ad_v dw + ad_W w1));
+//   dU_out = a0 dU0 + a1 (dU + dt (ad*_v dU + ad*_W U1));  then dw_out = Q + a1 dt K Z
 template <typename T>
-void launch_newton_pre(const Grid& g, const T* dU, const T* dw, const T* mu, const T* w1, const T* dmu, T* Z,
-                       hipStream_t st, Profiler* prof);
-template <typename T>
-void launch_newton_post(const Grid& g, const T* dU, const T* dw, const T* KZ, const T* v, const T* Wv, const T* U1,
-                        const T* w1, const T* dU0, const T* dw0, T* dU_out, T* dw_out, double dt, double a0,
-                        double a1, hipStream_t st, Profiler* prof);
+void launch_newton_stage(const Grid& g, const T* dU, const T* dw, const T* mu, const T* w1, const T* dmu, const T* v,
+                         const T* Wv, const T* U1, const T* dU0, const T* dw0, T* Z, T* Q, T* dU_out, double dt,
+                         double a0, double a1, hipStream_t st, Profiler* prof);
 // Newton final condition: s = -G.X, U = c s G + c r grad_h s
 template <typename T>
 void launch_newton_final(const Grid& g, const T* G, const T* X, const T* r, double c, T* s, T* U, hipStream_t st,

@@ -271,76 +271,65 @@ __global__ void __launch_bounds__(256)
 // first-order adjoint at the same stage and (W, dmu) = (K dmu, dmu) the
 // variation of the trajectory point.
 // ---------------------------------------------------------------------------
-// Z = dU + ad*_{dw} mu + ad*_{w1} dmu   (argument of K)
+// Fused Newton stage (the same split as the adjoint stage): with W = K dmu,
+//   Z     = dU + ad*_dw mu + ad*_w1 dmu                        (argument of K)
+//   Q     = a0 dw0 + a1 (dw - dt (ad_v dw + ad_W w1))          (dw_out = Q + a1 dt K Z)
+//   dU_out = a0 dU0 + a1 (dU + dt (ad*_v dU + ad*_W U1))
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_newton_pre(Geo<T> g, const T* __restrict__ dU, const T* __restrict__ dw, const T* __restrict__ mu,
-                 const T* __restrict__ w1, const T* __restrict__ dmu, T* __restrict__ Z) {
+    k_newton_stage(Geo<T> g, const T* __restrict__ dU, const T* __restrict__ dw, const T* __restrict__ mu,
+                   const T* __restrict__ w1, const T* __restrict__ dmu, const T* __restrict__ v,
+                   const T* __restrict__ Wv, const T* __restrict__ U1, const T* dU0, const T* dw0,
+                   T* __restrict__ Z, T* __restrict__ Q, T* dU_out, T dt, T a0, T a1) {
   int i0, i1, i2;
   if (!voxel(g, i0, i1, i2)) return;
   const Nbr nb = neighbours(g, i0, i1, i2);
-  T a[3], b[3], u[3];
+  T z[3], aU[3], aw[3], t[3], du[3], dwc[3];
   {
-    St7<T> Dw, M;
+    St7<T> Dw, Vs;
     load7(Dw, dw, nb, g.N);
-    load7(M, mu, nb, g.N);
-    adstar(Dw, M, g, a);
-  }
-  {
-    St7<T> W1, Dm;
-    load7(W1, w1, nb, g.N);
-    load7(Dm, dmu, nb, g.N);
-    adstar(W1, Dm, g, b);
-  }
-  load1(u, dU, nb.o[0], g.N);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) a[c] += b[c] + u[c];
-  store1(Z, a, nb.o[0], g.N);
-}
-
-// f = (ad*_v dU + ad*_W U1,  KZ - ad_v dw - ad_W w1);  out = a1 (y + dt f) + a0 y0
-template <typename T>
-__global__ void __launch_bounds__(256)
-    k_newton_post(Geo<T> g, const T* __restrict__ dU, const T* __restrict__ dw, const T* __restrict__ KZ,
-                  const T* __restrict__ v, const T* __restrict__ Wv, const T* __restrict__ U1,
-                  const T* __restrict__ w1, const T* dU0, const T* dw0, T* dU_out, T* dw_out, T dt, T a0, T a1) {
-  int i0, i1, i2;
-  if (!voxel(g, i0, i1, i2)) return;
-  const Nbr nb = neighbours(g, i0, i1, i2);
-  T aU[3], aw[3], t[3], du[3], dwc[3];
-  {
-    St7<T> V, D;
-    load7(V, v, nb, g.N);
+    load7(Vs, v, nb, g.N);
+    {
+      St7<T> M;
+      load7(M, mu, nb, g.N);
+      adstar(Dw, M, g, z);  // ad*_dw mu
+    }
+    ad(Vs, Dw, g, aw);  // ad_v dw
+    St7<T> D;
     load7(D, dU, nb, g.N);
-    adstar(V, D, g, aU);
+    adstar(Vs, D, g, aU);  // ad*_v dU
 #pragma unroll
-    for (int c = 0; c < 3; ++c) du[c] = D.f[0][c];
-    St7<T> E;
-    load7(E, dw, nb, g.N);
-    ad(V, E, g, aw);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) dwc[c] = E.f[0][c];
+    for (int c = 0; c < 3; ++c) {
+      du[c] = D.f[0][c];
+      dwc[c] = Dw.f[0][c];
+    }
   }
   {
-    St7<T> Wk, A;
-    load7(Wk, Wv, nb, g.N);
-    load7(A, U1, nb, g.N);
-    adstar(Wk, A, g, t);
+    St7<T> W1, Wk;
+    load7(W1, w1, nb, g.N);
+    {
+      St7<T> Dm;
+      load7(Dm, dmu, nb, g.N);
+      adstar(W1, Dm, g, t);  // ad*_w1 dmu
 #pragma unroll
-    for (int c = 0; c < 3; ++c) aU[c] += t[c];
-    St7<T> B;
-    load7(B, w1, nb, g.N);
-    ad(Wk, B, g, t);
+      for (int c = 0; c < 3; ++c) z[c] += t[c];
+    }
+    load7(Wk, Wv, nb, g.N);
+    ad(Wk, W1, g, t);  // ad_W w1
 #pragma unroll
     for (int c = 0; c < 3; ++c) aw[c] += t[c];
+    St7<T> A;
+    load7(A, U1, nb, g.N);
+    adstar(Wk, A, g, t);  // ad*_W U1
+#pragma unroll
+    for (int c = 0; c < 3; ++c) aU[c] += t[c];
   }
-  T kz[3];
-  load1(kz, KZ, nb.o[0], g.N);
-  T uo[3], wo[3];
+  T q[3], uo[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
+    z[c] += du[c];
     uo[c] = a1 * (du[c] + dt * aU[c]);
-    wo[c] = a1 * (dwc[c] + dt * (kz[c] - aw[c]));
+    q[c] = a1 * (dwc[c] - dt * aw[c]);
   }
   if (a0 != T(0)) {
     T u0[3], ww0[3];
@@ -349,11 +338,12 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       uo[c] += a0 * u0[c];
-      wo[c] += a0 * ww0[c];
+      q[c] += a0 * ww0[c];
     }
   }
+  store1(Z, z, nb.o[0], g.N);
+  store1(Q, q, nb.o[0], g.N);
   store1(dU_out, uo, nb.o[0], g.N);
-  store1(dw_out, wo, nb.o[0], g.N);
 }
 
 // delta m_1 = -grad J_1 . X (pointwise)
@@ -715,6 +705,71 @@ __global__ void __launch_bounds__(256)
   vstore3<T, VW>(U_out, uo, nb.o, g.N);
 }
 
+template <typename T, int VW, bool PAIR>
+__global__ void __launch_bounds__(256)
+    k_newton_stage_v(Geo<T> g, int RW, const T* __restrict__ dU, const T* __restrict__ dw, const T* __restrict__ mu,
+                     const T* __restrict__ w1, const T* __restrict__ dmu, const T* __restrict__ v,
+                     const T* __restrict__ Wv, const T* __restrict__ U1, const T* dU0, const T* dw0,
+                     T* __restrict__ Z, T* __restrict__ Q, T* dU_out, T dt, T a0, T a1) {
+  VNbr<VW> nb;
+  if (!vvoxel<T, VW>(g, RW, nb)) return;
+  T du[3][VW], dwc[3][VW], m[3][VW], w1c[3][VW], dm[3][VW], vc[3][VW], wk[3][VW], u1[3][VW];
+  vload3<T, VW>(du, dU, nb.o, g.N);
+  vload3<T, VW>(dwc, dw, nb.o, g.N);
+  vload3<T, VW>(m, mu, nb.o, g.N);
+  vload3<T, VW>(w1c, w1, nb.o, g.N);
+  vload3<T, VW>(dm, dmu, nb.o, g.N);
+  vload3<T, VW>(vc, v, nb.o, g.N);
+  vload3<T, VW>(wk, Wv, nb.o, g.N);
+  vload3<T, VW>(u1, U1, nb.o, g.N);
+  T z[3][VW] = {}, aU[3][VW] = {}, aw[3][VW] = {};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const T h = vinv2h<T, VW, PAIR>(g, nb, e);
+    VPair<T, VW> Dwp, Vp, W1p, Wkp;
+    vpair<T, VW, PAIR>(Dwp, dw, dwc, nb, e, g.N);
+    {
+      VPair<T, VW> Mp;
+      vpair<T, VW, PAIR>(Mp, mu, m, nb, e, g.N);
+      vadstar_dir<T, VW>(z, Dwp, Mp, m, e, h);  // ad*_dw mu
+    }
+    vpair<T, VW, PAIR>(Vp, v, vc, nb, e, g.N);
+    vad_dir<T, VW>(aw, Vp, Dwp, vc, dwc, e, h);  // ad_v dw
+    {
+      VPair<T, VW> Dp;
+      vpair<T, VW, PAIR>(Dp, dU, du, nb, e, g.N);
+      vadstar_dir<T, VW>(aU, Vp, Dp, du, e, h);  // ad*_v dU
+    }
+    vpair<T, VW, PAIR>(W1p, w1, w1c, nb, e, g.N);
+    {
+      VPair<T, VW> Dmp;
+      vpair<T, VW, PAIR>(Dmp, dmu, dm, nb, e, g.N);
+      vadstar_dir<T, VW>(z, W1p, Dmp, dm, e, h);  // ad*_w1 dmu
+    }
+    vpair<T, VW, PAIR>(Wkp, Wv, wk, nb, e, g.N);
+    vad_dir<T, VW>(aw, Wkp, W1p, wk, w1c, e, h);  // ad_W w1
+    {
+      VPair<T, VW> Ap;
+      vpair<T, VW, PAIR>(Ap, U1, u1, nb, e, g.N);
+      vadstar_dir<T, VW>(aU, Wkp, Ap, u1, e, h);  // ad*_W U1
+    }
+  }
+  T q[3][VW], uo[3][VW];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+      z[c][k] += du[c][k];
+      uo[c][k] = a1 * (du[c][k] + dt * aU[c][k]);
+      q[c][k] = a1 * (dwc[c][k] - dt * aw[c][k]);
+    }
+  vheun<T, VW>(uo, dU0, a0, nb.o, g.N);
+  vheun<T, VW>(q, dw0, a0, nb.o, g.N);
+  vstore3<T, VW>(Z, z, nb.o, g.N);
+  vstore3<T, VW>(Q, q, nb.o, g.N);
+  vstore3<T, VW>(dU_out, uo, nb.o, g.N);
+}
+
 // Lane width VW of the row-vectorised kernels for this grid (0: one voxel per thread).
 int row_vector_width(const Grid& g) { return row_vector_valid(g.n2, g.rowvec) ? g.rowvec : 0; }
 
@@ -732,6 +787,21 @@ Geo<T> make_vgeo(const Grid& g, int VW) {
 
 #define LDDMM_ROWVEC_AT(kern, vw, pr, ...) \
   LDDMM_LAUNCH(t.start, t.stop, kern<T LDDMM_COMMA vw LDDMM_COMMA pr>, grid_, block_, 0, st, gv, RW, __VA_ARGS__)
+// The same for kernels instantiated for VW = 1, 2 only.
+#define LDDMM_ROWVEC12(kern, ...)                                      \
+  do {                                                                 \
+    const Geo<T> gv = make_vgeo<T>(g, VW);                             \
+    const dim3 grid_(gv.ft.blocks), block_(gv.ft.BX, gv.ft.BY);        \
+    const int RW = g.n2 / VW;                                          \
+    if (VW == 1 && gv.pair)                                            \
+      LDDMM_ROWVEC_AT(kern, 1, true, __VA_ARGS__);                     \
+    else if (VW == 1)                                                  \
+      LDDMM_ROWVEC_AT(kern, 1, false, __VA_ARGS__);                    \
+    else if (gv.pair)                                                  \
+      LDDMM_ROWVEC_AT(kern, 2, true, __VA_ARGS__);                     \
+    else                                                               \
+      LDDMM_ROWVEC_AT(kern, 2, false, __VA_ARGS__);                    \
+  } while (0)
 #define LDDMM_ROWVEC(kern, ...)                                        \
   do {                                                                 \
     const Geo<T> gv = make_vgeo<T>(g, VW);                             \
@@ -819,20 +889,19 @@ void launch_gn_final(const Grid& g, const T* G, const T* X, double c, T* U, hipS
 }
 
 template <typename T>
-void launch_newton_pre(const Grid& g, const T* dU, const T* dw, const T* mu, const T* w1, const T* dmu, T* Z,
-                       hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, "newton_pre");
-  LDDMM_LAUNCH(t.start, t.stop, k_newton_pre<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), dU, dw, mu, w1, dmu,
-               Z);
-}
-
-template <typename T>
-void launch_newton_post(const Grid& g, const T* dU, const T* dw, const T* KZ, const T* v, const T* Wv, const T* U1,
-                        const T* w1, const T* dU0, const T* dw0, T* dU_out, T* dw_out, double dt, double a0,
-                        double a1, hipStream_t st, Profiler* prof) {
-  KernelTimer t(prof, a0 != 0.0 ? "newton_post_corr" : "newton_post_pred");
-  LDDMM_LAUNCH(t.start, t.stop, k_newton_post<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), dU, dw, KZ, v, Wv, U1,
-               w1, dU0 ? dU0 : dU, dw0 ? dw0 : dw, dU_out, dw_out, T(dt), T(a0), T(a1));
+void launch_newton_stage(const Grid& g, const T* dU, const T* dw, const T* mu, const T* w1, const T* dmu, const T* v,
+                         const T* Wv, const T* U1, const T* dU0, const T* dw0, T* Z, T* Q, T* dU_out, double dt,
+                         double a0, double a1, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, a0 != 0.0 ? "newton_stage_corr" : "newton_stage_pred");
+  // eight stencil fields: at most two voxels per lane keeps the registers in bounds
+  int VW = row_vector_width(g);
+  if (VW > 2) VW = row_vector_valid(g.n2, 2) ? 2 : 0;
+  if (VW) {
+    LDDMM_ROWVEC12(k_newton_stage_v, dU, dw, mu, w1, dmu, v, Wv, U1, dU0 ? dU0 : dU, dw0 ? dw0 : dw, Z, Q, dU_out,
+                   T(dt), T(a0), T(a1));
+    return;
+  }
+  LDDMM_LAUNCH(t.start, t.stop, k_newton_stage<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), dU, dw, mu, w1, dmu, v, Wv, U1, dU0 ? dU0 : dU, dw0 ? dw0 : dw, Z, Q, dU_out, T(dt), T(a0), T(a1));
 }
 
 template <typename T>
@@ -860,11 +929,9 @@ void launch_jacobian_det(const Grid& g, const T* u, T* det, hipStream_t st, Prof
   template void launch_scalar_times_vec<T>(const Grid&, const T*, const T*, double, T*, hipStream_t, Profiler*); \
   template void launch_gn_final<T>(const Grid&, const T*, const T*, double, T*, hipStream_t, Profiler*);        \
   template void launch_jacobian_det<T>(const Grid&, const T*, T*, hipStream_t, Profiler*);                      \
-  template void launch_newton_pre<T>(const Grid&, const T*, const T*, const T*, const T*, const T*, T*,          \
-                                     hipStream_t, Profiler*);                                                    \
-  template void launch_newton_post<T>(const Grid&, const T*, const T*, const T*, const T*, const T*, const T*,   \
-                                      const T*, const T*, const T*, T*, T*, double, double, double, hipStream_t, \
-                                      Profiler*);                                                                \
+  template void launch_newton_stage<T>(const Grid&, const T*, const T*, const T*, const T*, const T*, const T*,  \
+                                       const T*, const T*, const T*, const T*, T*, T*, T*, double, double, double, \
+                                       hipStream_t, Profiler*);                                                  \
   template void launch_newton_final<T>(const Grid&, const T*, const T*, const T*, double, T*, T*, hipStream_t,    \
                                        Profiler*);
 
