@@ -9,8 +9,13 @@
 // the grid it is the exact transpose of ad_v, which keeps the adjoint sweep the
 // exact transpose of the tangent sweep.
 //
-// Every kernel maps one thread to one voxel with a (64 x 4) block over (x2, x1)
-// and grid.z = x0; neighbours come through the cache hierarchy.
+// Two forms of each stage kernel: one voxel per thread, and row-vectorised (a
+// lane owns VW consecutive voxels of an x2 row, x2 neighbours come from the
+// adjacent lanes, x1 rows may be shared by the two halves of a wave).  Blocks are
+// laid out XCD-aware (FieldTiling); neighbours come through the cache hierarchy.
+// The adjoint and Newton stages leave their K application out: they write K's
+// argument and the rest of the w update, and the inverse transform adds the K
+// term on its way out.
 #include "lddmm.h"
 #include "lddmm_internal.h"
 
