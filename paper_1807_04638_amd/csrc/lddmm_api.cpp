@@ -818,19 +818,22 @@ class Engine {
     double rr = dot(cLr, cr);
     const double tol = eta * std::sqrt(rr);
     int it = 0;
+    // One host read per iteration: the step length is taken on the device from
+    // <d, Hd>, and the host reads that curvature together with the new residual.
     for (it = 1; it <= maxit; ++it) {
       apply_hessian(cd, cHd);
-      const double dHd = dot(cLd, cHd);
-      if (!(dHd > 0.0)) {  // non-positive curvature: keep x, or take -g on the first direction
+      dot_dev(cLd, cHd, 3, 5);
+      launch_cg_step<T>(V, rr, cell, dres + 5, cd, cHd, x, cr, st, &prof);
+      applyL(cr, cLr);
+      dot_dev(cLr, cr, 3, 6);
+      fetch(7);
+      const double dHd = cell * hres[5];
+      if (!(dHd > 0.0)) {  // non-positive curvature: x was left alone; take -g on the first direction
         if (it == 1) copy(x, cd, V);
         --it;
         break;
       }
-      const double a = rr / dHd;
-      launch_axpby<T>(V, a, cd, 1.0, x, st, &prof);
-      launch_axpby<T>(V, -a, cHd, 1.0, cr, st, &prof);
-      applyL(cr, cLr);
-      const double rr_new = dot(cLr, cr);
+      const double rr_new = cell * hres[6];
       if (std::sqrt(rr_new) <= tol) break;
       const double beta = rr_new / rr;
       launch_axpby<T>(V, 1.0, cr, beta, cd, st, &prof);
@@ -854,20 +857,24 @@ class Engine {
     double rz = dot(cr, cLr);
     const double tol = eta * std::sqrt(dot(gl2, gl2));
     int it = 0;
+    // One host read per iteration (curvature, residual norm and <r, K r>
+    // together); on the last iteration the K r it computes goes unused.
     for (it = 1; it <= maxit; ++it) {
       hessvec_core(cd, cLd);
       applyL(cLd, cHd);
-      const double dq = dot(cd, cHd);
+      dot_dev(cd, cHd, 3, 5);
+      launch_cg_step<T>(V, rz, cell, dres + 5, cd, cHd, x, cr, st, &prof);
+      dot_dev(cr, cr, 3, 6);
+      applyK(cr, cLr);
+      dot_dev(cr, cLr, 3, 4);
+      fetch(7);
+      const double dq = cell * hres[5];
       if (!(dq > 0.0)) {
         --it;
         break;
       }
-      const double a = rz / dq;
-      launch_axpby<T>(V, a, cd, 1.0, x, st, &prof);
-      launch_axpby<T>(V, -a, cHd, 1.0, cr, st, &prof);
-      if (std::sqrt(dot(cr, cr)) <= tol) break;
-      applyK(cr, cLr);
-      const double rz_new = dot(cr, cLr);
+      if (std::sqrt(cell * hres[6]) <= tol) break;
+      const double rz_new = cell * hres[4];
       launch_axpby<T>(V, 1.0, cLr, rz_new / rz, cd, st, &prof);
       rz = rz_new;
     }

@@ -238,6 +238,11 @@ void launch_minmax(const T* a, long long n, double* partials, double* out, hipSt
 template <typename T>
 void launch_axpby(long long n, double alpha, const T* x, double beta, T* y, hipStream_t st, Profiler* prof);
 // z = alpha x + beta y
+// CG step on the device: a = rr / (cell * dsum[0]) if that is positive, else 0;
+// x += a d, r -= a q.
+template <typename T>
+void launch_cg_step(long long n, double rr, double cell, const double* dsum, const T* d, const T* q, T* x, T* r,
+                    hipStream_t st, Profiler* prof);
 template <typename T>
 void launch_axpbyz(long long n, double alpha, const T* x, double beta, const T* y, T* z, hipStream_t st,
                    Profiler* prof);

@@ -140,6 +140,21 @@ __global__ void k_axpbyz(long long n, T alpha, const T* x, T beta, const T* y, T
     z[i] = alpha * x[i] + beta * y[i];
 }
 
+// CG update with the step length taken on the device: a = rr / (cell * *dsum)
+// when that curvature is positive, else 0 (the host sees the curvature at its
+// next read and stops); x += a d, r -= a q.
+template <typename T>
+__global__ void k_cg_step(long long n, double rr, double cell, const double* __restrict__ dsum,
+                          const T* __restrict__ d, const T* __restrict__ q, T* __restrict__ x, T* __restrict__ r) {
+  const double curv = cell * dsum[0];
+  const double a = curv > 0.0 ? rr / curv : 0.0;
+  const T ta = T(a), tb = T(-a), one = T(1);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    x[i] = ta * d[i] + one * x[i];
+    r[i] = tb * q[i] + one * r[i];
+  }
+}
+
 template <typename T>
 __global__ void k_fill(long long n, T value, T* y) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -197,6 +212,13 @@ void launch_axpbyz(long long n, double alpha, const T* x, double beta, const T* 
 }
 
 template <typename T>
+void launch_cg_step(long long n, double rr, double cell, const double* dsum, const T* d, const T* q, T* x, T* r,
+                    hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "cg_step");
+  LDDMM_LAUNCH(t.start, t.stop, k_cg_step<T>, ew_blocks(n), 256, 0, st, n, rr, cell, dsum, d, q, x, r);
+}
+
+template <typename T>
 void launch_fill(long long n, T value, T* y, hipStream_t st, Profiler* prof) {
   KernelTimer t(prof, "fill");
   LDDMM_LAUNCH(t.start, t.stop, k_fill<T>, ew_blocks(n), 256, 0, st, n, value, y);
@@ -208,6 +230,8 @@ void launch_fill(long long n, T value, T* y, hipStream_t st, Profiler* prof) {
   template void launch_minmax<T>(const T*, long long, double*, double*, hipStream_t, Profiler*);            \
   template void launch_axpby<T>(long long, double, const T*, double, T*, hipStream_t, Profiler*);           \
   template void launch_axpbyz<T>(long long, double, const T*, double, const T*, T*, hipStream_t, Profiler*); \
+  template void launch_cg_step<T>(long long, double, double, const double*, const T*, const T*, T*, T*,      \
+                                  hipStream_t, Profiler*);                                                  \
   template void launch_fill<T>(long long, T, T*, hipStream_t, Profiler*);
 
 LDDMM_RINST(float)
