@@ -141,6 +141,32 @@ def test_plane_walk_matches_one_plane_per_workgroup(dtype, grid):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("opts", [{}, {"fft.static": 0}, {"fft.force_split": 1}, {"fft.plane_grid": 7}])
+def test_sweeps_under_transform_paths(dtype, opts):
+    """The adjoint and Newton stages hand K's addend to the transform: the inverse
+    plane pass adds it on the compile-time path (one plane per workgroup or a
+    plane walk), an axpy after the transform does on the generic and split paths.
+    Gradient, GN Hv and Newton Hv against the oracle on each path."""
+    n = (32, 32, 32)
+    R, p = make(n, dtype, sigma2=0.05)
+    for k, v in opts.items():
+        R.set_option(k, v)
+    say(f"  options {opts} fused={R.get_option('fft.fused')} static_kernels={R.get_option('fft.static_kernels')} "
+        f"plane_walk={R.get_option('fft.plane_walk')}")
+    I0, I1 = images(n)
+    R.set_images(T(I0, dtype), T(I1, dtype))
+    v0 = random_velocity(n, 2004, 1.5, kc=2.0)
+    dv = random_field(n, 7, kc=3.0)
+    go, lin = O.gradient(v0, I0, I1, p)
+    g, _ = R.gradient(T(v0, dtype))
+    errs = dict(grad=rel(g, go), hv=rel(R.hessvec(T(dv, dtype)), O.hessvec(dv, lin, p)),
+                hv_newton=rel(R.hessvec(T(dv, dtype), newton=True), O.hessvec_newton(dv, lin, p)))
+    say("  ", errs)
+    assert errs["grad"] <= TOL[dtype]["grad"]
+    assert errs["hv"] <= TOL[dtype]["hv"] and errs["hv_newton"] <= TOL[dtype]["hv"]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_operator_head_grid_180x216x180(dtype):
     """Brain-shaped grid (radices 2, 3, 4, 5, 8): fused compile-time planes in
     FP32, the split path in FP64 (the half-plane exceeds the LDS)."""
@@ -274,6 +300,7 @@ def test_row_vectorised_stencils(n, dtype):
     tr = O.shoot(v0, p, I0)
     go, lin = O.gradient(v0, I0, I1, p)
     ho = O.hessvec(dv, lin, p)
+    hn = O.hessvec_newton(dv, lin, p)
     widths = [0] + [vw for vw in (1, 2, 4) if n[2] % vw == 0 and n[2] // vw in (32, 64)]
     shapes = [(vw, pr) for vw in widths for pr in ((0, 1) if vw and n[2] // vw == 32 else (1,))]
     for rowvec, pair in shapes:
@@ -285,10 +312,13 @@ def test_row_vectorised_stencils(n, dtype):
         out = R.shoot(T(v0, dtype))
         g, E = R.gradient(T(v0, dtype))
         hv = R.hessvec(T(dv, dtype))
-        errs = dict(v1=rel(out["v1"], tr.v[-1]), J1=rel(out["J1"], tr.J1), grad=rel(g, go), hv=rel(hv, ho))
+        hvn = R.hessvec(T(dv, dtype), newton=True)
+        errs = dict(v1=rel(out["v1"], tr.v[-1]), J1=rel(out["J1"], tr.J1), grad=rel(g, go), hv=rel(hv, ho),
+                    hv_newton=rel(hvn, hn))
         say(f"  rowvec={rowvec} pair_rows={pair}", errs)
         assert errs["v1"] <= TOL[dtype]["shoot"] and errs["J1"] <= TOL[dtype]["shoot"]
         assert errs["grad"] <= TOL[dtype]["grad"] and errs["hv"] <= TOL[dtype]["hv"]
+        assert errs["hv_newton"] <= TOL[dtype]["hv"]
         assert E == pytest.approx(lin.E, rel=TOL[dtype]["shoot"])
 
 
