@@ -529,13 +529,16 @@ class Engine {
   }
 
   // ---- tangent sweep: X_nt from X_0 = 0, dmu_0 = L dv ------------------------
+  // The first stage's K dmu_0 = K L dv is dv itself (K = L^-1 symbol by symbol),
+  // so it takes dv without a transform.
   void tangent(const T* dv) {
     applyL(dv, Mu);
     launch_fill<T>(3 * N, T(0), X, st, &prof);
     for (int n = 0; n < P.nt; ++n) {
       const Step c = traj_view(n);
-      applyK(Mu, W);
-      launch_tangent_stage<T>(g, X, Mu, W, c.v, c.mu, nullptr, nullptr, Xs, Mus, dt, 0.0, 1.0, st, &prof);
+      if (n > 0) applyK(Mu, W);
+      launch_tangent_stage<T>(g, X, Mu, n > 0 ? W : dv, c.v, c.mu, nullptr, nullptr, Xs, Mus, dt, 0.0, 1.0, st,
+                              &prof);
       applyK(Mus, W);
       launch_tangent_stage<T>(g, Xs, Mus, W, c.vs, c.mus, X, Mu, X, Mu, dt, 0.5, 0.5, st, &prof);
     }
@@ -643,7 +646,10 @@ class Engine {
     for (int n = 0; n < P.nt; ++n) {
       const Step c = traj_view(n);
       copy(tdmu[n], Mu, V);
-      applyK(Mu, tdmuK[n]);
+      if (n > 0)
+        applyK(Mu, tdmuK[n]);
+      else
+        copy(tdmuK[0], dv, V);  // K L dv = dv
       launch_tangent_stage<T>(g, X, Mu, tdmuK[n], c.v, c.mu, nullptr, nullptr, Xs, Mus, dt, 0.0, 1.0, st, &prof);
       copy(tdmus[n], Mus, V);
       applyK(Mus, tdmusK[n]);
