@@ -1121,11 +1121,13 @@ template <typename T>
 FftTuning default_tuning(const SpectralPlan<T>& sp) {
   FftTuning t;
   const size_t cb = sizeof(cplx<T>);
-  // measured best on MI355X at 32^3 .. 256^3: 1024-thread plane workgroups,
-  // 256-thread pencil workgroups with 128-byte (FP32) / 128-byte (FP64) rows
+  // measured best on MI355X at 32^3 .. 256^3 inside the Hessian-vector product:
+  // 1024-thread plane workgroups, 256-thread pencil workgroups with 256-byte rows
+  // (32 FP32 / 16 FP64 pencils); the autotuner keeps this start unless another
+  // shape is clearly faster
   t.plane_threads = 1024;
   t.pencil_threads = 256;
-  int tb = int(128 / cb);
+  int tb = int(256 / cb);
   while (tb > 1 && ((size_t(sp.n0) * tb + sp.n0) * cb + sp.n0 * sizeof(T) > sp.max_lds ||
                     (size_t(sp.n1) * tb + sp.n1) * cb > sp.max_lds))
     tb /= 2;

@@ -515,23 +515,30 @@ class Engine {
     launch_adjoint_stage<T>(g, U, Wh, c.mus, c.vs, nullptr, nullptr, Z, Qw, Us, dt, 0.0, 1.0, st, &prof);
     applyK_add(Z, Qw, dt, Whs);
   }
-  void adjoint_corr(const Step& c) {
-    launch_adjoint_stage<T>(g, Us, Whs, c.mu, c.v, U, Wh, Z, Qw, U, dt, 0.5, 0.5, st, &prof);
-    applyK_add(Z, Qw, 0.5 * dt, Wh);
+  // out = w (default Wh) + 2 vadd when vadd is given
+  void adjoint_corr(const Step& c, T* out = nullptr, const T* vadd = nullptr) {
+    launch_adjoint_stage<T>(g, Us, Whs, c.mu, c.v, U, Wh, Z, Qw, U, dt, 0.5, 0.5, st, &prof, vadd, 2.0);
+    applyK_add(Z, Qw, 0.5 * dt, out ? out : Wh);
   }
-  void backward() {
+  // With out: the last stage writes 2 vadd + w_0 (the V-gradient form) to out
+  // instead of w_0 to Wh.
+  void backward(T* out = nullptr, const T* vadd = nullptr) {
     launch_fill<T>(3 * N, T(0), Wh, st, &prof);
     for (int n = P.nt - 1; n >= 0; --n) {
       const Step c = traj_view(n);
       adjoint_pred(c);
-      adjoint_corr(c);
+      if (n == 0 && out)
+        adjoint_corr(c, out, vadd);
+      else
+        adjoint_corr(c);
     }
   }
 
   // ---- tangent sweep: X_nt from X_0 = 0, dmu_0 = L dv ------------------------
   // The first stage's K dmu_0 = K L dv is dv itself (K = L^-1 symbol by symbol),
-  // so it takes dv without a transform.
-  void tangent(const T* dv) {
+  // so it takes dv without a transform.  With Ufin the last stage writes the GN
+  // final condition (2 / sigma^2) (G . X_nt) G to Ufin instead of X_nt.
+  void tangent(const T* dv, T* Ufin = nullptr) {
     applyL(dv, Mu);
     launch_fill<T>(3 * N, T(0), X, st, &prof);
     for (int n = 0; n < P.nt; ++n) {
@@ -540,14 +547,17 @@ class Engine {
       launch_tangent_stage<T>(g, X, Mu, n > 0 ? W : dv, c.v, c.mu, nullptr, nullptr, Xs, Mus, dt, 0.0, 1.0, st,
                               &prof);
       applyK(Mus, W);
-      launch_tangent_stage<T>(g, Xs, Mus, W, c.vs, c.mus, X, Mu, X, Mu, dt, 0.5, 0.5, st, &prof);
+      if (Ufin && n == P.nt - 1)
+        launch_tangent_stage<T>(g, Xs, Mus, W, c.vs, c.mus, X, Mu, Ufin, nullptr, dt, 0.5, 0.5, st, &prof, G,
+                                2.0 / P.sigma2);
+      else
+        launch_tangent_stage<T>(g, Xs, Mus, W, c.vs, c.mus, X, Mu, X, Mu, dt, 0.5, 0.5, st, &prof);
     }
   }
 
   void gradient_core(T* gout) {
     launch_scalar_times_vec<T>(g, res, G, -2.0 / P.sigma2, U, st, &prof);
-    backward();
-    launch_axpbyz<T>(3 * N, 2.0, lin_v0, 1.0, Wh, gout, st, &prof);
+    backward(gout, lin_v0);  // gout = 2 v0 + w_0
   }
 
   int gradient(const T* v0, T* gout, double* energy_out) {
@@ -557,10 +567,8 @@ class Engine {
   }
 
   void hessvec_kernels(const T* dv, T* hv) {
-    tangent(dv);
-    launch_gn_final<T>(g, G, X, 2.0 / P.sigma2, U, st, &prof);
-    backward();
-    launch_axpbyz<T>(3 * N, 2.0, dv, 1.0, Wh, hv, st, &prof);
+    tangent(dv, U);      // U = (2 / sigma^2) (G . X_nt) G
+    backward(hv, dv);    // hv = 2 dv + w_0
   }
 
   void drop_graph() {

@@ -183,7 +183,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
     k_tangent_stage(Geo<T> g, const T* __restrict__ X, const T* __restrict__ dmu, const T* __restrict__ W,
                     const T* __restrict__ v, const T* __restrict__ mu, const T* X0, const T* dmu0, T* X_out,
-                    T* dmu_out, T dt, T a0, T a1) {
+                    T* dmu_out, T dt, T a0, T a1, const T* __restrict__ Gf, T cf) {
   int i0, i1, i2;
   if (!voxel(g, i0, i1, i2)) return;
   const Nbr nb = neighbours(g, i0, i1, i2);
@@ -215,6 +215,15 @@ __global__ void __launch_bounds__(256)
       mo[c] += a0 * m0v[c];
     }
   }
+  if (Gf) {  // last stage of the sweep: X_out receives cf (G . X) G, dmu is not kept
+    T gv[3];
+    load1(gv, Gf, nb.o[0], g.N);
+    const T sg = cf * (gv[0] * xo[0] + gv[1] * xo[1] + gv[2] * xo[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xo[c] = sg * gv[c];
+    store1(X_out, xo, nb.o[0], g.N);
+    return;
+  }
   store1(X_out, xo, nb.o[0], g.N);
   store1(dmu_out, mo, nb.o[0], g.N);
 }
@@ -226,7 +235,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
     k_adjoint_stage(Geo<T> g, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ mu,
                     const T* __restrict__ v, const T* U0, const T* w0, T* __restrict__ Z, T* __restrict__ Q,
-                    T* U_out, T dt, T a0, T a1) {
+                    T* U_out, T dt, T a0, T a1, const T* __restrict__ qadd, T qs) {
   int i0, i1, i2;
   if (!voxel(g, i0, i1, i2)) return;
   const Nbr nb = neighbours(g, i0, i1, i2);
@@ -264,6 +273,12 @@ __global__ void __launch_bounds__(256)
       uo[c] += a0 * u0[c];
       q[c] += a0 * ww0[c];
     }
+  }
+  if (qadd) {
+    T qa[3];
+    load1(qa, qadd, nb.o[0], g.N);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q[c] += qs * qa[c];
   }
   store1(Z, z, nb.o[0], g.N);
   store1(Q, q, nb.o[0], g.N);
@@ -622,7 +637,7 @@ template <typename T, int VW, bool PAIR>
 __global__ void __launch_bounds__(256)
     k_tangent_stage_v(Geo<T> g, int RW, const T* __restrict__ X, const T* __restrict__ dmu, const T* __restrict__ W,
                       const T* __restrict__ v, const T* __restrict__ mu, const T* X0, const T* dmu0, T* X_out,
-                      T* dmu_out, T dt, T a0, T a1) {
+                      T* dmu_out, T dt, T a0, T a1, const T* __restrict__ Gf, T cf) {
   VNbr<VW> nb;
   if (!vvoxel<T, VW>(g, RW, nb)) return;
   T x[3][VW], vc[3][VW], dm[3][VW];
@@ -659,6 +674,18 @@ __global__ void __launch_bounds__(256)
     }
   vheun<T, VW>(xo, X0, a0, nb.o, g.N);
   vheun<T, VW>(mo, dmu0, a0, nb.o, g.N);
+  if (Gf) {  // last stage of the sweep: X_out receives cf (G . X) G, dmu is not kept
+    T gv[3][VW];
+    vload3<T, VW>(gv, Gf, nb.o, g.N);
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+      const T sg = cf * (gv[0][k] * xo[0][k] + gv[1][k] * xo[1][k] + gv[2][k] * xo[2][k]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xo[c][k] = sg * gv[c][k];
+    }
+    vstore3<T, VW>(X_out, xo, nb.o, g.N);
+    return;
+  }
   vstore3<T, VW>(X_out, xo, nb.o, g.N);
   vstore3<T, VW>(dmu_out, mo, nb.o, g.N);
 }
@@ -667,7 +694,7 @@ template <typename T, int VW, bool PAIR>
 __global__ void __launch_bounds__(256)
     k_adjoint_stage_v(Geo<T> g, int RW, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ mu,
                       const T* __restrict__ v, const T* U0, const T* w0, T* __restrict__ Z, T* __restrict__ Q,
-                      T* U_out, T dt, T a0, T a1) {
+                      T* U_out, T dt, T a0, T a1, const T* __restrict__ qadd, T qs) {
   VNbr<VW> nb;
   if (!vvoxel<T, VW>(g, RW, nb)) return;
   T u[3][VW], vc[3][VW], wc[3][VW], m[3][VW];
@@ -705,6 +732,7 @@ __global__ void __launch_bounds__(256)
     }
   vheun<T, VW>(q, w0, a0, nb.o, g.N);
   vheun<T, VW>(uo, U0, a0, nb.o, g.N);
+  if (qadd) vheun<T, VW>(q, qadd, qs, nb.o, g.N);
   vstore3<T, VW>(Z, z, nb.o, g.N);
   vstore3<T, VW>(Q, q, nb.o, g.N);
   vstore3<T, VW>(U_out, uo, nb.o, g.N);
@@ -853,25 +881,27 @@ void launch_epdiff_stage(const Grid& g, const T* v, const T* mu, const T* mu0, T
 template <typename T>
 void launch_tangent_stage(const Grid& g, const T* X, const T* dmu, const T* W, const T* v, const T* mu,
                           const T* X0, const T* dmu0, T* X_out, T* dmu_out, double dt, double a0, double a1,
-                          hipStream_t st, Profiler* prof) {
+                          hipStream_t st, Profiler* prof, const T* Gfin, double cfin) {
   KernelTimer t(prof, a0 != 0.0 ? "tangent_stage_corr" : "tangent_stage_pred");
   if (const int VW = row_vector_width(g)) {
     LDDMM_ROWVEC(k_tangent_stage_v, X, dmu, W, v, mu, X0 ? X0 : X, dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt), T(a0),
-                 T(a1));
+                 T(a1), Gfin, T(cfin));
     return;
   }
-  LDDMM_LAUNCH(t.start, t.stop, k_tangent_stage<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), X, dmu, W, v, mu, X0 ? X0 : X, dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt), T(a0), T(a1));
+  LDDMM_LAUNCH(t.start, t.stop, k_tangent_stage<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), X, dmu, W, v, mu, X0 ? X0 : X, dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt), T(a0), T(a1), Gfin, T(cfin));
 }
 
 template <typename T>
 void launch_adjoint_stage(const Grid& g, const T* U, const T* w, const T* mu, const T* v, const T* U0, const T* w0,
-                          T* Z, T* Q, T* U_out, double dt, double a0, double a1, hipStream_t st, Profiler* prof) {
+                          T* Z, T* Q, T* U_out, double dt, double a0, double a1, hipStream_t st, Profiler* prof,
+                          const T* qadd, double qs) {
   KernelTimer t(prof, a0 != 0.0 ? "adjoint_stage_corr" : "adjoint_stage_pred");
   if (const int VW = row_vector_width(g)) {
-    LDDMM_ROWVEC(k_adjoint_stage_v, U, w, mu, v, U0 ? U0 : U, w0 ? w0 : w, Z, Q, U_out, T(dt), T(a0), T(a1));
+    LDDMM_ROWVEC(k_adjoint_stage_v, U, w, mu, v, U0 ? U0 : U, w0 ? w0 : w, Z, Q, U_out, T(dt), T(a0), T(a1), qadd,
+                 T(qs));
     return;
   }
-  LDDMM_LAUNCH(t.start, t.stop, k_adjoint_stage<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), U, w, mu, v, U0 ? U0 : U, w0 ? w0 : w, Z, Q, U_out, T(dt), T(a0), T(a1));
+  LDDMM_LAUNCH(t.start, t.stop, k_adjoint_stage<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), U, w, mu, v, U0 ? U0 : U, w0 ? w0 : w, Z, Q, U_out, T(dt), T(a0), T(a1), qadd, T(qs));
 }
 
 template <typename T>
@@ -927,9 +957,11 @@ void launch_jacobian_det(const Grid& g, const T* u, T* det, hipStream_t st, Prof
   template void launch_epdiff_stage<T>(const Grid&, const T*, const T*, const T*, T*, double, double, double,    \
                                        hipStream_t, Profiler*);                                                  \
   template void launch_tangent_stage<T>(const Grid&, const T*, const T*, const T*, const T*, const T*, const T*, \
-                                        const T*, T*, T*, double, double, double, hipStream_t, Profiler*);       \
+                                        const T*, T*, T*, double, double, double, hipStream_t, Profiler*,        \
+                                        const T*, double);                                                       \
   template void launch_adjoint_stage<T>(const Grid&, const T*, const T*, const T*, const T*, const T*, const T*, \
-                                        T*, T*, T*, double, double, double, hipStream_t, Profiler*);             \
+                                        T*, T*, T*, double, double, double, hipStream_t, Profiler*, const T*,    \
+                                        double);                                                                 \
   template void launch_residual_grad<T>(const Grid&, const T*, const T*, T*, T*, hipStream_t, Profiler*);       \
   template void launch_scalar_times_vec<T>(const Grid&, const T*, const T*, double, T*, hipStream_t, Profiler*); \
   template void launch_gn_final<T>(const Grid&, const T*, const T*, double, T*, hipStream_t, Profiler*);        \
