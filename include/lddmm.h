@@ -263,11 +263,12 @@ int lddmm_get_option(lddmm_ctx* ctx, const char* key, int64_t* value);
  * compile-time vs generic kernels, plane walk over one workgroup per compute
  * unit or two planes per workgroup) and the stencil widths ("stencil.rowvec",
  * "stencil.pair_rows", timed on the tangent stage) on this context's grid with HIP events
- * (reps applications each) and keep the fastest; the shape in place when the
- * call starts is kept unless another is more than 3 % faster, so repeated
- * calls settle on the same shape.  *tried = variants timed,
- * *ms_per_apply = best time of one K application of a vector field (either
- * may be NULL).  Synchronises. */
+ * (reps repetitions each; a transform shape is timed as a K application followed
+ * by a tangent stage, the way the sweeps use it) and keep the fastest; the shape
+ * in place when the call starts is kept unless another is more than 3 % faster,
+ * so repeated calls settle on the same shape.  *tried = variants timed,
+ * *ms_per_apply = one K application of a vector field with the chosen shape
+ * (either may be NULL).  Synchronises. */
 int lddmm_autotune(lddmm_ctx* ctx, int reps, int* tried, double* ms_per_apply);
 
 /* Wait for all work of the context's stream. */
