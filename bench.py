@@ -74,6 +74,7 @@ def log(*a):
 TUNED_KEYS = (
     "fft.plane_threads",
     "fft.plane_grid",
+    "fft.plane_halves_used",
     "fft.pencil_threads",
     "fft.pencil_tb",
     "fft.rows_rb",
@@ -122,9 +123,9 @@ def recorded_traffic(kernel, tuned):
 def shape_keys(kernel):
     """Launch-shape options that change a kernel's memory traffic."""
     if kernel.startswith("fft_pencil"):
-        return ("fft.pencil_tb", "fft.pencil_threads", "fft.fused", "fft.static_kernels")
+        return ("fft.pencil_tb", "fft.pencil_threads", "fft.fused", "fft.static_kernels", "fft.plane_halves_used")
     if kernel.startswith("fft_"):
-        return ("fft.plane_threads", "fft.rows_rb", "fft.fused", "fft.static_kernels")
+        return ("fft.plane_threads", "fft.rows_rb", "fft.fused", "fft.static_kernels", "fft.plane_halves_used")
     return ("stencil.rowvec",)
 
 
@@ -396,11 +397,13 @@ def main():
         if args.shape and dtype == torch.float32:
             shape = json.loads(args.shape)
             for key, val in shape.items():
-                if key in ("fft.fused", "fft.static_kernels"):
-                    if R.get_option(key) != val:
-                        raise SystemExit(f"bench.py: launch shape {key}={val} is not what this grid gives")
-                else:
+                if key == "fft.plane_halves_used":
+                    R.set_option("fft.plane_halves", val)
+                elif key not in ("fft.fused", "fft.static_kernels"):
                     R.set_option(key, val)
+            for key in ("fft.fused", "fft.static_kernels", "fft.plane_halves_used"):
+                if key in shape and R.get_option(key) != shape[key]:
+                    raise SystemExit(f"bench.py: launch shape {key}={shape[key]} is not what this grid gives")
             log(f"[bench] launch shape set: {shape}")
         elif not args.no_tune:
             tried, ms = R.autotune(reps=5)

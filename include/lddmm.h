@@ -237,6 +237,17 @@ int lddmm_profile_read(lddmm_ctx* ctx, const char** names, int64_t* counts, doub
  *                                           (compile-time plane kernels; not with 1024 threads
  *                                           in FP64)
  *   "fft.plane_walk"      read-only: workgroups of the plane walk in use (0: none)
+ *   "fft.plane_halves"    0 | 1             1: the even and the odd x1 rows of a plane are two
+ *                                           workgroups' units (half the LDS, twice the units,
+ *                                           so the units spread evenly over the compute
+ *                                           units), each transformed along x1 at half length;
+ *                                           the x0 pencil pass merges the two halves (the first
+ *                                           radix-2 step of the x1 transform) before its
+ *                                           transform and splits them after.  Needs an even N1,
+ *                                           compile-time kernels for the grid, no plane walk
+ *                                           and an even fft.pencil_tb of 8 to 32; otherwise
+ *                                           whole planes are used.  Default 1
+ *   "fft.plane_halves_used" read-only: 1 if half planes are in use
  *   "fft.fused"           read-only: 1 if the fused plane path is in use
  *   "fft.static_kernels"  read-only: number of passes using compile-time kernels
  *   "traj.policy"         read-only: 0 store-all, 1 checkpoint, 2 recompute

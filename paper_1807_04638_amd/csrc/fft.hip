@@ -269,6 +269,13 @@ struct PencilArgs {
   const T* ksq0;
   const T* ksq1;
   const T* ksq2;
+  // MODE 3 (x0 pencils over half planes): sequence q pairs slot q of the even
+  // half (at +0) with slot q of the odd half (at +hs); twx[k1 slot] = W_{n1}^{k1}
+  // with k1 the half transform's frequency; ksq1 holds |k1|^2 for k1 (first
+  // k1half entries) and k1 + n1/2 (next k1half) per slot
+  int hs;
+  int k1half;
+  const cplx<T>* twx;
 };
 
 // MODE 0: forward only, 1: inverse only, 2: forward, symbol, inverse.
@@ -469,7 +476,7 @@ __device__ __forceinline__ void rows_c2r_static(cplx<T>* A, const cplx<T>* tw2, 
 }
 
 // First DIF stage of COUNT rows of length H straight from global memory (row s
-// at src + s * H), in two halves: rows_first_load brings a thread's inputs into
+// at src + s * RS, RS = H for consecutive rows), in two halves: rows_first_load brings a thread's inputs into
 // registers and rows_first_compute transforms them into LDS rows of stride H + 1,
 // so the loads of the next plane can be in flight while the current one is
 // transformed.  Lanes walk a row's butterflies first, so each load is a
@@ -481,7 +488,7 @@ struct RowStageIn {
   cplx<T> v[iters][R];
 };
 
-template <typename T, int H, int COUNT, int NT>
+template <typename T, int H, int COUNT, int NT, int RS = H>
 __device__ __forceinline__ void rows_first_load(RowStageIn<T, H, COUNT, NT>& in, const cplx<T>* __restrict__ src) {
   using I = RowStageIn<T, H, COUNT, NT>;
 #pragma unroll
@@ -490,7 +497,7 @@ __device__ __forceinline__ void rows_first_load(RowStageIn<T, H, COUNT, NT>& in,
     if (I::total % NT != 0 && b >= I::total) continue;
     const int r = b / I::S, j = b - r * I::S;
 #pragma unroll
-    for (int q = 0; q < I::R; ++q) in.v[it][q] = src[r * H + j + q * I::S];
+    for (int q = 0; q < I::R; ++q) in.v[it][q] = src[r * RS + j + q * I::S];
   }
 }
 
@@ -519,9 +526,9 @@ __device__ __forceinline__ void rows_first_compute(cplx<T>* A, RowStageIn<T, H, 
 }
 
 // Last DIT stage of COUNT rows (the inverse of the first row stage) straight to
-// global memory (row s at dst + s * H).  ADD: dst = add + scale * (result), the
+// global memory (row s at dst + s * RS).  ADD: dst = add + scale * (result), the
 // addend (same layout as dst) loaded before the butterfly so its latency overlaps.
-template <typename T, int H, int COUNT, int NT, bool ADD = false>
+template <typename T, int H, int COUNT, int NT, bool ADD = false, int RS = H>
 __device__ __forceinline__ void rows_last_stage_global(const cplx<T>* A, cplx<T>* __restrict__ dst,
                                                        const cplx<T>* tw, const cplx<T>* __restrict__ add = nullptr,
                                                        T scale = T(0)) {
@@ -536,7 +543,7 @@ __device__ __forceinline__ void rows_last_stage_global(const cplx<T>* A, cplx<T>
     cplx<T> ad[ADD ? R : 1];
     if constexpr (ADD) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) ad[q] = add[r * H + j + q * S];
+      for (int q = 0; q < R; ++q) ad[q] = add[r * RS + j + q * S];
     }
     cplx<T> v[R];
     v[0] = A[r * M + j];
@@ -555,7 +562,7 @@ __device__ __forceinline__ void rows_last_stage_global(const cplx<T>* A, cplx<T>
       for (int q = 0; q < R; ++q) v[q] = {ad[q].x + scale * v[q].x, ad[q].y + scale * v[q].y};
     }
 #pragma unroll
-    for (int q = 0; q < R; ++q) dst[r * H + j + q * S] = v[q];
+    for (int q = 0; q < R; ++q) dst[r * RS + j + q * S] = v[q];
   }
 }
 
@@ -585,35 +592,42 @@ __device__ __forceinline__ PlaneLds<T> carve_static(unsigned char* smem, int row
 // apart before the store: with Z the transform of X[0] + i X[N2/2] along x1,
 // the two spectra are (Z[k] + conj Z[-k]) / 2 and (Z[k] - conj Z[-k]) / 2i.
 //
-// Plane p of a call is component p / n0 at x0 = p % n0.  WALK = false: one
-// plane per workgroup, grid (n0, components).  WALK = true: a 1D grid of G
+// Plane p of a call is component p / n0 at x0 = p % n0.  XS = 2 (half planes):
+// unit p is the even (h = 0) or odd (h = 1) x1 rows of plane p / 2, N1 of them,
+// a transform of length N1 along x1 whose spectrum the x0 pencil pass merges
+// with the other half's (the first radix-2 step of the length-2 N1 transform,
+// by decimation in x1); units of one plane are consecutive in the spectrum, so
+// the layout is [component][x0][h][k1 slot][k2 slot].  With XS = 1 every unit
+// is a whole plane.  WALK = false: one unit per workgroup, grid (XS n0,
+// components).  WALK = true: a 1D grid of G
 // workgroups, workgroup g taking planes g, g + G, g + 2G, ...; the inputs of the
 // next plane's first stage are loaded into registers while the current plane
 // is transformed and stored, so with fewer workgroups than planes the memory
 // phases of consecutive planes overlap inside one workgroup.
-template <typename T, int H, int N1, int NT, bool WALK>
+template <typename T, int H, int N1, int NT, bool WALK, int XS = 1>
 __global__ void __launch_bounds__(NT) k_plane_fwd_s(const T* __restrict__ in, cplx<T>* __restrict__ spec,
                                                     PlaneArgs<T> a) {
   using P1 = typename PlanOf<N1>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int M = H + 1;
   PlaneLds<T> L = carve_static<T, H, N1>(smem, N1, a, true);
-  const long long plane_len = (long long)N1 * 2 * H;
+  const long long plane_len = (long long)N1 * XS * 2 * H;  // reals of one (x1, x2) plane
+  const int per_comp = a.n0 * XS;
   auto plane_src = [&](int q) {
-    const int comp = q / a.n0, x0 = q - comp * a.n0;
-    return reinterpret_cast<const cplx<T>*>(in + comp * a.N + x0 * plane_len);
+    const int comp = q / per_comp, r = q - comp * per_comp, x0 = r / XS, h = r - x0 * XS;
+    return reinterpret_cast<const cplx<T>*>(in + comp * a.N + x0 * plane_len + h * 2 * H);
   };
-  int p = WALK ? int(blockIdx.x) : int(blockIdx.y) * a.n0 + int(blockIdx.x);
+  int p = WALK ? int(blockIdx.x) : int(blockIdx.y) * per_comp + int(blockIdx.x);
   // the first plane's row twiddles come from global memory: the LDS copy is
   // complete only after the first barrier
   const cplx<T>* tw_first = a.tw2;
   RowStageIn<T, H, N1, NT> rin;
-  rows_first_load<T, H, N1, NT>(rin, plane_src(p));
+  rows_first_load<T, H, N1, NT, XS * H>(rin, plane_src(p));
   for (;;) {
     rows_first_compute<T, H, N1, NT>(L.A, rin, tw_first);
     __syncthreads();
     const int pn = WALK ? p + int(gridDim.x) : a.planes;
-    if (WALK && pn < a.planes) rows_first_load<T, H, N1, NT>(rin, plane_src(pn));
+    if (WALK && pn < a.planes) rows_first_load<T, H, N1, NT, XS * H>(rin, plane_src(pn));
     rows_r2c_static<T, H, N1, NT, true, 1>(L.A, L.tw2, L.twr, L.slot2);
     lds_fft_static<T, P1, false, true, H, M, 1, NT, 0, P1::nf - 1>(L.A, L.tw1);
     // Last column stage (stride 1, no twiddles) straight to the spectrum:
@@ -737,15 +751,16 @@ __device__ __forceinline__ void cols_first_stage_global(cplx<T>* A, const cplx<T
   }
 }
 
-template <typename T, int H, int N1, int NT, bool WALK, bool ADD = false>
+template <typename T, int H, int N1, int NT, bool WALK, bool ADD = false, int XS = 1>
 __global__ void __launch_bounds__(NT) k_plane_inv_s(const cplx<T>* __restrict__ spec, T* __restrict__ out,
                                                     PlaneArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int M = H + 1;
   using P1 = typename PlanOf<N1>::type;
   PlaneLds<T> L = carve_static<T, H, N1>(smem, N1, a, true);
-  const long long plane_len = (long long)N1 * 2 * H;
-  int p = WALK ? int(blockIdx.x) : int(blockIdx.y) * a.n0 + int(blockIdx.x);
+  const long long plane_len = (long long)N1 * XS * 2 * H;
+  const int per_comp = a.n0 * XS;
+  int p = WALK ? int(blockIdx.x) : int(blockIdx.y) * per_comp + int(blockIdx.x);
   // first column stage straight from the spectrum, consecutive threads on
   // consecutive columns; one plane per workgroup loads and transforms in one go
   // (fewer live registers), the walk keeps the next plane's inputs in registers
@@ -761,13 +776,14 @@ __global__ void __launch_bounds__(NT) k_plane_inv_s(const cplx<T>* __restrict__ 
     if (WALK && pn < a.planes) cols_first_load<T, H, N1, NT>(cin, spec + (long long)pn * (N1 * M));
     lds_fft_static<T, P1, true, true, H, M, 1, NT, 1>(L.A, L.tw1);
     rows_c2r_static<T, H, N1, NT, true, 1>(L.A, L.tw2, L.twr, L.slot2);
-    const int comp = p / a.n0, x0 = p - comp * a.n0;
-    cplx<T>* dst = reinterpret_cast<cplx<T>*>(out + comp * a.N + x0 * plane_len);
+    const int comp = p / per_comp, r = p - comp * per_comp, x0 = r / XS, h = r - x0 * XS;
+    const long long off = comp * a.N + x0 * plane_len + h * 2 * H;
+    cplx<T>* dst = reinterpret_cast<cplx<T>*>(out + off);
     if constexpr (ADD)
-      rows_last_stage_global<T, H, N1, NT, true>(
-          L.A, dst, L.tw2, reinterpret_cast<const cplx<T>*>(a.add + comp * a.N + x0 * plane_len), a.add_scale);
+      rows_last_stage_global<T, H, N1, NT, true, XS * H>(L.A, dst, L.tw2,
+                                                         reinterpret_cast<const cplx<T>*>(a.add + off), a.add_scale);
     else
-      rows_last_stage_global<T, H, N1, NT>(L.A, dst, L.tw2);
+      rows_last_stage_global<T, H, N1, NT, false, XS * H>(L.A, dst, L.tw2);
     if (!WALK || pn >= a.planes) break;
     __syncthreads();  // the last row stage reads the LDS the next plane overwrites
     p = pn;
@@ -822,26 +838,33 @@ __global__ void __launch_bounds__(NT) k_rows_inv_s(const cplx<T>* __restrict__ s
 
 // Pencils along an axis of power-of-two length N, TB per workgroup; each thread
 // keeps one sequence t = tid % TB, so the symbol's (k1, k2) part is looked up
-// once per sequence.
+// once per sequence.  MODE 3 is MODE 2 over half planes: TB pairs per
+// workgroup, the pair's two half-plane spectra Y0 (even x1 rows) and Y1 (odd)
+// become the pencils of k1 and k1 + n1/2 on load (X = Y0 +- W_{n1}^{k1} Y1), and
+// go back to halves on store (Y0 = Xa + Xb, Y1 = conj(W_{n1}^{k1}) (Xa - Xb)), so
+// the LDS holds TS = 2 TB sequences.
 template <typename T, int MODE, int N, int TB, int NT>
 __global__ void __launch_bounds__(NT) k_pencil_s(cplx<T>* __restrict__ spec, PencilArgs<T> a) {
-  static_assert(NT % TB == 0, "threads must cover whole rows of the tile");
+  constexpr bool PAIR = MODE == 3;
+  constexpr int TS = PAIR ? 2 * TB : TB;
+  static_assert(NT % TS == 0, "threads must cover whole rows of the tile");
   using PN = typename PlanOf<N>::type;
   static_assert(PN::nf >= 2, "first and last stages are fused with different neighbours");
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* tw = A + N * TB;
+  cplx<T>* tw = A + N * TS;
   T* ksq0 = reinterpret_cast<T*>(tw + N);
   T* ksq12 = ksq0 + N;
   for (int i = threadIdx.x; i < N; i += NT) tw[i] = a.tw[i];
   const int q0 = blockIdx.x * TB;
   const int cnt = (a.nin - q0) < TB ? (a.nin - q0) : TB;
-  if (MODE == 2) {
+  if (MODE >= 2) {
     for (int i = threadIdx.x; i < N; i += NT) ksq0[i] = a.ksq0[i];
-    if (threadIdx.x < TB) {
-      const int q = q0 + int(threadIdx.x);
+    if (threadIdx.x < TS) {
+      const int u = int(threadIdx.x), hb = PAIR ? u / TB : 0;
+      const int q = q0 + u - hb * TB;
       const int s1 = q / a.M, s2 = q - s1 * a.M;
-      ksq12[threadIdx.x] = q < a.nin ? a.ksq1[s1] + a.ksq2[s2] : T(0);
+      ksq12[u] = q < a.nin ? a.ksq1[hb * a.k1half + s1] + a.ksq2[s2] : T(0);
     }
   }
   const int t = int(threadIdx.x) % TB;
@@ -849,7 +872,38 @@ __global__ void __launch_bounds__(NT) k_pencil_s(cplx<T>* __restrict__ spec, Pen
   const bool live = t < cnt;
   constexpr int R0 = PN::radix(0), S0 = N / R0;  // first DIF / last DIT stage
   constexpr int total0 = TB * S0;
-  if (MODE != 1) {
+  cplx<T> wx = {T(1), T(0)};  // W_{n1}^{k1} of the thread's pair
+  if (PAIR && live) wx = a.twx[(q0 + t) / a.M];
+  if (PAIR) {
+    // first DIF stage of both pencils of a pair straight from the two halves
+#pragma unroll
+    for (int b0 = 0; b0 < total0; b0 += NT) {
+      const int b = b0 + int(threadIdx.x);
+      if (total0 % NT != 0 && b >= total0) continue;
+      const int j = b / TB;
+      cplx<T> va[R0], vb[R0];
+#pragma unroll
+      for (int q = 0; q < R0; ++q) {
+        const long long o = (long long)(j + q * S0) * a.es + t;
+        const cplx<T> y0 = live ? base[o] : cplx<T>{T(0), T(0)};
+        const cplx<T> y1 = live ? base[o + a.hs] : cplx<T>{T(0), T(0)};
+        const cplx<T> wy = c_mul(wx, y1);
+        va[q] = {y0.x + wy.x, y0.y + wy.y};
+        vb[q] = {y0.x - wy.x, y0.y - wy.y};
+      }
+      Dft<T, R0, -1>::run(va);
+      Dft<T, R0, -1>::run(vb);
+      A[j * TS + t] = va[0];
+      A[j * TS + TB + t] = vb[0];
+      cplx<T> w[R0];
+      twiddle_powers<T, R0>(w, j, 1, a.tw);
+#pragma unroll
+      for (int q = 1; q < R0; ++q) {
+        A[(j + q * S0) * TS + t] = c_mul(va[q], w[q]);
+        A[(j + q * S0) * TS + TB + t] = c_mul(vb[q], w[q]);
+      }
+    }
+  } else if (MODE != 1) {
     // first DIF stage straight from the spectrum: consecutive lanes take
     // consecutive pencils (contiguous); twiddles from global memory (the LDS copy
     // is complete only after the barrier)
@@ -877,16 +931,44 @@ __global__ void __launch_bounds__(NT) k_pencil_s(cplx<T>* __restrict__ spec, Pen
     }
   }
   __syncthreads();
-  if (MODE == 2) {
-    lds_fft_static<T, PN, false, true, TB, TB, 1, NT, 1, PN::nf - 1>(A, tw);
-    fused_symbol_stage<T, PN, TB, TB, NT>(A, ksq0, ksq12[t], a.alpha, a.s, a.scale, a.op == LDDMM_OP_K);
-    lds_fft_static<T, PN, true, true, TB, TB, 1, NT, 1, PN::nf - 1>(A, tw);
+  if (MODE >= 2) {
+    lds_fft_static<T, PN, false, true, TS, TS, 1, NT, 1, PN::nf - 1>(A, tw);
+    fused_symbol_stage<T, PN, TS, TS, NT>(A, ksq0, ksq12[int(threadIdx.x) % TS], a.alpha, a.s, a.scale,
+                                          a.op == LDDMM_OP_K);
+    lds_fft_static<T, PN, true, true, TS, TS, 1, NT, 1, PN::nf - 1>(A, tw);
   } else if (MODE == 0) {
     lds_fft_static<T, PN, false, true, TB, TB, 1, NT, 1>(A, tw);
   } else {
     lds_fft_static<T, PN, true, true, TB, TB, 1, NT, 0, PN::nf - 1>(A, tw);
   }
-  if (MODE != 0) {
+  if (PAIR) {
+    // last DIT stage of both pencils, then back to the two halves
+#pragma unroll
+    for (int b0 = 0; b0 < total0; b0 += NT) {
+      const int b = b0 + int(threadIdx.x);
+      if (total0 % NT != 0 && b >= total0) continue;
+      const int j = b / TB;
+      cplx<T> va[R0], vb[R0], w[R0];
+      twiddle_powers<T, R0>(w, j, 1, tw);
+      va[0] = A[j * TS + t];
+      vb[0] = A[j * TS + TB + t];
+#pragma unroll
+      for (int q = 1; q < R0; ++q) {
+        va[q] = c_mulc(A[(j + q * S0) * TS + t], w[q]);
+        vb[q] = c_mulc(A[(j + q * S0) * TS + TB + t], w[q]);
+      }
+      Dft<T, R0, +1>::run(va);
+      Dft<T, R0, +1>::run(vb);
+      if (live) {
+#pragma unroll
+        for (int q = 0; q < R0; ++q) {
+          const long long o = (long long)(j + q * S0) * a.es + t;
+          base[o] = {va[q].x + vb[q].x, va[q].y + vb[q].y};
+          base[o + a.hs] = c_mulc(cplx<T>{va[q].x - vb[q].x, va[q].y - vb[q].y}, wx);
+        }
+      }
+    }
+  } else if (MODE != 0) {
     // last DIT stage straight to the spectrum
 #pragma unroll
     for (int b0 = 0; b0 < total0; b0 += NT) {
@@ -981,6 +1063,51 @@ void plane_static(const FftPlan& p2, const FftPlan& p1, void*& f, void*& i, void
   f = i = ia = nullptr;
 }
 
+// Half planes (XS = 2): N1 is half the x1 length; one unit per workgroup.
+template <typename T, int NT>
+void plane_static_halves(const FftPlan& p2, const FftPlan& p1h, void*& f, void*& i, void*& ia) {
+  const int H = p2.n, N1 = p1h.n;
+#define LDDMM_HALVES_CASE(h, n1)                                                                   \
+  if (H == h && N1 == n1 && plan_matches<PlanOf<h>::type>(p2) && plan_matches<PlanOf<n1>::type>(p1h)) { \
+    f = (void*)(PlaneFwdFn<T>)k_plane_fwd_s<T, h, n1, NT, false, 2>;                               \
+    i = (void*)(PlaneInvFn<T>)k_plane_inv_s<T, h, n1, NT, false, false, 2>;                        \
+    ia = (void*)(PlaneInvFn<T>)k_plane_inv_s<T, h, n1, NT, false, true, 2>;                        \
+    return;                                                                                        \
+  }
+  LDDMM_HALVES_CASE(8, 8)
+  LDDMM_HALVES_CASE(16, 16)
+  LDDMM_HALVES_CASE(32, 32)
+  LDDMM_HALVES_CASE(64, 64)
+  LDDMM_HALVES_CASE(128, 128)
+  LDDMM_HALVES_CASE(40, 40)
+  LDDMM_HALVES_CASE(48, 48)
+  LDDMM_HALVES_CASE(56, 56)
+#undef LDDMM_HALVES_CASE
+  f = i = ia = nullptr;
+}
+
+// x0 pencils with the symbol over half planes, TBP pairs per workgroup
+template <typename T>
+void* pencil_static_pairs(const FftPlan& pl, int TBP) {
+  const int N = pl.n;
+#define LDDMM_PAIRS_N(n)                                                                 \
+  if (N == n && plan_matches<PlanOf<n>::type>(pl)) {                                     \
+    if (TBP == 4) return (void*)(PencilFn<T>)k_pencil_s<T, 3, n, 4, 256>;                \
+    if (TBP == 8) return (void*)(PencilFn<T>)k_pencil_s<T, 3, n, 8, 256>;                \
+    if (TBP == 16) return (void*)(PencilFn<T>)k_pencil_s<T, 3, n, 16, 256>;              \
+  }
+  LDDMM_PAIRS_N(16)
+  LDDMM_PAIRS_N(32)
+  LDDMM_PAIRS_N(64)
+  LDDMM_PAIRS_N(128)
+  LDDMM_PAIRS_N(256)
+  LDDMM_PAIRS_N(80)
+  LDDMM_PAIRS_N(96)
+  LDDMM_PAIRS_N(112)
+#undef LDDMM_PAIRS_N
+  return nullptr;
+}
+
 template <typename T, int MODE>
 void* pencil_static(const FftPlan& pl, int TB) {
   const int N = pl.n;
@@ -1047,8 +1174,21 @@ int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& 
   const int n0 = sp.n0, n1 = sp.n1, H = sp.H, M = sp.M;
   const int tb = tune.pencil_tb;
   const size_t tables = size_t(H + H / 2 + 1) * cb + size_t(H + 1) * sizeof(int);
-  const size_t plane_lds = size_t(n1) * M * cb + size_t(n1) * cb + tables;
-  const bool fused = !tune.force_split && plane_lds <= sp.max_lds;
+  size_t plane_lds = size_t(n1) * M * cb + size_t(n1) * cb + tables;
+  // half planes: compile-time kernels only, one unit per workgroup, pencil
+  // tiles of whole pairs
+  void* hk[4] = {nullptr, nullptr, nullptr, nullptr};
+  const int n1h = n1 / 2;
+  const size_t half_lds = size_t(n1h) * M * cb + size_t(n1h) * cb + tables;
+  if (tune.plane_halves && !tune.force_split && tune.plane_grid == 0 && tune.use_static && sp.tw1h &&
+      tune.pencil_threads == 256 && tb % 2 == 0 && half_lds <= sp.max_lds) {
+    if (tune.plane_threads == 512) plane_static_halves<T, 512>(sp.p2, sp.p1h, hk[0], hk[1], hk[2]);
+    if (tune.plane_threads == 1024) plane_static_halves<T, 1024>(sp.p2, sp.p1h, hk[0], hk[1], hk[2]);
+    hk[3] = pencil_static_pairs<T>(sp.p0, tb / 2);
+  }
+  const bool halves = hk[0] && hk[3];
+  if (halves) plane_lds = half_lds;
+  const bool fused = halves || (!tune.force_split && plane_lds <= sp.max_lds);
   // the compile-time pencils also keep TB per-sequence symbol terms
   const size_t p0 = (size_t(n0) * tb + n0) * cb + size_t(n0 + tb) * sizeof(T);
   const size_t p1 = (size_t(n1) * tb + n1) * cb + size_t(n1 + tb) * sizeof(T);
@@ -1063,7 +1203,13 @@ int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& 
   // plane walk: compile-time plane kernels only
   const bool walk = tune.plane_grid > 0;
   int plane_grid = 0;
-  if (fused) {
+  if (halves) {
+    k[KF_PLANE_FWD] = hk[0];
+    k[KF_PLANE_INV] = hk[1];
+    k[KF_PLANE_INV_ADD] = hk[2];
+    k[KF_PENCIL0] = hk[3];
+    nstatic += 2;
+  } else if (fused) {
     if (use_static) {
       if (tune.plane_threads == 512 && walk) plane_static<T, 512, true>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV], k[KF_PLANE_INV_ADD]);
       if (tune.plane_threads == 512 && !walk) plane_static<T, 512, false>(sp.p2, sp.p1, k[KF_PLANE_FWD], k[KF_PLANE_INV], k[KF_PLANE_INV_ADD]);
@@ -1104,11 +1250,13 @@ int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& 
       k[KF_PENCIL1I] = pencil_generic<T>(1, tune.pencil_threads);
     }
   }
-  if (use_static && tune.pencil_threads == 256) k[KF_PENCIL0] = pencil_static<T, 2>(sp.p0, tb);
-  if (k[KF_PENCIL0])
-    nstatic++;
-  else
-    k[KF_PENCIL0] = pencil_generic<T>(2, tune.pencil_threads);
+  if (!halves) {
+    if (use_static && tune.pencil_threads == 256) k[KF_PENCIL0] = pencil_static<T, 2>(sp.p0, tb);
+    if (k[KF_PENCIL0])
+      nstatic++;
+    else
+      k[KF_PENCIL0] = pencil_generic<T>(2, tune.pencil_threads);
+  }
   for (void* f : k)
     if (f && hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, int(sp.max_lds)) !=
                  hipSuccess) {
@@ -1117,6 +1265,7 @@ int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& 
     }
   sp.tune = tune;
   sp.fused = fused;
+  sp.halves = halves;
   sp.plane_grid = plane_grid;
   sp.plane_lds = plane_lds;
   sp.pencil0_lds = p0;
@@ -1132,11 +1281,19 @@ FftTuning default_tuning(const SpectralPlan<T>& sp) {
   FftTuning t;
   const size_t cb = sizeof(cplx<T>);
   // measured best on MI355X at 32^3 .. 256^3 inside the Hessian-vector product:
-  // 1024-thread plane workgroups, 256-thread pencil workgroups with 256-byte rows
-  // (32 FP32 / 16 FP64 pencils); the autotuner keeps this start unless another
-  // shape is clearly faster
+  // 1024-thread plane workgroups (512 for FP32 half planes), 256-thread pencil
+  // workgroups with 256-byte rows (32 FP32 / 16 FP64 pencils); the autotuner
+  // keeps this start unless another shape is clearly faster
   t.plane_threads = 1024;
   t.pencil_threads = 256;
+  // half planes where compile-time kernels exist (spectral_configure falls back
+  // to whole planes otherwise)
+  t.plane_halves = 1;
+  if (sizeof(T) == 4 && sp.tw1h) {
+    void *f = nullptr, *i = nullptr, *ia = nullptr;
+    plane_static_halves<T, 512>(sp.p2, sp.p1h, f, i, ia);
+    if (f) t.plane_threads = 512;
+  }
   int tb = int(256 / cb);
   while (tb > 1 && ((size_t(sp.n0) * tb + sp.n0) * cb + sp.n0 * sizeof(T) > sp.max_lds ||
                     (size_t(sp.n1) * tb + sp.n1) * cb > sp.max_lds))
@@ -1190,6 +1347,23 @@ int spectral_init(SpectralPlan<T>& sp, const int n[3], size_t max_lds, std::stri
   if ((rc = upload(&sp.ksq0, k0, by))) return rc;
   if ((rc = upload(&sp.ksq1, k1, by))) return rc;
   if ((rc = upload(&sp.ksq2, k2, by))) return rc;
+  // half-plane tables: the x1 transform of half length, the merge twiddles
+  // W_{n1}^{k1} and |k1|^2, |k1 + n1/2|^2 per slot of the half transform
+  if (n[1] % 2 == 0 && n[1] >= 8 && make_plan(n[1] / 2, sp.p1h)) {
+    const int h1 = n[1] / 2;
+    if ((rc = upload(&sp.tw1h, twiddles<T>(h1, h1), by))) return rc;
+    std::vector<cplx<T>> wx(h1);
+    std::vector<T> kx(n[1]);
+    for (int p = 0; p < h1; ++p) {
+      const int k = digit_reverse(sp.p1h, p);
+      const double ang = -2.0 * M_PI * double(k) / double(n[1]);
+      wx[p] = {T(std::cos(ang)), T(std::sin(ang))};
+      kx[p] = T(fold_sq(k, n[1]));
+      kx[h1 + p] = T(fold_sq(k + h1, n[1]));
+    }
+    if ((rc = upload(&sp.twx, wx, by))) return rc;
+    if ((rc = upload(&sp.ksq1x, kx, by))) return rc;
+  }
   const size_t spec_bytes = size_t(3) * n[0] * n[1] * M * sizeof(cplx<T>);
   if (hipMalloc(reinterpret_cast<void**>(&sp.spec), spec_bytes) != hipSuccess) {
     err = "out of device memory (spectrum workspace)";
@@ -1202,7 +1376,7 @@ int spectral_init(SpectralPlan<T>& sp, const int n[3], size_t max_lds, std::stri
 
 template <typename T>
 void spectral_free(SpectralPlan<T>& sp) {
-  void* ptrs[] = {sp.tw0, sp.tw1, sp.tw2, sp.twr, sp.slot2, sp.ksq0, sp.ksq1, sp.ksq2, sp.spec};
+  void* ptrs[] = {sp.tw0, sp.tw1, sp.tw2, sp.twr, sp.slot2, sp.ksq0, sp.ksq1, sp.ksq2, sp.spec, sp.tw1h, sp.twx, sp.ksq1x};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   sp = SpectralPlan<T>();
@@ -1245,13 +1419,29 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   k0.ksq0 = sp.ksq0;
   k0.ksq1 = sp.ksq1;
   k0.ksq2 = sp.ksq2;
-  const dim3 g0((P + tu.pencil_tb - 1) / tu.pencil_tb, ncomp);
+  k0.hs = 0;
+  k0.k1half = 0;
+  k0.twx = nullptr;
+  dim3 g0((P + tu.pencil_tb - 1) / tu.pencil_tb, ncomp);
+  if (sp.halves) {
+    // units (component, x0, h): the x1 transform of half length; pencils in pairs
+    pa.planes = 2 * ncomp * sp.n0;
+    pa.tw1 = sp.tw1h;
+    const int tbp = tu.pencil_tb / 2, pairs = P / 2;
+    k0.nin = pairs;
+    k0.tb = tbp;
+    k0.hs = pairs;
+    k0.k1half = sp.n1 / 2;
+    k0.ksq1 = sp.ksq1x;
+    k0.twx = sp.twx;
+    g0 = dim3((pairs + tbp - 1) / tbp, ncomp);
+  }
   const PencilFn<T> pencil0 = (PencilFn<T>)sp.kfn[KF_PENCIL0];
 
   if (sp.fused) {
     // plane walk: at most plane_grid workgroups, never more than there are planes
     const dim3 gp = sp.plane_grid > 0 ? dim3(unsigned(sp.plane_grid < pa.planes ? sp.plane_grid : pa.planes))
-                                      : dim3(sp.n0, ncomp);
+                                      : dim3(sp.halves ? 2 * sp.n0 : sp.n0, ncomp);
     {
       KernelTimer t(prof, "fft_plane_fwd");
       LDDMM_LAUNCH(t.start, t.stop, ((PlaneFwdFn<T>)sp.kfn[KF_PLANE_FWD]), gp, tu.plane_threads, sp.plane_lds, st, in, sp.spec, pa);

@@ -710,6 +710,7 @@ class Engine {
     if (reps <= 0) reps = 5;
     (void)hipStreamSynchronize(st);
     const FftTuning start = sp.tune;
+    const bool start_halves = sp.halves;  // in use, not only requested
     FftTuning best = start;
     float best_ms = -1.f, start_ms = -1.f;
     int count = 0;
@@ -725,16 +726,20 @@ class Engine {
     for (int pt : {512, 1024})
       for (int tb : {8, 16, 32})
         for (int stc : {1, 0})
-          for (int gi = 0; gi < 3; ++gi) {
-          if (gi > 0 && (grids[gi] == 0 || stc == 0 || grids[gi] == grids[gi - 1])) continue;
+          for (int gi = 0; gi < 4; ++gi) {
+          // gi = 0: half planes; 1: whole planes, one per workgroup; 2, 3: plane walks
+          if (gi > 1 && (grids[gi - 1] == 0 || stc == 0 || grids[gi - 1] == grids[gi - 2])) continue;
+          if (gi == 0 && stc == 0) continue;
           FftTuning t = start;
           t.plane_threads = pt;
           t.pencil_tb = tb;
           t.pencil_threads = 256;
           t.use_static = stc;
-          t.plane_grid = grids[gi];
+          t.plane_grid = gi > 0 ? grids[gi - 1] : 0;
+          t.plane_halves = gi == 0 ? 1 : 0;
           std::string msg;
           if (spectral_configure(sp, t, msg) != 0) continue;
+          if (gi == 0 && !sp.halves) continue;  // no half-plane kernels for this shape
           // each K application is followed by a tangent stage, as in the sweeps:
           // timed alone, back to back, the shapes rank differently than in use
           applyK(W, Z);
@@ -754,7 +759,7 @@ class Engine {
           }
           if (t.plane_threads == start.plane_threads && t.pencil_tb == start.pencil_tb &&
               t.pencil_threads == start.pencil_threads && t.use_static == start.use_static &&
-              t.plane_grid == start.plane_grid)
+              t.plane_grid == start.plane_grid && (t.plane_halves != 0) == start_halves)
             start_ms = ms;
         }
     // Keep the starting shape unless another one is clearly faster: variants
@@ -1062,6 +1067,8 @@ class Engine {
       t.use_static = value != 0;
     else if (k == "fft.plane_grid")
       t.plane_grid = int(value);
+    else if (k == "fft.plane_halves")
+      t.plane_halves = value != 0;
     else if (k == "exec.graph") {
       if (value != 0 && !st) return fail(LDDMM_EINVAL, "exec.graph needs a non-default stream");
       (void)hipStreamSynchronize(st);
@@ -1116,6 +1123,10 @@ class Engine {
       *value = g.pair_rows;
     else if (k == "fft.plane_walk")
       *value = sp.plane_grid;
+    else if (k == "fft.plane_halves")
+      *value = t.plane_halves;
+    else if (k == "fft.plane_halves_used")
+      *value = sp.halves ? 1 : 0;
     else if (k == "traj.policy")
       *value = traj_policy;
     else if (k == "traj.every")

@@ -120,6 +120,7 @@ struct FftTuning {
   int force_split = 0;       // 1: use the split path even where the plane fits the LDS
   int use_static = 1;        // 1: compile-time kernels where instantiated (power-of-two lengths)
   int plane_grid = 0;        // 0: one (x1, x2) plane per workgroup; G > 0: G workgroups walk the planes
+  int plane_halves = 0;      // 1: even and odd x1 rows of a plane as two units, merged in the x0 pencil pass
 };
 
 template <typename T>
@@ -135,7 +136,12 @@ struct SpectralPlan {
   T* ksq1 = nullptr;
   T* ksq2 = nullptr;
   cplx<T>* spec = nullptr;                   // workspace: 3 * n0 * n1 * M complex
+  FftPlan p1h{};                             // length n1 / 2 (half planes; n = 0 when n1 is odd)
+  cplx<T>* tw1h = nullptr;                   // exp(-2 pi i m / (n1 / 2))
+  cplx<T>* twx = nullptr;                    // exp(-2 pi i k1 / n1) per slot of the half transform
+  T* ksq1x = nullptr;                        // |k1|^2, then |k1 + n1/2|^2, per slot of the half transform
   bool fused = false;                        // (x2, x1) plane fits one workgroup's LDS
+  bool halves = false;                       // half planes in use
   size_t plane_lds = 0, pencil0_lds = 0, pencil1_lds = 0, rows_lds = 0;
   size_t max_lds = 0;                        // LDS bytes available to one workgroup
   FftTuning tune{};

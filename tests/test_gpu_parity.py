@@ -98,7 +98,8 @@ def test_operator_parity(n, dtype):
 @pytest.mark.parametrize("n", [(32, 32, 32), (64, 64, 64), (16, 32, 64), (80, 80, 80), (112, 112, 112)])
 @pytest.mark.parametrize("opts", [{"fft.static": 0}, {"fft.static": 1}, {"fft.force_split": 1},
                                   {"fft.force_split": 1, "fft.static": 0}, {"fft.plane_threads": 256, "fft.pencil_tb": 32},
-                                  {"fft.plane_grid": 7}, {"fft.plane_grid": 2, "fft.plane_threads": 512}])
+                                  {"fft.plane_grid": 7}, {"fft.plane_grid": 2, "fft.plane_threads": 512},
+                                  {"fft.plane_halves": 0}, {"fft.plane_threads": 512, "fft.pencil_tb": 8}])
 def test_operator_transform_variants(n, dtype, opts):
     """Every transform path (compile-time / generic kernels, fused / split passes,
     launch shapes, plane walks with a ragged last round) against the oracle on
@@ -107,7 +108,7 @@ def test_operator_transform_variants(n, dtype, opts):
     for k, v in opts.items():
         R.set_option(k, v)
     say(f"  options {opts} fused={R.get_option('fft.fused')} static_kernels={R.get_option('fft.static_kernels')} "
-        f"plane_walk={R.get_option('fft.plane_walk')}")
+        f"plane_walk={R.get_option('fft.plane_walk')} halves={R.get_option('fft.plane_halves_used')}")
     f = rounded(random_field(n, 3, kc=max(n) / 3), dtype)
     Lf = O.apply_L(f, p)
     assert rel(R.apply_K(T(f, dtype)), O.apply_K(f, p)) <= TOL[dtype]["op"]
@@ -124,7 +125,9 @@ def test_plane_walk_matches_one_plane_per_workgroup(dtype, grid):
     R, p = make(n, dtype, alpha=0.0025)
     f = rounded(random_field(n, 21, kc=20.0), dtype)
     ft = T(f, dtype)
+    R.set_option("fft.plane_halves", 0)
     R.set_option("fft.plane_grid", 0)
+    assert R.get_option("fft.plane_halves_used") == 0
     ref_K, ref_L = R.apply_K(ft).clone(), R.apply_L(ft).clone()
     ref_s = R.apply_K(ft[1].contiguous()).clone()
     threads = 1024 if dtype == torch.float32 else 512
@@ -141,7 +144,8 @@ def test_plane_walk_matches_one_plane_per_workgroup(dtype, grid):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("opts", [{}, {"fft.static": 0}, {"fft.force_split": 1}, {"fft.plane_grid": 7}])
+@pytest.mark.parametrize("opts", [{}, {"fft.static": 0}, {"fft.force_split": 1}, {"fft.plane_grid": 7},
+                                  {"fft.plane_halves": 0}])
 def test_sweeps_under_transform_paths(dtype, opts):
     """The adjoint and Newton stages hand K's addend to the transform: the inverse
     plane pass adds it on the compile-time path (one plane per workgroup or a
@@ -152,7 +156,7 @@ def test_sweeps_under_transform_paths(dtype, opts):
     for k, v in opts.items():
         R.set_option(k, v)
     say(f"  options {opts} fused={R.get_option('fft.fused')} static_kernels={R.get_option('fft.static_kernels')} "
-        f"plane_walk={R.get_option('fft.plane_walk')}")
+        f"plane_walk={R.get_option('fft.plane_walk')} halves={R.get_option('fft.plane_halves_used')}")
     I0, I1 = images(n)
     R.set_images(T(I0, dtype), T(I1, dtype))
     v0 = random_velocity(n, 2004, 1.5, kc=2.0)
@@ -164,6 +168,33 @@ def test_sweeps_under_transform_paths(dtype, opts):
     say("  ", errs)
     assert errs["grad"] <= TOL[dtype]["grad"]
     assert errs["hv"] <= TOL[dtype]["hv"] and errs["hv_newton"] <= TOL[dtype]["hv"]
+
+
+@pytest.mark.parametrize("n, dtype", [((128, 128, 128), torch.float32), ((128, 128, 128), torch.float64),
+                                      ((256, 256, 256), torch.float32), ((96, 80, 80), torch.float64)])
+def test_half_planes_match_whole_planes(n, dtype):
+    """Half planes (even and odd x1 rows as separate units, merged by the x0
+    pencil pass) give the transform of whole planes (or, where a whole plane
+    exceeds the LDS, of the split passes), for vector and scalar fields, K and L,
+    and the adjoint stage's fused addend; and K stays within the oracle's
+    tolerance at 128^3."""
+    R, p = make(n, dtype, alpha=0.0025)
+    f = rounded(random_field(n, 23, kc=20.0), dtype)
+    ft = T(f, dtype)
+    assert R.get_option("fft.plane_halves_used") == 1
+    got = [R.apply_K(ft).clone(), R.apply_L(ft).clone(), R.apply_K(ft[2].contiguous()).clone()]
+    R.set_option("fft.plane_halves", 0)
+    assert R.get_option("fft.plane_halves_used") == 0
+    say(f"  reference path: fused={R.get_option('fft.fused')}")
+    ref = [R.apply_K(ft), R.apply_L(ft), R.apply_K(ft[2].contiguous())]
+    # two roundings of L's transforms, each within the bound against the exact result
+    tol_l = 2 * l_tol(p, f, ref[1].double().cpu().numpy(), dtype)
+    for a, b, tol in zip(got, ref, (TOL[dtype]["op"], tol_l, TOL[dtype]["op"])):
+        e = rel(a, b.cpu())
+        say(f"  halves vs whole: rel {e:.2e} (tol {tol:.1e})")
+        assert e <= tol
+    if n == (128, 128, 128):
+        assert rel(got[0], O.apply_K(f, p)) <= TOL[dtype]["op"]
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
