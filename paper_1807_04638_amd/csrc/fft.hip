@@ -1044,13 +1044,16 @@ enum { KF_PLANE_FWD, KF_PLANE_INV, KF_ROWS_FWD, KF_ROWS_INV, KF_PENCIL0, KF_PENC
 template <typename T, int NT, bool WALK>
 void plane_static(const FftPlan& p2, const FftPlan& p1, void*& f, void*& i, void*& ia) {
   const int H = p2.n, N1 = p1.n;
+// The walk keeps a plane's first-stage inputs in registers: not offered for
+// planes larger than 64 x 128 complex, where they would spill.
 #define LDDMM_PLANE_CASE(h, n1)                                                                   \
-  if (H == h && N1 == n1 && plan_matches<PlanOf<h>::type>(p2) && plan_matches<PlanOf<n1>::type>(p1)) { \
-    f = (void*)(PlaneFwdFn<T>)k_plane_fwd_s<T, h, n1, NT, WALK>;                                  \
-    i = (void*)(PlaneInvFn<T>)k_plane_inv_s<T, h, n1, NT, WALK, false>;                           \
-    ia = (void*)(PlaneInvFn<T>)k_plane_inv_s<T, h, n1, NT, WALK, true>;                           \
-    return;                                                                                       \
-  }
+  if constexpr (!WALK || (h) * (n1) <= 64 * 128)                                                  \
+    if (H == h && N1 == n1 && plan_matches<PlanOf<h>::type>(p2) && plan_matches<PlanOf<n1>::type>(p1)) { \
+      f = (void*)(PlaneFwdFn<T>)k_plane_fwd_s<T, h, n1, NT, WALK>;                                \
+      i = (void*)(PlaneInvFn<T>)k_plane_inv_s<T, h, n1, NT, WALK, false>;                         \
+      ia = (void*)(PlaneInvFn<T>)k_plane_inv_s<T, h, n1, NT, WALK, true>;                         \
+      return;                                                                                     \
+    }
   LDDMM_PLANE_CASE(8, 16)
   LDDMM_PLANE_CASE(16, 32)
   LDDMM_PLANE_CASE(32, 64)
@@ -1082,6 +1085,7 @@ void plane_static_halves(const FftPlan& p2, const FftPlan& p1h, void*& f, void*&
   LDDMM_HALVES_CASE(40, 40)
   LDDMM_HALVES_CASE(48, 48)
   LDDMM_HALVES_CASE(56, 56)
+  LDDMM_HALVES_CASE(90, 108)
 #undef LDDMM_HALVES_CASE
   f = i = ia = nullptr;
 }
@@ -1104,6 +1108,7 @@ void* pencil_static_pairs(const FftPlan& pl, int TBP) {
   LDDMM_PAIRS_N(80)
   LDDMM_PAIRS_N(96)
   LDDMM_PAIRS_N(112)
+  LDDMM_PAIRS_N(180)
 #undef LDDMM_PAIRS_N
   return nullptr;
 }
@@ -1290,9 +1295,10 @@ FftTuning default_tuning(const SpectralPlan<T>& sp) {
   // to whole planes otherwise)
   t.plane_halves = 1;
   if (sizeof(T) == 4 && sp.tw1h) {
+    // small FP32 half planes (up to 64 x 65 complex) run best with 512 threads
     void *f = nullptr, *i = nullptr, *ia = nullptr;
     plane_static_halves<T, 512>(sp.p2, sp.p1h, f, i, ia);
-    if (f) t.plane_threads = 512;
+    if (f && size_t(sp.n1 / 2) * sp.M <= size_t(64) * 65) t.plane_threads = 512;
   }
   int tb = int(256 / cb);
   while (tb > 1 && ((size_t(sp.n0) * tb + sp.n0) * cb + sp.n0 * sizeof(T) > sp.max_lds ||

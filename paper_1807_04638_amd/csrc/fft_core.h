@@ -390,6 +390,7 @@ LDDMM_PLAN(56, 8, 7)
 LDDMM_PLAN(80, 8, 2, 5)
 LDDMM_PLAN(90, 2, 3, 3, 5)
 LDDMM_PLAN(96, 8, 4, 3)
+LDDMM_PLAN(108, 4, 3, 3, 3)
 LDDMM_PLAN(112, 8, 2, 7)
 LDDMM_PLAN(180, 4, 3, 3, 5)
 LDDMM_PLAN(216, 8, 3, 3, 3)

@@ -175,9 +175,9 @@ def test_sweeps_under_transform_paths(dtype, opts):
 def test_half_planes_match_whole_planes(n, dtype):
     """Half planes (even and odd x1 rows as separate units, merged by the x0
     pencil pass) give the transform of whole planes (or, where a whole plane
-    exceeds the LDS, of the split passes), for vector and scalar fields, K and L,
-    and the adjoint stage's fused addend; and K stays within the oracle's
-    tolerance at 128^3."""
+    exceeds the LDS, of the split passes), for vector and scalar fields, K and L;
+    and K stays within the oracle's tolerance at 128^3.  (The inverse pass that
+    adds K's addend is covered by the sweeps under the default transform path.)"""
     R, p = make(n, dtype, alpha=0.0025)
     f = rounded(random_field(n, 23, kc=20.0), dtype)
     ft = T(f, dtype)
@@ -198,12 +198,18 @@ def test_half_planes_match_whole_planes(n, dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-def test_operator_head_grid_180x216x180(dtype):
-    """Brain-shaped grid (radices 2, 3, 4, 5, 8): fused compile-time planes in
-    FP32, the split path in FP64 (the half-plane exceeds the LDS)."""
+@pytest.mark.parametrize("halves", [1, 0])
+def test_operator_head_grid_180x216x180(dtype, halves):
+    """Brain-shaped grid (radices 2, 3, 4, 5, 8): half planes (fused in both
+    precisions), or whole planes: fused compile-time planes in FP32, the split
+    path in FP64 (a whole plane exceeds the LDS)."""
     n = (180, 216, 180)
     R, p = make(n, dtype, alpha=0.0025)
-    say(f"  fused={R.get_option('fft.fused')} static_kernels={R.get_option('fft.static_kernels')}")
+    R.set_option("fft.plane_halves", halves)
+    say(f"  fused={R.get_option('fft.fused')} static_kernels={R.get_option('fft.static_kernels')} "
+        f"halves={R.get_option('fft.plane_halves_used')}")
+    assert R.get_option("fft.plane_halves_used") == halves
+    assert R.get_option("fft.fused") == (1 if halves or dtype == torch.float32 else 0)
     assert R.get_option("fft.static_kernels") >= 2
     f = rounded(random_field(n, 14, kc=10.0), dtype)
     Lf = O.apply_L(f, p)
