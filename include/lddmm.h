@@ -227,7 +227,9 @@ int lddmm_profile_read(lddmm_ctx* ctx, const char** names, int64_t* counts, doub
  * beyond rounding).  Keys:
  *   "fft.plane_threads"   256 | 512 | 1024  threads of an (x1, x2) plane workgroup
  *   "fft.pencil_threads"  256 | 512         threads of a pencil workgroup
- *   "fft.pencil_tb"       1..128            contiguous pencils per workgroup
+ *   "fft.pencil_tb"       1..128            contiguous pencils per workgroup (with half planes:
+ *                                           pencil_tb / 2 pairs of half-plane spectra, the
+ *                                           pencils of k1 and k1 + N1/2 of each pair)
  *   "fft.rows_rb"         1..64             rows per workgroup (split path)
  *   "fft.force_split"     0 | 1             split transform path even where a plane fits
  *   "fft.static"          0 | 1             compile-time kernels for power-of-two lengths
