@@ -1390,7 +1390,7 @@ void spectral_free(SpectralPlan<T>& sp) {
 
 template <typename T>
 void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, double alpha, int s, int op,
-                    hipStream_t st, Profiler* prof, const T* add, double add_scale) {
+                    hipStream_t st, Profiler* prof, const T* add, double add_scale, double out_scale) {
   PlaneArgs<T> pa;
   pa.n0 = sp.n0;
   pa.n1 = sp.n1;
@@ -1421,7 +1421,7 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   k0.alpha = T(alpha);
   k0.s = s;
   k0.op = op;
-  k0.scale = T(1.0 / (double(sp.n0) * sp.n1 * sp.n2));
+  k0.scale = T(out_scale / (double(sp.n0) * sp.n1 * sp.n2));  // the inverse's 1/N and the caller's factor
   k0.ksq0 = sp.ksq0;
   k0.ksq1 = sp.ksq1;
   k0.ksq2 = sp.ksq2;
@@ -1507,7 +1507,7 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   template FftTuning default_tuning<T>(const SpectralPlan<T>&);                                          \
   template void spectral_free<T>(SpectralPlan<T>&);                                                      \
   template void spectral_apply<T>(const SpectralPlan<T>&, const T*, T*, int, double, int, int, hipStream_t, \
-                                  Profiler*, const T*, double);
+                                  Profiler*, const T*, double, double);
 
 LDDMM_SINST(float)
 LDDMM_SINST(double)

@@ -400,6 +400,10 @@ class Engine {
   void applyK_add(const T* in, const T* add, double scale, T* out) {
     spectral_apply(sp, in, out, 3, P.alpha, P.s, LDDMM_OP_K, st, &prof, add, scale);
   }
+  // out = scale K in (vector fields)
+  void applyK_scaled(const T* in, double scale, T* out) {
+    spectral_apply(sp, in, out, 3, P.alpha, P.s, LDDMM_OP_K, st, &prof, static_cast<const T*>(nullptr), 0.0, scale);
+  }
   void copy(T* dst, const T* src, long long count) {
     (void)hipMemcpyAsync(dst, src, size_t(count) * sizeof(T), hipMemcpyDeviceToDevice, st);
   }
@@ -515,18 +519,28 @@ class Engine {
     launch_adjoint_stage<T>(g, U, Wh, c.mus, c.vs, nullptr, nullptr, Z, Qw, Us, dt, 0.0, 1.0, st, &prof);
     applyK_add(Z, Qw, dt, Whs);
   }
+  // The sweep's first stage starts from w = 0: ad*_w mu and ad_v w vanish, so
+  // Z = U and Q = 0.  The U update U + dt ad*_v U is the EPDiff stage's operator
+  // taken with -dt, and the predictor of w is dt K U.
+  void adjoint_pred_first(const Step& c) {
+    launch_epdiff_stage<T>(g, c.vs, U, nullptr, Us, -dt, 0.0, 1.0, st, &prof);
+    applyK_scaled(U, dt, Whs);
+  }
   // out = w (default Wh) + 2 vadd when vadd is given
   void adjoint_corr(const Step& c, T* out = nullptr, const T* vadd = nullptr) {
     launch_adjoint_stage<T>(g, Us, Whs, c.mu, c.v, U, Wh, Z, Qw, U, dt, 0.5, 0.5, st, &prof, vadd, 2.0);
     applyK_add(Z, Qw, 0.5 * dt, out ? out : Wh);
   }
   // With out: the last stage writes 2 vadd + w_0 (the V-gradient form) to out
-  // instead of w_0 to Wh.
+  // instead of w_0 to Wh.  (The first corrector reads the zero start value of w.)
   void backward(T* out = nullptr, const T* vadd = nullptr) {
     launch_fill<T>(3 * N, T(0), Wh, st, &prof);
     for (int n = P.nt - 1; n >= 0; --n) {
       const Step c = traj_view(n);
-      adjoint_pred(c);
+      if (n == P.nt - 1)
+        adjoint_pred_first(c);
+      else
+        adjoint_pred(c);
       if (n == 0 && out)
         adjoint_corr(c, out, vadd);
       else

@@ -161,11 +161,13 @@ template <typename T>
 int spectral_configure(SpectralPlan<T>& sp, const FftTuning& tune, std::string& err);
 template <typename T>
 FftTuning default_tuning(const SpectralPlan<T>& sp);
-// out = K in (op = 0) or L in (op = 1) for ncomp components; in == out allowed.
-// With add != nullptr: out = add + add_scale * (K or L) in, add == out allowed.
+// out = K in (op = 0) or L in (op = 1) for ncomp components, times out_scale;
+// in == out allowed.  With add != nullptr: out = add + add_scale * out_scale *
+// (K or L) in, add == out allowed.
 template <typename T>
 void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, double alpha, int s, int op,
-                    hipStream_t st, Profiler* prof, const T* add = nullptr, double add_scale = 0.0);
+                    hipStream_t st, Profiler* prof, const T* add = nullptr, double add_scale = 0.0,
+                    double out_scale = 1.0);
 
 // ---------------------------------------------------------------------------
 // Field kernels (stencils, Heun stages, final conditions) - stencil.hip
