@@ -262,8 +262,9 @@ int lddmm_profile_read(lddmm_ctx* ctx, const char** names, int64_t* counts, doub
  *   "stencil.rowvec"      0, 1, 2, 4        voxels per lane of the row-vectorised stencil
  *                                           kernels (0: one voxel per thread); nonzero
  *                                           values need N2 / value = 32 or 64.  Default:
- *                                           the smallest valid width in FP64, 0 in FP32;
- *                                           same operators, summed in another order
+ *                                           the smallest valid width in FP64, the widest
+ *                                           in FP32, 0 where none is valid; same
+ *                                           operators, summed in another order
  *   "stencil.pair_rows"   0 | 1             with N2 / rowvec = 32 and N1 even a wave holds two
  *                                           x1 rows; 1: the row each half needs from the other
  *                                           comes by a lane swap instead of a load.  Default 1

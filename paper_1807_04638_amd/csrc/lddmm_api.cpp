@@ -190,16 +190,16 @@ class Engine {
     g.h0 = 2.0 * M_PI / p.n[0];
     g.h1 = 2.0 * M_PI / p.n[1];
     g.h2 = 2.0 * M_PI / p.n[2];
-    // stencil kernels: FP64 rows of 32-256 voxels go row-vectorised by default
-    // (measured faster there); FP32 starts at one voxel per thread.  The
-    // autotuner times both.
+    // stencil kernels: rows of 32-256 voxels go row-vectorised by default, the
+    // smallest valid width in FP64 and the widest in FP32 (32-lane rows, paired
+    // where N1 is even), the widths the autotuner keeps on MI355X; other rows
+    // take one voxel per thread.  The autotuner times them all.
     g.rowvec = 0;
-    if (sizeof(T) == 8)
-      for (int vw : {1, 2, 4})
-        if (row_vector_valid(g.n2, vw)) {
-          g.rowvec = vw;
-          break;
-        }
+    for (int vw : {1, 2, 4})
+      if (row_vector_valid(g.n2, vw)) {
+        g.rowvec = vw;
+        if (sizeof(T) == 8) break;
+      }
     N = g.N;
     cell = g.h0 * g.h1 * g.h2;
     dt = 1.0 / p.nt;

@@ -631,10 +631,16 @@ FULL = (128, 128, 128)
 
 
 def full_case(dtype):
+    """The benchmark's workload size and launch configuration: the context is
+    autotuned as bench.py does before it times the solve."""
     R, p = make(FULL, dtype, nt=10, alpha=0.0025, s=2, sigma2=1.0)
     I0 = phantom(FULL, 24, (4.0, 12.0), True, 1000)
     I1 = phantom(FULL, 24, (4.0, 12.0), True, 1001)
     R.set_images(T(I0, dtype), T(I1, dtype))
+    R.autotune(reps=5)
+    keys = ("fft.plane_threads", "fft.pencil_tb", "fft.plane_halves_used", "fft.plane_walk", "stencil.rowvec",
+            "stencil.pair_rows")
+    say(f"  launch shape after autotune: { {k: R.get_option(k) for k in keys} }")
     return R, p, I0, I1
 
 
