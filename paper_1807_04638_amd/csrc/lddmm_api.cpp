@@ -108,6 +108,7 @@ class Engine {
   int cus = 0;  // compute units of the device (plane-walk candidates of the autotuner)
   hipGraphExec_t hv_exec = nullptr;
   const T* graph_dv = nullptr;
+  const T* graph_ldv = nullptr;
   T* graph_hv = nullptr;
   Profiler prof;
   SpectralPlan<T> sp;
@@ -551,21 +552,25 @@ class Engine {
   // ---- tangent sweep: X_nt from X_0 = 0, dmu_0 = L dv ------------------------
   // The first stage's K dmu_0 = K L dv is dv itself (K = L^-1 symbol by symbol),
   // so it takes dv without a transform.  With Ufin the last stage writes the GN
-  // final condition (2 / sigma^2) (G . X_nt) G to Ufin instead of X_nt.
-  void tangent(const T* dv, T* Ufin = nullptr) {
-    applyL(dv, Mu);
+  // final condition (2 / sigma^2) (G . X_nt) G to Ufin instead of X_nt.  With
+  // Ldv (= L dv, read only) the first step reads dmu_0 from there instead of
+  // applying L.
+  void tangent(const T* dv, T* Ufin = nullptr, const T* Ldv = nullptr) {
+    if (!Ldv) applyL(dv, Mu);
+    const T* Mu0 = Ldv ? Ldv : Mu;
     launch_fill<T>(3 * N, T(0), X, st, &prof);
     for (int n = 0; n < P.nt; ++n) {
       const Step c = traj_view(n);
+      const T* Min = n > 0 ? Mu : Mu0;  // dmu at the step's start
       if (n > 0) applyK(Mu, W);
-      launch_tangent_stage<T>(g, X, Mu, n > 0 ? W : dv, c.v, c.mu, nullptr, nullptr, Xs, Mus, dt, 0.0, 1.0, st,
+      launch_tangent_stage<T>(g, X, Min, n > 0 ? W : dv, c.v, c.mu, nullptr, nullptr, Xs, Mus, dt, 0.0, 1.0, st,
                               &prof);
       applyK(Mus, W);
       if (Ufin && n == P.nt - 1)
-        launch_tangent_stage<T>(g, Xs, Mus, W, c.vs, c.mus, X, Mu, Ufin, nullptr, dt, 0.5, 0.5, st, &prof, G,
+        launch_tangent_stage<T>(g, Xs, Mus, W, c.vs, c.mus, X, Min, Ufin, nullptr, dt, 0.5, 0.5, st, &prof, G,
                                 2.0 / P.sigma2);
       else
-        launch_tangent_stage<T>(g, Xs, Mus, W, c.vs, c.mus, X, Mu, X, Mu, dt, 0.5, 0.5, st, &prof);
+        launch_tangent_stage<T>(g, Xs, Mus, W, c.vs, c.mus, X, Min, X, Mu, dt, 0.5, 0.5, st, &prof);
     }
   }
 
@@ -580,15 +585,18 @@ class Engine {
     return hip_status("gradient");
   }
 
-  void hessvec_kernels(const T* dv, T* hv) {
-    tangent(dv, U);      // U = (2 / sigma^2) (G . X_nt) G
-    backward(hv, dv);    // hv = 2 dv + w_0
+  // Ldv: L dv when the caller already has it (CG keeps the L-image of its
+  // direction); else the tangent sweep applies L itself.
+  void hessvec_kernels(const T* dv, T* hv, const T* Ldv = nullptr) {
+    tangent(dv, U, Ldv);  // U = (2 / sigma^2) (G . X_nt) G
+    backward(hv, dv);     // hv = 2 dv + w_0
   }
 
   void drop_graph() {
     if (hv_exec) (void)hipGraphExecDestroy(hv_exec);
     hv_exec = nullptr;
     graph_dv = nullptr;
+    graph_ldv = nullptr;
     graph_hv = nullptr;
   }
 
@@ -597,22 +605,22 @@ class Engine {
   // (dv, hv) pair and replayed; the linearization's data change, not its
   // addresses.  Store-all trajectories only (the segment bookkeeping of the
   // other policies lives on the host), and never while profiling.
-  void hessvec_core(const T* dv, T* hv) {
+  void hessvec_core(const T* dv, T* hv, const T* Ldv = nullptr) {
     if (!use_graph || traj_policy != TRAJ_STORE_ALL || prof.enabled || !st) {
-      hessvec_kernels(dv, hv);
+      hessvec_kernels(dv, hv, Ldv);
       return;
     }
-    if (!hv_exec || graph_dv != dv || graph_hv != hv) {
+    if (!hv_exec || graph_dv != dv || graph_hv != hv || graph_ldv != Ldv) {
       drop_graph();
       hipGraph_t graph = nullptr;
       if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        hessvec_kernels(dv, hv);
+        hessvec_kernels(dv, hv, Ldv);
         return;
       }
-      hessvec_kernels(dv, hv);
+      hessvec_kernels(dv, hv, Ldv);
       if (hipStreamEndCapture(st, &graph) != hipSuccess || !graph) {
         (void)hipGetLastError();
-        hessvec_kernels(dv, hv);
+        hessvec_kernels(dv, hv, Ldv);
         return;
       }
       const hipError_t e = hipGraphInstantiate(&hv_exec, graph, nullptr, nullptr, 0);
@@ -620,10 +628,11 @@ class Engine {
       if (e != hipSuccess) {
         hv_exec = nullptr;
         (void)hipGetLastError();
-        hessvec_kernels(dv, hv);
+        hessvec_kernels(dv, hv, Ldv);
         return;
       }
       graph_dv = dv;
+      graph_ldv = Ldv;
       graph_hv = hv;
     }
     (void)hipGraphLaunch(hv_exec, st);
@@ -711,12 +720,13 @@ class Engine {
     return hip_status("hessvec_newton");
   }
 
-  // Hessian applied inside CG.
-  void apply_hessian(const T* dv, T* hv) {
+  // Hessian applied inside CG; Ldv = L dv (the GN product takes it instead of
+  // applying L to dv).
+  void apply_hessian(const T* dv, T* hv, const T* Ldv) {
     if (use_newton)
       newton_core(dv, hv);
     else
-      hessvec_core(dv, hv);
+      hessvec_core(dv, hv, Ldv);
   }
 
   // ---- autotuner: time the transform variants on this grid, keep the fastest
@@ -872,7 +882,7 @@ class Engine {
     // One host read per iteration: the step length is taken on the device from
     // <d, Hd>, and the host reads that curvature together with the new residual.
     for (it = 1; it <= maxit; ++it) {
-      apply_hessian(cd, cHd);
+      apply_hessian(cd, cHd, cLd);
       dot_dev(cLd, cHd, 3, 5);
       launch_cg_step<T>(V, rr, cell, dres + 5, cd, cHd, x, cr, st, &prof);
       applyL(cr, cLr);
