@@ -476,6 +476,33 @@ def test_cg_parity(dtype):
     assert rel(x, xo) <= (1e-10 if dtype == torch.float64 else 1e-4)
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [(32, 32, 32), (16, 12, 20)])
+@pytest.mark.parametrize("nt", [1, 2])
+def test_short_horizons(nt, n, dtype):
+    """nt = 1 and 2: the adjoint sweep's first stage (w = 0, taken as the EPDiff
+    operator with -dt and dt K U) is also its last (the one that writes 2 v + w_0
+    or 2 dv + w_0); the tangent sweep's first stage is also the one that writes
+    the GN final condition.  Gradient, Hv and CG (which hands its tracked L d to
+    the Hv) against the oracle, on the row-vectorised (32^3) and one-voxel (N2 =
+    20) stencil paths."""
+    R, p = make(n, dtype, nt=nt, sigma2=0.05)
+    I0, I1 = images(n)
+    R.set_images(T(I0, dtype), T(I1, dtype))
+    v0 = random_velocity(n, 2005, 1.0, kc=2.0)
+    g, _ = R.gradient(T(v0, dtype))
+    go, lin = O.gradient(v0, I0, I1, p)
+    dv = random_field(n, 6, kc=3.0)
+    hv = R.hessvec(T(dv, dtype))
+    x, its = R.cg_solve(g, 0.05, 5)
+    xo, its_o = O.cg_v(lambda d: O.hessvec(d, lin, p), g.double().cpu().numpy(), p, 0.05, 5)
+    errs = dict(grad=rel(g, go), hv=rel(hv, O.hessvec(dv, lin, p)), cg=rel(x, xo))
+    say(f"  nt={nt} rowvec={R.get_option('stencil.rowvec')} its {its} vs {its_o}", errs)
+    assert errs["grad"] <= TOL[dtype]["grad"] and errs["hv"] <= TOL[dtype]["hv"]
+    assert its == its_o
+    assert errs["cg"] <= (1e-10 if dtype == torch.float64 else 1e-4)
+
+
 # ------------------------------------------------------------------ a9: GN loop
 def test_gn_solve_parity_fp64():
     n = (16, 16, 16)
