@@ -527,25 +527,27 @@ class Engine {
     launch_epdiff_stage<T>(g, c.vs, U, nullptr, Us, -dt, 0.0, 1.0, st, &prof);
     applyK_scaled(U, dt, Whs);
   }
-  // out = w (default Wh) + 2 vadd when vadd is given
-  void adjoint_corr(const Step& c, T* out = nullptr, const T* vadd = nullptr) {
-    launch_adjoint_stage<T>(g, Us, Whs, c.mu, c.v, U, Wh, Z, Qw, U, dt, 0.5, 0.5, st, &prof, vadd, 2.0);
+  // out = w (default Wh) + 2 vadd when vadd is given; zero: launcher flag for a
+  // zero start value of w (not read)
+  void adjoint_corr(const Step& c, T* out = nullptr, const T* vadd = nullptr, int zero = 0) {
+    launch_adjoint_stage<T>(g, Us, Whs, c.mu, c.v, U, Wh, Z, Qw, U, dt, 0.5, 0.5, st, &prof, vadd, 2.0, zero);
     applyK_add(Z, Qw, 0.5 * dt, out ? out : Wh);
   }
   // With out: the last stage writes 2 vadd + w_0 (the V-gradient form) to out
-  // instead of w_0 to Wh.  (The first corrector reads the zero start value of w.)
+  // instead of w_0 to Wh.  The sweep starts from w = 0: the row-vectorised
+  // first corrector does not read it, the one-voxel kernels read a zero fill.
   void backward(T* out = nullptr, const T* vadd = nullptr) {
-    launch_fill<T>(3 * N, T(0), Wh, st, &prof);
+    const bool zs = stencil_zero_start(g);
+    if (!zs) launch_fill<T>(3 * N, T(0), Wh, st, &prof);
     for (int n = P.nt - 1; n >= 0; --n) {
       const Step c = traj_view(n);
-      if (n == P.nt - 1)
+      const bool first = n == P.nt - 1;
+      if (first)
         adjoint_pred_first(c);
       else
         adjoint_pred(c);
-      if (n == 0 && out)
-        adjoint_corr(c, out, vadd);
-      else
-        adjoint_corr(c);
+      const bool last = n == 0 && out;
+      adjoint_corr(c, last ? out : nullptr, last ? vadd : nullptr, first && zs ? 2 : 0);
     }
   }
 
@@ -558,19 +560,24 @@ class Engine {
   void tangent(const T* dv, T* Ufin = nullptr, const T* Ldv = nullptr) {
     if (!Ldv) applyL(dv, Mu);
     const T* Mu0 = Ldv ? Ldv : Mu;
-    launch_fill<T>(3 * N, T(0), X, st, &prof);
+    // X_0 = 0: the row-vectorised first stages do not read it, the one-voxel
+    // kernels read a zero fill
+    const bool zs = stencil_zero_start(g);
+    if (!zs) launch_fill<T>(3 * N, T(0), X, st, &prof);
     for (int n = 0; n < P.nt; ++n) {
       const Step c = traj_view(n);
       const T* Min = n > 0 ? Mu : Mu0;  // dmu at the step's start
+      const bool z0 = n == 0 && zs;
       if (n > 0) applyK(Mu, W);
       launch_tangent_stage<T>(g, X, Min, n > 0 ? W : dv, c.v, c.mu, nullptr, nullptr, Xs, Mus, dt, 0.0, 1.0, st,
-                              &prof);
+                              &prof, nullptr, 0.0, z0 ? 1 : 0);
       applyK(Mus, W);
       if (Ufin && n == P.nt - 1)
         launch_tangent_stage<T>(g, Xs, Mus, W, c.vs, c.mus, X, Min, Ufin, nullptr, dt, 0.5, 0.5, st, &prof, G,
-                                2.0 / P.sigma2);
+                                2.0 / P.sigma2, z0 ? 2 : 0);
       else
-        launch_tangent_stage<T>(g, Xs, Mus, W, c.vs, c.mus, X, Min, X, Mu, dt, 0.5, 0.5, st, &prof);
+        launch_tangent_stage<T>(g, Xs, Mus, W, c.vs, c.mus, X, Min, X, Mu, dt, 0.5, 0.5, st, &prof, nullptr, 0.0,
+                                z0 ? 2 : 0);
     }
   }
 

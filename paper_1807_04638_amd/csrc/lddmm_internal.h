@@ -181,10 +181,12 @@ void launch_epdiff_stage(const Grid& g, const T* v, const T* mu, const T* mu0, T
 //   dmu_out = a0 dmu0 + a1 (dmu + dt (-ad*_W mu - ad*_v dmu))
 // With Gfin: X_out receives cfin (Gfin . X_new) Gfin instead and dmu_out is not
 // written (the last stage of the sweep feeding the GN final condition).
+// zero (row-vectorised kernels only, see stencil_zero_start): 1, X is zero and
+// not read; 2, X0 is zero and not read.
 template <typename T>
 void launch_tangent_stage(const Grid& g, const T* X, const T* dmu, const T* W, const T* v, const T* mu,
                           const T* X0, const T* dmu0, T* X_out, T* dmu_out, double dt, double a0, double a1,
-                          hipStream_t st, Profiler* prof, const T* Gfin = nullptr, double cfin = 0.0);
+                          hipStream_t st, Profiler* prof, const T* Gfin = nullptr, double cfin = 0.0, int zero = 0);
 // Full Newton sweep (first-order adjoint terms kept).
 // Fused Newton stage with the K application left out (W = K dmu):
 //   Z = dU + ad*_dw mu + ad*_w1 dmu;  Q = a0 dw0 + a1 (dw - dt (ad_v dw + ad_W w1));
@@ -202,10 +204,14 @@ void launch_newton_final(const Grid& g, const T* G, const T* X, const T* r, doub
 //   Q     = a0 w0 + a1 (w - dt ad_v w)          (then w_out = Q + a1 dt K Z)
 //   U_out = a0 U0 + a1 (U + dt ad*_v U)
 // With qadd: Q += qs qadd (the last stage adds 2 v of the V-gradient 2 v + w_0).
+// zero (row-vectorised kernels only): 2, w0 is zero and not read.
 template <typename T>
 void launch_adjoint_stage(const Grid& g, const T* U, const T* w, const T* mu, const T* v, const T* U0, const T* w0,
                           T* Z, T* Q, T* U_out, double dt, double a0, double a1, hipStream_t st, Profiler* prof,
-                          const T* qadd = nullptr, double qs = 0.0);
+                          const T* qadd = nullptr, double qs = 0.0, int zero = 0);
+// True when the stage launchers honour `zero` (the row-vectorised kernels run);
+// otherwise the caller provides the zero fields.
+bool stencil_zero_start(const Grid& g);
 // r = J1 - I1, G = grad_h J1
 template <typename T>
 void launch_residual_grad(const Grid& g, const T* J1, const T* I1, T* r, T* G, hipStream_t st, Profiler* prof);

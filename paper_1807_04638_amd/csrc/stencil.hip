@@ -26,6 +26,8 @@ bool row_vector_valid(int n2, int vw) {
   return n2 % vw == 0 && (n2 / vw == 32 || n2 / vw == 64);
 }
 
+bool stencil_zero_start(const Grid& g) { return row_vector_valid(g.n2, g.rowvec); }
+
 FieldTiling make_field_tiling(const Grid& g) {
   FieldTiling t;
   int bx = (g.n2 + 31) / 32 * 32;
@@ -633,25 +635,30 @@ __global__ void __launch_bounds__(256)
   vstore3<T, VW>(mu_out, out, nb.o, g.N);
 }
 
-template <typename T, int VW, bool PAIR>
+// ZS (the sweep's first step starts from X = 0): bit 1, the stage's X is zero
+// and not read (no ad_v X); bit 2, its start value X0 is zero and not read.
+template <typename T, int VW, bool PAIR, int ZS = 0>
 __global__ void __launch_bounds__(256)
     k_tangent_stage_v(Geo<T> g, int RW, const T* __restrict__ X, const T* __restrict__ dmu, const T* __restrict__ W,
                       const T* __restrict__ v, const T* __restrict__ mu, const T* X0, const T* dmu0, T* X_out,
                       T* dmu_out, T dt, T a0, T a1, const T* __restrict__ Gf, T cf) {
   VNbr<VW> nb;
   if (!vvoxel<T, VW>(g, RW, nb)) return;
-  T x[3][VW], vc[3][VW], dm[3][VW];
-  vload3<T, VW>(x, X, nb.o, g.N);
+  T x[3][VW] = {}, vc[3][VW], dm[3][VW];
+  if constexpr (!(ZS & 1)) vload3<T, VW>(x, X, nb.o, g.N);
   vload3<T, VW>(vc, v, nb.o, g.N);
   vload3<T, VW>(dm, dmu, nb.o, g.N);
   T aX[3][VW] = {}, t1[3][VW] = {}, t2[3][VW] = {};
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    VPair<T, VW> Vp, Xp, Dp;
+    VPair<T, VW> Vp, Dp;
     vpair<T, VW, PAIR>(Vp, v, vc, nb, e, g.N);
-    vpair<T, VW, PAIR>(Xp, X, x, nb, e, g.N);
+    if constexpr (!(ZS & 1)) {
+      VPair<T, VW> Xp;
+      vpair<T, VW, PAIR>(Xp, X, x, nb, e, g.N);
+      vad_dir<T, VW>(aX, Vp, Xp, vc, x, e, vinv2h<T, VW, PAIR>(g, nb, e));  // ad_v X
+    }
     vpair<T, VW, PAIR>(Dp, dmu, dm, nb, e, g.N);
-    vad_dir<T, VW>(aX, Vp, Xp, vc, x, e, vinv2h<T, VW, PAIR>(g, nb, e));   // ad_v X
     vadstar_dir<T, VW>(t2, Vp, Dp, dm, e, vinv2h<T, VW, PAIR>(g, nb, e));  // ad*_v dmu
   }
   T w[3][VW], m[3][VW];
@@ -672,7 +679,7 @@ __global__ void __launch_bounds__(256)
       xo[c][k] = a1 * (x[c][k] + dt * (w[c][k] + aX[c][k]));
       mo[c][k] = a1 * (dm[c][k] - dt * (t1[c][k] + t2[c][k]));
     }
-  vheun<T, VW>(xo, X0, a0, nb.o, g.N);
+  if constexpr (!(ZS & 2)) vheun<T, VW>(xo, X0, a0, nb.o, g.N);
   vheun<T, VW>(mo, dmu0, a0, nb.o, g.N);
   if (Gf) {  // last stage of the sweep: X_out receives cf (G . X) G, dmu is not kept
     T gv[3][VW];
@@ -690,7 +697,8 @@ __global__ void __launch_bounds__(256)
   vstore3<T, VW>(dmu_out, mo, nb.o, g.N);
 }
 
-template <typename T, int VW, bool PAIR>
+// ZS bit 2: the start value w0 is zero and not read (the sweep's first corrector).
+template <typename T, int VW, bool PAIR, int ZS = 0>
 __global__ void __launch_bounds__(256)
     k_adjoint_stage_v(Geo<T> g, int RW, const T* __restrict__ U, const T* __restrict__ w, const T* __restrict__ mu,
                       const T* __restrict__ v, const T* U0, const T* w0, T* __restrict__ Z, T* __restrict__ Q,
@@ -730,7 +738,7 @@ __global__ void __launch_bounds__(256)
       q[c][k] = a1 * (wc[c][k] - dt * aw[c][k]);
       uo[c][k] = a1 * (u[c][k] + dt * aU[c][k]);
     }
-  vheun<T, VW>(q, w0, a0, nb.o, g.N);
+  if constexpr (!(ZS & 2)) vheun<T, VW>(q, w0, a0, nb.o, g.N);
   vheun<T, VW>(uo, U0, a0, nb.o, g.N);
   if (qadd) vheun<T, VW>(q, qadd, qs, nb.o, g.N);
   vstore3<T, VW>(Z, z, nb.o, g.N);
@@ -854,6 +862,29 @@ Geo<T> make_vgeo(const Grid& g, int VW) {
       LDDMM_ROWVEC_AT(kern, 4, false, __VA_ARGS__);                    \
   } while (0)
 
+// The same for the tangent and adjoint kernels with their zero-start variant ZS.
+#define LDDMM_ROWVEC_Z_AT(kern, vw, pr, z, ...)                                                       \
+  LDDMM_LAUNCH(t.start, t.stop, kern<T LDDMM_COMMA vw LDDMM_COMMA pr LDDMM_COMMA z>, grid_, block_, 0, st, gv, RW, \
+               __VA_ARGS__)
+#define LDDMM_ROWVEC_Z(kern, z, ...)                                   \
+  do {                                                                 \
+    const Geo<T> gv = make_vgeo<T>(g, VW);                             \
+    const dim3 grid_(gv.ft.blocks), block_(gv.ft.BX, gv.ft.BY);        \
+    const int RW = g.n2 / VW;                                          \
+    if (VW == 1 && gv.pair)                                            \
+      LDDMM_ROWVEC_Z_AT(kern, 1, true, z, __VA_ARGS__);                \
+    else if (VW == 1)                                                  \
+      LDDMM_ROWVEC_Z_AT(kern, 1, false, z, __VA_ARGS__);               \
+    else if (VW == 2 && gv.pair)                                       \
+      LDDMM_ROWVEC_Z_AT(kern, 2, true, z, __VA_ARGS__);                \
+    else if (VW == 2)                                                  \
+      LDDMM_ROWVEC_Z_AT(kern, 2, false, z, __VA_ARGS__);               \
+    else if (gv.pair)                                                  \
+      LDDMM_ROWVEC_Z_AT(kern, 4, true, z, __VA_ARGS__);                \
+    else                                                               \
+      LDDMM_ROWVEC_Z_AT(kern, 4, false, z, __VA_ARGS__);               \
+  } while (0)
+
 dim3 ft_grid(const Grid& g) { return dim3(make_field_tiling(g).blocks); }
 dim3 ft_block(const Grid& g) {
   const FieldTiling t = make_field_tiling(g);
@@ -881,11 +912,18 @@ void launch_epdiff_stage(const Grid& g, const T* v, const T* mu, const T* mu0, T
 template <typename T>
 void launch_tangent_stage(const Grid& g, const T* X, const T* dmu, const T* W, const T* v, const T* mu,
                           const T* X0, const T* dmu0, T* X_out, T* dmu_out, double dt, double a0, double a1,
-                          hipStream_t st, Profiler* prof, const T* Gfin, double cfin) {
+                          hipStream_t st, Profiler* prof, const T* Gfin, double cfin, int zero) {
   KernelTimer t(prof, a0 != 0.0 ? "tangent_stage_corr" : "tangent_stage_pred");
   if (const int VW = row_vector_width(g)) {
-    LDDMM_ROWVEC(k_tangent_stage_v, X, dmu, W, v, mu, X0 ? X0 : X, dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt), T(a0),
-                 T(a1), Gfin, T(cfin));
+    if (zero == 1)
+      LDDMM_ROWVEC_Z(k_tangent_stage_v, 1, X, dmu, W, v, mu, X0 ? X0 : X, dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt),
+                     T(a0), T(a1), Gfin, T(cfin));
+    else if (zero == 2)
+      LDDMM_ROWVEC_Z(k_tangent_stage_v, 2, X, dmu, W, v, mu, X0 ? X0 : X, dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt),
+                     T(a0), T(a1), Gfin, T(cfin));
+    else
+      LDDMM_ROWVEC_Z(k_tangent_stage_v, 0, X, dmu, W, v, mu, X0 ? X0 : X, dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt),
+                     T(a0), T(a1), Gfin, T(cfin));
     return;
   }
   LDDMM_LAUNCH(t.start, t.stop, k_tangent_stage<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), X, dmu, W, v, mu, X0 ? X0 : X, dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt), T(a0), T(a1), Gfin, T(cfin));
@@ -894,11 +932,15 @@ void launch_tangent_stage(const Grid& g, const T* X, const T* dmu, const T* W, c
 template <typename T>
 void launch_adjoint_stage(const Grid& g, const T* U, const T* w, const T* mu, const T* v, const T* U0, const T* w0,
                           T* Z, T* Q, T* U_out, double dt, double a0, double a1, hipStream_t st, Profiler* prof,
-                          const T* qadd, double qs) {
+                          const T* qadd, double qs, int zero) {
   KernelTimer t(prof, a0 != 0.0 ? "adjoint_stage_corr" : "adjoint_stage_pred");
   if (const int VW = row_vector_width(g)) {
-    LDDMM_ROWVEC(k_adjoint_stage_v, U, w, mu, v, U0 ? U0 : U, w0 ? w0 : w, Z, Q, U_out, T(dt), T(a0), T(a1), qadd,
-                 T(qs));
+    if (zero == 2)
+      LDDMM_ROWVEC_Z(k_adjoint_stage_v, 2, U, w, mu, v, U0 ? U0 : U, w0 ? w0 : w, Z, Q, U_out, T(dt), T(a0), T(a1),
+                     qadd, T(qs));
+    else
+      LDDMM_ROWVEC_Z(k_adjoint_stage_v, 0, U, w, mu, v, U0 ? U0 : U, w0 ? w0 : w, Z, Q, U_out, T(dt), T(a0), T(a1),
+                     qadd, T(qs));
     return;
   }
   LDDMM_LAUNCH(t.start, t.stop, k_adjoint_stage<T>, ft_grid(g), ft_block(g), 0, st, make_geo<T>(g), U, w, mu, v, U0 ? U0 : U, w0 ? w0 : w, Z, Q, U_out, T(dt), T(a0), T(a1), qadd, T(qs));
@@ -958,10 +1000,10 @@ void launch_jacobian_det(const Grid& g, const T* u, T* det, hipStream_t st, Prof
                                        hipStream_t, Profiler*);                                                  \
   template void launch_tangent_stage<T>(const Grid&, const T*, const T*, const T*, const T*, const T*, const T*, \
                                         const T*, T*, T*, double, double, double, hipStream_t, Profiler*,        \
-                                        const T*, double);                                                       \
+                                        const T*, double, int);                                                  \
   template void launch_adjoint_stage<T>(const Grid&, const T*, const T*, const T*, const T*, const T*, const T*, \
                                         T*, T*, T*, double, double, double, hipStream_t, Profiler*, const T*,    \
-                                        double);                                                                 \
+                                        double, int);                                                            \
   template void launch_residual_grad<T>(const Grid&, const T*, const T*, T*, T*, hipStream_t, Profiler*);       \
   template void launch_scalar_times_vec<T>(const Grid&, const T*, const T*, double, T*, hipStream_t, Profiler*); \
   template void launch_gn_final<T>(const Grid&, const T*, const T*, double, T*, hipStream_t, Profiler*);        \
