@@ -56,6 +56,10 @@ def kernel_bytes(n, esize):
         "tangent_stage_corr": 9 * V,
         "adjoint_stage_pred": 7 * V,
         "adjoint_stage_corr": 9 * V,
+        # the sweeps' first stages, which do not read their zero start field
+        "tangent_stage_pred_first": 6 * V,
+        "tangent_stage_corr_first": 8 * V,
+        "adjoint_stage_corr_first": 8 * V,
         "epdiff_stage_pred": 3 * V,
         "epdiff_stage_corr": 4 * V,
         "sl_step": 4 * V,

@@ -913,7 +913,9 @@ template <typename T>
 void launch_tangent_stage(const Grid& g, const T* X, const T* dmu, const T* W, const T* v, const T* mu,
                           const T* X0, const T* dmu0, T* X_out, T* dmu_out, double dt, double a0, double a1,
                           hipStream_t st, Profiler* prof, const T* Gfin, double cfin, int zero) {
-  KernelTimer t(prof, a0 != 0.0 ? "tangent_stage_corr" : "tangent_stage_pred");
+  const bool zs = zero != 0 && row_vector_width(g) != 0;  // the zero-start variant runs
+  KernelTimer t(prof, a0 != 0.0 ? (zs ? "tangent_stage_corr_first" : "tangent_stage_corr")
+                                : (zs ? "tangent_stage_pred_first" : "tangent_stage_pred"));
   if (const int VW = row_vector_width(g)) {
     if (zero == 1)
       LDDMM_ROWVEC_Z(k_tangent_stage_v, 1, X, dmu, W, v, mu, X0 ? X0 : X, dmu0 ? dmu0 : dmu, X_out, dmu_out, T(dt),
@@ -933,7 +935,8 @@ template <typename T>
 void launch_adjoint_stage(const Grid& g, const T* U, const T* w, const T* mu, const T* v, const T* U0, const T* w0,
                           T* Z, T* Q, T* U_out, double dt, double a0, double a1, hipStream_t st, Profiler* prof,
                           const T* qadd, double qs, int zero) {
-  KernelTimer t(prof, a0 != 0.0 ? "adjoint_stage_corr" : "adjoint_stage_pred");
+  const bool zs = zero != 0 && row_vector_width(g) != 0;  // the zero-start variant runs
+  KernelTimer t(prof, a0 != 0.0 ? (zs ? "adjoint_stage_corr_first" : "adjoint_stage_corr") : "adjoint_stage_pred");
   if (const int VW = row_vector_width(g)) {
     if (zero == 2)
       LDDMM_ROWVEC_Z(k_adjoint_stage_v, 2, U, w, mu, v, U0 ? U0 : U, w0 ? w0 : w, Z, Q, U_out, T(dt), T(a0), T(a1),
