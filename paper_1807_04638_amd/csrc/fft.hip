@@ -525,9 +525,21 @@ __device__ __forceinline__ void rows_first_compute(cplx<T>* A, RowStageIn<T, H, 
   }
 }
 
+// Store with the non-temporal hint.  The inverse plane pass writes a field that
+// only the next kernel reads, so its lines need not stay in the caches; with the
+// hint the pass measured 7-10 % faster and the whole Hessian-vector product
+// 0.5-2.5 % faster (the other passes' loads and stores measured slower with it).
+template <typename T>
+__device__ __forceinline__ void store_streaming(cplx<T>* p, const cplx<T>& v) {
+  typedef T pair __attribute__((ext_vector_type(2)));
+  const pair x = {v.x, v.y};
+  __builtin_nontemporal_store(x, reinterpret_cast<pair*>(p));
+}
+
 // Last DIT stage of COUNT rows (the inverse of the first row stage) straight to
-// global memory (row s at dst + s * RS).  ADD: dst = add + scale * (result), the
-// addend (same layout as dst) loaded before the butterfly so its latency overlaps.
+// global memory (row s at dst + s * RS), with streaming stores.  ADD: dst = add +
+// scale * (result), the addend (same layout as dst) loaded before the butterfly
+// so its latency overlaps.
 template <typename T, int H, int COUNT, int NT, bool ADD = false, int RS = H>
 __device__ __forceinline__ void rows_last_stage_global(const cplx<T>* A, cplx<T>* __restrict__ dst,
                                                        const cplx<T>* tw, const cplx<T>* __restrict__ add = nullptr,
@@ -562,7 +574,7 @@ __device__ __forceinline__ void rows_last_stage_global(const cplx<T>* A, cplx<T>
       for (int q = 0; q < R; ++q) v[q] = {ad[q].x + scale * v[q].x, ad[q].y + scale * v[q].y};
     }
 #pragma unroll
-    for (int q = 0; q < R; ++q) dst[r * RS + j + q * S] = v[q];
+    for (int q = 0; q < R; ++q) store_streaming(dst + (r * RS + j + q * S), v[q]);
   }
 }
 
