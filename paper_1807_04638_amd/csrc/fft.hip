@@ -1023,13 +1023,19 @@ std::vector<cplx<T>> twiddles(int n, int count) {
   return t;
 }
 
-template <typename V>
-int upload(V** dst, const std::vector<V>& src, size_t& bytes) {
-  const size_t b = src.size() * sizeof(V);
-  if (hipMalloc(reinterpret_cast<void**>(dst), b) != hipSuccess) return LDDMM_ENOMEM;
-  bytes += b;
-  return hipMemcpy(*dst, src.data(), b, hipMemcpyHostToDevice) == hipSuccess ? 0 : LDDMM_EHIP;
-}
+// Host image of the transform tables: each table at a 256-byte aligned offset
+// of one blob, uploaded with a single copy (into a context allocation or a
+// caller-provided device region).
+struct TableBlob {
+  std::vector<unsigned char> host;
+  template <typename V>
+  size_t put(const std::vector<V>& src) {
+    const size_t off = (host.size() + 255) & ~size_t(255);
+    host.resize(off + src.size() * sizeof(V));
+    std::memcpy(host.data() + off, src.data(), src.size() * sizeof(V));
+    return off;
+  }
+};
 
 int fold_sq(int k, int n) {
   const int a = k <= n - k ? k : n - k;
@@ -1326,8 +1332,11 @@ FftTuning default_tuning(const SpectralPlan<T>& sp) {
   return t;
 }
 
+// Plans and the host image of the tables; device pointers are offsets into
+// the table block until spectral_place_tables sets its base.
 template <typename T>
-int spectral_init(SpectralPlan<T>& sp, const int n[3], size_t max_lds, std::string& err) {
+int spectral_plan_tables(SpectralPlan<T>& sp, const int n[3], size_t max_lds, std::string& err, TableBlob& blob,
+                         size_t off[12]) {
   sp = SpectralPlan<T>();
   sp.n0 = n[0];
   sp.n1 = n[1];
@@ -1344,16 +1353,15 @@ int spectral_init(SpectralPlan<T>& sp, const int n[3], size_t max_lds, std::stri
     return LDDMM_EUNSUPPORTED;
   }
   const int H = sp.H, M = sp.M;
-  int rc = 0;
-  size_t& by = sp.bytes;
-  if ((rc = upload(&sp.tw0, twiddles<T>(n[0], n[0]), by))) return rc;
-  if ((rc = upload(&sp.tw1, twiddles<T>(n[1], n[1]), by))) return rc;
-  if ((rc = upload(&sp.tw2, twiddles<T>(H, H), by))) return rc;
-  if ((rc = upload(&sp.twr, twiddles<T>(n[2], H / 2 + 1), by))) return rc;
+  for (int i = 0; i < 12; ++i) off[i] = size_t(-1);
+  off[0] = blob.put(twiddles<T>(n[0], n[0]));
+  off[1] = blob.put(twiddles<T>(n[1], n[1]));
+  off[2] = blob.put(twiddles<T>(H, H));
+  off[3] = blob.put(twiddles<T>(n[2], H / 2 + 1));
   std::vector<int> slot(H + 1);
   for (int p = 0; p < H; ++p) slot[digit_reverse(sp.p2, p)] = p;
   slot[H] = H;
-  if ((rc = upload(&sp.slot2, slot, by))) return rc;
+  off[4] = blob.put(slot);
   std::vector<T> k0(n[0]), k1(n[1]), k2(M);
   for (int p = 0; p < n[0]; ++p) k0[p] = T(fold_sq(digit_reverse(sp.p0, p), n[0]));
   for (int p = 0; p < n[1]; ++p) k1[p] = T(fold_sq(digit_reverse(sp.p1, p), n[1]));
@@ -1362,14 +1370,14 @@ int spectral_init(SpectralPlan<T>& sp, const int n[3], size_t max_lds, std::stri
     k2[p] = T(k * k);
   }
   k2[H] = T(H * H);
-  if ((rc = upload(&sp.ksq0, k0, by))) return rc;
-  if ((rc = upload(&sp.ksq1, k1, by))) return rc;
-  if ((rc = upload(&sp.ksq2, k2, by))) return rc;
+  off[5] = blob.put(k0);
+  off[6] = blob.put(k1);
+  off[7] = blob.put(k2);
   // half-plane tables: the x1 transform of half length, the merge twiddles
   // W_{n1}^{k1} and |k1|^2, |k1 + n1/2|^2 per slot of the half transform
   if (n[1] % 2 == 0 && n[1] >= 8 && make_plan(n[1] / 2, sp.p1h)) {
     const int h1 = n[1] / 2;
-    if ((rc = upload(&sp.tw1h, twiddles<T>(h1, h1), by))) return rc;
+    off[8] = blob.put(twiddles<T>(h1, h1));
     std::vector<cplx<T>> wx(h1);
     std::vector<T> kx(n[1]);
     for (int p = 0; p < h1; ++p) {
@@ -1379,24 +1387,101 @@ int spectral_init(SpectralPlan<T>& sp, const int n[3], size_t max_lds, std::stri
       kx[p] = T(fold_sq(k, n[1]));
       kx[h1 + p] = T(fold_sq(k + h1, n[1]));
     }
-    if ((rc = upload(&sp.twx, wx, by))) return rc;
-    if ((rc = upload(&sp.ksq1x, kx, by))) return rc;
+    off[9] = blob.put(wx);
+    off[10] = blob.put(kx);
   }
-  const size_t spec_bytes = size_t(3) * n[0] * n[1] * M * sizeof(cplx<T>);
+  return 0;
+}
+
+// Point the plan's tables into the device copy of the blob at `base`.
+template <typename T>
+void spectral_place_tables(SpectralPlan<T>& sp, unsigned char* base, const size_t off[12]) {
+  auto at = [&](size_t o) { return o == size_t(-1) ? nullptr : static_cast<void*>(base + o); };
+  sp.tw0 = static_cast<cplx<T>*>(at(off[0]));
+  sp.tw1 = static_cast<cplx<T>*>(at(off[1]));
+  sp.tw2 = static_cast<cplx<T>*>(at(off[2]));
+  sp.twr = static_cast<cplx<T>*>(at(off[3]));
+  sp.slot2 = static_cast<int*>(at(off[4]));
+  sp.ksq0 = static_cast<T*>(at(off[5]));
+  sp.ksq1 = static_cast<T*>(at(off[6]));
+  sp.ksq2 = static_cast<T*>(at(off[7]));
+  sp.tw1h = static_cast<cplx<T>*>(at(off[8]));
+  sp.twx = static_cast<cplx<T>*>(at(off[9]));
+  sp.ksq1x = static_cast<T*>(at(off[10]));
+}
+
+template <typename T>
+size_t spectrum_bytes(const SpectralPlan<T>& sp, int ncomp) {
+  return size_t(ncomp) * sp.n0 * sp.n1 * sp.M * sizeof(cplx<T>);
+}
+
+template <typename T>
+int spectral_init(SpectralPlan<T>& sp, const int n[3], size_t max_lds, std::string& err) {
+  TableBlob blob;
+  size_t off[12];
+  int rc = spectral_plan_tables(sp, n, max_lds, err, blob, off);
+  if (rc) return rc;
+  void* tables = nullptr;
+  if (hipMalloc(&tables, blob.host.size()) != hipSuccess) {
+    err = "out of device memory (transform tables)";
+    return LDDMM_ENOMEM;
+  }
+  sp.table_mem = tables;
+  sp.bytes += blob.host.size();
+  if (hipMemcpy(tables, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    err = "cannot upload the transform tables";
+    return LDDMM_EHIP;
+  }
+  spectral_place_tables(sp, static_cast<unsigned char*>(tables), off);
+  const size_t spec_bytes = spectrum_bytes(sp, 3);
   if (hipMalloc(reinterpret_cast<void**>(&sp.spec), spec_bytes) != hipSuccess) {
     err = "out of device memory (spectrum workspace)";
     return LDDMM_ENOMEM;
   }
-  by += spec_bytes;
+  sp.bytes += spec_bytes;
+  if ((rc = spectral_configure(sp, default_tuning(sp), err))) return rc;
+  return 0;
+}
+
+template <typename T>
+int spectral_init_in(SpectralPlan<T>& sp, const int n[3], int ncomp, size_t max_lds, unsigned char* region,
+                     size_t region_bytes, hipStream_t st, std::vector<unsigned char>& host_tables,
+                     std::string& err) {
+  TableBlob blob;
+  size_t off[12];
+  int rc = spectral_plan_tables(sp, n, max_lds, err, blob, off);
+  if (rc) return rc;
+  const size_t tab = (blob.host.size() + 255) & ~size_t(255);
+  const size_t need = tab + spectrum_bytes(sp, ncomp);
+  if (need > region_bytes) {
+    err = "grid " + std::to_string(n[0]) + "x" + std::to_string(n[1]) + "x" + std::to_string(n[2]) + " with " +
+          std::to_string(ncomp) + " component(s) needs " + std::to_string(need) +
+          " bytes of static workspace; it holds " + std::to_string(region_bytes);
+    sp = SpectralPlan<T>();
+    return LDDMM_EUNSUPPORTED;
+  }
+  host_tables.swap(blob.host);
+  // the region may still be read by earlier work on this stream
+  if (hipStreamSynchronize(st) != hipSuccess ||
+      hipMemcpyAsync(region, host_tables.data(), host_tables.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    err = "cannot upload the transform tables";
+    sp = SpectralPlan<T>();
+    return LDDMM_EHIP;
+  }
+  spectral_place_tables(sp, region, off);
+  sp.spec = reinterpret_cast<cplx<T>*>(region + tab);
+  sp.owns_memory = false;
   if ((rc = spectral_configure(sp, default_tuning(sp), err))) return rc;
   return 0;
 }
 
 template <typename T>
 void spectral_free(SpectralPlan<T>& sp) {
-  void* ptrs[] = {sp.tw0, sp.tw1, sp.tw2, sp.twr, sp.slot2, sp.ksq0, sp.ksq1, sp.ksq2, sp.spec, sp.tw1h, sp.twx, sp.ksq1x};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  if (sp.owns_memory) {
+    if (sp.table_mem) (void)hipFree(sp.table_mem);
+    if (sp.spec) (void)hipFree(sp.spec);
+  }
   sp = SpectralPlan<T>();
 }
 
@@ -1515,6 +1600,9 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
 
 #define LDDMM_SINST(T)                                                                                   \
   template int spectral_init<T>(SpectralPlan<T>&, const int[3], size_t, std::string&);                  \
+  template int spectral_init_in<T>(SpectralPlan<T>&, const int[3], int, size_t, unsigned char*, size_t,     \
+                                   hipStream_t, std::vector<unsigned char>&, std::string&);               \
+  template size_t spectrum_bytes<T>(const SpectralPlan<T>&, int);                                        \
   template int spectral_configure<T>(SpectralPlan<T>&, const FftTuning&, std::string&);                 \
   template FftTuning default_tuning<T>(const SpectralPlan<T>&);                                          \
   template void spectral_free<T>(SpectralPlan<T>&);                                                      \

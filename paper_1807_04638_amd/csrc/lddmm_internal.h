@@ -136,6 +136,8 @@ struct SpectralPlan {
   T* ksq1 = nullptr;
   T* ksq2 = nullptr;
   cplx<T>* spec = nullptr;                   // workspace: 3 * n0 * n1 * M complex
+  void* table_mem = nullptr;                 // device block holding the tables above
+  bool owns_memory = true;                   // false: tables and spectrum live in a caller's region
   FftPlan p1h{};                             // length n1 / 2 (half planes; n = 0 when n1 is odd)
   cplx<T>* tw1h = nullptr;                   // exp(-2 pi i m / (n1 / 2))
   cplx<T>* twx = nullptr;                    // exp(-2 pi i k1 / n1) per slot of the half transform
@@ -154,6 +156,18 @@ struct SpectralPlan {
 // Returns 0 or a negative LDDMM_E* code.  max_lds = bytes of LDS per workgroup.
 template <typename T>
 int spectral_init(SpectralPlan<T>& sp, const int n[3], size_t max_lds, std::string& err);
+// The same plan with its tables and a spectrum workspace for ncomp components
+// placed in a caller-provided device region of region_bytes (nothing is
+// allocated): the tables are copied there on stream st, after and before a
+// synchronisation of st; host_tables keeps their host image.  LDDMM_EUNSUPPORTED
+// (with the bytes needed in err) if the region is too small.
+template <typename T>
+int spectral_init_in(SpectralPlan<T>& sp, const int n[3], int ncomp, size_t max_lds, unsigned char* region,
+                     size_t region_bytes, hipStream_t st, std::vector<unsigned char>& host_tables,
+                     std::string& err);
+// Bytes of the spectrum workspace for ncomp components.
+template <typename T>
+size_t spectrum_bytes(const SpectralPlan<T>& sp, int ncomp);
 template <typename T>
 void spectral_free(SpectralPlan<T>& sp);
 // Apply new launch shapes; LDDMM_EINVAL / LDDMM_EUNSUPPORTED if they do not fit.
