@@ -299,7 +299,9 @@ int lddmm_memory_bytes(lddmm_ctx* ctx, int64_t* bytes);
  * caller working on another stream synchronises before handing buffers over.
  * lddmm_batch_gn_solve / _hessvec run the pairs concurrently on one host
  * thread per pair (concurrent != 0) or one after the other, and return after
- * every pair has finished; the first failing status is returned. */
+ * every pair has finished and its results are written (each pair's stream is
+ * synchronised); the first failing status is returned.  Their pointer arrays
+ * hold one entry per pair; a NULL entry gives LDDMM_EINVAL before any work. */
 typedef struct lddmm_batch lddmm_batch;
 int lddmm_batch_create(const lddmm_params* per_pair, int npairs, lddmm_batch** out);
 int lddmm_batch_destroy(lddmm_batch* batch);

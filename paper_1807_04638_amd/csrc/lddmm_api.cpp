@@ -1475,13 +1475,20 @@ int lddmm_batch_sync(lddmm_batch* b) {
 int lddmm_batch_gn_solve(lddmm_batch* b, void* const* v0_inout, const lddmm_solve_opts* opts,
                          lddmm_solve_report* reports, int concurrent) {
   if (!b || !v0_inout) return LDDMM_EINVAL;
+  for (size_t i = 0; i < b->ctx.size(); ++i)
+    if (!v0_inout[i]) return LDDMM_EINVAL;
   return for_pairs(b, concurrent, [&](int i) {
-    return lddmm_gn_solve(b->ctx[i], v0_inout[i], opts, reports ? &reports[i] : nullptr, nullptr, 0);
+    const int rc = lddmm_gn_solve(b->ctx[i], v0_inout[i], opts, reports ? &reports[i] : nullptr, nullptr, 0);
+    // the solve's last copy into v0 may still be in flight on the pair's stream
+    const bool synced = hipStreamSynchronize(ctx_stream(b->ctx[i])) == hipSuccess;
+    return rc ? rc : (synced ? LDDMM_OK : LDDMM_EHIP);
   });
 }
 
 int lddmm_batch_hessvec(lddmm_batch* b, void* const* dv, void* const* hv, int reps, int concurrent) {
   if (!b || !dv || !hv || reps < 1) return LDDMM_EINVAL;
+  for (size_t i = 0; i < b->ctx.size(); ++i)
+    if (!dv[i] || !hv[i]) return LDDMM_EINVAL;
   return for_pairs(b, concurrent, [&](int i) {
     for (int r = 0; r < reps; ++r) {
       const int rc = lddmm_hessvec(b->ctx[i], nullptr, dv[i], hv[i]);

@@ -435,22 +435,39 @@ class Batch:
         if rc != OK:
             raise LddmmError(rc, f"{what}: {self.lib.lddmm_strerror(rc).decode()}")
 
+    def _fields(self, ts, name):
+        """Check one vector field per pair (count, shape, dtype, device, contiguity)."""
+        ts = list(ts)
+        if len(ts) != len(self.contexts):
+            raise ValueError(f"{name}: {len(ts)} fields for {len(self.contexts)} pairs")
+        for i, t in enumerate(ts):
+            if t is None:
+                raise ValueError(f"{name}[{i}] is required")
+            R = self.contexts[i]
+            shape = (3,) + R.n
+            if tuple(t.shape) != shape or t.dtype != R.dtype or t.device != R.device or not t.is_contiguous():
+                raise ValueError(
+                    f"{name}[{i}]: expected contiguous {R.dtype} {shape} on {R.device}, "
+                    f"got {t.dtype} {tuple(t.shape)} on {t.device}"
+                )
+        return (_vp * len(ts))(*[t.data_ptr() for t in ts])
+
     def gn_solve(self, v0s, concurrent=True, gn_iters=None, cg_iters=20, max_halvings=10, c1=1e-4, gtol=1e-3,
                  eta_max=0.5, method="gn_v"):
+        ptrs = self._fields(v0s, "v0s")
         torch.cuda.current_stream(self.device).synchronize()
-        ptrs = (_vp * len(v0s))(*[t.data_ptr() for t in v0s])
         if gn_iters is None:
             gn_iters = 50 if method == "gd" else 10
         o = SolveOpts(gn_iters, cg_iters, max_halvings, METHODS[method], c1, gtol, eta_max)
-        reps = (SolveReport * len(v0s))()
+        reps = (SolveReport * len(self.contexts))()
         self._rc(self.lib.lddmm_batch_gn_solve(self._b, ptrs, ctypes.byref(o), reps, 1 if concurrent else 0),
                  "batch_gn_solve")
         return [{k: getattr(r, k) for k, _ in SolveReport._fields_} for r in reps]
 
     def hessvec(self, dvs, hvs, reps=1, concurrent=True):
+        a = self._fields(dvs, "dvs")
+        b = self._fields(hvs, "hvs")
         torch.cuda.current_stream(self.device).synchronize()
-        a = (_vp * len(dvs))(*[t.data_ptr() for t in dvs])
-        b = (_vp * len(hvs))(*[t.data_ptr() for t in hvs])
         self._rc(self.lib.lddmm_batch_hessvec(self._b, a, b, int(reps), 1 if concurrent else 0), "batch_hessvec")
 
     def autotune(self, reps=5):

@@ -122,3 +122,34 @@ def test_batch_uneven_sizes_matches_single_contexts(dtype):
     for i in range(len(sizes)):
         assert torch.equal(hvs[i], B.contexts[i].hessvec(dvs[i]))
     B.close()
+
+
+def test_batch_results_are_complete_on_return():
+    """lddmm_batch_gn_solve returns after every pair's results are written: v0s
+    read on torch's stream right after a solve that stops on its iteration cap
+    (the last step accepted, so the solve ends with a copy into v0) equal the
+    single-context solves made beforehand."""
+    from paper_1807_04638_amd import Batch, Registration
+
+    dtype = torch.float32
+    sizes = [(24, 24, 24), (16, 20, 24), (28, 28, 28)]
+    data = [pair(n, 10 + i) for i, n in enumerate(sizes)]
+    refs = []
+    for i, n in enumerate(sizes):
+        R = Registration(n, 4, 0.01, 2, 0.02, dtype=dtype)
+        R.set_images(T(data[i][0], dtype), T(data[i][1], dtype))
+        v = torch.zeros((3,) + n, dtype=dtype, device=DEV)
+        tr = R.gn_solve(v, gn_iters=2, cg_iters=3)
+        assert tr.report["stop_reason"] == 0 and tr.log[-1]["tau"] > 0
+        refs.append(v)
+        R.close()
+    torch.cuda.synchronize()
+    B = Batch([dict(n=n, nt=4, alpha=0.01, s=2, sigma2=0.02) for n in sizes], dtype=dtype)
+    for i, (I0, I1) in enumerate(data):
+        B.contexts[i].set_images(T(I0, dtype), T(I1, dtype))
+    say("[case] batch results on return")
+    vs = [torch.zeros((3,) + n, dtype=dtype, device=DEV) for n in sizes]
+    B.gn_solve(vs, concurrent=True, gn_iters=2, cg_iters=3)
+    for i in range(len(sizes)):
+        assert torch.equal(vs[i], refs[i]), i
+    B.close()
