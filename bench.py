@@ -70,6 +70,39 @@ def kernel_bytes(n, esize):
     }
 
 
+# Compulsory HBM floor of the Hessian-vector product (16 V per time step and
+# sweep): per step and sweep the stage kernels read the 4 coefficient fields and
+# read and write the 2-field state once (8 V over the step's 2 stage launches,
+# 4 V each), and each of the 2 K applications makes 2 round trips of a vector
+# field (4 V, shared by its 3 transform passes).  Per Hv: 32 V nt.
+def floor_bytes_per_launch(group, n, esize):
+    V = 3 * n[0] * n[1] * n[2] * esize
+    if group.startswith("fft_"):
+        return 4 * V / 3
+    if group.endswith("_stage"):
+        return 4 * V
+    return None
+
+
+def hv_floor_bytes(n, nt, esize):
+    return 32 * 3 * n[0] * n[1] * n[2] * esize * nt
+
+
+# Profiler launch names -> kernel template (the rocprof kernel name without its
+# template arguments): predictor, corrector and first-stage launches of one
+# template form one group.
+def kernel_group(name):
+    if name.startswith("tangent_stage"):
+        return "tangent_stage"
+    if name.startswith("adjoint_stage"):
+        return "adjoint_stage"
+    if name.startswith("epdiff_stage"):
+        return "epdiff_stage"
+    if name.startswith("fft_plane_inv"):
+        return "fft_plane_inv"
+    return name
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -158,37 +191,53 @@ def time_events(torch, fn, reps):
     return start.elapsed_time(stop) / reps  # ms
 
 
-def cpu_baseline(spec, I0, I1, v0t, solve_over_hv):
-    """Time the FP64 oracle's Hessian-vector product on the host, on a bounded
-    sample: the same 128^3 pair and operators over 2 of the nt time steps (the
-    sweep cost is linear in nt).  Scaled to nt steps, then to one solve by the
-    GPU's solve-time / Hv-time ratio."""
+def cpu_baseline(spec, I0, I1, v0t, rep):
+    """Time the FP64 oracle on the host on a bounded sample of the workload: one
+    linearization (shoot with trajectory store, SL transport, final conditions),
+    one adjoint sweep (the gradient at that linearization) and one Gauss-Newton
+    Hessian-vector product, all at the full grid and nt, each timed once.  A
+    solve is extrapolated from these per-operation times and the GPU solve's
+    operation counts (linearizations, adjoint sweeps, Hessian-vector products)."""
     import numpy as np
 
     import oracle as O
     from synth import random_field
 
-    nt_s = 2
-    p = O.Params(spec.n, spec.alpha, spec.s, nt_s, spec.sigma2)
-    lin = O.linearize(0.5 * np.asarray(v0t), I0, I1, p)
+    p = O.Params(spec.n, spec.alpha, spec.s, spec.nt, spec.sigma2)
+    v = 0.5 * np.asarray(v0t)
     dv = random_field(spec.n, 7)
     t = time.perf_counter()
+    lin = O.linearize(v, I0, I1, p)
+    t_lin = time.perf_counter() - t
+    log(f"[bench] oracle linearization {t_lin:.1f} s")
+    t = time.perf_counter()
+    O.gradient(v, I0, I1, p, lin)
+    t_bw = time.perf_counter() - t
+    log(f"[bench] oracle adjoint sweep {t_bw:.1f} s")
+    t = time.perf_counter()
     O.hessvec(dv, lin, p)
-    dt = time.perf_counter() - t
-    hv_full = dt * spec.nt / nt_s
-    per_solve = hv_full * solve_over_hv
+    t_hv = time.perf_counter() - t
+    log(f"[bench] oracle Hessian-vector product {t_hv:.1f} s")
+    n_lin = 1 + rep["shoots"]
+    n_bw = rep["gradients"]
+    n_hv = rep["hessvecs"]
+    per_solve = n_lin * t_lin + n_bw * t_bw + n_hv * t_hv
+    cores = O.lddmm_oracle._WORKERS
     return {
         "value": round(60.0 / per_solve, 5),
         "unit": "GN solves/min",
-        "cores": os.cpu_count(),
+        "cores": cores,
         "kind": "oracle",
+        "extrapolated": True,
         "sample": (
-            f"one FP64 oracle Hessian-vector product at {spec.n[0]}x{spec.n[1]}x{spec.n[2]} over {nt_s} of "
-            f"{spec.nt} time steps ({dt:.1f} s; scipy.fft on {os.cpu_count()} threads, numpy elementwise on one), "
-            f"scaled x{spec.nt / nt_s:g} to nt={spec.nt} ({hv_full:.1f} s per Hv) and x{solve_over_hv:.1f} "
-            "(GPU solve/Hv time ratio) to a solve"
+            f"FP64 oracle at {spec.n[0]}x{spec.n[1]}x{spec.n[2]}, nt={spec.nt}, timed once each: linearization "
+            f"{t_lin:.1f} s, adjoint sweep {t_bw:.1f} s, Hessian-vector product {t_hv:.1f} s (scipy.fft on {cores} "
+            f"threads, numpy elementwise on one); a GN solve extrapolated as {n_lin} linearizations + {n_bw} adjoint "
+            f"sweeps + {n_hv} Hessian-vector products (the GPU solve's counts) = {per_solve:.0f} s"
         ),
-        "hv_per_s": round(1.0 / hv_full, 5),
+        "hv_per_s": round(1.0 / t_hv, 5),
+        "gradients_per_s": round(1.0 / (t_lin + t_bw), 5),
+        "shoot_s": round(t_lin, 2),
     }
 
 
@@ -260,7 +309,8 @@ def batch_bench(args, torch, synth, Batch, Registration):
         "speedup_hv": round(out["concurrent"]["hv_per_s"] / out["sequential"]["hv_per_s"], 3),
         "speedup_solves": round(out["concurrent"]["gn_solves_per_min"] / out["sequential"]["gn_solves_per_min"], 3),
     }
-    print(json.dumps(line), flush=True)
+    B.close()
+    return line
 
 
 def precision_bench(args, torch, synth, Registration, spec):
@@ -334,7 +384,71 @@ def precision_bench(args, torch, synth, Registration, spec):
         "fp32_speedup_vs_fp64": round(b["s"] / a["s"], 3),
         "reference": "FP64 GPU path (oracle-pinned at small sizes)",
     }
-    print(json.dumps(line), flush=True)
+    return line
+
+
+def memory_bench(args, torch, synth, Registration, spec):
+    """Trajectory memory policies at 256^3, nt = 32 (FP32): store every step,
+    checkpoint every 4 steps, full recompute.  For each: device bytes the
+    context holds (trajectory and the whole context), the drop in free device
+    memory while it runs, and Hessian-vector products/s at one linearization.
+    The three give bitwise the same Hv (checked here on the first component)."""
+    dev = torch.device("cuda:0")
+    n = spec.n
+    log(f"[bench] memory policies {spec.name}: building inputs")
+    I0 = synth.phantom(n, spec.n_blobs, spec.sigma_range, spec.classes, 1000, shells=spec.shells)
+    v0t = synth.random_velocity(n, 2000, spec.disp_vox)
+    R = Registration(n, spec.nt, spec.alpha, spec.s, spec.sigma2, dtype=torch.float32, device=dev,
+                     checkpoint_every=-1)
+    t0 = torch.tensor(I0, dtype=torch.float32, device=dev)
+    R.set_images(t0, t0)
+    vt = torch.tensor(v0t, dtype=torch.float32, device=dev)
+    I1 = R.shoot(vt, want=("J1",))["J1"] + torch.tensor(synth.noise(n, 3000, spec.noise_sd), dtype=torch.float32,
+                                                         device=dev)
+    R.close()
+    del R
+    vlin = 0.5 * vt
+    dv = torch.randn((3,) + n, device=dev, generator=torch.Generator(device=dev).manual_seed(9))
+    out = {}
+    first = None
+    for name, every in (("store_all", 0), ("checkpoint_4", 4), ("recompute", -1)):
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        free0 = torch.cuda.mem_get_info(dev)[0]
+        R = Registration(n, spec.nt, spec.alpha, spec.s, spec.sigma2, dtype=torch.float32, device=dev,
+                         checkpoint_every=every)
+        R.set_images(t0, I1)
+        if every == 0 and not args.no_graph:
+            R.set_option("exec.graph", 1)
+        R.linearize(vlin)
+        hv = torch.empty_like(dv)
+        R.hessvec(dv, out=hv)
+        reps = 3 if every >= 0 else 2
+        ms = time_events(torch, lambda: R.hessvec(dv, out=hv), reps)
+        free1 = torch.cuda.mem_get_info(dev)[0]
+        if first is None:
+            first = hv.clone()
+            same = True
+        else:
+            same = bool(torch.equal(hv, first))
+        out[name] = {
+            "checkpoint_every": every,
+            "traj_policy": R.get_option("traj.policy"),
+            "trajectory_bytes": R.get_option("traj.bytes"),
+            "context_bytes": R.memory_bytes(),
+            "device_bytes_in_use": int(free0 - free1),
+            "hv_per_s": round(1e3 / ms, 3),
+            "ms_per_hv": round(ms, 2),
+            "hv_bitwise_equal_to_store_all": same,
+        }
+        log(f"[bench] {name}: {out[name]}")
+        R.close()
+        del R, hv
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"{spec.name}: {n[0]}x{n[1]}x{n[2]} pair, nt={spec.nt}, FP32, alpha={spec.alpha}, s={spec.s}",
+        "policies": out,
+    }
 
 
 def main():
@@ -346,6 +460,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the GN-L2 and gradient-descent solves")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the head-grid, batch16 and 256^3 memory-policy workloads")
     ap.add_argument("--hv-reps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true", help="keep the default transform launch shapes")
     ap.add_argument("--no-graph", action="store_true", help="launch Hessian-vector products kernel by kernel")
@@ -383,14 +499,17 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.workload == "batch16":
-        batch_bench(args, torch, synth, Batch, Registration)
+        print(json.dumps(batch_bench(args, torch, synth, Batch, Registration)), flush=True)
         return
     spec = synth.WORKLOADS[args.workload]
     # everything runs on a dedicated stream so the contexts can replay graphs
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.set_stream(stream)
     if args.workload == "head180x216x180":
-        precision_bench(args, torch, synth, Registration, spec)
+        print(json.dumps(precision_bench(args, torch, synth, Registration, spec)), flush=True)
+        return
+    if args.workload == "pair256":
+        print(json.dumps(memory_bench(args, torch, synth, Registration, spec)), flush=True)
         return
     log(f"[bench] workload {spec.name} n={spec.n} nt={spec.nt}: building inputs")
     I0, I1, v0t = make_pair(spec, torch.float64, dev, torch, Registration, synth)
@@ -479,25 +598,53 @@ def main():
     prof = R.profile_read()
     R.profile_enable(False)
     nbytes = kernel_bytes(spec.n, 4)
+    tuned = {k: R.get_option(k) for k in TUNED_KEYS}
+    total_ms = sum(v[1] for v in prof.values())
     kernels = {}
     for name, (cnt, ms) in prof.items():
         avg_us = 1e3 * ms / max(cnt, 1)
         kb = nbytes.get(name)
         kernels[name] = {
+            "group": kernel_group(name),
             "launches_per_hv": cnt / 5,
             "avg_us": round(avg_us, 2),
-            "share": round(ms / sum(v[1] for v in prof.values()), 4),
-            "GBps": round(kb / (avg_us * 1e-6) / 1e9, 1) if kb else None,
+            "share": round(ms / total_ms, 4),
+            "ledger_bytes": kb,
+            "ledger_GBps": round(kb / (avg_us * 1e-6) / 1e9, 1) if kb else None,
+            "traffic": recorded_traffic(name, tuned),
         }
-    tuned = {k: R.get_option(k) for k in TUNED_KEYS}
-    for name in kernels:
-        kernels[name]["traffic"] = recorded_traffic(name, tuned)
-    dom = max((k for k in kernels if k in nbytes), key=lambda k: prof[k][1])
-    dom_bytes = nbytes[dom]
-    dom_avg_s = kernels[dom]["avg_us"] * 1e-6
+    # kernel templates (predictor, corrector and first stages together), each
+    # priced at its share of the Hessian-vector product's compulsory floor
+    groups = {}
+    for name, k in kernels.items():
+        g = groups.setdefault(k["group"], {"launches_per_hv": 0.0, "ms_per_hv": 0.0, "members": [], "traffic_sum": 0.0,
+                                           "traffic_known": True})
+        g["launches_per_hv"] += k["launches_per_hv"]
+        g["ms_per_hv"] += prof[name][1] / 5
+        g["members"].append(name)
+        if k["traffic"] is None:
+            g["traffic_known"] = False
+        else:
+            g["traffic_sum"] += k["traffic"] * k["launches_per_hv"]
+    for gname, g in groups.items():
+        fb = floor_bytes_per_launch(gname, spec.n, 4)
+        avg_us = 1e3 * g["ms_per_hv"] / g["launches_per_hv"]
+        g["avg_us"] = round(avg_us, 2)
+        g["floor_bytes_per_launch"] = int(fb) if fb else None
+        g["floor_GBps"] = round(fb / (avg_us * 1e-6) / 1e9, 1) if fb else None
+        g["traffic"] = int(g["traffic_sum"] / g["launches_per_hv"]) if g["traffic_known"] else None
+        g["ms_per_hv"] = round(g["ms_per_hv"], 4)
+        del g["traffic_sum"], g["traffic_known"]
+    dom = max((g for g in groups if groups[g]["floor_bytes_per_launch"]), key=lambda g: groups[g]["ms_per_hv"])
+    dom_bytes = groups[dom]["floor_bytes_per_launch"]
+    dom_avg_s = groups[dom]["avg_us"] * 1e-6
     achieved = dom_bytes / dom_avg_s / 1e9
-    hv_bytes = sum(nbytes[k] * kernels[k]["launches_per_hv"] for k in kernels if k in nbytes)
-    log(f"[bench] dominant kernel {dom}: {kernels[dom]}")
+    hv_ledger = sum(nbytes[k] * kernels[k]["launches_per_hv"] for k in kernels if k in nbytes)
+    hv_floor = hv_floor_bytes(spec.n, spec.nt, 4)
+    counted = [k for k in kernels if kernels[k]["traffic"] is not None]
+    hv_counter = (sum(kernels[k]["traffic"] * kernels[k]["launches_per_hv"] for k in kernels)
+                  if len(counted) == len(kernels) else None)
+    log(f"[bench] dominant kernel template {dom}: {groups[dom]}")
 
     # practical HBM ceiling for reference: a plain 1 GiB device copy (read + write)
     src = torch.ones(256 * 2**20, dtype=torch.float32, device=dev)
@@ -547,7 +694,8 @@ def main():
     # plain FP64 path
     fp64 = None
     if not args.no_fp64:
-        del R
+        R.close()
+        R = None
         torch.cuda.empty_cache()
         R64 = context(torch.float64)
         v64 = torch.tensor(0.5 * v0t, dtype=torch.float64, device=dev)
@@ -570,10 +718,29 @@ def main():
         del R64
         torch.cuda.empty_cache()
 
+    # the other workloads, bounded in time: precision policy on the head grid,
+    # the batch of 16 uneven pairs, trajectory memory policies at 256^3
+    extra = {}
+    if not args.no_extra:
+        if R is not None:
+            R.close()
+            R = None
+        torch.cuda.empty_cache()
+        for key, fn in (
+            ("head180x216x180", lambda: precision_bench(args, torch, synth, Registration,
+                                                        synth.WORKLOADS["head180x216x180"])),
+            ("batch16", lambda: batch_bench(args, torch, synth, Batch, Registration)),
+            ("pair256_memory", lambda: memory_bench(args, torch, synth, Registration, synth.WORKLOADS["pair256"])),
+        ):
+            log(f"[bench] extra workload {key}")
+            extra[key] = fn()
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        cpu = cpu_baseline(spec, I0, I1, v0t, ms_per_step / hv_ms)
+        cpu = cpu_baseline(spec, I0, I1, v0t, rep)
 
     value = 60.0 * args.steps / T
     out = {
@@ -612,8 +779,12 @@ def main():
         "fp64": fp64,
         "fp32_speedup_vs_fp64": round(fp64["ms_per_solve"] / ms_per_step, 3) if fp64 else None,
         "variants": variants,
-        "hv_algorithmic_GBps": round(hv_bytes / (hv_ms * 1e-3) / 1e9, 1),
-        "hv_algorithmic_bytes": int(hv_bytes),
+        "hv_floor_bytes": int(hv_floor),
+        "floor_frac": round(hv_floor / (hv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "hv_ledger_bytes": int(hv_ledger),
+        "hv_ledger_GBps": round(hv_ledger / (hv_ms * 1e-3) / 1e9, 1),
+        "hv_counter_bytes": int(hv_counter) if hv_counter else None,
+        "counter_over_floor": round(hv_counter / hv_floor, 3) if hv_counter else None,
         "roofline": {
             "bound": "hbm",
             "kernel": dom,
@@ -621,14 +792,17 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": kernels[dom]["traffic"],
+            "traffic": groups[dom]["traffic"],
             "bytes_per_launch": int(dom_bytes),
-            "avg_launch_us": kernels[dom]["avg_us"],
+            "avg_launch_us": groups[dom]["avg_us"],
+            "launches_per_hv": groups[dom]["launches_per_hv"],
         },
         "launch_shape": tuned,
+        "kernel_groups": groups,
         "kernels": kernels,
         "hbm_copy_GBps": round(copy_GBps, 1),
         "cpu_baseline": cpu,
+        "workloads": extra,
     }
     print(json.dumps(out), flush=True)
 
