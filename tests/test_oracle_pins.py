@@ -338,6 +338,122 @@ def test_regularisation_gradient_exact():
     assert (ep - em) / (2 * eps) == pytest.approx(2 * O.inner_V(v0, d, p), rel=1e-10)
 
 
+# --------------------------------------------------------------------------- SL in time
+def _sl_flow(y, t):
+    """Velocity along one axis varying in space and time (periodic in y)."""
+    return 0.35 * (1.0 + 1.5 * t) * np.sin(y) + 0.25 * t * t * np.cos(2.0 * y) + 0.1
+
+
+def _sl_line_case(nt, axis=2, N=4096):
+    """SL transport (R7) of a flow along `axis` that depends on that coordinate and
+    on time: returns the grid points of that axis and the transported displacement
+    u_1 along it.  Along the axis the grid is fine, so interpolation errors stay
+    far below the time-stepping errors examined."""
+    n = [4, 4, 4]
+    n[axis] = N
+    p = P(tuple(n), nt=nt)
+    x = O.grid_coords(p)
+    vs = []
+    for k in range(nt + 1):
+        v = np.zeros((3,) + tuple(n))
+        v[axis] = _sl_flow(x[axis], k / nt)
+        vs.append(v)
+    u = O.sl_transport(vs, p)
+    idx = [0, 0, 0]
+    idx[axis] = slice(None)
+    others = np.delete(u, axis, axis=0)
+    return np.arange(N) * p.h[axis], u[axis][tuple(idx)], float(np.abs(others).max())
+
+
+def _characteristic_foot(y, steps=400):
+    """Exact foot point at t = 0 of the characteristic through y at t = 1,
+    dy/dt = flow(y, t), by classical RK4 with many steps."""
+    h = 1.0 / steps
+    t = 1.0
+    for _ in range(steps):
+        k1 = _sl_flow(y, t)
+        k2 = _sl_flow(y - 0.5 * h * k1, t - 0.5 * h)
+        k3 = _sl_flow(y - 0.5 * h * k2, t - 0.5 * h)
+        k4 = _sl_flow(y - h * k3, t - h)
+        y = y - h / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+        t -= h
+    return y
+
+
+def _heun_foot(y, nt):
+    """Heun's method (explicit trapezoid: Euler predictor, average of the two slopes)
+    applied to the characteristic ODE backward in time from t = 1 to 0 in nt steps."""
+    dt = 1.0 / nt
+    for k in range(nt, 0, -1):
+        s1 = _sl_flow(y, k * dt)
+        s2 = _sl_flow(y - dt * s1, (k - 1) * dt)
+        y = y - 0.5 * dt * (s1 + s2)
+    return y
+
+
+@pytest.mark.parametrize("axis", [2, 0])
+def test_sl_backtrace_is_heun_on_the_characteristics(axis):
+    """State equation (Section 2.3) by R7: with a velocity varying in space and time
+    the transported displacement equals Heun's method on the backward
+    characteristics (textbook form, exact velocities) up to interpolation error,
+    and converges to the exact characteristics at second order in dt."""
+    y = None
+    errs = []
+    for nt in (8, 16, 32):
+        y, u1, off = _sl_line_case(nt, axis)
+        assert off == 0.0
+        heun = _heun_foot(y.copy(), nt) - y
+        assert np.abs(u1 - heun).max() <= 2e-5, (nt, np.abs(u1 - heun).max())
+        errs.append(np.abs(u1 - (_characteristic_foot(y.copy()) - y)).max())
+    r = [errs[k] / errs[k + 1] for k in range(2)]
+    assert all(3.5 <= q <= 4.5 for q in r), (errs, r)
+
+
+# --------------------------------------------------------------------------- P-16
+def test_transported_momentum_identity():
+    """EPDiff (Section 2.2) transports the momentum as a one-form density along the
+    flow whose inverse map the state equation (Section 2.3) carries:
+    mu_1 = det(D psi) (D psi)^T mu_0 o psi with psi = id + u_1.  Shooting (R6) and
+    SL transport (R7) are discretised separately, so the identity holds to
+    discretisation error, which shrinks as the same smooth case is refined."""
+    gaps = []
+    for N in (16, 32):
+        p, _, _, v0, _ = smooth_case((N, N, N), nt=16, amp=0.3)
+        x = O.grid_coords(p)
+        tr = O.shoot(v0, p, np.zeros(p.n))
+        u = tr.u
+        Dpsi = np.empty((3, 3) + p.n)
+        for c in range(3):
+            for d in range(3):
+                Dpsi[c, d] = O.ddx(u[c], d, p) + (1.0 if c == d else 0.0)
+        m0 = O.interp(tr.mu[0], x + u, p)
+        rhs = O.jacobian_det(u, p)[None] * np.einsum("cd...,c...->d...", Dpsi, m0)
+        gaps.append(np.linalg.norm(rhs - tr.mu[-1]) / np.linalg.norm(tr.mu[-1]))
+        # the identity carries content: mu changes along the geodesic by far more
+        assert np.linalg.norm(tr.mu[0] - tr.mu[-1]) >= 5 * gaps[-1] * np.linalg.norm(tr.mu[-1])
+    assert gaps[0] <= 0.05 and gaps[1] <= gaps[0] / 2.0, gaps
+
+
+# --------------------------------------------------------------------------- VJP
+def test_vjp_matches_finite_differences_of_the_warped_image():
+    """The autograd backward (adjoint Jacobi sweep as a vector-Jacobian product,
+    Section 2.2) against central FD of the plain sum l(J_1) = sum gbar J_1 through
+    the forward shooting and SL transport: optimise-then-discretise, so the gap is
+    discretisation-level and shrinks when the same smooth case is refined."""
+    gaps = []
+    for N in (16, 32):
+        p, I0, I1, v0, d = smooth_case((N, N, N), nt=10, amp=0.2)
+        x = O.grid_coords(p)
+        lin = O.linearize(v0, I0, I1, p)
+        gbar = np.sin(x[0] + x[1]) * np.cos(x[2]) + 0.3
+        g = O.vjp_J1(gbar, lin, p)
+        d = d / np.sqrt(np.sum(d * d))
+        eps = 1e-4
+        fd = (np.sum(gbar * O.shoot(v0 + eps * d, p, I0).J1) - np.sum(gbar * O.shoot(v0 - eps * d, p, I0).J1)) / (2 * eps)
+        gaps.append(abs(fd - np.sum(g * d)) / abs(fd))
+    assert gaps[0] <= 5e-2 and gaps[1] <= gaps[0] / 2.0, gaps
+
+
 # --------------------------------------------------------------------------- P-15
 def test_jacobi_incremental_image_matches_literal_transport():
     errs = []
@@ -618,16 +734,43 @@ def test_planted_mistakes(monkeypatch):
         a, b = orig["_adjoint_rhs_variation"](U, w, dv, dmu, mu, p)
         return a, b + 2 * OM.ad(dv, w, p)
 
+    def sl_swapped_times(u, v_old, v_new, p, x=None):  # the two velocity times exchanged in the backtrace
+        if x is None:
+            x = OM.grid_coords(p)
+        X = x - 0.5 * p.dt * (v_old + OM.interp(v_new, x - p.dt * v_old, p))
+        return OM.interp(u, X, p) + (X - x)
+
+    def sl_frozen_time(u, v_old, v_new, p, x=None):  # v_n at both evaluations: no time variation
+        if x is None:
+            x = OM.grid_coords(p)
+        X = x - 0.5 * p.dt * (v_old + OM.interp(v_old, x - p.dt * v_old, p))
+        return OM.interp(u, X, p) + (X - x)
+
+    def vjp_without_L(gbar, lin, p):  # returns w_0 instead of L w_0
+        _, w0 = OM.backward_sweep(-np.asarray(gbar)[None] * lin.G, lin.tr, p)
+        return w0
+
+    def vjp_gbar_sign(gbar, lin, p):  # U^(1) = +gbar grad J_1
+        return orig["vjp_J1"](-np.asarray(gbar), lin, p)
+
     orig["pcg_l2"] = OM.pcg_l2
     orig["_adjoint_rhs_variation"] = OM._adjoint_rhs_variation
+    orig["vjp_J1"] = OM.vjp_J1
+    sl_pin = lambda: test_sl_backtrace_is_heun_on_the_characteristics(2)
     cases = [
+        ("sl_step", sl_swapped_times, [sl_pin]),
+        ("sl_step", sl_frozen_time, [sl_pin]),
+        ("vjp_J1", vjp_without_L, [test_vjp_matches_finite_differences_of_the_warped_image]),
+        ("vjp_J1", vjp_gbar_sign, [test_vjp_matches_finite_differences_of_the_warped_image]),
         ("_adjoint_rhs_variation", variation_wrong_sign, [test_newton_sweep_is_the_exact_linearisation]),
         ("pcg_l2", pcg_unpreconditioned_beta, [test_pcg_l2_iterates_equal_cg_v_and_dense_solve]),
         ("ad", ad_transposed, [test_ad_constant_velocity_closed_form]),
-        ("ad_star", ad_star_sign, [test_ad_identities, test_dot_product_tangent_vs_backward]),
+        ("ad_star", ad_star_sign, [test_ad_identities, test_dot_product_tangent_vs_backward,
+                                   test_transported_momentum_identity]),
         ("backward_sweep", bw_wrong_order, [test_dot_product_tangent_vs_backward]),
         ("symbol_L", symbol_wrong_power, [lambda: test_L_K_single_modes((8, 8, 8))]),
-        ("sl_step", sl_forward_foot, [test_shoot_constant_velocity_translates, test_sl_stationary_shear_exact]),
+        ("sl_step", sl_forward_foot, [test_shoot_constant_velocity_translates, test_sl_stationary_shear_exact,
+                                      test_transported_momentum_identity]),
     ]
     for name, bad, checks in cases:
         plant(name, bad)
