@@ -315,7 +315,34 @@ int lddmm_batch_hessvec(lddmm_batch* batch, void* const* dv, void* const* hv, in
 /* lddmm_autotune on every context. */
 int lddmm_batch_autotune(lddmm_batch* batch, int reps);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): lddmm_apply_operator without
+ * a context.  out = K in or L in (op) for a field of ncomp (1 or 3) components
+ * of dtype on the grid n[3] (same limits as lddmm_params.n), with
+ * L = (Id - alpha Laplacian)^s; in == out is allowed; in and out are device
+ * pointers on the current device, ordered on hip_stream (NULL = the legacy
+ * default stream).  Same kernels and launch shapes as an untuned context.
+ * Workspace: nothing is allocated.  The transform tables and the spectrum live in
+ * one static device array of LDDMM_NOALLOC_WORKSPACE_BYTES per device, held from
+ * the first call on that device until the process ends; the tables take a few
+ * KB and the spectrum ncomp * N0 * N1 * (N2/2 + 1) complex values of dtype (e.g.
+ * 128^3 vector fields in FP64, 160^3 in FP32).  Larger requests return
+ * LDDMM_EUNSUPPORTED with the bytes needed in lddmm_last_error(NULL).
+ * The first call for a grid and dtype on a device (and the first after another
+ * grid or dtype was used there) copies the tables into the array, synchronising
+ * hip_stream before and after; it returns LDDMM_ESTATE while hip_stream is being
+ * captured.  Later calls with the same grid and dtype only enqueue kernels.
+ * Every call on a device shares that device's array: calls that overlap in time
+ * on one device (other streams or host threads without ordering between them)
+ * race and give undefined results.  Errors of this call: lddmm_last_error(NULL)
+ * gives the calling thread's last message. */
+#define LDDMM_NOALLOC_WORKSPACE_BYTES (64 * 1024 * 1024)
+int lddmm_apply_operator_noalloc(const int32_t n[3], int dtype, double alpha, int s, int op, int ncomp,
+                                 const void* in, void* out, void* hip_stream);
+
 const char* lddmm_strerror(int status);
+/* Last error message of ctx; with ctx == NULL, of the calling thread's last failed
+ * lddmm_apply_operator_noalloc ("null context" if there was none). */
 const char* lddmm_last_error(lddmm_ctx* ctx);
 
 #ifdef __cplusplus

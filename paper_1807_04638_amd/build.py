@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblddmm.so")
 
-SOURCES = ["fft.hip", "stencil.hip", "sl.hip", "reduce.hip", "lddmm_api.cpp"]
+SOURCES = ["fft.hip", "stencil.hip", "sl.hip", "reduce.hip", "noalloc.hip", "lddmm_api.cpp"]
 
 ARCH = "gfx950"
 FLAGS = [

@@ -25,6 +25,9 @@
 
 namespace lddmm {
 
+// Message of the calling thread's last failed context-free call (noalloc.hip).
+const char* noalloc_last_error();
+
 // ---------------------------------------------------------------------------
 // Profiler
 // ---------------------------------------------------------------------------
@@ -1376,7 +1379,11 @@ const char* lddmm_strerror(int status) {
   }
 }
 
-const char* lddmm_last_error(lddmm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* lddmm_last_error(lddmm_ctx* ctx) {
+  if (ctx) return ctx->err.c_str();
+  const char* m = lddmm::noalloc_last_error();
+  return m[0] ? m : "null context";
+}
 
 }  // extern "C"
 

@@ -127,6 +127,11 @@ SIGNATURES = {
     ),
     "lddmm_batch_hessvec": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int]),
     "lddmm_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lddmm_apply_operator_noalloc": (
+        ctypes.c_int,
+        [ctypes.POINTER(ctypes.c_int32), ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
+         _vp, _vp],
+    ),
     "lddmm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "lddmm_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -166,6 +171,35 @@ class Trace:
 
     report: dict
     log: list
+
+
+def apply_operator_noalloc(op, f, alpha, s=2, out=None):
+    """K f (op = OP_K) or L f (op = OP_L) without a context and without any
+    device allocation by the library (``lddmm_apply_operator_noalloc``): the
+    transform's workspace is the library's static per-device array.  f is a
+    contiguous float32/float64 scalar (N0, N1, N2) or vector (3, N0, N1, N2)
+    field on the current HIP device; out (same shape, dtype, device) may be f
+    itself.  Ordered on torch's current stream."""
+    lib = load_library()
+    if f.dim() not in (3, 4) or (f.dim() == 4 and f.shape[0] != 3):
+        raise ValueError("f must be (N0, N1, N2) or (3, N0, N1, N2)")
+    if f.dtype not in (torch.float32, torch.float64) or f.device.type != "cuda" or not f.is_contiguous():
+        raise ValueError("f must be a contiguous float32/float64 tensor on a HIP device")
+    if out is None:
+        out = torch.empty_like(f)
+    elif out.shape != f.shape or out.dtype != f.dtype or out.device != f.device or not out.is_contiguous():
+        raise ValueError("out must match f's shape, dtype and device and be contiguous")
+    ncomp = 3 if f.dim() == 4 else 1
+    n = (ctypes.c_int32 * 3)(*[int(x) for x in f.shape[-3:]])
+    dtype = F32 if f.dtype == torch.float32 else F64
+    with torch.cuda.device(f.device):
+        st = torch.cuda.current_stream(f.device).cuda_stream
+        rc = lib.lddmm_apply_operator_noalloc(n, dtype, float(alpha), int(s), int(op), ncomp, _ptr(f), _ptr(out),
+                                              ctypes.c_void_p(st))
+    if rc != OK:
+        msg = lib.lddmm_last_error(None) or b""
+        raise LddmmError(rc, f"apply_operator_noalloc: {lib.lddmm_strerror(rc).decode()}: {msg.decode()}")
+    return out
 
 
 class Registration:
