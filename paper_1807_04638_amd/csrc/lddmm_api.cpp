@@ -124,7 +124,6 @@ class Engine {
   std::vector<T*> tmu, tv, tmus, tvs;
   // trajectory memory policy: store every step, keep mu every c steps and
   // re-materialise one segment at a time, or keep mu_0 only and replay
-  enum { TRAJ_STORE_ALL = 0, TRAJ_CHECKPOINT = 1, TRAJ_RECOMPUTE = 2 };
   int traj_policy = TRAJ_STORE_ALL, traj_every = 0;
   size_t traj_bytes = 0;
   std::vector<T*> ck;                                 // mu_{k c} (checkpoint) or mu_0 (recompute)
@@ -238,41 +237,11 @@ class Engine {
   }
 
 
-  // ---- trajectory memory ----------------------------------------------------
-  // Fields held per policy (V = one vector field):
-  //   store-all   4 nt + 2             (mu_n, v_n for n <= nt; mu*_n, v*_n for n < nt)
-  //   checkpoint  ceil(nt/c) + 4 c + 1 (mu every c steps; one segment: mu, v, mu*, v*)
-  //   recompute   7                    (mu_0; rolling mu, v pairs; mu*, v*)
-  static size_t traj_fields(int policy, int nt, int c) {
-    if (policy == TRAJ_STORE_ALL) return size_t(4) * nt + 2;
-    if (policy == TRAJ_CHECKPOINT) return size_t((nt + c - 1) / c) + size_t(4) * c + 1;
-    return 7;
-  }
-
+  // ---- trajectory memory (policy: choose_trajectory) -------------------------
   int alloc_trajectory(const lddmm_params& p, size_t vbytes) {
     const int nt = p.nt;
-    int policy = TRAJ_STORE_ALL, c = 0;
-    if (p.checkpoint_every > 0) {
-      policy = TRAJ_CHECKPOINT;
-      c = std::min(p.checkpoint_every, nt);
-    } else if (p.checkpoint_every < 0) {
-      policy = TRAJ_RECOMPUTE;
-    } else if (p.mem_budget_bytes > 0) {
-      // automatic: the cheapest policy in recomputation whose total fits the budget
-      const size_t fixed = bytes;  // workspace allocated so far
-      const size_t budget = size_t(p.mem_budget_bytes);
-      if (fixed + traj_fields(TRAJ_STORE_ALL, nt, 0) * vbytes <= budget) {
-        policy = TRAJ_STORE_ALL;
-      } else {
-        policy = TRAJ_RECOMPUTE;
-        for (int cc = nt; cc >= 1; --cc)
-          if (fixed + traj_fields(TRAJ_CHECKPOINT, nt, cc) * vbytes <= budget) {
-            policy = TRAJ_CHECKPOINT;
-            c = cc;
-            break;
-          }
-      }
-    }
+    const TrajChoice ch = choose_trajectory(nt, p.checkpoint_every, (long long)p.mem_budget_bytes, bytes, vbytes);
+    const int policy = ch.policy, c = ch.every;
     traj_policy = policy;
     traj_every = c;
     const size_t before = bytes;

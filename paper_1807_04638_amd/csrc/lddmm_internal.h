@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "fft_core.h"
+#include "index_math.h"
 
 namespace lddmm {
 
@@ -69,43 +70,11 @@ struct Grid {
   int pair_rows = 1;     // row-vectorised stencils: x1 rows shared by the two halves of a wave
 };
 
-// True if the row-vectorised stencil kernels take vw voxels per lane on rows of
-// n2 voxels: vw in {1, 2, 4} and a row is 32 or 64 lanes.
-bool row_vector_valid(int n2, int vw);
-
-// Voxel tiling of the field kernels: a block covers BX x BY voxels of one x0
-// plane (BX spans a whole x2 row when N2 <= 256, so x2 halos stay inside the
-// tile).  With XCD-aware mapping the 8 XCDs (which take blocks round-robin)
-// each own a contiguous slab of x1 rows for every x0, so x1 halos and the
-// neighbouring x0 planes a block needs were loaded into the same L2.
-struct FieldTiling {
-  int BX, BY;      // block shape (threads)
-  int TX, TY;      // tiles along x2 and x1
-  int slab;        // tile rows of x1 per XCD (0: plain linear order)
-  unsigned blocks; // TX * TY * N0
-};
 FieldTiling make_field_tiling(const Grid& g);
 
 // Voxel (i0, i1, i2) of the calling thread under tiling t; false outside the grid.
 __device__ __forceinline__ bool tile_voxel(const FieldTiling& t, int n1, int n2, int& i0, int& i1, int& i2) {
-  const int b = blockIdx.x;
-  int bx, by;
-  if (t.slab) {
-    const int x = b & 7, k = b >> 3;
-    const int r = k / t.TX;
-    bx = k - r * t.TX;
-    const int rz = r / t.slab;
-    by = x * t.slab + (r - rz * t.slab);
-    i0 = rz;
-  } else {
-    const int r = b / t.TX;
-    bx = b - r * t.TX;
-    i0 = r / t.TY;
-    by = r - i0 * t.TY;
-  }
-  i2 = bx * t.BX + threadIdx.x;
-  i1 = by * t.BY + threadIdx.y;
-  return i2 < n2 && i1 < n1;
+  return tile_voxel_at(t, int(blockIdx.x), int(threadIdx.x), int(threadIdx.y), n1, n2, i0, i1, i2);
 }
 
 // ---------------------------------------------------------------------------

@@ -37,11 +37,6 @@ SlGeo<T> make_sl_geo(const Grid& g) {
   return o;
 }
 
-__device__ __forceinline__ int wrap(int j, int n) {
-  j %= n;
-  return j < 0 ? j + n : j;
-}
-
 // Corners and weights of the trilinear stencil at voxel (i0, i1, i2) displaced by
 // (d0, d1, d2) voxels.  The two x2 corners of each (x0, x1) pair are adjacent in
 // memory unless the lower one is the last of its row (periodic wrap), so a pair
@@ -58,17 +53,13 @@ struct Tri {
 
 template <typename T>
 __device__ __forceinline__ Tri<T> tri_setup(const SlGeo<T>& g, int i0, int i1, int i2, T d0, T d1, T d2) {
-  // offsets beyond a million voxels (or NaN) are clamped: the periodic wrap keeps
-  // every index in range and the integer conversion cannot overflow
-  constexpr T lim = T(1.0e6);
-  d0 = fmin(fmax(d0, -lim), lim);
-  d1 = fmin(fmax(d1, -lim), lim);
-  d2 = fmin(fmax(d2, -lim), lim);
-  const T f0 = floor(d0), f1 = floor(d1), f2 = floor(d2);
-  const T t0 = d0 - f0, t1 = d1 - f1, t2 = d2 - f2;
-  const int a0 = wrap(i0 + int(f0), g.n0), a1 = wrap(i1 + int(f1), g.n1), a2 = wrap(i2 + int(f2), g.n2);
-  const int b0 = a0 + 1 == g.n0 ? 0 : a0 + 1;
-  const int b1 = a1 + 1 == g.n1 ? 0 : a1 + 1;
+  // cells and weights per axis (offsets clamped, indices wrapped: sl_axis)
+  int a0, b0, a1, b1, a2, b2;
+  T t0, t1, t2;
+  sl_axis(i0, d0, g.n0, a0, b0, t0);
+  sl_axis(i1, d1, g.n1, a1, b1, t1);
+  sl_axis(i2, d2, g.n2, a2, b2, t2);
+  (void)b2;
   const int s0 = g.n1 * g.n2;
   const int r0[2] = {a0 * s0, b0 * s0};
   const int r1[2] = {a1 * g.n2, b1 * g.n2};

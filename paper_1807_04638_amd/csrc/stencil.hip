@@ -21,25 +21,9 @@
 
 namespace lddmm {
 
-bool row_vector_valid(int n2, int vw) {
-  if (vw != 1 && vw != 2 && vw != 4) return false;
-  return n2 % vw == 0 && (n2 / vw == 32 || n2 / vw == 64);
-}
-
 bool stencil_zero_start(const Grid& g) { return row_vector_valid(g.n2, g.rowvec); }
 
-FieldTiling make_field_tiling(const Grid& g) {
-  FieldTiling t;
-  int bx = (g.n2 + 31) / 32 * 32;
-  if (bx > 256) bx = 256;
-  t.BX = bx;
-  t.BY = 256 / bx > 0 ? 256 / bx : 1;
-  t.TX = (g.n2 + t.BX - 1) / t.BX;
-  t.TY = (g.n1 + t.BY - 1) / t.BY;
-  t.slab = (t.TY % 8 == 0) ? t.TY / 8 : 0;
-  t.blocks = unsigned(t.TX) * unsigned(t.TY) * unsigned(g.n0);
-  return t;
-}
+FieldTiling make_field_tiling(const Grid& g) { return field_tiling(g.n0, g.n1, g.n2); }
 
 namespace {
 
@@ -80,9 +64,9 @@ __device__ __forceinline__ bool voxel(const Geo<T>& g, int& i0, int& i1, int& i2
 
 template <typename T>
 __device__ __forceinline__ Nbr neighbours(const Geo<T>& g, int i0, int i1, int i2) {
-  const int p0 = i0 + 1 == g.n0 ? 0 : i0 + 1, m0 = i0 == 0 ? g.n0 - 1 : i0 - 1;
-  const int p1 = i1 + 1 == g.n1 ? 0 : i1 + 1, m1 = i1 == 0 ? g.n1 - 1 : i1 - 1;
-  const int p2 = i2 + 1 == g.n2 ? 0 : i2 + 1, m2 = i2 == 0 ? g.n2 - 1 : i2 - 1;
+  const int p0 = periodic_next(i0, g.n0), m0 = periodic_prev(i0, g.n0);
+  const int p1 = periodic_next(i1, g.n1), m1 = periodic_prev(i1, g.n1);
+  const int p2 = periodic_next(i2, g.n2), m2 = periodic_prev(i2, g.n2);
   const int s0 = g.n1 * g.n2;
   const int r0 = i0 * s0, rp0 = p0 * s0, rm0 = m0 * s0;
   const int r1 = i1 * g.n2;
@@ -467,8 +451,8 @@ __device__ __forceinline__ bool vvoxel(const Geo<T>& g, int RW, VNbr<VW>& nb) {
   int i0, i1, j;
   if (!tile_voxel(g.ft, g.n1, g.n2 / VW, i0, i1, j)) return false;
   const int i2 = j * VW;
-  const int p0 = i0 + 1 == g.n0 ? 0 : i0 + 1, m0 = i0 == 0 ? g.n0 - 1 : i0 - 1;
-  const int p1 = i1 + 1 == g.n1 ? 0 : i1 + 1, m1 = i1 == 0 ? g.n1 - 1 : i1 - 1;
+  const int p0 = periodic_next(i0, g.n0), m0 = periodic_prev(i0, g.n0);
+  const int p1 = periodic_next(i1, g.n1), m1 = periodic_prev(i1, g.n1);
   const int s0 = g.n1 * g.n2;
   const int r1 = i1 * g.n2 + i2;
   nb.o = i0 * s0 + r1;
@@ -477,9 +461,7 @@ __device__ __forceinline__ bool vvoxel(const Geo<T>& g, int RW, VNbr<VW>& nb) {
   nb.ox[2] = i0 * s0 + p1 * g.n2 + i2;
   nb.ox[3] = i0 * s0 + m1 * g.n2 + i2;
   const int lane = int(threadIdx.x + threadIdx.y * blockDim.x) & 63;
-  const int base = lane & ~(RW - 1);
-  nb.left = base | ((lane - 1) & (RW - 1));
-  nb.right = base | ((lane + 1) & (RW - 1));
+  row_lanes(lane, RW, nb.left, nb.right);
   nb.upper = lane >= 32;
   return true;
 }
