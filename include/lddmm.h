@@ -297,11 +297,25 @@ int lddmm_memory_bytes(lddmm_ctx* ctx, int64_t* bytes);
  * Hessian-vector product enabled.  The contexts are used with the functions
  * above (lddmm_batch_get); their calls are ordered on their own streams, so a
  * caller working on another stream synchronises before handing buffers over.
- * lddmm_batch_gn_solve / _hessvec run the pairs concurrently on one host
- * thread per pair (concurrent != 0) or one after the other, and return after
- * every pair has finished and its results are written (each pair's stream is
- * synchronised); the first failing status is returned.  Their pointer arrays
- * hold one entry per pair; a NULL entry gives LDDMM_EINVAL before any work. */
+ * lddmm_batch_gn_solve / _hessvec take a mode (argument `concurrent`):
+ *   LDDMM_BATCH_SEQUENTIAL  one pair after the other;
+ *   LDDMM_BATCH_THREADS     one host thread per pair, each on its pair's stream;
+ *   LDDMM_BATCH_LOCKSTEP    every phase of the solve (gradient, each CG
+ *                           iteration, <g, p>, each line-search trial) is enqueued
+ *                           for all pairs that need it before one wait (the
+ *                           launches by one persistent host worker per pair); the
+ *                           CG scalars stay on the device, and a CG iteration or a
+ *                           Hessian-vector product of several pairs is one graph
+ *                           spanning their streams (store-all trajectories).  All
+ *                           pairs must share a dtype (else: threads).
+ * Every mode gives bitwise the results of lddmm_gn_solve / lddmm_hessvec on each
+ * context alone.  They return after every pair has finished and its results are
+ * written (each pair's stream is synchronised); the first failing status is
+ * returned.  Their pointer arrays hold one entry per pair; a NULL entry gives
+ * LDDMM_EINVAL before any work. */
+#define LDDMM_BATCH_SEQUENTIAL 0
+#define LDDMM_BATCH_THREADS 1
+#define LDDMM_BATCH_LOCKSTEP 2
 typedef struct lddmm_batch lddmm_batch;
 int lddmm_batch_create(const lddmm_params* per_pair, int npairs, lddmm_batch** out);
 int lddmm_batch_destroy(lddmm_batch* batch);

@@ -13,8 +13,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <thread>
 #include <cmath>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
+#include <thread>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -145,8 +148,14 @@ class Engine {
   T *cr = nullptr, *cd = nullptr, *cHd = nullptr, *cLr = nullptr, *cLd = nullptr, *cx = nullptr;
   T *gv = nullptr, *Lg = nullptr, *trial = nullptr, *tmpS = nullptr;
   double* partials = nullptr;
+  // FP64 results on the device and their pinned host mirror.  Slots: 0 dot
+  // scratch; 2, 3 energy sums; 4-7 CG sums; 8, 9 check (non-finite count, max
+  // |x|); 10 gradient norm sum; 11 <g, p> sum.  cgs: CG scalar block.
+  static constexpr int kResSlots = 16;
   double* dres = nullptr;
-  double* hres = nullptr;  // pinned host mirror of dres
+  double* hres = nullptr;
+  double* cgs = nullptr;
+  double* hcg = nullptr;  // pinned host mirror of cgs
 
   // full Newton Hessian: first-order adjoint (U^, w) at the two stage inputs of
   // every backward step, and the tangent's trajectory variations (dmu, K dmu) at
@@ -228,11 +237,14 @@ class Engine {
     if (hipMalloc(&q, sizeof(double) * 2 * kReduceBlocks) != hipSuccess) return fail(LDDMM_ENOMEM, "partials");
     allocs.push_back(q);
     partials = static_cast<double*>(q);
-    if (hipMalloc(&q, sizeof(double) * 8) != hipSuccess) return fail(LDDMM_ENOMEM, "results");
+    if (hipMalloc(&q, sizeof(double) * (kResSlots + kCgSlots)) != hipSuccess) return fail(LDDMM_ENOMEM, "results");
     allocs.push_back(q);
     dres = static_cast<double*>(q);
-    if (hipHostMalloc(reinterpret_cast<void**>(&hres), sizeof(double) * 8, hipHostMallocDefault) != hipSuccess)
+    cgs = dres + kResSlots;
+    if (hipHostMalloc(reinterpret_cast<void**>(&hres), sizeof(double) * (kResSlots + kCgSlots),
+                      hipHostMallocDefault) != hipSuccess)
       return fail(LDDMM_ENOMEM, "pinned results");
+    hcg = hres + kResSlots;
     return 0;
   }
 
@@ -385,6 +397,12 @@ class Engine {
     (void)hipMemcpyAsync(hres, dres, sizeof(double) * k, hipMemcpyDeviceToHost, st);
     (void)hipStreamSynchronize(st);
   }
+  // enqueue a copy of every result slot and the CG scalars to the host mirror;
+  // readable after wait()
+  void post_fetch() {
+    (void)hipMemcpyAsync(hres, dres, sizeof(double) * (kResSlots + kCgSlots), hipMemcpyDeviceToHost, st);
+  }
+  void wait() { (void)hipStreamSynchronize(st); }
   // dres[slot] = sum a.b over ncomp components (FP64), enqueued only
   void dot_dev(const T* a, const T* b, int ncomp, int slot) {
     launch_dot(a, b, ncomp * N, partials, dres + slot, st, &prof);
@@ -473,15 +491,28 @@ class Engine {
     return hip_status("linearize");
   }
 
-  void linearize_nocheck(const T* v0) {
+  // Linearization in two halves: the device work (trajectory store, residual,
+  // G = grad J_1 and the sums of both energy terms in dres[2], dres[3]), then,
+  // once those sums are on the host, the energy.
+  void linearize_enqueue(const T* v0) {
     if (v0 != lin_v0) copy(lin_v0, v0, 3 * N);
     shoot_core(lin_v0, true, true, J1, nullptr, nullptr);
     launch_residual_grad<T>(g, J1, I1, res, G, st, &prof);
-    Ereg = dot(store_slot_mu0(), lin_v0);
-    Edata = dot(res, res, 1) / P.sigma2;
+    dot_dev(store_slot_mu0(), lin_v0, 3, 2);
+    dot_dev(res, res, 1, 3);
+  }
+  void linearize_finish() {
+    Ereg = cell * hres[2];
+    Edata = cell * hres[3] / P.sigma2;
     E = Ereg + Edata;
     linearized = true;
     ++lin_epoch;
+  }
+  void linearize_nocheck(const T* v0) {
+    linearize_enqueue(v0);
+    post_fetch();
+    wait();
+    linearize_finish();
   }
 
   // ---- adjoint Jacobi sweep (transposed Heun) ------------------------------
@@ -571,12 +602,20 @@ class Engine {
     backward(hv, dv);     // hv = 2 dv + w_0
   }
 
-  void drop_graph() {
+  void drop_hv_graph() {
     if (hv_exec) (void)hipGraphExecDestroy(hv_exec);
     hv_exec = nullptr;
     graph_dv = nullptr;
     graph_ldv = nullptr;
     graph_hv = nullptr;
+  }
+  // every captured graph (launch shapes or options changed); graph_gen tells
+  // batches that graphs they captured from this context are stale
+  int graph_gen = 0;
+  void drop_graph() {
+    drop_hv_graph();
+    drop_cg_graph();
+    ++graph_gen;
   }
 
   // The Hv at a fixed linearization is a fixed sequence of launches on fixed
@@ -590,7 +629,7 @@ class Engine {
       return;
     }
     if (!hv_exec || graph_dv != dv || graph_hv != hv || graph_ldv != Ldv) {
-      drop_graph();
+      drop_hv_graph();
       hipGraph_t graph = nullptr;
       if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         hessvec_kernels(dv, hv, Ldv);
@@ -846,82 +885,140 @@ class Engine {
     return hip_status("vjp");
   }
 
-  // ---- CG in V -------------------------------------------------------------
-  // Solves H x = -g; ||r||_V <= eta ||g||_V or maxit.  Uses cr/cd/cHd/cLr/cLd.
-  int cg(const T* gin, T* x, double eta, int maxit, int* iters) {
+  // ---- CG in V and PCG in L2, scalars on the device ---------------------------
+  // CG in V for H x = -g (||r||_V <= eta ||g||_V or maxit): r, d, H d, L r, L d in
+  // cr, cd, cHd, cLr, cLd.  The CG in V tracks the L-image of its direction
+  // linearly (L d = L r + beta L d) for its inner products, and the GN product
+  // takes it as its start value.
+  // PCG in L2 for (L H) x = -g_L2 with preconditioner K (the "GN, L2" variant):
+  // r, z = K r, d, q = L H d in cr, cLr, cd, cHd; H d itself in cLd; stops at
+  // ||r||_L2 <= eta ||g_L2||_L2.
+  // Every decision (step length, stop, beta) is taken on the device from the
+  // FP64 sums; the host only reads whether the solve is still active.
+  bool cg_l2 = false;  // the solve in progress is the PCG in L2
+  int cg_maxit = 0;
+  void cg_begin(const T* gin, T* x, double eta, int maxit, bool l2) {
     const long long V = 3 * N;
+    cg_l2 = l2;
+    cg_maxit = maxit;
     launch_axpbyz<T>(V, -1.0, gin, 0.0, gin, cr, st, &prof);
-    copy(cd, cr, V);
     launch_fill<T>(V, T(0), x, st, &prof);
-    applyL(cr, cLr);
-    copy(cLd, cLr, V);
-    double rr = dot(cLr, cr);
-    const double tol = eta * std::sqrt(rr);
-    int it = 0;
-    // One host read per iteration: the step length is taken on the device from
-    // <d, Hd>, and the host reads that curvature together with the new residual.
-    for (it = 1; it <= maxit; ++it) {
-      apply_hessian(cd, cHd, cLd);
+    if (!l2) {
+      copy(cd, cr, V);
+      applyL(cr, cLr);
+      copy(cLd, cLr, V);
+      dot_dev(cLr, cr, 3, 4);
+      launch_cg_begin(cgs, dres + 4, dres + 4, cell, eta, maxit, 1, st, &prof);
+    } else {
+      applyK(cr, cLr);
+      copy(cd, cLr, V);
+      dot_dev(cr, cLr, 3, 4);
+      dot_dev(gin, gin, 3, 7);
+      launch_cg_begin(cgs, dres + 4, dres + 7, cell, eta, maxit, 0, st, &prof);
+    }
+  }
+  // One iteration (enqueue only; a no-op in effect once the solve has stopped).
+  // hess_kernels: launch the Hessian kernel by kernel (inside a capture).
+  void cg_iteration(T* x, bool hess_kernels = false) {
+    const long long V = 3 * N;
+    if (!cg_l2) {
+      if (hess_kernels && !use_newton)
+        hessvec_kernels(cd, cHd, cLd);
+      else
+        apply_hessian(cd, cHd, cLd);
       dot_dev(cLd, cHd, 3, 5);
-      launch_cg_step<T>(V, rr, cell, dres + 5, cd, cHd, x, cr, st, &prof);
+      launch_cg_alpha(cgs, dres + 5, cell, st, &prof);
+      launch_cg_step_dev<T>(V, cgs, cd, cHd, x, cr, st, &prof);
       applyL(cr, cLr);
       dot_dev(cLr, cr, 3, 6);
-      fetch(7);
-      const double dHd = cell * hres[5];
-      if (!(dHd > 0.0)) {  // non-positive curvature: x was left alone; take -g on the first direction
-        if (it == 1) copy(x, cd, V);
-        --it;
-        break;
-      }
-      const double rr_new = cell * hres[6];
-      if (std::sqrt(rr_new) <= tol) break;
-      const double beta = rr_new / rr;
-      launch_axpby<T>(V, 1.0, cr, beta, cd, st, &prof);
-      launch_axpby<T>(V, 1.0, cLr, beta, cLd, st, &prof);
-      rr = rr_new;
-    }
-    if (it > maxit) it = maxit;
-    if (iters) *iters = it;
-    return 0;
-  }
-
-  // PCG in L2 for (L H) x = -g_L2 with preconditioner K (the "GN, L2" variant):
-  // r, z = K r, d, q = L H d in cr, cLr, cd, cHd; H d itself in cLd.  Stops at
-  // ||r||_L2 <= eta ||g_L2||_L2.
-  int pcg_l2(const T* gl2, T* x, double eta, int maxit, int* iters) {
-    const long long V = 3 * N;
-    launch_axpbyz<T>(V, -1.0, gl2, 0.0, gl2, cr, st, &prof);
-    applyK(cr, cLr);
-    copy(cd, cLr, V);
-    launch_fill<T>(V, T(0), x, st, &prof);
-    double rz = dot(cr, cLr);
-    const double tol = eta * std::sqrt(dot(gl2, gl2));
-    int it = 0;
-    // One host read per iteration (curvature, residual norm and <r, K r>
-    // together); on the last iteration the K r it computes goes unused.
-    for (it = 1; it <= maxit; ++it) {
-      hessvec_core(cd, cLd);
+      launch_cg_beta(cgs, dres + 6, dres + 6, cell, st, &prof);
+      launch_cg_direction<T>(V, cgs, cr, cd, st, &prof);
+      launch_cg_direction<T>(V, cgs, cLr, cLd, st, &prof);
+    } else {
+      if (hess_kernels)
+        hessvec_kernels(cd, cLd);
+      else
+        hessvec_core(cd, cLd);
       applyL(cLd, cHd);
       dot_dev(cd, cHd, 3, 5);
-      launch_cg_step<T>(V, rz, cell, dres + 5, cd, cHd, x, cr, st, &prof);
+      launch_cg_alpha(cgs, dres + 5, cell, st, &prof);
+      launch_cg_step_dev<T>(V, cgs, cd, cHd, x, cr, st, &prof);
       dot_dev(cr, cr, 3, 6);
       applyK(cr, cLr);
       dot_dev(cr, cLr, 3, 4);
-      fetch(7);
-      const double dq = cell * hres[5];
-      if (!(dq > 0.0)) {
-        --it;
-        break;
-      }
-      if (std::sqrt(cell * hres[6]) <= tol) break;
-      const double rz_new = cell * hres[4];
-      launch_axpby<T>(V, 1.0, cLr, rz_new / rz, cd, st, &prof);
-      rz = rz_new;
+      launch_cg_beta(cgs, dres + 4, dres + 6, cell, st, &prof);
+      launch_cg_direction<T>(V, cgs, cLr, cd, st, &prof);
     }
-    if (it > maxit) it = maxit;
-    if (iters) *iters = it;
+  }
+  bool cg_active() const { return hcg[CG_ACTIVE] != 0.0; }
+  int cg_iters_done() const { return int(hcg[CG_ITERS]); }
+
+  // The CG iteration replayed from a captured graph (exec.graph, store-all, Gauss-
+  // Newton Hessian, not profiling): its launches and buffers are fixed for the
+  // context, only the data change.  cgi_graph is kept for batches, which nest it.
+  hipGraph_t cgi_graph = nullptr;
+  hipGraphExec_t cgi_exec = nullptr;
+  T* cgi_x = nullptr;
+  bool cgi_l2 = false;
+  bool cg_graph_ok() const { return use_graph && traj_policy == TRAJ_STORE_ALL && !prof.enabled && st && !use_newton; }
+  void drop_cg_graph() {
+    if (cgi_exec) (void)hipGraphExecDestroy(cgi_exec);
+    if (cgi_graph) (void)hipGraphDestroy(cgi_graph);
+    cgi_exec = nullptr;
+    cgi_graph = nullptr;
+    cgi_x = nullptr;
+  }
+  // Capture one iteration for (x, method) unless already captured; false if
+  // capture is not possible (the caller then runs the iteration eagerly).
+  bool ensure_cg_graph(T* x) {
+    if (!cg_graph_ok()) return false;
+    if (cgi_graph && cgi_x == x && cgi_l2 == cg_l2) return true;
+    drop_cg_graph();
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    cg_iteration(x, true);
+    hipGraph_t graph = nullptr;
+    if (hipStreamEndCapture(st, &graph) != hipSuccess || !graph) {
+      (void)hipGetLastError();
+      return false;
+    }
+    if (hipGraphInstantiate(&cgi_exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipGraphDestroy(graph);
+      cgi_exec = nullptr;
+      return false;
+    }
+    cgi_graph = graph;
+    cgi_x = x;
+    cgi_l2 = cg_l2;
+    return true;
+  }
+  void cg_step_enqueue(T* x) {
+    if (ensure_cg_graph(x))
+      (void)hipGraphLaunch(cgi_exec, st);
+    else
+      cg_iteration(x);
+  }
+  // Whole solve on this context: one host read per iteration to stop early.
+  int krylov(const T* gin, T* x, double eta, int maxit, bool l2, int* iters) {
+    cg_begin(gin, x, eta, maxit, l2);
+    for (int it = 1; it <= maxit; ++it) {
+      cg_step_enqueue(x);
+      post_fetch();
+      wait();
+      if (!cg_active()) break;
+    }
+    if (maxit < 1) {
+      post_fetch();
+      wait();
+    }
+    if (iters) *iters = cg_iters_done();
     return 0;
   }
+  int cg(const T* gin, T* x, double eta, int maxit, int* iters) { return krylov(gin, x, eta, maxit, false, iters); }
+  int pcg_l2(const T* gl2, T* x, double eta, int maxit, int* iters) { return krylov(gl2, x, eta, maxit, true, iters); }
 
   int cg_solve(const T* gin, T* x, double eta, int maxit, int* iters) {
     if (!linearized) return fail(LDDMM_ESTATE, "cg_solve without a linearization");
@@ -931,113 +1028,232 @@ class Engine {
   }
 
   // ---- inexact Gauss-Newton-Krylov -----------------------------------------
-  int gn_solve(T* v, const lddmm_solve_opts* o, lddmm_solve_report* rep, lddmm_iter_log* log, int log_cap) {
+  // The solve is a sequence of phases, each an enqueue followed (after the host
+  // has the results) by a decision: the gradient at the current iterate, the
+  // Krylov solve for the step, <g, p>, the Armijo trials, the bookkeeping of the
+  // iteration.  gn_solve runs the phases of one context in order; a batch runs
+  // each phase for all of its contexts before waiting once (gn_* below).
+  struct Gn {
+    lddmm_solve_opts op{};
+    int method = LDDMM_GN_V;
+    int k = 0;
+    bool done = false;
+    bool at_v = false;  // the current linearization is at v
+    bool lin_pending = false;
+    bool needs_krylov = false;
+    bool searching = false;
+    bool accepted = false;
+    double g0 = 0, ginf0 = 0, gn = 0, ginf = 0, eta = 0, gp = 0, tau = 1, sign = 1;
+    double E0 = 0, Er0 = 0, Ed0 = 0;
+    const T* dir = nullptr;
+    int its = 0, trials = 0, h = 0;
+    T* v = nullptr;
+    lddmm_solve_report R{};
+    lddmm_iter_log* log = nullptr;
+    int log_cap = 0;
+  };
+  Gn gs;
+  struct NewtonScope {  // CG applies the Newton Hessian for this solve only
+    bool& flag;
+    NewtonScope(bool& f, bool on) : flag(f) { flag = on; }
+    ~NewtonScope() { flag = false; }
+  };
+
+  int gn_setup(T* v, const lddmm_solve_opts* o, lddmm_iter_log* log, int log_cap) {
     if (!have_images) return fail(LDDMM_ESTATE, "images not set");
     if (int rc = check_finite(v, 3 * N, "v0")) return rc;
-    lddmm_solve_opts op{};
-    if (o) op = *o;
-    const int method = op.method;
-    if (method != LDDMM_GN_V && method != LDDMM_GN_L2 && method != LDDMM_GD_V && method != LDDMM_NEWTON_V)
+    Gn s;
+    if (o) s.op = *o;
+    s.method = s.op.method;
+    if (s.method != LDDMM_GN_V && s.method != LDDMM_GN_L2 && s.method != LDDMM_GD_V && s.method != LDDMM_NEWTON_V)
       return fail(LDDMM_EINVAL, "unknown optimisation method");
-    if (method == LDDMM_NEWTON_V)
+    if (s.method == LDDMM_NEWTON_V)
       if (int rc = ensure_newton()) return rc;
-    struct NewtonScope {  // CG applies the Newton Hessian for this solve only
-      bool& flag;
-      NewtonScope(bool& f, bool on) : flag(f) { flag = on; }
-      ~NewtonScope() { flag = false; }
-    } newton_scope(use_newton, method == LDDMM_NEWTON_V);
-    if (op.gn_iters <= 0) op.gn_iters = method == LDDMM_GD_V ? 50 : 10;
-    if (op.cg_iters <= 0) op.cg_iters = 20;
-    if (op.max_halvings <= 0) op.max_halvings = 10;
-    if (op.c1 <= 0) op.c1 = 1e-4;
-    if (op.gtol <= 0) op.gtol = 1e-3;
-    if (op.eta_max <= 0) op.eta_max = 0.5;
-    lddmm_solve_report R{};
+    if (s.op.gn_iters <= 0) s.op.gn_iters = s.method == LDDMM_GD_V ? 50 : 10;
+    if (s.op.cg_iters <= 0) s.op.cg_iters = 20;
+    if (s.op.max_halvings <= 0) s.op.max_halvings = 10;
+    if (s.op.c1 <= 0) s.op.c1 = 1e-4;
+    if (s.op.gtol <= 0) s.op.gtol = 1e-3;
+    if (s.op.eta_max <= 0) s.op.eta_max = 0.5;
+    s.v = v;
+    s.log = log;
+    s.log_cap = log_cap;
+    gs = s;
+    return 0;
+  }
+
+  // Gradient phase: linearize at v unless an accepted trial already did (each
+  // line-search trial is a full linearization: the trajectory store costs the same
+  // writes as a plain shoot's scratch), the gradient, its L-image, and the sums of
+  // the method's gradient norm and max |g|.
+  void gn_grad_enqueue() {
+    Gn& s = gs;
     const long long V = 3 * N;
-    double g0 = 0, ginf0 = 0;
-    // Each line-search trial is a full linearization (trajectory store, residual,
-    // grad J_1, energy): the store costs the same writes as the scratch buffers
-    // of a plain shoot, and an accepted trial is then already the next
-    // iteration's linearization.
-    bool at_v = false;  // the current linearization is at v
-    for (int k = 0; k < op.gn_iters; ++k) {
-      if (!at_v) linearize_nocheck(v);
-      at_v = true;
-      gradient_core(gv);
-      R.gradients++;
-      if (k == 0) R.E_first = E;
-      applyL(gv, Lg);
-      // the method's gradient and norm: g_V with ||g||_V, or g_L2 = L g_V with ||.||_L2
-      const double gn = method == LDDMM_GN_L2 ? std::sqrt(dot(Lg, Lg)) : std::sqrt(std::max(0.0, dot(Lg, gv)));
-      const double ginf = maxabs(method == LDDMM_GN_L2 ? Lg : gv, V);
-      if (k == 0) {
-        g0 = gn;
-        ginf0 = ginf;
-      }
-      R.g_rel_final = g0 > 0 ? gn / g0 : 0.0;
-      if (g0 == 0.0 || gn / g0 <= op.gtol) {
-        R.stop_reason = 1;
-        break;
-      }
-      // search direction p and the slope <g, p> of E along it (same value in V and L2)
-      double eta = 0.0, gp = 0.0, tau = 1.0, sign = 1.0;
-      const T* dir = cx;
-      int its = 0;
-      if (method == LDDMM_GD_V) {
-        dir = gv;
-        sign = -1.0;
-        gp = -gn * gn;
-        tau = 0.5;
-      } else {
-        eta = std::min(op.eta_max, std::sqrt(gn / g0));
-        if (method == LDDMM_GN_V || method == LDDMM_NEWTON_V)
-          cg(gv, cx, eta, op.cg_iters, &its);
-        else
-          pcg_l2(Lg, cx, eta, op.cg_iters, &its);
-        R.cg_total += its;
-        R.hessvecs += its;
-        gp = dot(Lg, cx);
-      }
-      const double E0 = E, Er0 = Ereg, Ed0 = Edata;
-      bool accepted = false;
-      int trials = 0;
-      for (int h = 0; h <= op.max_halvings; ++h) {
-        launch_axpbyz<T>(V, 1.0, v, sign * tau, dir, trial, st, &prof);
-        linearize_nocheck(trial);
-        at_v = false;
-        R.shoots++;
-        trials++;
-        if (E <= E0 + op.c1 * tau * gp) {
-          accepted = true;
-          break;
-        }
-        tau *= 0.5;
-      }
-      if (log && k < log_cap) {
-        lddmm_iter_log& L = log[k];
-        L.E = E0;
-        L.E_reg = Er0;
-        L.E_data = Ed0;
-        L.mse_rel = base_sq > 0 ? 100.0 * Ed0 * P.sigma2 / base_sq : 0.0;
-        L.g_norm = gn;
-        L.g_inf_rel = ginf0 > 0 ? ginf / ginf0 : 0.0;
-        L.eta = eta;
-        L.tau = accepted ? tau : 0.0;
-        L.cg_iters = its;
-        L.ls_trials = trials;
-      }
-      R.iters = k + 1;
-      if (!accepted) {
-        R.stop_reason = 2;
-        break;
-      }
-      copy(v, trial, V);
-      at_v = true;  // the accepted trial's linearization is the one at the new v
+    s.lin_pending = !s.at_v;
+    if (s.lin_pending) linearize_enqueue(s.v);
+    gradient_core(gv);
+    applyL(gv, Lg);
+    // the method's gradient and norm: g_V with ||g||_V, or g_L2 = L g_V with ||.||_L2
+    if (s.method == LDDMM_GN_L2)
+      dot_dev(Lg, Lg, 3, 10);
+    else
+      dot_dev(Lg, gv, 3, 10);
+    launch_check(s.method == LDDMM_GN_L2 ? Lg : gv, V, partials, dres + 8, st, &prof);
+    post_fetch();
+  }
+  void gn_grad_finish() {
+    Gn& s = gs;
+    if (s.lin_pending) linearize_finish();
+    s.lin_pending = false;
+    s.at_v = true;
+    s.R.gradients++;
+    if (s.k == 0) s.R.E_first = E;
+    s.gn = s.method == LDDMM_GN_L2 ? std::sqrt(cell * hres[10]) : std::sqrt(std::max(0.0, cell * hres[10]));
+    s.ginf = hres[9];
+    if (s.k == 0) {
+      s.g0 = s.gn;
+      s.ginf0 = s.ginf;
     }
-    if (!at_v) linearize_nocheck(v);
-    R.E_final = E;
-    R.mse_rel_final = base_sq > 0 ? 100.0 * Edata * P.sigma2 / base_sq : 0.0;
-    if (rep) *rep = R;
+    s.R.g_rel_final = s.g0 > 0 ? s.gn / s.g0 : 0.0;
+    if (s.g0 == 0.0 || s.gn / s.g0 <= s.op.gtol) {
+      s.R.stop_reason = 1;
+      s.done = true;
+      return;
+    }
+    // search direction p and the slope <g, p> of E along it (same value in V and L2)
+    s.eta = 0.0;
+    s.gp = 0.0;
+    s.tau = 1.0;
+    s.sign = 1.0;
+    s.its = 0;
+    s.dir = cx;
+    s.needs_krylov = s.method != LDDMM_GD_V;
+    if (!s.needs_krylov) {
+      s.dir = gv;
+      s.sign = -1.0;
+      s.gp = -s.gn * s.gn;
+      s.tau = 0.5;
+    } else {
+      s.eta = std::min(s.op.eta_max, std::sqrt(s.gn / s.g0));
+    }
+  }
+  // Krylov phase (CG in V or PCG in L2), begun here and stepped by the caller.
+  void gn_krylov_begin() {
+    Gn& s = gs;
+    cg_begin(s.method == LDDMM_GN_L2 ? Lg : gv, cx, s.eta, s.op.cg_iters, s.method == LDDMM_GN_L2);
+  }
+  // <g, p> after the Krylov solve
+  void gn_slope_enqueue() {
+    Gn& s = gs;
+    s.its = cg_iters_done();
+    s.R.cg_total += s.its;
+    s.R.hessvecs += s.its;
+    dot_dev(Lg, cx, 3, 11);
+    post_fetch();
+  }
+  void gn_slope_finish() { gs.gp = cell * hres[11]; }
+  void gn_search_begin() {
+    Gn& s = gs;
+    s.E0 = E;
+    s.Er0 = Ereg;
+    s.Ed0 = Edata;
+    s.accepted = false;
+    s.trials = 0;
+    s.h = 0;
+    s.searching = true;
+  }
+  void gn_trial_enqueue() {
+    Gn& s = gs;
+    launch_axpbyz<T>(3 * N, 1.0, s.v, s.sign * s.tau, s.dir, trial, st, &prof);
+    linearize_enqueue(trial);
+    s.at_v = false;
+    post_fetch();
+  }
+  void gn_trial_finish() {
+    Gn& s = gs;
+    linearize_finish();
+    s.R.shoots++;
+    s.trials++;
+    if (E <= s.E0 + s.op.c1 * s.tau * s.gp) {
+      s.accepted = true;
+      s.searching = false;
+      return;
+    }
+    s.tau *= 0.5;
+    if (++s.h > s.op.max_halvings) s.searching = false;
+  }
+  // end of an outer iteration: log, accept the step or stop
+  void gn_iteration_end() {
+    Gn& s = gs;
+    if (s.log && s.k < s.log_cap) {
+      lddmm_iter_log& L = s.log[s.k];
+      L.E = s.E0;
+      L.E_reg = s.Er0;
+      L.E_data = s.Ed0;
+      L.mse_rel = base_sq > 0 ? 100.0 * s.Ed0 * P.sigma2 / base_sq : 0.0;
+      L.g_norm = s.gn;
+      L.g_inf_rel = s.ginf0 > 0 ? s.ginf / s.ginf0 : 0.0;
+      L.eta = s.eta;
+      L.tau = s.accepted ? s.tau : 0.0;
+      L.cg_iters = s.its;
+      L.ls_trials = s.trials;
+    }
+    s.R.iters = s.k + 1;
+    if (!s.accepted) {
+      s.R.stop_reason = 2;
+      s.done = true;
+      return;
+    }
+    copy(s.v, trial, 3 * N);
+    s.at_v = true;  // the accepted trial's linearization is the one at the new v
+    if (++s.k >= s.op.gn_iters) s.done = true;
+  }
+  // after the last iteration: the linearization at the returned v and the report
+  void gn_final_enqueue() {
+    if (!gs.at_v) linearize_enqueue(gs.v);
+    post_fetch();
+  }
+  void gn_final_finish(lddmm_solve_report* rep) {
+    Gn& s = gs;
+    if (!s.at_v) linearize_finish();
+    s.at_v = true;
+    s.R.E_final = E;
+    s.R.mse_rel_final = base_sq > 0 ? 100.0 * Edata * P.sigma2 / base_sq : 0.0;
+    if (rep) *rep = s.R;
+  }
+
+  int gn_solve(T* v, const lddmm_solve_opts* o, lddmm_solve_report* rep, lddmm_iter_log* log, int log_cap) {
+    if (int rc = gn_setup(v, o, log, log_cap)) return rc;
+    NewtonScope newton_scope(use_newton, gs.method == LDDMM_NEWTON_V);
+    Gn& s = gs;
+    while (!s.done) {
+      gn_grad_enqueue();
+      wait();
+      gn_grad_finish();
+      if (s.done) break;
+      if (s.needs_krylov) {
+        gn_krylov_begin();
+        for (int it = 1; it <= s.op.cg_iters; ++it) {
+          cg_step_enqueue(cx);
+          post_fetch();
+          wait();
+          if (!cg_active()) break;
+        }
+        gn_slope_enqueue();
+        wait();
+        gn_slope_finish();
+      }
+      gn_search_begin();
+      while (s.searching) {
+        gn_trial_enqueue();
+        wait();
+        gn_trial_finish();
+      }
+      gn_iteration_end();
+    }
+    gn_final_enqueue();
+    wait();
+    gn_final_finish(rep);
     return hip_status("gn_solve");
   }
 
@@ -1359,9 +1575,91 @@ const char* lddmm_last_error(lddmm_ctx* ctx) {
 // ---------------------------------------------------------------------------
 // Batches
 // ---------------------------------------------------------------------------
+// Persistent host workers of a batch: run(set, fn) calls fn(i) for every pair i of
+// set, pair i on worker i, and returns when all are done.  The lockstep solve
+// uses them to enqueue a phase's launches for all pairs in parallel.
+class PairWorkers {
+ public:
+  void start(int n, int device) {
+    stop_ = false;
+    gen_.assign(n, 0);
+    for (int i = 0; i < n; ++i)
+      th_.emplace_back([this, i, device]() {
+        (void)hipSetDevice(device);
+        uint64_t seen = 0;
+        while (true) {
+          std::function<void(int)> job;
+          {
+            std::unique_lock<std::mutex> lk(mu_);
+            cv_.wait(lk, [&] { return stop_ || gen_[i] != seen; });
+            if (stop_) return;
+            seen = gen_[i];
+            job = job_;
+          }
+          job(i);
+          {
+            std::lock_guard<std::mutex> lk(mu_);
+            if (--pending_ == 0) done_.notify_all();
+          }
+        }
+      });
+  }
+  void run(const std::vector<int>& set, const std::function<void(int)>& fn) {
+    if (set.empty()) return;
+    if (set.size() == 1 || th_.empty()) {
+      for (int i : set) fn(i);
+      return;
+    }
+    std::unique_lock<std::mutex> lk(mu_);
+    job_ = fn;
+    pending_ = int(set.size());
+    for (int i : set) ++gen_[i];
+    cv_.notify_all();
+    done_.wait(lk, [&] { return pending_ == 0; });
+  }
+  ~PairWorkers() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+
+ private:
+  std::mutex mu_;
+  std::condition_variable cv_, done_;
+  std::vector<std::thread> th_;
+  std::vector<uint64_t> gen_;
+  std::function<void(int)> job_;
+  int pending_ = 0;
+  bool stop_ = false;
+};
+
 struct lddmm_batch {
   std::vector<lddmm_ctx*> ctx;
   int device = 0;
+  PairWorkers workers;
+  // Graphs spanning every pair: captured on the batch stream, forked to and
+  // joined from the pairs' streams with events.
+  hipStream_t bst = nullptr;
+  hipEvent_t ev_b = nullptr;
+  std::vector<hipEvent_t> ev;
+  // one CG iteration of a set of pairs (bit i = pair i; bit 63: PCG in L2), valid
+  // for the pairs' graph generations it was captured with
+  std::vector<std::pair<uint64_t, hipGraphExec_t>> cg_all;
+  std::vector<int> cg_gens;
+  // one Gauss-Newton Hv of every pair for the dv / hv pointers it was captured with
+  hipGraphExec_t hv_all = nullptr;
+  std::vector<const void*> hv_ptrs;
+  std::vector<int> hv_gens;
+  void drop_graphs() {
+    for (auto& e : cg_all) (void)hipGraphExecDestroy(e.second);
+    cg_all.clear();
+    if (hv_all) (void)hipGraphExecDestroy(hv_all);
+    hv_all = nullptr;
+    hv_ptrs.clear();
+  }
 };
 
 namespace {
@@ -1390,6 +1688,232 @@ int for_pairs(lddmm_batch* b, int concurrent, F fn) {
   return LDDMM_OK;
 }
 
+template <typename T>
+lddmm::Engine<T>* engine_of(lddmm_ctx* c);
+template <>
+lddmm::Engine<float>* engine_of<float>(lddmm_ctx* c) {
+  return c->f.get();
+}
+template <>
+lddmm::Engine<double>* engine_of<double>(lddmm_ctx* c) {
+  return c->d.get();
+}
+
+// Capture fn(i) for the pairs of `set` into one graph on the batch stream (each
+// pair's work on its own stream, forked and joined with events).
+template <class F>
+hipGraphExec_t capture_across(lddmm_batch* b, const std::vector<int>& set, F fn) {
+  if (hipStreamBeginCapture(b->bst, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  (void)hipEventRecord(b->ev_b, b->bst);
+  for (int i : set) {
+    const hipStream_t s = ctx_stream(b->ctx[i]);
+    (void)hipStreamWaitEvent(s, b->ev_b, 0);
+    fn(i);
+    (void)hipEventRecord(b->ev[i], s);
+    (void)hipStreamWaitEvent(b->bst, b->ev[i], 0);
+  }
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(b->bst, &g) != hipSuccess || !g) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  hipGraphExec_t ex = nullptr;
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    ex = nullptr;
+  }
+  (void)hipGraphDestroy(g);
+  return ex;
+}
+
+// Launch a graph spanning the pairs of `set`, ordered after their streams' work
+// and before anything enqueued on them afterwards.
+void launch_across(lddmm_batch* b, const std::vector<int>& set, hipGraphExec_t ex) {
+  for (int i : set) {
+    (void)hipEventRecord(b->ev[i], ctx_stream(b->ctx[i]));
+    (void)hipStreamWaitEvent(b->bst, b->ev[i], 0);
+  }
+  (void)hipGraphLaunch(ex, b->bst);
+  (void)hipEventRecord(b->ev_b, b->bst);
+  for (int i : set) (void)hipStreamWaitEvent(ctx_stream(b->ctx[i]), b->ev_b, 0);
+}
+
+template <typename T>
+std::vector<int> graph_gens(lddmm_batch* b) {
+  std::vector<int> g;
+  for (lddmm_ctx* c : b->ctx) g.push_back(engine_of<T>(c)->graph_gen);
+  return g;
+}
+
+// One CG iteration of the pairs in `live` (a subset of the solve's Krylov set):
+// one graph spanning them where every pair can be captured, else each pair's
+// own iteration graph (or kernels).
+template <typename T>
+void batch_cg_step(lddmm_batch* b, const std::vector<int>& live) {
+  bool all_graph = live.size() > 1 && b->ctx.size() <= 63;
+  for (int i : live) all_graph = all_graph && engine_of<T>(b->ctx[i])->cg_graph_ok();
+  if (all_graph) {
+    if (graph_gens<T>(b) != b->cg_gens) {
+      b->drop_graphs();
+      b->cg_gens = graph_gens<T>(b);
+    }
+    // key: the pairs, and bit 63 for the PCG in L2 (the method of the solve)
+    uint64_t mask = engine_of<T>(b->ctx[live[0]])->cg_l2 ? uint64_t(1) << 63 : 0;
+    for (int i : live) mask |= uint64_t(1) << i;
+    hipGraphExec_t ex = nullptr;
+    for (auto& e : b->cg_all)
+      if (e.first == mask) ex = e.second;
+    if (!ex) {
+      ex = capture_across(b, live, [&](int i) {
+        auto* E = engine_of<T>(b->ctx[i]);
+        E->cg_iteration(E->cx, true);
+      });
+      if (ex) b->cg_all.emplace_back(mask, ex);
+    }
+    if (ex) {
+      launch_across(b, live, ex);
+      return;
+    }
+  }
+  for (int i : live) {
+    auto* E = engine_of<T>(b->ctx[i]);
+    E->cg_step_enqueue(E->cx);
+  }
+}
+
+// Gauss-Newton solves of every pair in lockstep: each phase (gradient, Krylov
+// iteration, <g, p>, line-search trial, final linearization) is enqueued for all
+// pairs that need it (by the batch's per-pair workers, or as one graph spanning
+// the pairs for a CG iteration) before the host waits once for them.
+// Per pair, the same kernels run in the same order with the same decisions as
+// lddmm_gn_solve on that pair alone.
+template <typename T>
+int batch_gn_lockstep(lddmm_batch* b, void* const* v0, const lddmm_solve_opts* opts, lddmm_solve_report* reps) {
+  using E_t = lddmm::Engine<T>;
+  const int n = int(b->ctx.size());
+  std::vector<E_t*> E(n);
+  for (int i = 0; i < n; ++i) {
+    E[i] = engine_of<T>(b->ctx[i]);
+    b->ctx[i]->err.clear();
+    if (int rc = E[i]->gn_setup(static_cast<T*>(v0[i]), opts, nullptr, 0)) return rc;
+  }
+  std::vector<std::unique_ptr<typename E_t::NewtonScope>> scopes;
+  for (int i = 0; i < n; ++i)
+    scopes.emplace_back(new typename E_t::NewtonScope(E[i]->use_newton, E[i]->gs.method == LDDMM_NEWTON_V));
+  auto pick = [&](auto pred) {
+    std::vector<int> out;
+    for (int i = 0; i < n; ++i)
+      if (pred(i)) out.push_back(i);
+    return out;
+  };
+  while (true) {
+    const std::vector<int> act = pick([&](int i) { return !E[i]->gs.done; });
+    if (act.empty()) break;
+    b->workers.run(act, [&](int i) { E[i]->gn_grad_enqueue(); });
+    for (int i : act) {
+      E[i]->wait();
+      E[i]->gn_grad_finish();
+    }
+    const std::vector<int> kr = pick([&](int i) { return !E[i]->gs.done && E[i]->gs.needs_krylov; });
+    b->workers.run(kr, [&](int i) { E[i]->gn_krylov_begin(); });
+    std::vector<int> live = kr;
+    const int maxit = kr.empty() ? 0 : E[kr[0]]->gs.op.cg_iters;
+    for (int it = 1; it <= maxit && !live.empty(); ++it) {
+      batch_cg_step<T>(b, live);
+      for (int i : live) E[i]->post_fetch();
+      std::vector<int> next;
+      for (int i : live) {
+        E[i]->wait();
+        if (E[i]->cg_active()) next.push_back(i);
+      }
+      live.swap(next);
+    }
+    for (int i : kr) E[i]->gn_slope_enqueue();
+    for (int i : kr) {
+      E[i]->wait();
+      E[i]->gn_slope_finish();
+    }
+    const std::vector<int> srch = pick([&](int i) { return !E[i]->gs.done; });
+    for (int i : srch) E[i]->gn_search_begin();
+    while (true) {
+      const std::vector<int> tr = pick([&](int i) { return !E[i]->gs.done && E[i]->gs.searching; });
+      if (tr.empty()) break;
+      b->workers.run(tr, [&](int i) { E[i]->gn_trial_enqueue(); });
+      for (int i : tr) {
+        E[i]->wait();
+        E[i]->gn_trial_finish();
+      }
+    }
+    for (int i : srch) E[i]->gn_iteration_end();
+  }
+  b->workers.run(pick([](int) { return true; }), [&](int i) { E[i]->gn_final_enqueue(); });
+  int rc = 0;
+  for (int i = 0; i < n; ++i) {
+    E[i]->wait();
+    E[i]->gn_final_finish(reps ? &reps[i] : nullptr);
+    if (!rc) rc = E[i]->hip_status("batch_gn_solve");
+  }
+  return rc;
+}
+
+// reps Gauss-Newton Hessian-vector products of every pair at its current
+// linearization, each round one graph spanning all pairs where they can be
+// captured (store-all trajectories, graph replay on), else pair by pair.
+template <typename T>
+int batch_hessvec_lockstep(lddmm_batch* b, void* const* dv, void* const* hv, int reps) {
+  const int n = int(b->ctx.size());
+  std::vector<int> all(n);
+  bool graph = n > 1;
+  for (int i = 0; i < n; ++i) {
+    all[i] = i;
+    auto* E = engine_of<T>(b->ctx[i]);
+    if (!E->linearized) {
+      b->ctx[i]->err = "hessvec without a linearization";
+      return LDDMM_ESTATE;
+    }
+    graph = graph && E->use_graph && E->traj_policy == lddmm::TRAJ_STORE_ALL && !E->prof.enabled;
+  }
+  if (graph) {
+    std::vector<const void*> ptrs;
+    for (int i = 0; i < n; ++i) {
+      ptrs.push_back(dv[i]);
+      ptrs.push_back(hv[i]);
+    }
+    if (!b->hv_all || ptrs != b->hv_ptrs || graph_gens<T>(b) != b->hv_gens) {
+      if (b->hv_all) (void)hipGraphExecDestroy(b->hv_all);
+      b->hv_all = capture_across(b, all, [&](int i) {
+        engine_of<T>(b->ctx[i])->hessvec_kernels(static_cast<const T*>(dv[i]), static_cast<T*>(hv[i]));
+      });
+      b->hv_ptrs = ptrs;
+      b->hv_gens = graph_gens<T>(b);
+    }
+    graph = b->hv_all != nullptr;
+  }
+  for (int r = 0; r < reps; ++r) {
+    if (graph) {
+      launch_across(b, all, b->hv_all);
+    } else {
+      for (int i = 0; i < n; ++i)
+        engine_of<T>(b->ctx[i])->hessvec_core(static_cast<const T*>(dv[i]), static_cast<T*>(hv[i]));
+    }
+  }
+  int rc = 0;
+  for (int i = 0; i < n; ++i) {
+    if (hipStreamSynchronize(ctx_stream(b->ctx[i])) != hipSuccess && !rc) rc = LDDMM_EHIP;
+    if (!rc) rc = engine_of<T>(b->ctx[i])->hip_status("batch_hessvec");
+  }
+  return rc;
+}
+
+bool same_dtype(lddmm_batch* b) {
+  for (lddmm_ctx* c : b->ctx)
+    if (c->dtype != b->ctx[0]->dtype) return false;
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1402,12 +1926,24 @@ int lddmm_batch_create(const lddmm_params* per_pair, int npairs, lddmm_batch** o
     delete b;
     return LDDMM_EHIP;
   }
+  if (hipStreamCreateWithFlags(&b->bst, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_b, hipEventDisableTiming) != hipSuccess) {
+    lddmm_batch_destroy(b);
+    return LDDMM_EHIP;
+  }
   for (int i = 0; i < npairs; ++i) {
     hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
       lddmm_batch_destroy(b);
       return LDDMM_EHIP;
     }
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamDestroy(s);
+      lddmm_batch_destroy(b);
+      return LDDMM_EHIP;
+    }
+    b->ev.push_back(e);
     lddmm_ctx* c = nullptr;
     const int rc = lddmm_create(&per_pair[i], s, &c);
     if (rc) {
@@ -1424,13 +1960,19 @@ int lddmm_batch_create(const lddmm_params* per_pair, int npairs, lddmm_batch** o
     }
     b->ctx.push_back(c);
   }
+  b->workers.start(npairs, b->device);
   *out = b;
   return LDDMM_OK;
 }
 
 int lddmm_batch_destroy(lddmm_batch* b) {
   if (!b) return LDDMM_EINVAL;
+  if (b->bst) (void)hipStreamSynchronize(b->bst);
+  b->drop_graphs();
   for (lddmm_ctx* c : b->ctx) lddmm_destroy(c);
+  for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+  if (b->ev_b) (void)hipEventDestroy(b->ev_b);
+  if (b->bst) (void)hipStreamDestroy(b->bst);
   delete b;
   return LDDMM_OK;
 }
@@ -1453,6 +1995,9 @@ int lddmm_batch_gn_solve(lddmm_batch* b, void* const* v0_inout, const lddmm_solv
   if (!b || !v0_inout) return LDDMM_EINVAL;
   for (size_t i = 0; i < b->ctx.size(); ++i)
     if (!v0_inout[i]) return LDDMM_EINVAL;
+  if (concurrent == LDDMM_BATCH_LOCKSTEP && same_dtype(b))
+    return b->ctx[0]->dtype == LDDMM_F32 ? batch_gn_lockstep<float>(b, v0_inout, opts, reports)
+                                         : batch_gn_lockstep<double>(b, v0_inout, opts, reports);
   return for_pairs(b, concurrent, [&](int i) {
     const int rc = lddmm_gn_solve(b->ctx[i], v0_inout[i], opts, reports ? &reports[i] : nullptr, nullptr, 0);
     // the solve's last copy into v0 may still be in flight on the pair's stream
@@ -1465,6 +2010,9 @@ int lddmm_batch_hessvec(lddmm_batch* b, void* const* dv, void* const* hv, int re
   if (!b || !dv || !hv || reps < 1) return LDDMM_EINVAL;
   for (size_t i = 0; i < b->ctx.size(); ++i)
     if (!dv[i] || !hv[i]) return LDDMM_EINVAL;
+  if (concurrent == LDDMM_BATCH_LOCKSTEP && same_dtype(b))
+    return b->ctx[0]->dtype == LDDMM_F32 ? batch_hessvec_lockstep<float>(b, dv, hv, reps)
+                                         : batch_hessvec_lockstep<double>(b, dv, hv, reps);
   return for_pairs(b, concurrent, [&](int i) {
     for (int r = 0; r < reps; ++r) {
       const int rc = lddmm_hessvec(b->ctx[i], nullptr, dv[i], hv[i]);

@@ -250,4 +250,23 @@ void launch_axpbyz(long long n, double alpha, const T* x, double beta, const T* 
 template <typename T>
 void launch_fill(long long n, T value, T* y, hipStream_t st, Profiler* prof);
 
+// CG with its scalars on the device: a block of kCgSlots doubles per solve.
+// num / stop / curv point at FP64 sums (cell factor not applied) left by
+// launch_dot.  V-CG: num = stop = <L r, r>; PCG in L2: num = <r, K r>, stop =
+// <r, r>.  The host reads CG_ACTIVE / CG_ITERS to end early; nothing else needs it.
+enum { CG_RZ = 0, CG_TOL, CG_ACTIVE, CG_AX, CG_AR, CG_BETA, CG_ITERS, CG_NEGCURV, CG_MAXIT, CG_FIRSTD, kCgSlots };
+// first_d: non-positive curvature on the first direction returns x = d (CG in V)
+void launch_cg_begin(double* s, const double* num, const double* stop, double cell, double eta, int maxit,
+                     int first_d, hipStream_t st, Profiler* prof);
+// step lengths from <d, H d>; counts the iteration or stops on non-positive curvature
+void launch_cg_alpha(double* s, const double* curv, double cell, hipStream_t st, Profiler* prof);
+// stop test on the new residual (or at maxit iterations), else beta and the next numerator
+void launch_cg_beta(double* s, const double* num, const double* stop, double cell, hipStream_t st, Profiler* prof);
+template <typename T>
+void launch_cg_step_dev(long long n, const double* s, const T* d, const T* q, T* x, T* r, hipStream_t st,
+                        Profiler* prof);
+// y = x + beta y
+template <typename T>
+void launch_cg_direction(long long n, const double* s, const T* x, T* y, hipStream_t st, Profiler* prof);
+
 }  // namespace lddmm

@@ -155,6 +155,82 @@ __global__ void k_cg_step(long long n, double rr, double cell, const double* __r
   }
 }
 
+// ---- CG scalars kept on the device (one block of kCgSlots doubles per solve) --
+// Start: rz = cell * num[0] (the numerator of the first step length), tol = eta *
+// sqrt(cell * stop[0]), active, no iterations yet; at most maxit iterations;
+// first_d: non-positive curvature on the first direction takes x = d.
+__global__ void k_cg_begin(double* __restrict__ s, const double* __restrict__ num, const double* __restrict__ stop,
+                           double cell, double eta, int maxit, int first_d) {
+  s[CG_MAXIT] = double(maxit);
+  s[CG_FIRSTD] = double(first_d);
+  s[CG_RZ] = cell * num[0];
+  s[CG_TOL] = eta * sqrt(cell * stop[0]);
+  s[CG_ACTIVE] = 1.0;
+  s[CG_AX] = 0.0;
+  s[CG_AR] = 0.0;
+  s[CG_BETA] = 0.0;
+  s[CG_ITERS] = 0.0;
+  s[CG_NEGCURV] = 0.0;
+}
+
+// Step length from the curvature cell * curv[0] = <d, H d>: a = rz / curvature
+// when it is positive (the iteration counts); otherwise the solve stops without
+// counting it, and on its first direction x takes d itself (steepest descent,
+// x = 0 + 1 d).  An inactive solve takes no step.
+__global__ void k_cg_alpha(double* __restrict__ s, const double* __restrict__ curv, double cell) {
+  double ax = 0.0, ar = 0.0;
+  if (s[CG_ACTIVE] != 0.0) {
+    const double c = cell * curv[0];
+    if (c > 0.0) {
+      ax = ar = s[CG_RZ] / c;
+      s[CG_ITERS] += 1.0;
+    } else {
+      ax = (s[CG_ITERS] == 0.0 && s[CG_FIRSTD] != 0.0) ? 1.0 : 0.0;
+      s[CG_ACTIVE] = 0.0;
+      s[CG_NEGCURV] = 1.0;
+    }
+  }
+  s[CG_AX] = ax;
+  s[CG_AR] = ar;
+}
+
+// After the step: stop once sqrt(cell * stop[0]) <= tol or after maxit
+// iterations; else beta =
+// rz_new / rz with rz_new = cell * num[0].  beta = 0 when inactive.
+__global__ void k_cg_beta(double* __restrict__ s, const double* __restrict__ num, const double* __restrict__ stop,
+                          double cell) {
+  double beta = 0.0;
+  if (s[CG_ACTIVE] != 0.0) {
+    if (sqrt(cell * stop[0]) <= s[CG_TOL] || s[CG_ITERS] >= s[CG_MAXIT]) {
+      s[CG_ACTIVE] = 0.0;
+    } else {
+      const double rz_new = cell * num[0];
+      beta = rz_new / s[CG_RZ];
+      s[CG_RZ] = rz_new;
+    }
+  }
+  s[CG_BETA] = beta;
+}
+
+// x += ax d, r -= ar q with the step lengths of the scalar block.
+template <typename T>
+__global__ void k_cg_step_dev(long long n, const double* __restrict__ s, const T* __restrict__ d,
+                              const T* __restrict__ q, T* __restrict__ x, T* __restrict__ r) {
+  const T ta = T(s[CG_AX]), tb = T(-s[CG_AR]), one = T(1);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    x[i] = ta * d[i] + one * x[i];
+    r[i] = tb * q[i] + one * r[i];
+  }
+}
+
+// y = x + beta y with beta from the scalar block.
+template <typename T>
+__global__ void k_cg_direction(long long n, const double* __restrict__ s, const T* __restrict__ x, T* __restrict__ y) {
+  const T one = T(1), b = T(s[CG_BETA]);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = one * x[i] + b * y[i];
+}
+
 template <typename T>
 __global__ void k_fill(long long n, T value, T* y) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -218,6 +294,35 @@ void launch_cg_step(long long n, double rr, double cell, const double* dsum, con
   LDDMM_LAUNCH(t.start, t.stop, k_cg_step<T>, ew_blocks(n), 256, 0, st, n, rr, cell, dsum, d, q, x, r);
 }
 
+void launch_cg_begin(double* s, const double* num, const double* stop, double cell, double eta, int maxit,
+                     int first_d, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "cg_scalars");
+  LDDMM_LAUNCH(t.start, t.stop, k_cg_begin, 1, 1, 0, st, s, num, stop, cell, eta, maxit, first_d);
+}
+
+void launch_cg_alpha(double* s, const double* curv, double cell, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "cg_scalars");
+  LDDMM_LAUNCH(t.start, t.stop, k_cg_alpha, 1, 1, 0, st, s, curv, cell);
+}
+
+void launch_cg_beta(double* s, const double* num, const double* stop, double cell, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "cg_scalars");
+  LDDMM_LAUNCH(t.start, t.stop, k_cg_beta, 1, 1, 0, st, s, num, stop, cell);
+}
+
+template <typename T>
+void launch_cg_step_dev(long long n, const double* s, const T* d, const T* q, T* x, T* r, hipStream_t st,
+                        Profiler* prof) {
+  KernelTimer t(prof, "cg_step");
+  LDDMM_LAUNCH(t.start, t.stop, k_cg_step_dev<T>, ew_blocks(n), 256, 0, st, n, s, d, q, x, r);
+}
+
+template <typename T>
+void launch_cg_direction(long long n, const double* s, const T* x, T* y, hipStream_t st, Profiler* prof) {
+  KernelTimer t(prof, "axpby");
+  LDDMM_LAUNCH(t.start, t.stop, k_cg_direction<T>, ew_blocks(n), 256, 0, st, n, s, x, y);
+}
+
 template <typename T>
 void launch_fill(long long n, T value, T* y, hipStream_t st, Profiler* prof) {
   KernelTimer t(prof, "fill");
@@ -232,7 +337,10 @@ void launch_fill(long long n, T value, T* y, hipStream_t st, Profiler* prof) {
   template void launch_axpbyz<T>(long long, double, const T*, double, const T*, T*, hipStream_t, Profiler*); \
   template void launch_cg_step<T>(long long, double, double, const double*, const T*, const T*, T*, T*,      \
                                   hipStream_t, Profiler*);                                                  \
-  template void launch_fill<T>(long long, T, T*, hipStream_t, Profiler*);
+  template void launch_fill<T>(long long, T, T*, hipStream_t, Profiler*);                                   \
+  template void launch_cg_step_dev<T>(long long, const double*, const T*, const T*, T*, T*, hipStream_t,     \
+                                      Profiler*);                                                           \
+  template void launch_cg_direction<T>(long long, const double*, const T*, T*, hipStream_t, Profiler*);
 
 LDDMM_RINST(float)
 LDDMM_RINST(double)

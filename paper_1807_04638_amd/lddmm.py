@@ -486,23 +486,43 @@ class Batch:
                 )
         return (_vp * len(ts))(*[t.data_ptr() for t in ts])
 
+    MODES = {"sequential": 0, "threads": 1, "lockstep": 2}
+
+    def _mode(self, concurrent, mode, default):
+        if mode is None:
+            return self.MODES[default] if concurrent else self.MODES["sequential"]
+        if mode not in self.MODES:
+            raise ValueError(f"mode must be one of {sorted(self.MODES)}")
+        return self.MODES[mode]
+
     def gn_solve(self, v0s, concurrent=True, gn_iters=None, cg_iters=20, max_halvings=10, c1=1e-4, gtol=1e-3,
-                 eta_max=0.5, method="gn_v"):
+                 eta_max=0.5, method="gn_v", mode=None):
+        """Solve every pair from its v0 (updated in place).  mode: "sequential",
+        "threads" (one host thread per pair, each pair at its own pace; its CG
+        iterations replayed from its own graph) or "lockstep" (each phase
+        enqueued for all pairs before one wait, CG iterations as one graph
+        spanning the pairs); default "threads" (measured faster for whole solves:
+        lockstep waits for the slowest pair at every phase), or "sequential" with
+        concurrent=False.  Every mode gives bitwise the single-context results."""
+        m = self._mode(concurrent, mode, "threads")
         ptrs = self._fields(v0s, "v0s")
         torch.cuda.current_stream(self.device).synchronize()
         if gn_iters is None:
             gn_iters = 50 if method == "gd" else 10
         o = SolveOpts(gn_iters, cg_iters, max_halvings, METHODS[method], c1, gtol, eta_max)
         reps = (SolveReport * len(self.contexts))()
-        self._rc(self.lib.lddmm_batch_gn_solve(self._b, ptrs, ctypes.byref(o), reps, 1 if concurrent else 0),
-                 "batch_gn_solve")
+        self._rc(self.lib.lddmm_batch_gn_solve(self._b, ptrs, ctypes.byref(o), reps, m), "batch_gn_solve")
         return [{k: getattr(r, k) for k, _ in SolveReport._fields_} for r in reps]
 
-    def hessvec(self, dvs, hvs, reps=1, concurrent=True):
+    def hessvec(self, dvs, hvs, reps=1, concurrent=True, mode=None):
+        """reps Gauss-Newton Hv of every pair at its current linearization (modes as
+        in gn_solve; "lockstep", the default, replays one graph spanning all pairs
+        per round)."""
+        m = self._mode(concurrent, mode, "lockstep")
         a = self._fields(dvs, "dvs")
         b = self._fields(hvs, "hvs")
         torch.cuda.current_stream(self.device).synchronize()
-        self._rc(self.lib.lddmm_batch_hessvec(self._b, a, b, int(reps), 1 if concurrent else 0), "batch_hessvec")
+        self._rc(self.lib.lddmm_batch_hessvec(self._b, a, b, int(reps), m), "batch_hessvec")
 
     def autotune(self, reps=5):
         self._rc(self.lib.lddmm_batch_autotune(self._b, int(reps)), "batch_autotune")

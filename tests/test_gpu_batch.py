@@ -1,5 +1,6 @@
 """Batched form: autotuner, hipGraph replay of the Hessian-vector product, and
-batches of pairs of uneven sizes solved concurrently on their own streams.
+batches of pairs of uneven sizes solved in lockstep (graphs spanning the pairs),
+on one host thread per pair, or one after the other.
 
 Every check compares with the plain single-context path or the oracle on the
 same inputs; graph replays are compared with eager results on every replay,
@@ -101,7 +102,7 @@ def test_batch_uneven_sizes_matches_single_contexts(dtype):
         assert B.contexts[i].get_option("exec.graph") == 1
     v_batch = [torch.zeros((3,) + n, dtype=dtype, device=DEV) for n in sizes]
     say(f"[case] batch of {len(sizes)} {dtype}")
-    reps = B.gn_solve(v_batch, concurrent=True, gn_iters=3, cg_iters=5)
+    reps = B.gn_solve(v_batch, gn_iters=3, cg_iters=5, mode="lockstep")
     for i, n in enumerate(sizes):
         R = Registration(n, 4, 0.01, 2, 0.02, dtype=dtype)
         R.set_images(T(data[i][0], dtype), T(data[i][1], dtype))
@@ -110,17 +111,49 @@ def test_batch_uneven_sizes_matches_single_contexts(dtype):
         say(f"  pair {i} {n}: batch E {reps[i]['E_final']:.6g} single {tr.report['E_final']:.6g}")
         assert reps[i] == tr.report
         assert torch.equal(v_batch[i], v)
-    # sequential batch runs give the same as concurrent ones
-    v_seq = [torch.zeros((3,) + n, dtype=dtype, device=DEV) for n in sizes]
-    reps_seq = B.gn_solve(v_seq, concurrent=False, gn_iters=3, cg_iters=5)
-    assert reps_seq == reps
-    assert all(torch.equal(a, b) for a, b in zip(v_seq, v_batch))
+    # the other batch modes give the same
+    for mode in ("sequential", "threads"):
+        v_m = [torch.zeros((3,) + n, dtype=dtype, device=DEV) for n in sizes]
+        say(f"  mode {mode}")
+        reps_m = B.gn_solve(v_m, gn_iters=3, cg_iters=5, mode=mode)
+        assert reps_m == reps
+        assert all(torch.equal(a, b) for a, b in zip(v_m, v_batch))
     # batched Hessian-vector products at each pair's final linearization
     dvs = [T(random_field(n, 30 + i, kc=2.0), dtype) for i, n in enumerate(sizes)]
-    hvs = [torch.empty_like(d) for d in dvs]
-    B.hessvec(dvs, hvs, reps=2, concurrent=True)
-    for i in range(len(sizes)):
-        assert torch.equal(hvs[i], B.contexts[i].hessvec(dvs[i]))
+    for mode in ("lockstep", "threads"):
+        hvs = [torch.empty_like(d) for d in dvs]
+        B.hessvec(dvs, hvs, reps=2, mode=mode)
+        for i in range(len(sizes)):
+            assert torch.equal(hvs[i], B.contexts[i].hessvec(dvs[i])), (mode, i)
+    B.close()
+
+
+@pytest.mark.parametrize("method", ["gn_l2", "gd", "newton"])
+def test_batch_lockstep_methods_match_single_contexts(method):
+    """The lockstep batch (one host thread, every phase enqueued for all pairs,
+    CG scalars on the device, CG iterations as graphs spanning the pairs) gives
+    bitwise the single-context solve of each pair for every solve method."""
+    from paper_1807_04638_amd import Batch, Registration
+
+    dtype = torch.float64
+    sizes = [(16, 16, 16), (24, 20, 16), (16, 12, 20)]
+    data = [pair(n, 20 + i) for i, n in enumerate(sizes)]
+    its = 4 if method == "gd" else 3
+    B = Batch([dict(n=n, nt=4, alpha=0.01, s=2, sigma2=0.02) for n in sizes], dtype=dtype)
+    for i, (I0, I1) in enumerate(data):
+        B.contexts[i].set_images(T(I0, dtype), T(I1, dtype))
+    say(f"[case] lockstep batch {method}")
+    vs = [torch.zeros((3,) + n, dtype=dtype, device=DEV) for n in sizes]
+    reps = B.gn_solve(vs, gn_iters=its, cg_iters=5, method=method, mode="lockstep")
+    for i, n in enumerate(sizes):
+        R = Registration(n, 4, 0.01, 2, 0.02, dtype=dtype)
+        R.set_images(T(data[i][0], dtype), T(data[i][1], dtype))
+        v = torch.zeros((3,) + n, dtype=dtype, device=DEV)
+        tr = R.gn_solve(v, gn_iters=its, cg_iters=5, method=method)
+        say(f"  pair {i}: {reps[i]['iters']} iterations, {reps[i]['cg_total']} CG, E {reps[i]['E_final']:.8g}")
+        assert reps[i] == tr.report
+        assert torch.equal(vs[i], v)
+        R.close()
     B.close()
 
 
@@ -147,9 +180,10 @@ def test_batch_results_are_complete_on_return():
     B = Batch([dict(n=n, nt=4, alpha=0.01, s=2, sigma2=0.02) for n in sizes], dtype=dtype)
     for i, (I0, I1) in enumerate(data):
         B.contexts[i].set_images(T(I0, dtype), T(I1, dtype))
-    say("[case] batch results on return")
-    vs = [torch.zeros((3,) + n, dtype=dtype, device=DEV) for n in sizes]
-    B.gn_solve(vs, concurrent=True, gn_iters=2, cg_iters=3)
-    for i in range(len(sizes)):
-        assert torch.equal(vs[i], refs[i]), i
+    for mode in ("lockstep", "threads"):
+        say(f"[case] batch results on return ({mode})")
+        vs = [torch.zeros((3,) + n, dtype=dtype, device=DEV) for n in sizes]
+        B.gn_solve(vs, gn_iters=2, cg_iters=3, mode=mode)
+        for i in range(len(sizes)):
+            assert torch.equal(vs[i], refs[i]), (mode, i)
     B.close()
