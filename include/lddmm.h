@@ -259,9 +259,13 @@ int lddmm_profile_read(lddmm_ctx* ctx, const char** names, int64_t* counts, doub
  *   "exec.graph"          0 | 1             replay Hessian-vector products from a captured
  *                                           hipGraph (store-all trajectories; needs a
  *                                           non-default stream)
+ *   "exec.branch_k"       0 | 1             in captured graphs, record the transform of a
+ *                                           vector field as three independent per-component
+ *                                           chains (their passes may overlap); bitwise the
+ *                                           same results.  Chosen by lddmm_autotune
  *   "stencil.rowvec"      0, 1, 2, 4        voxels per lane of the row-vectorised stencil
  *                                           kernels (0: one voxel per thread); nonzero
- *                                           values need N2 / value = 32 or 64.  Default:
+ *                                           values need 32 <= N2 / value <= 64.  Default:
  *                                           the smallest valid width in FP64, the widest
  *                                           in FP32, 0 where none is valid; same
  *                                           operators, summed in another order
@@ -275,8 +279,9 @@ int lddmm_get_option(lddmm_ctx* ctx, const char* key, int64_t* value);
 
 /* Autotuner: time the transform variants (plane workgroup size, pencil tile,
  * compile-time vs generic kernels, plane walk over one workgroup per compute
- * unit or two planes per workgroup) and the stencil widths ("stencil.rowvec",
- * "stencil.pair_rows", timed on the tangent stage) on this context's grid with HIP events
+ * unit or two planes per workgroup), the stencil widths ("stencil.rowvec",
+ * "stencil.pair_rows", timed on the tangent stage) and, on a non-default stream,
+ * "exec.branch_k" (timed as graph replays) on this context's grid with HIP events
  * (reps repetitions each; a transform shape is timed as a K application followed
  * by a tangent stage, the way the sweeps use it) and keep the fastest; the shape
  * in place when the call starts is kept unless another is more than 3 % faster,

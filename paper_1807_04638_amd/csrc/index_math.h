@@ -75,19 +75,23 @@ LDI_HD bool tile_voxel_at(const FieldTiling& t, int b, int tx, int ty, int n1, i
 LDI_HD int periodic_next(int i, int n) { return i + 1 == n ? 0 : i + 1; }
 LDI_HD int periodic_prev(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 
-// Row-vectorised stencils: a row of RW (32 or 64) lanes of a wave; the lanes
-// holding the x2 neighbours of `lane`, periodic inside its row.
+// Row-vectorised stencils: a row of RW lanes (32 <= RW <= 64) starts a 32-lane
+// half of a wave (RW = 32: two rows per wave) or a whole wave (RW > 32; lanes
+// RW..63 hold no voxel).  The lanes holding the x2 neighbours of `lane`,
+// periodic inside its row.
 LDI_HD void row_lanes(int lane, int RW, int& left, int& right) {
-  const int base = lane & ~(RW - 1);
-  left = base | ((lane - 1) & (RW - 1));
-  right = base | ((lane + 1) & (RW - 1));
+  const int seg = RW <= 32 ? 32 : 64;
+  const int base = lane & ~(seg - 1);
+  const int pos = lane - base;
+  left = base + (pos == 0 ? RW - 1 : (pos - 1) % RW);
+  right = base + (pos + 1) % RW;
 }
 
 // Host: a row-vectorised width vw (voxels per lane) is valid when a row of n2
-// voxels is 32 or 64 lanes.
+// voxels is 32 to 64 lanes.
 inline bool row_vector_valid(int n2, int vw) {
   if (vw != 1 && vw != 2 && vw != 4) return false;
-  return n2 % vw == 0 && (n2 / vw == 32 || n2 / vw == 64);
+  return n2 % vw == 0 && n2 / vw >= 32 && n2 / vw <= 64;
 }
 
 // Semi-Lagrangian gather along one axis: grid index i displaced by d voxels.

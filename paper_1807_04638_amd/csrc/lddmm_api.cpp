@@ -171,6 +171,12 @@ class Engine {
   ~Engine() {
     if (st) (void)hipStreamSynchronize(st);
     drop_graph();
+    for (int c = 0; c < 3; ++c) {
+      if (bst_c[c]) (void)hipStreamSynchronize(bst_c[c]);
+      if (bst_c[c]) (void)hipStreamDestroy(bst_c[c]);
+      if (bev_c[c]) (void)hipEventDestroy(bev_c[c]);
+    }
+    if (bev_fork) (void)hipEventDestroy(bev_fork);
     if (own_stream && st) (void)hipStreamDestroy(st);
     spectral_free(sp);
     for (void* p : allocs) (void)hipFree(p);
@@ -375,19 +381,48 @@ class Engine {
   }
 
   // ---- primitives -------------------------------------------------------
-  void applyK(const T* in, T* out, int ncomp = 3) {
-    spectral_apply(sp, in, out, ncomp, P.alpha, P.s, LDDMM_OP_K, st, &prof);
+  // While a graph is captured with exec.branch_k = 1, a vector field's transform
+  // is recorded as three independent per-component chains (forked from st onto
+  // the branch streams and joined back), so the passes of one component can
+  // overlap those of another.
+  bool branch_k = false;   // option
+  bool capturing = false;  // a graph capture on st is in progress
+  hipStream_t bst_c[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t bev_fork = nullptr, bev_c[3] = {nullptr, nullptr, nullptr};
+  int ensure_branch_streams() {
+    if (bst_c[0]) return 0;
+    if (hipEventCreateWithFlags(&bev_fork, hipEventDisableTiming) != hipSuccess) return LDDMM_EHIP;
+    for (int c = 0; c < 3; ++c)
+      if (hipStreamCreateWithFlags(&bst_c[c], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&bev_c[c], hipEventDisableTiming) != hipSuccess)
+        return LDDMM_EHIP;
+    return 0;
   }
-  void applyL(const T* in, T* out, int ncomp = 3) {
-    spectral_apply(sp, in, out, ncomp, P.alpha, P.s, LDDMM_OP_L, st, &prof);
+  void spectral(const T* in, T* out, int ncomp, int op, const T* add = nullptr, double add_scale = 0.0,
+                double out_scale = 1.0) {
+    if (ncomp != 3 || !capturing || !branch_k || !bst_c[0]) {
+      spectral_apply(sp, in, out, ncomp, P.alpha, P.s, op, st, &prof, add, add_scale, out_scale);
+      return;
+    }
+    (void)hipEventRecord(bev_fork, st);
+    const size_t cstride = size_t(sp.n0) * sp.n1 * sp.M;
+    for (int c = 0; c < 3; ++c) {
+      (void)hipStreamWaitEvent(bst_c[c], bev_fork, 0);
+      SpectralPlan<T> spc = sp;
+      spc.spec = sp.spec + c * cstride;
+      spectral_apply(spc, in + c * N, out + c * N, 1, P.alpha, P.s, op, bst_c[c], &prof, add ? add + c * N : nullptr,
+                     add_scale, out_scale);
+      (void)hipEventRecord(bev_c[c], bst_c[c]);
+    }
+    for (int c = 0; c < 3; ++c) (void)hipStreamWaitEvent(st, bev_c[c], 0);
   }
+  void applyK(const T* in, T* out, int ncomp = 3) { spectral(in, out, ncomp, LDDMM_OP_K); }
+  void applyL(const T* in, T* out, int ncomp = 3) { spectral(in, out, ncomp, LDDMM_OP_L); }
   // out = add + scale K in (vector fields): the adjoint stage's w update
-  void applyK_add(const T* in, const T* add, double scale, T* out) {
-    spectral_apply(sp, in, out, 3, P.alpha, P.s, LDDMM_OP_K, st, &prof, add, scale);
-  }
+  void applyK_add(const T* in, const T* add, double scale, T* out) { spectral(in, out, 3, LDDMM_OP_K, add, scale); }
   // out = scale K in (vector fields)
   void applyK_scaled(const T* in, double scale, T* out) {
-    spectral_apply(sp, in, out, 3, P.alpha, P.s, LDDMM_OP_K, st, &prof, static_cast<const T*>(nullptr), 0.0, scale);
+    spectral(in, out, 3, LDDMM_OP_K, nullptr, 0.0, scale);
   }
   void copy(T* dst, const T* src, long long count) {
     (void)hipMemcpyAsync(dst, src, size_t(count) * sizeof(T), hipMemcpyDeviceToDevice, st);
@@ -635,7 +670,9 @@ class Engine {
         hessvec_kernels(dv, hv, Ldv);
         return;
       }
+      capturing = true;
       hessvec_kernels(dv, hv, Ldv);
+      capturing = false;
       if (hipStreamEndCapture(st, &graph) != hipSuccess || !graph) {
         (void)hipGetLastError();
         hessvec_kernels(dv, hv, Ldv);
@@ -849,6 +886,49 @@ class Engine {
       prof.enabled = was;
       return fail(rc, msg);
     }
+    // Transforms of a vector field as one chain or as three per-component chains
+    // (exec.branch_k, graphs only): timed as replays of a captured graph of K
+    // applications, each followed by a tangent stage; the start setting is kept
+    // unless the other is more than 3 % faster.
+    if (st && ensure_branch_streams() == 0) {
+      const bool start_bk = branch_k;
+      float tb[2] = {-1.f, -1.f};
+      for (int bk = 0; bk < 2; ++bk) {
+        branch_k = bk != 0;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t ex = nullptr;
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+          (void)hipGetLastError();
+          break;
+        }
+        capturing = true;
+        for (int r = 0; r < reps; ++r) {
+          applyK(W, Z);
+          launch_tangent_stage<T>(g, X, Mu, Z, Xs, Mus, X, Mu, Us, Whs, dt, 0.0, 1.0, st, nullptr);
+        }
+        capturing = false;
+        if (hipStreamEndCapture(st, &graph) != hipSuccess || !graph ||
+            hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) != hipSuccess) {
+          (void)hipGetLastError();
+          if (graph) (void)hipGraphDestroy(graph);
+          break;
+        }
+        (void)hipGraphLaunch(ex, st);  // warm-up
+        (void)hipEventRecord(a, st);
+        (void)hipGraphLaunch(ex, st);
+        (void)hipEventRecord(b, st);
+        (void)hipEventSynchronize(b);
+        (void)hipEventElapsedTime(&tb[bk], a, b);
+        ++count;
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGraphDestroy(graph);
+      }
+      branch_k = start_bk;
+      if (tb[0] > 0.f && tb[1] > 0.f) {
+        const int other = start_bk ? 0 : 1;
+        if (tb[other] * 1.03f < tb[start_bk ? 1 : 0]) branch_k = other != 0;
+      }
+    }
     // reported: one K application of the chosen shape, timed alone
     applyK(W, Z);
     (void)hipEventRecord(a, st);
@@ -978,7 +1058,9 @@ class Engine {
       (void)hipGetLastError();
       return false;
     }
+    capturing = true;
     cg_iteration(x, true);
+    capturing = false;
     hipGraph_t graph = nullptr;
     if (hipStreamEndCapture(st, &graph) != hipSuccess || !graph) {
       (void)hipGetLastError();
@@ -1296,9 +1378,16 @@ class Engine {
       return 0;
     } else if (k == "stencil.rowvec") {
       if (value != 0 && !row_vector_valid(g.n2, int(value)))
-        return fail(LDDMM_EINVAL, "stencil.rowvec: N2 / value must be 32 or 64 with value 1, 2 or 4");
+        return fail(LDDMM_EINVAL, "stencil.rowvec: N2 / value must be 32 to 64 with value 1, 2 or 4");
       (void)hipStreamSynchronize(st);
       g.rowvec = int(value);
+      drop_graph();
+      return 0;
+    } else if (k == "exec.branch_k") {
+      if (value != 0 && value != 1) return fail(LDDMM_EINVAL, "exec.branch_k: 0 or 1");
+      (void)hipStreamSynchronize(st);
+      if (value && ensure_branch_streams()) return fail(LDDMM_EHIP, "cannot create the branch streams");
+      branch_k = value != 0;
       drop_graph();
       return 0;
     } else if (k == "stencil.pair_rows") {
@@ -1356,6 +1445,8 @@ class Engine {
       *value = lin_epoch;
     else if (k == "exec.graph")
       *value = use_graph ? 1 : 0;
+    else if (k == "exec.branch_k")
+      *value = branch_k ? 1 : 0;
     else if (k == "stencil.rowvec")
       *value = g.rowvec;
     else
@@ -1769,7 +1860,9 @@ void batch_cg_step(lddmm_batch* b, const std::vector<int>& live) {
     if (!ex) {
       ex = capture_across(b, live, [&](int i) {
         auto* E = engine_of<T>(b->ctx[i]);
+        E->capturing = true;
         E->cg_iteration(E->cx, true);
+        E->capturing = false;
       });
       if (ex) b->cg_all.emplace_back(mask, ex);
     }
@@ -1885,7 +1978,10 @@ int batch_hessvec_lockstep(lddmm_batch* b, void* const* dv, void* const* hv, int
     if (!b->hv_all || ptrs != b->hv_ptrs || graph_gens<T>(b) != b->hv_gens) {
       if (b->hv_all) (void)hipGraphExecDestroy(b->hv_all);
       b->hv_all = capture_across(b, all, [&](int i) {
-        engine_of<T>(b->ctx[i])->hessvec_kernels(static_cast<const T*>(dv[i]), static_cast<T*>(hv[i]));
+        auto* E = engine_of<T>(b->ctx[i]);
+        E->capturing = true;
+        E->hessvec_kernels(static_cast<const T*>(dv[i]), static_cast<T*>(hv[i]));
+        E->capturing = false;
       });
       b->hv_ptrs = ptrs;
       b->hv_gens = graph_gens<T>(b);

@@ -424,9 +424,10 @@ __global__ void __launch_bounds__(256) k_jacobian_det(Geo<T> g, const T* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Row-vectorised variants for N2 = VW * RW with RW = 32 or 64 lanes.  A lane
+// Row-vectorised variants for N2 = VW * RW with 32 <= RW <= 64 lanes.  A lane
 // owns VW consecutive voxels of an x2 row and a row is RW consecutive lanes of
-// one wavefront, so every x0 or x1 neighbour is one VW-wide load and the x2
+// one wavefront (rows of 32 lanes fill a half wave each, longer rows a whole
+// wave with lanes RW..63 idle), so every x0 or x1 neighbour is one VW-wide load and the x2
 // neighbours come from the two adjacent lanes (periodic inside the row).  Same
 // operators as the kernels above, accumulated one direction at a time; about a
 // third of their load instructions, which is what limits those kernels (the

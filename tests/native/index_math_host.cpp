@@ -80,14 +80,31 @@ void check_pairs(int n0, int n1, int lanes) {
       if (!va || !vc) continue;
       expect(a1 % 2 == 0 && c1 == a1 + 1 && a0 == c0 && a2 == c2, "paired rows", a1, c1, a2 - c2);
     }
-  for (int RW : {32, 64})
-    for (int lane = 0; lane < 64; ++lane) {
-      int l, r;
-      row_lanes(lane, RW, l, r);
-      const int base = lane / RW * RW;
-      expect(l >= base && l < base + RW && r >= base && r < base + RW, "row lanes inside the row", lane, l, r);
-      expect(l == base + (lane - base + RW - 1) % RW && r == base + (lane - base + 1) % RW, "row lanes periodic",
-             lane, l, r);
+}
+
+// Row-vectorised rows of RW lanes (32 to 64): every voxel lane's x2 neighbour
+// lanes lie inside its own row, periodically; a launch over (N0, N1, RW) lanes
+// puts each row at the start of a 32-lane half (RW = 32) or of a wave (RW > 32)
+// with the lane's position in the row equal to its x2 index.
+void check_row_lanes(int n0, int n1, int RW) {
+  const int seg = RW <= 32 ? 32 : 64;
+  for (int lane = 0; lane < 64; ++lane) {
+    const int base = lane / seg * seg, pos = lane - base;
+    int l, r;
+    row_lanes(lane, RW, l, r);
+    expect(l >= 0 && l < 64 && r >= 0 && r < 64, "row lanes in the wave", lane, l, r);
+    if (pos >= RW) continue;  // no voxel on this lane
+    expect(l >= base && l < base + RW && r >= base && r < base + RW, "row lanes inside the row", lane, l, r);
+    expect(l == base + (pos + RW - 1) % RW && r == base + (pos + 1) % RW, "row lanes periodic", lane, l, r);
+  }
+  const FieldTiling t = field_tiling(n0, n1, RW);
+  const int threads = t.BX * t.BY;
+  for (unsigned b = 0; b < t.blocks; ++b)
+    for (int tid = 0; tid < threads; ++tid) {
+      int i0, i1, j;
+      if (!tile_voxel_at(t, int(b), tid % t.BX, tid / t.BX, n1, RW, i0, i1, j)) continue;
+      const int lane = tid & 63, pos = lane - lane / seg * seg;
+      expect(pos == j, "lane position = x2 lane index", lane, j);
     }
 }
 
@@ -238,6 +255,16 @@ int main() {
     check_pairs(4, n1, 32);
   }
   check_pairs(128, 128, 32);
+  for (int RW : {32, 33, 40, 45, 48, 54, 56, 63, 64})
+    for (int n1 : {4, 7, 12, 216}) check_row_lanes(4, n1, RW);
+  for (int n2 : {64, 80, 96, 112, 128, 180, 216, 256}) {
+    // the widths the engine may take for a row of n2 voxels
+    for (int vw : {1, 2, 4}) {
+      const bool ok = row_vector_valid(n2, vw);
+      expect(ok == (n2 % vw == 0 && n2 / vw >= 32 && n2 / vw <= 64), "row width validity", n2, vw);
+      if (ok) check_tiling(4, 12, n2 / vw);
+    }
+  }
   for (int n : {4, 5, 6, 7, 8, 12, 64, 128, 180, 216, 256, 512}) check_periodic(n);
   for (int n : {4, 5, 7, 20, 64, 128, 180, 216, 256}) {
     check_sl_axis<float>(n, rng);

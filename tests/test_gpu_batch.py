@@ -32,14 +32,15 @@ def pair(n, seed):
     return I0, I1
 
 
+@pytest.mark.parametrize("branch_k", [0, 1])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_graph_replay_matches_eager(dtype):
+def test_graph_replay_matches_eager(dtype, branch_k):
     from paper_1807_04638_amd import Registration
 
     n = (32, 32, 32)
     s = torch.cuda.Stream(device=DEV)
     with torch.cuda.stream(s):
-        say(f"[case] graph replay {dtype}")
+        say(f"[case] graph replay {dtype} branch_k={branch_k}")
         R = Registration(n, 5, 0.01, 2, 0.05, dtype=dtype)
         I0, I1 = pair(n, 0)
         R.set_images(T(I0, dtype), T(I1, dtype))
@@ -47,6 +48,7 @@ def test_graph_replay_matches_eager(dtype):
         dv = T(random_field(n, 13, kc=3.0), dtype)
         eager = R.hessvec(dv)
         R.set_option("exec.graph", 1)
+        R.set_option("exec.branch_k", branch_k)  # transforms as per-component chains in the graph
         hv = torch.empty_like(dv)
         for rep in range(4):
             R.hessvec(dv, out=hv)

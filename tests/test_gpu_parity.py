@@ -322,14 +322,16 @@ def test_hessvec_parity(n, dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("n", [(10, 6, 64), (8, 12, 128), (6, 8, 256), (6, 7, 128)])
+@pytest.mark.parametrize("n", [(10, 6, 64), (8, 12, 128), (6, 8, 256), (6, 7, 128), (6, 8, 180), (8, 6, 80),
+                               (6, 8, 112), (6, 8, 216)])
 def test_row_vectorised_stencils(n, dtype):
-    """Every stencil width a row of N2 = 64, 128, 256 allows: one voxel per
-    thread (stencil.rowvec = 0) and VW = 1, 2, 4 voxels per lane with x2
-    neighbours across lanes (N2 / VW = 32 or 64); with 32-lane rows both with
-    and without the x1 row shared by the two halves of a wave (N1 odd: the
-    pairing stays off).  Each against the oracle on shooting, the gradient and
-    the Hessian-vector product."""
+    """Every stencil width a row of N2 voxels allows: one voxel per thread
+    (stencil.rowvec = 0) and VW = 1, 2, 4 voxels per lane with x2 neighbours
+    across lanes (rows of 32 to 64 lanes: N2 = 180 and 216 take 45 and 54 lanes
+    of a wave at VW = 4, N2 = 80 and 112 take 40 and 56 lanes at VW = 2); with
+    32-lane rows both with and without the x1 row shared by the two halves of a
+    wave (N1 odd: the pairing stays off).  Each against the oracle on shooting,
+    the gradient and the Hessian-vector product."""
     I0, I1 = images(n)
     v0 = random_velocity(n, 2003, 0.5, kc=2.0)  # coarse x0/x1 axes: keep the flow well resolved
     dv = random_field(n, 6, kc=3.0)
@@ -338,7 +340,7 @@ def test_row_vectorised_stencils(n, dtype):
     go, lin = O.gradient(v0, I0, I1, p)
     ho = O.hessvec(dv, lin, p)
     hn = O.hessvec_newton(dv, lin, p)
-    widths = [0] + [vw for vw in (1, 2, 4) if n[2] % vw == 0 and n[2] // vw in (32, 64)]
+    widths = [0] + [vw for vw in (1, 2, 4) if n[2] % vw == 0 and 32 <= n[2] // vw <= 64]
     shapes = [(vw, pr) for vw in widths for pr in ((0, 1) if vw and n[2] // vw == 32 else (1,))]
     for rowvec, pair in shapes:
         R, _ = make(n, dtype, sigma2=0.05)
