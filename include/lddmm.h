@@ -211,6 +211,38 @@ int lddmm_cg_solve(lddmm_ctx* ctx, const void* g, void* x, double eta, int maxit
 int lddmm_gn_solve(lddmm_ctx* ctx, void* v0_inout, const lddmm_solve_opts* opts,
                    lddmm_solve_report* report, lddmm_iter_log* log, int log_cap);
 
+/* PDE-LDDMM, the comparison method of Section 2.3 (energy eq. LS-LDDMM with the
+ * state eq. FirstOrder1, adjoint eq. FirstOrder2, gradient eq. FirstOrder3 and the
+ * second-order system SecondOrder1-3 with the Gauss-Newton drops of its last
+ * paragraph), on the context's grid, nt, L, sigma2 and images.
+ * Velocity fields over time: stationary != 0, one vector field v (v_t = v);
+ * stationary == 0, nt + 1 vector fields v_0..v_nt at t_n = n / nt, stacked
+ * ([nt+1][3][N0][N1][N2]).  Gradients and Hessian products have the same layout.
+ * Discretisation: the image transported by the SL step of the main method
+ * (m_{n+1} = m_n o X_n); the adjoint lambda (continuity equation) along forward
+ * characteristics with a trapezoidal divergence factor exp(dt/2 (div v_n(x) +
+ * div v_{n+1}(Y)))); the incremental state with a trapezoidal source; products
+ * over time with trapezoid weights.  Optimise-then-discretise: gradient and
+ * Hessian agree with the discrete energy to discretisation error.
+ * The first call allocates 8 (nt + 1) vector and 2 nt + 8 scalar fields.
+ *
+ * E = int <L v_t, v_t> dt + sigma2^-1 ||m(1) - I_1||^2; m1 (scalar, may be NULL)
+ * = m(1).  Becomes the current PDE linearization. */
+int lddmm_pde_energy(lddmm_ctx* ctx, int stationary, const void* v, void* m1, double* energy);
+/* L2 gradient 2 L v_t + lambda(t) grad m(t) (stationary: 2 L v + its time
+ * integral of lambda grad m); linearizes at v. */
+int lddmm_pde_gradient(lddmm_ctx* ctx, int stationary, const void* v, void* g, double* energy);
+/* Gauss-Newton Hessian in L2: 2 L dv_t + dlambda(t) grad m(t), dlambda the adjoint
+ * of -(2/sigma2) dm(1); v == NULL reuses the current PDE linearization
+ * (LDDMM_ESTATE if there is none for this parameterisation). */
+int lddmm_pde_hessvec(lddmm_ctx* ctx, int stationary, const void* v, const void* dv, void* hv);
+/* Gauss-Newton-Krylov from v_inout (updated in place): PCG in the space-time L2
+ * product with preconditioner K per time point, forcing eta = min(eta_max,
+ * sqrt(||g|| / ||g_0||)), Armijo backtracking v <- v + tau p; opts->method is
+ * ignored.  Report and log as for lddmm_gn_solve (L2 norms). */
+int lddmm_pde_gn_solve(lddmm_ctx* ctx, int stationary, void* v_inout, const lddmm_solve_opts* opts,
+                       lddmm_solve_report* report, lddmm_iter_log* log, int log_cap);
+
 /* Jacobian determinant det(I + D_h u) (central differences) of a displacement u
  * (vector field) into det (scalar field), plus its extrema (either may be NULL;
  * synchronises when requested). */

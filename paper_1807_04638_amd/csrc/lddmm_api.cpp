@@ -1454,6 +1454,264 @@ class Engine {
     return 0;
   }
 
+  // ---- PDE-LDDMM (Section 2.3), the comparison method ----------------------
+  // Velocities over time: stationary, one vector field; non-stationary, nt + 1
+  // vector fields v_0..v_nt at t_n = n dt, stacked ([nt+1][3][N0][N1][N2]).  The
+  // state m_n is the image transported by SL, the adjoint lambda the continuity
+  // equation along forward characteristics; gradient and Gauss-Newton Hessian in
+  // the space-time L2 product (trapezoid weights in time), solved by PCG with K
+  // per time point.  Workspace allocated on first use.
+  bool pde_ready = false, pde_lin = false, pde_stat = false;
+  T *pv = nullptr, *pg = nullptr, *ptrial = nullptr, *px = nullptr, *pr = nullptr, *pz = nullptr, *pd = nullptr,
+    *pq = nullptr, *pacc = nullptr;
+  std::vector<T*> pm, pD;              // m_n and div v_n, n = 0..nt
+  T *plam[2] = {nullptr, nullptr}, *pdm[2] = {nullptr, nullptr}, *psrc[2] = {nullptr, nullptr};
+  double pE = 0, pEreg = 0, pEdata = 0;
+
+  int pde_slices(bool stationary) const { return stationary ? 1 : P.nt + 1; }
+  // quadrature weight of time point n (trapezoid, dt)
+  double pde_w(int n) const { return (n == 0 || n == P.nt) ? 0.5 * dt : dt; }
+  int ensure_pde() {
+    if (pde_ready) return 0;
+    const long long V = 3 * N, S = (long long)(P.nt + 1) * V;
+    for (T** q : {&pv, &pg, &ptrial, &px, &pr, &pz, &pd, &pq})
+      if (alloc(q, S)) return fail(LDDMM_ENOMEM, "out of device memory (PDE-LDDMM workspace)");
+    if (alloc(&pacc, V)) return fail(LDDMM_ENOMEM, "out of device memory (PDE-LDDMM workspace)");
+    pm.assign(P.nt + 1, nullptr);
+    pD.assign(P.nt + 1, nullptr);
+    for (auto* vec : {&pm, &pD})
+      for (T*& q : *vec)
+        if (alloc(&q, N)) return fail(LDDMM_ENOMEM, "out of device memory (PDE-LDDMM workspace)");
+    for (T** q : {&plam[0], &plam[1], &pdm[0], &pdm[1], &psrc[0], &psrc[1]})
+      if (alloc(q, N)) return fail(LDDMM_ENOMEM, "out of device memory (PDE-LDDMM workspace)");
+    pde_ready = true;
+    return 0;
+  }
+  // time point n of a stack (every point is the single field when stationary)
+  const T* slice(const T* stack, int n, bool stationary) const {
+    return stationary ? stack : stack + (long long)n * 3 * N;
+  }
+  T* slice(T* stack, int n, bool stationary) const { return stationary ? stack : stack + (long long)n * 3 * N; }
+
+  // FP64 space-time L2 product sum_n w_n <a_n, b_n> of two stacks (synchronising)
+  double pde_dot(const T* a, const T* b, bool stationary) {
+    const long long V = 3 * N;
+    if (stationary) return dot(a, b);
+    dot_dev(a, b, 3 * (P.nt + 1), 12);                                  // all time points
+    launch_dot(a, b, V, partials, dres + 13, st, &prof);                  // t = 0
+    launch_dot(a + P.nt * V, b + P.nt * V, V, partials, dres + 14, st, &prof);  // t = 1
+    post_fetch();
+    wait();
+    return cell * dt * (hres[12] - 0.5 * hres[13] - 0.5 * hres[14]);
+  }
+  // state sweep, divergences and both energy terms at the stack v (copied)
+  void pde_linearize(const T* v, bool stationary) {
+    const long long V = 3 * N;
+    const int ns = pde_slices(stationary);
+    if (v != pv) copy(pv, v, ns * V);
+    copy(pm[0], I0, N);
+    for (int n = 0; n < P.nt; ++n)
+      launch_pde_state<T>(g, pm[n], slice(pv, n, stationary), slice(pv, n + 1, stationary), pm[n + 1], dt, st, &prof);
+    for (int n = 0; n < ns; ++n) launch_div<T>(g, slice(pv, n, stationary), pD[n], st, &prof);
+    // regulariser: <L v, v> (stationary) or sum_n w_n <L v_n, v_n>
+    double ereg = 0;
+    for (int n = 0; n < ns; ++n) {
+      applyL(slice(pv, n, stationary), pacc);
+      const double d = dot(pacc, slice(pv, n, stationary));
+      ereg += stationary ? d : pde_w(n) * d;
+    }
+    launch_axpbyz<T>(N, 1.0, pm[P.nt], -1.0, I1, tmpS, st, &prof);
+    pEreg = ereg;
+    pEdata = dot(tmpS, tmpS, 1) / P.sigma2;
+    pE = pEreg + pEdata;
+    pde_lin = true;
+    pde_stat = stationary;
+  }
+  // Backward sweep of a final lambda in plam[nt & 1]: out = 2 L base + sum over
+  // time of lambda_n grad m_n (per time point, or its time integral when stationary).
+  void pde_backward(const T* base, T* out, bool stationary) {
+    const long long V = 3 * N;
+    if (stationary) launch_fill<T>(V, T(0), pacc, st, &prof);
+    for (int n = P.nt; n >= 0; --n) {
+      const T* lam = plam[n & 1];
+      if (n < P.nt)
+        launch_pde_adjoint<T>(g, plam[(n + 1) & 1], pD[stationary ? 0 : n], pD[stationary ? 0 : n + 1],
+                              slice(pv, n, stationary), slice(pv, n + 1, stationary), plam[n & 1], dt, st, &prof);
+      if (stationary) {
+        launch_pde_lambda_grad<T>(g, pm[n], lam, pde_w(n), pacc, st, &prof);
+      } else {
+        T* o = slice(out, n, false);
+        applyL(slice(base, n, false), o);
+        launch_axpby<T>(V, 0.0, o, 2.0, o, st, &prof);
+        launch_pde_lambda_grad<T>(g, pm[n], lam, 1.0, o, st, &prof);
+      }
+    }
+    if (stationary) {
+      applyL(base, out);
+      launch_axpby<T>(V, 1.0, pacc, 2.0, out, st, &prof);
+    }
+  }
+  int pde_check(bool stationary) {
+    if (!have_images) return fail(LDDMM_ESTATE, "images not set");
+    (void)stationary;
+    return ensure_pde();
+  }
+  int pde_energy(bool stationary, const T* v, T* m1, double* energy) {
+    if (int rc = pde_check(stationary)) return rc;
+    if (int rc = check_finite(v, (long long)pde_slices(stationary) * 3 * N, "v")) return rc;
+    pde_linearize(v, stationary);
+    if (m1) copy(m1, pm[P.nt], N);
+    if (energy) *energy = pE;
+    return hip_status("pde_energy");
+  }
+  void pde_gradient_core(T* gout) {
+    launch_axpbyz<T>(N, -2.0 / P.sigma2, pm[P.nt], 2.0 / P.sigma2, I1, plam[P.nt & 1], st, &prof);
+    pde_backward(pv, gout, pde_stat);
+  }
+  int pde_gradient(bool stationary, const T* v, T* gout, double* energy) {
+    if (int rc = pde_energy(stationary, v, nullptr, energy)) return rc;
+    pde_gradient_core(gout);
+    return hip_status("pde_gradient");
+  }
+  // Gauss-Newton Hessian at the current PDE linearization
+  void pde_hessvec_core(const T* dv, T* hv) {
+    const bool stationary = pde_stat;
+    launch_fill<T>(N, T(0), pdm[0], st, &prof);
+    launch_pde_source<T>(g, pm[0], slice(dv, 0, stationary), psrc[0], st, &prof);
+    for (int n = 0; n < P.nt; ++n) {
+      launch_pde_source<T>(g, pm[n + 1], slice(dv, n + 1, stationary), psrc[(n + 1) & 1], st, &prof);
+      launch_pde_incr<T>(g, pdm[n & 1], psrc[n & 1], psrc[(n + 1) & 1], slice(pv, n, stationary),
+                         slice(pv, n + 1, stationary), pdm[(n + 1) & 1], dt, st, &prof);
+    }
+    launch_axpbyz<T>(N, -2.0 / P.sigma2, pdm[P.nt & 1], 0.0, pdm[P.nt & 1], plam[P.nt & 1], st, &prof);
+    pde_backward(dv, hv, stationary);
+  }
+  int pde_hessvec(bool stationary, const T* v, const T* dv, T* hv) {
+    if (int rc = pde_check(stationary)) return rc;
+    if (v) {
+      if (int rc = pde_energy(stationary, v, nullptr, nullptr)) return rc;
+    } else if (!pde_lin || pde_stat != stationary) {
+      return fail(LDDMM_ESTATE, "pde_hessvec without a PDE linearization of this parameterisation");
+    }
+    pde_hessvec_core(dv, hv);
+    return hip_status("pde_hessvec");
+  }
+  // K per time point
+  void pde_precondition(const T* r, T* z, bool stationary) {
+    for (int n = 0; n < pde_slices(stationary); ++n) applyK(slice(r, n, stationary), slice(z, n, stationary));
+  }
+  // PCG in the space-time L2 product for H x = -g, preconditioner K
+  int pde_pcg(const T* gin, T* x, double eta, int maxit) {
+    const bool stn = pde_stat;
+    const long long S = (long long)pde_slices(stn) * 3 * N;
+    launch_axpbyz<T>(S, -1.0, gin, 0.0, gin, pr, st, &prof);
+    launch_fill<T>(S, T(0), x, st, &prof);
+    pde_precondition(pr, pz, stn);
+    copy(pd, pz, S);
+    double rz = pde_dot(pr, pz, stn);
+    const double tol = eta * std::sqrt(pde_dot(gin, gin, stn));
+    int it = 0;
+    for (it = 1; it <= maxit; ++it) {
+      pde_hessvec_core(pd, pq);
+      const double dq = pde_dot(pd, pq, stn);
+      if (!(dq > 0.0)) {
+        --it;
+        break;
+      }
+      const double a = rz / dq;
+      launch_axpby<T>(S, a, pd, 1.0, x, st, &prof);
+      launch_axpby<T>(S, -a, pq, 1.0, pr, st, &prof);
+      if (std::sqrt(pde_dot(pr, pr, stn)) <= tol) break;
+      pde_precondition(pr, pz, stn);
+      const double rz_new = pde_dot(pr, pz, stn);
+      launch_axpby<T>(S, 1.0, pz, rz_new / rz, pd, st, &prof);
+      rz = rz_new;
+    }
+    if (it > maxit) it = maxit;
+    return it;
+  }
+  int pde_gn_solve(bool stationary, T* v, const lddmm_solve_opts* o, lddmm_solve_report* rep, lddmm_iter_log* log,
+                   int log_cap) {
+    if (int rc = pde_check(stationary)) return rc;
+    const long long S = (long long)pde_slices(stationary) * 3 * N;
+    if (int rc = check_finite(v, S, "v")) return rc;
+    lddmm_solve_opts op{};
+    if (o) op = *o;
+    if (op.gn_iters <= 0) op.gn_iters = 10;
+    if (op.cg_iters <= 0) op.cg_iters = 20;
+    if (op.max_halvings <= 0) op.max_halvings = 10;
+    if (op.c1 <= 0) op.c1 = 1e-4;
+    if (op.gtol <= 0) op.gtol = 1e-3;
+    if (op.eta_max <= 0) op.eta_max = 0.5;
+    lddmm_solve_report R{};
+    double g0 = 0, ginf0 = 0;
+    bool at_v = false;
+    for (int k = 0; k < op.gn_iters; ++k) {
+      if (!at_v) pde_linearize(v, stationary);
+      at_v = true;
+      pde_gradient_core(pg);
+      R.gradients++;
+      if (k == 0) R.E_first = pE;
+      const double gn = std::sqrt(pde_dot(pg, pg, stationary));
+      const double ginf = maxabs(pg, S);
+      if (k == 0) {
+        g0 = gn;
+        ginf0 = ginf;
+      }
+      R.g_rel_final = g0 > 0 ? gn / g0 : 0.0;
+      if (g0 == 0.0 || gn / g0 <= op.gtol) {
+        R.stop_reason = 1;
+        break;
+      }
+      const double eta = std::min(op.eta_max, std::sqrt(gn / g0));
+      const int its = pde_pcg(pg, px, eta, op.cg_iters);
+      R.cg_total += its;
+      R.hessvecs += its;
+      const double gp = pde_dot(pg, px, stationary);
+      const double E0 = pE, Er0 = pEreg, Ed0 = pEdata;
+      double tau = 1.0;
+      bool accepted = false;
+      int trials = 0;
+      for (int h = 0; h <= op.max_halvings; ++h) {
+        launch_axpbyz<T>(S, 1.0, v, tau, px, ptrial, st, &prof);
+        pde_linearize(ptrial, stationary);
+        at_v = false;
+        R.shoots++;
+        trials++;
+        if (pE <= E0 + op.c1 * tau * gp) {
+          accepted = true;
+          break;
+        }
+        tau *= 0.5;
+      }
+      if (log && k < log_cap) {
+        lddmm_iter_log& L = log[k];
+        L.E = E0;
+        L.E_reg = Er0;
+        L.E_data = Ed0;
+        L.mse_rel = base_sq > 0 ? 100.0 * Ed0 * P.sigma2 / base_sq : 0.0;
+        L.g_norm = gn;
+        L.g_inf_rel = ginf0 > 0 ? ginf / ginf0 : 0.0;
+        L.eta = eta;
+        L.tau = accepted ? tau : 0.0;
+        L.cg_iters = its;
+        L.ls_trials = trials;
+      }
+      R.iters = k + 1;
+      if (!accepted) {
+        R.stop_reason = 2;
+        break;
+      }
+      copy(v, ptrial, S);
+      at_v = true;  // the accepted trial's linearization is the one at the new v
+    }
+    if (!at_v) pde_linearize(v, stationary);
+    R.E_final = pE;
+    R.mse_rel_final = base_sq > 0 ? 100.0 * pEdata * P.sigma2 / base_sq : 0.0;
+    if (rep) *rep = R;
+    return hip_status("pde_gn_solve");
+  }
+
   int jacobian(const T* uin, T* det, double* mn, double* mx) {
     T* out = det ? det : tmpS;
     launch_jacobian_det<T>(g, uin, out, st, &prof);
@@ -1598,6 +1856,28 @@ int lddmm_gn_solve(lddmm_ctx* ctx, void* v0_inout, const lddmm_solve_opts* opts,
                    lddmm_iter_log* log, int log_cap) {
   if (!v0_inout || log_cap < 0) return LDDMM_EINVAL;
   LDDMM_DISPATCH(ctx, E.gn_solve(static_cast<T*>(v0_inout), opts, report, log, log_cap));
+}
+
+int lddmm_pde_energy(lddmm_ctx* ctx, int stationary, const void* v, void* m1, double* energy) {
+  if (!v) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.pde_energy(stationary != 0, static_cast<const T*>(v), static_cast<T*>(m1), energy));
+}
+
+int lddmm_pde_gradient(lddmm_ctx* ctx, int stationary, const void* v, void* g, double* energy) {
+  if (!v || !g) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.pde_gradient(stationary != 0, static_cast<const T*>(v), static_cast<T*>(g), energy));
+}
+
+int lddmm_pde_hessvec(lddmm_ctx* ctx, int stationary, const void* v, const void* dv, void* hv) {
+  if (!dv || !hv) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.pde_hessvec(stationary != 0, static_cast<const T*>(v), static_cast<const T*>(dv),
+                                    static_cast<T*>(hv)));
+}
+
+int lddmm_pde_gn_solve(lddmm_ctx* ctx, int stationary, void* v_inout, const lddmm_solve_opts* opts,
+                       lddmm_solve_report* report, lddmm_iter_log* log, int log_cap) {
+  if (!v_inout || log_cap < 0) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.pde_gn_solve(stationary != 0, static_cast<T*>(v_inout), opts, report, log, log_cap));
 }
 
 int lddmm_jacobian_det(lddmm_ctx* ctx, const void* u, void* det, double* det_min, double* det_max) {

@@ -220,6 +220,31 @@ void launch_sl_step(const Grid& g, const T* u_old, const T* v_old, const T* v_ne
 template <typename T>
 void launch_compose(const Grid& g, const T* I, const T* u, T* J, hipStream_t st, Profiler* prof);
 
+// PDE-LDDMM (Section 2.3, the comparison method): the image transported by the
+// state equation, the adjoint (continuity) equation, the incremental state.
+// m_new(x) = m_old(X), X the Heun foot of launch_sl_step
+template <typename T>
+void launch_pde_state(const Grid& g, const T* m_old, const T* v_old, const T* v_new, T* m_new, double dt,
+                      hipStream_t st, Profiler* prof);
+// dm_new(x) = dm_old(X) + dt/2 (s_old(X) + s_new(x))
+template <typename T>
+void launch_pde_incr(const Grid& g, const T* dm_old, const T* s_old, const T* s_new, const T* v_old, const T* v_new,
+                     T* dm_new, double dt, hipStream_t st, Profiler* prof);
+// lam_old(x) = lam_new(Y) exp(dt/2 (D_old(x) + D_new(Y))), Y = x + dt/2 (v_old(x) + v_new(x + dt v_old(x)))
+template <typename T>
+void launch_pde_adjoint(const Grid& g, const T* lam_new, const T* D_old, const T* D_new, const T* v_old,
+                        const T* v_new, T* lam_old, double dt, hipStream_t st, Profiler* prof);
+// D = div_h v
+template <typename T>
+void launch_div(const Grid& g, const T* v, T* D, hipStream_t st, Profiler* prof);
+// out += w lam grad_h m
+template <typename T>
+void launch_pde_lambda_grad(const Grid& g, const T* m, const T* lam, double w, T* out, hipStream_t st,
+                            Profiler* prof);
+// s = -grad_h m . dv
+template <typename T>
+void launch_pde_source(const Grid& g, const T* m, const T* dv, T* s, hipStream_t st, Profiler* prof);
+
 // ---------------------------------------------------------------------------
 // Reductions and BLAS-1 - reduce.hip.  Reductions are deterministic two-stage
 // (fixed grid, fixed summation order, no atomics) and accumulate in double.

@@ -106,6 +106,14 @@ SIGNATURES = {
         ctypes.c_int,
         [_vp, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveReport), ctypes.POINTER(IterLog), ctypes.c_int],
     ),
+    "lddmm_pde_energy": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _c_double_p]),
+    "lddmm_pde_gradient": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _c_double_p]),
+    "lddmm_pde_hessvec": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
+    "lddmm_pde_gn_solve": (
+        ctypes.c_int,
+        [_vp, ctypes.c_int, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveReport), ctypes.POINTER(IterLog),
+         ctypes.c_int],
+    ),
     "lddmm_jacobian_det": (ctypes.c_int, [_vp, _vp, _vp, _c_double_p, _c_double_p]),
     "lddmm_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lddmm_profile_read": (
@@ -380,6 +388,65 @@ class Registration:
         self._check(
             self.lib.lddmm_gn_solve(self._ctx, _ptr(v0), ctypes.byref(o), ctypes.byref(rep), logs, cap), "gn_solve"
         )
+        rd = {k: getattr(rep, k) for k, _ in SolveReport._fields_}
+        log = [{k: getattr(logs[i], k) for k, _ in IterLog._fields_} for i in range(min(rep.iters, cap))]
+        return Trace(rd, log)
+
+    # ---- PDE-LDDMM (Section 2.3 comparison method) ---------------------------
+    def _pde_field(self, t, stationary, name):
+        shape = (3,) + self.n if stationary else (self.nt + 1, 3) + self.n
+        if t is None:
+            raise ValueError(f"{name} is required")
+        if tuple(t.shape) != shape or t.dtype != self.dtype or t.device != self.device or not t.is_contiguous():
+            raise ValueError(f"{name}: expected contiguous {self.dtype} {shape} on {self.device}, got "
+                             f"{t.dtype} {tuple(t.shape)} on {t.device}")
+        if self.stream is None:
+            torch.cuda.current_stream(self.device).synchronize()
+        return t
+
+    def empty_velocity(self, stationary):
+        shape = (3,) + self.n if stationary else (self.nt + 1, 3) + self.n
+        return torch.empty(shape, dtype=self.dtype, device=self.device)
+
+    def pde_energy(self, v, stationary=True, m1=True):
+        """PDE-LDDMM energy at v (one field, or nt + 1 stacked when not stationary);
+        returns (E, m(1) or None).  Becomes the current PDE linearization."""
+        self._pde_field(v, stationary, "v")
+        out = self.empty_scalar() if m1 else None
+        e = ctypes.c_double()
+        self._check(self.lib.lddmm_pde_energy(self._ctx, int(bool(stationary)), _ptr(v), _ptr(out), ctypes.byref(e)),
+                    "pde_energy")
+        return e.value, out
+
+    def pde_gradient(self, v, stationary=True, out=None):
+        """L2 gradient of PDE-LDDMM at v; returns (g, E)."""
+        self._pde_field(v, stationary, "v")
+        out = self.empty_velocity(stationary) if out is None else self._pde_field(out, stationary, "g")
+        e = ctypes.c_double()
+        self._check(self.lib.lddmm_pde_gradient(self._ctx, int(bool(stationary)), _ptr(v), _ptr(out), ctypes.byref(e)),
+                    "pde_gradient")
+        return out, e.value
+
+    def pde_hessvec(self, dv, stationary=True, v=None, out=None):
+        """Gauss-Newton Hessian of PDE-LDDMM in L2 (v None: the current linearization)."""
+        self._pde_field(dv, stationary, "dv")
+        if v is not None:
+            self._pde_field(v, stationary, "v")
+        out = self.empty_velocity(stationary) if out is None else self._pde_field(out, stationary, "hv")
+        self._check(self.lib.lddmm_pde_hessvec(self._ctx, int(bool(stationary)), _ptr(v), _ptr(dv), _ptr(out)),
+                    "pde_hessvec")
+        return out
+
+    def pde_gn_solve(self, v, stationary=True, gn_iters=10, cg_iters=20, max_halvings=10, c1=1e-4, gtol=1e-3,
+                     eta_max=0.5):
+        """Gauss-Newton-Krylov for PDE-LDDMM from v (updated in place); returns a Trace."""
+        self._pde_field(v, stationary, "v")
+        o = SolveOpts(gn_iters, cg_iters, max_halvings, 0, c1, gtol, eta_max)
+        rep = SolveReport()
+        cap = max(1, gn_iters)
+        logs = (IterLog * cap)()
+        self._check(self.lib.lddmm_pde_gn_solve(self._ctx, int(bool(stationary)), _ptr(v), ctypes.byref(o),
+                                                ctypes.byref(rep), logs, cap), "pde_gn_solve")
         rd = {k: getattr(rep, k) for k, _ in SolveReport._fields_}
         log = [{k: getattr(logs[i], k) for k, _ in IterLog._fields_} for i in range(min(rep.iters, cap))]
         return Trace(rd, log)
