@@ -411,6 +411,40 @@ def precision_bench(args, torch, synth, Registration, spec):
     return line
 
 
+def pde_bench(args, torch, Registration, spec, I0, I1):
+    """PDE-LDDMM (the comparison method of Section 2.3) on the same pair: a
+    Gauss-Newton-Krylov solve from v = 0 with stationary and with non-stationary
+    velocities (nt + 1 fields), FP32, and Gauss-Newton Hessian products/s."""
+    dev = torch.device("cuda:0")
+    R = Registration(spec.n, spec.nt, spec.alpha, spec.s, spec.sigma2, dtype=torch.float32, device=dev)
+    R.set_images(torch.tensor(I0, dtype=torch.float32, device=dev), torch.tensor(I1, dtype=torch.float32, device=dev))
+    R.autotune(reps=3)
+    out = {}
+    for stationary in (True, False):
+        key = "stationary" if stationary else "non_stationary"
+        v = R.empty_velocity(stationary).zero_()
+        R.pde_gn_solve(v, stationary, gn_iters=1, cg_iters=2)  # warm-up
+        v.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        tr = R.pde_gn_solve(v, stationary, gn_iters=spec.gn_iters, cg_iters=spec.cg_iters)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t
+        dv = torch.randn(v.shape, device=dev, generator=torch.Generator(device=dev).manual_seed(11))
+        hv = torch.empty_like(dv)
+        R.pde_hessvec(dv, stationary, v=v, out=hv)
+        ms = time_events(torch, lambda: R.pde_hessvec(dv, stationary, out=hv), 5)
+        rep = tr.report
+        out[key] = {"solves_per_min": round(60.0 / ts, 3), "ms_per_solve": round(1e3 * ts, 1),
+                    "hv_per_s": round(1e3 / ms, 2), "iters": rep["iters"], "cg_total": rep["cg_total"],
+                    "line_search_shoots": rep["shoots"], "mse_rel_final": rep["mse_rel_final"],
+                    "E_final": rep["E_final"], "stop_reason": rep["stop_reason"]}
+        log(f"[bench] PDE-LDDMM {key}: {out[key]}")
+    R.close()
+    return {"workload": f"{spec.name}: the same pair, PDE-LDDMM (velocity over time), FP32, nt={spec.nt}, "
+                        f"GN<={spec.gn_iters}, PCG<={spec.cg_iters} in L2 with preconditioner K", **out}
+
+
 def memory_bench(args, torch, synth, Registration, spec):
     """Trajectory memory policies at 256^3, nt = 32 (FP32): store every step,
     checkpoint every 4 steps, full recompute.  For each: device bytes the
@@ -485,7 +519,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the GN-L2 and gradient-descent solves")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the head-grid, batch16 and 256^3 memory-policy workloads")
+                    help="skip the head-grid, batch16, 256^3 memory-policy and PDE-LDDMM workloads")
     ap.add_argument("--hv-reps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true", help="keep the default transform launch shapes")
     ap.add_argument("--no-graph", action="store_true", help="launch Hessian-vector products kernel by kernel")
@@ -755,6 +789,7 @@ def main():
                                                         synth.WORKLOADS["head180x216x180"])),
             ("batch16", lambda: batch_bench(args, torch, synth, Batch, Registration)),
             ("pair256_memory", lambda: memory_bench(args, torch, synth, Registration, synth.WORKLOADS["pair256"])),
+            ("pair128_pde_lddmm", lambda: pde_bench(args, torch, Registration, spec, I0, I1)),
         ):
             log(f"[bench] extra workload {key}")
             extra[key] = fn()
