@@ -27,12 +27,15 @@ namespace lddmm {
 // plane (BX spans a whole x2 row when N2 <= 256, so x2 halos stay inside the
 // tile).  With XCD-aware mapping the 8 XCDs (which take blocks round-robin)
 // each own a contiguous slab of x1 rows for every x0, so x1 halos and the
-// neighbouring x0 planes a block needs were loaded into the same L2.
+// neighbouring x0 planes a block needs were loaded into the same L2.  XCD x
+// owns tile rows [x TY / 8, (x + 1) TY / 8) (rounded down), so where 8 does not
+// divide TY the slabs differ by one row; the grid then holds 8 slab blocks per
+// (x2 tile, x0 plane) and the blocks past an XCD's own rows do nothing.
 struct FieldTiling {
   int BX, BY;      // block shape (threads)
   int TX, TY;      // tiles along x2 and x1
-  int slab;        // tile rows of x1 per XCD (0: plain linear order)
-  unsigned blocks; // TX * TY * N0
+  int slab;        // most tile rows of x1 one XCD owns (0: plain linear order)
+  unsigned blocks; // TX * N0 * (8 slab, or TY in linear order)
 };
 
 // Host: the tiling of an n0 x n1 x n2 grid (n2 = row length in lanes for the
@@ -45,21 +48,29 @@ inline FieldTiling field_tiling(int n0, int n1, int n2) {
   t.BY = 256 / bx > 0 ? 256 / bx : 1;
   t.TX = (n2 + t.BX - 1) / t.BX;
   t.TY = (n1 + t.BY - 1) / t.BY;
-  t.slab = (t.TY % 8 == 0) ? t.TY / 8 : 0;
-  t.blocks = unsigned(t.TX) * unsigned(t.TY) * unsigned(n0);
+  // XCD-aware order where the largest slab is at most 15 % above the mean
+  // (uneven slabs make the XCDs with one more row finish last)
+  const int s = (t.TY + 7) / 8;
+  t.slab = (t.TY >= 8 && 800 * s <= 115 * t.TY) ? s : 0;
+  t.blocks = unsigned(t.TX) * unsigned(t.slab ? 8 * t.slab : t.TY) * unsigned(n0);
   return t;
 }
 
 // Voxel (i0, i1, i2) of thread (tx, ty) of block b under tiling t; false for the
-// threads of an edge tile that fall outside the grid.
+// threads of an edge tile that fall outside the grid and for every thread of a
+// block past its XCD's own slab.
 LDI_HD bool tile_voxel_at(const FieldTiling& t, int b, int tx, int ty, int n1, int n2, int& i0, int& i1, int& i2) {
   int bx, by;
+  bool own = true;
   if (t.slab) {
     const int x = b & 7, k = b >> 3;
     const int r = k / t.TX;
     bx = k - r * t.TX;
     const int rz = r / t.slab;
-    by = x * t.slab + (r - rz * t.slab);
+    const int ry = r - rz * t.slab;
+    const int lo = (x * t.TY) >> 3, rows = (((x + 1) * t.TY) >> 3) - lo;
+    own = ry < rows;
+    by = lo + ry;
     i0 = rz;
   } else {
     const int r = b / t.TX;
@@ -69,7 +80,7 @@ LDI_HD bool tile_voxel_at(const FieldTiling& t, int b, int tx, int ty, int n1, i
   }
   i2 = bx * t.BX + tx;
   i1 = by * t.BY + ty;
-  return i2 < n2 && i1 < n1;
+  return own && i2 < n2 && i1 < n1;
 }
 
 LDI_HD int periodic_next(int i, int n) { return i + 1 == n ? 0 : i + 1; }

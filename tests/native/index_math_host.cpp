@@ -36,7 +36,12 @@ void expect(bool ok, const char* what, long long a = 0, long long b = 0, long lo
 void check_tiling(int n0, int n1, int n2) {
   const FieldTiling t = field_tiling(n0, n1, n2);
   expect(t.BX % 32 == 0 && t.BX >= 32 && t.BX <= 256 && t.BX * t.BY <= 256, "block shape", t.BX, t.BY);
-  expect(t.blocks == unsigned(t.TX) * unsigned(t.TY) * unsigned(n0), "block count", t.blocks);
+  expect(t.blocks == unsigned(t.TX) * unsigned(t.slab ? 8 * t.slab : t.TY) * unsigned(n0), "block count", t.blocks);
+  if (t.slab) {
+    expect(t.slab == (t.TY + 7) / 8 && 8 * t.slab <= 1.15 * t.TY, "slab balance", t.slab, t.TY);
+  } else {
+    expect(t.TY < 8 || 8 * ((t.TY + 7) / 8) > 1.15 * t.TY, "linear order only where slabs would be uneven", t.TY);
+  }
   std::vector<uint8_t> seen(size_t(n0) * n1 * n2, 0);
   for (unsigned b = 0; b < t.blocks; ++b) {
     for (int ty = 0; ty < t.BY; ++ty)
@@ -49,11 +54,13 @@ void check_tiling(int n0, int n1, int n2) {
         seen.at((size_t(i0) * n1 + i1) * n2 + i2) += 1;
       }
     if (t.slab) {
-      // XCD-aware order: block b runs on XCD b mod 8, which owns x1 tiles
-      // [x slab, (x + 1) slab) of every x0 plane
+      // XCD-aware order: block b runs on XCD x = b mod 8, which owns x1 tiles
+      // [x TY / 8, (x + 1) TY / 8) of every x0 plane
       int i0, i1, i2;
-      tile_voxel_at(t, int(b), 0, 0, n1, n2, i0, i1, i2);
-      expect((i1 / t.BY) / t.slab == int(b & 7), "XCD slab ownership", b, i1);
+      if (tile_voxel_at(t, int(b), 0, 0, n1, n2, i0, i1, i2)) {
+        const int x = int(b & 7), by = i1 / t.BY;
+        expect(by >= x * t.TY / 8 && by < (x + 1) * t.TY / 8, "XCD slab ownership", b, i1);
+      }
     }
   }
   long long once = 0;
@@ -248,6 +255,11 @@ int main() {
                           {4, 216, 180}, {8, 128, 128}, {4, 256, 256}, {128, 128, 128}, {16, 24, 30},
                           {180, 216, 180}, {7, 10, 8},    {4, 80, 80},   {4, 96, 112}};
   for (const auto& n : grids) check_tiling(n[0], n[1], n[2]);
+  // rows of 33 to 64 lanes take 4 x1 rows per block: tile-row counts that 8 divides,
+  // that it does not (uneven slabs, padded grid: 216 / 4 = 54, 100 / 4 = 25) and
+  // where slabs would be too uneven (linear order)
+  for (int n1 : {12, 20, 28, 32, 54, 60, 100, 112, 216, 217})
+    for (int lanes : {40, 45, 54, 56, 64}) check_tiling(3, n1, lanes);
   // row-vectorised launches tile (N0, N1, N2 / VW) lanes
   for (int n1 : {4, 8, 64, 128, 216, 256}) {
     check_tiling(4, n1, 32);

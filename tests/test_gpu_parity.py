@@ -323,12 +323,15 @@ def test_hessvec_parity(n, dtype):
 
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("n", [(10, 6, 64), (8, 12, 128), (6, 8, 256), (6, 7, 128), (6, 8, 180), (8, 6, 80),
-                               (6, 8, 112), (6, 8, 216)])
+                               (6, 8, 112), (6, 8, 216), (6, 8, 96), (6, 7, 96), (6, 8, 192), (6, 60, 180),
+                               (6, 112, 112)])
 def test_row_vectorised_stencils(n, dtype):
     """Every stencil width a row of N2 voxels allows: one voxel per thread
     (stencil.rowvec = 0) and VW = 1, 2, 4 voxels per lane with x2 neighbours
     across lanes (rows of 32 to 64 lanes: N2 = 180 and 216 take 45 and 54 lanes
-    of a wave at VW = 4, N2 = 80 and 112 take 40 and 56 lanes at VW = 2); with
+    of a wave at VW = 4, N2 = 80, 96 and 112 40, 48 and 56 lanes at VW = 2, N2 =
+    192 48 lanes at VW = 4; N1 = 60 and 112 give 15 and 28 tile rows of 4 x1
+    rows, split over the 8 XCDs in slabs of 1 or 2 and 3 or 4 rows); with
     32-lane rows both with and without the x1 row shared by the two halves of a
     wave (N1 odd: the pairing stays off).  Each against the oracle on shooting,
     the gradient and the Hessian-vector product."""
