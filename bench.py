@@ -122,7 +122,7 @@ TUNED_KEYS = (
 )
 KERNEL_SOURCES = {
     "fft": ("paper_1807_04638_amd/csrc/fft.hip", "paper_1807_04638_amd/csrc/fft_core.h"),
-    "stencil": ("paper_1807_04638_amd/csrc/stencil.hip",),
+    "stencil": ("paper_1807_04638_amd/csrc/stencil.hip", "paper_1807_04638_amd/csrc/index_math.h"),
 }
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_pair128_fp32.md")
 

@@ -295,7 +295,7 @@ int lddmm_profile_read(lddmm_ctx* ctx, const char** names, int64_t* counts, doub
  *                                           vector field as three independent per-component
  *                                           chains (their passes may overlap); bitwise the
  *                                           same results.  Chosen by lddmm_autotune
- *   "stencil.rowvec"      0, 1, 2, 4        voxels per lane of the row-vectorised stencil
+ *   "stencil.rowvec"      0, 1, 2, 3, 4     voxels per lane of the row-vectorised stencil
  *                                           kernels (0: one voxel per thread); nonzero
  *                                           values need 32 <= N2 / value <= 64.  Default:
  *                                           the smallest valid width in FP64, the widest

@@ -98,10 +98,10 @@ LDI_HD void row_lanes(int lane, int RW, int& left, int& right) {
   right = base + (pos + 1) % RW;
 }
 
-// Host: a row-vectorised width vw (voxels per lane) is valid when a row of n2
-// voxels is 32 to 64 lanes.
+// Host: a row-vectorised width vw (voxels per lane: 1, 2, 3 or 4) is valid when
+// a row of n2 voxels is 32 to 64 lanes.
 inline bool row_vector_valid(int n2, int vw) {
-  if (vw != 1 && vw != 2 && vw != 4) return false;
+  if (vw < 1 || vw > 4) return false;
   return n2 % vw == 0 && n2 / vw >= 32 && n2 / vw <= 64;
 }
 

@@ -213,7 +213,7 @@ class Engine {
     // where N1 is even), the widths the autotuner keeps on MI355X; other rows
     // take one voxel per thread.  The autotuner times them all.
     g.rowvec = 0;
-    for (int vw : {1, 2, 4})
+    for (int vw : {1, 2, 3, 4})
       if (row_vector_valid(g.n2, vw)) {
         g.rowvec = vw;
         if (sizeof(T) == 8) break;
@@ -853,7 +853,7 @@ class Engine {
       const int start_vw = g.rowvec, start_pair = g.pair_rows;
       int best_vw = start_vw, best_pair = start_pair;
       float best_t = -1.f, start_t = -1.f;
-      for (int vp : {0, 1, 2, 4, 0x11, 0x12, 0x14}) {
+      for (int vp : {0, 1, 2, 3, 4, 0x11, 0x12, 0x13, 0x14}) {
         const int vw = vp & 0xf, pr = vp >> 4;
         if (vw != 0 && !row_vector_valid(g.n2, vw)) continue;
         if (pr && (vw == 0 || g.n2 / vw != 32 || g.n1 % 2 != 0)) continue;  // pairing needs 32-lane rows
@@ -1378,7 +1378,7 @@ class Engine {
       return 0;
     } else if (k == "stencil.rowvec") {
       if (value != 0 && !row_vector_valid(g.n2, int(value)))
-        return fail(LDDMM_EINVAL, "stencil.rowvec: N2 / value must be 32 to 64 with value 1, 2 or 4");
+        return fail(LDDMM_EINVAL, "stencil.rowvec: N2 / value must be 32 to 64 with value 1, 2, 3 or 4");
       (void)hipStreamSynchronize(st);
       g.rowvec = int(value);
       drop_graph();

@@ -474,12 +474,25 @@ __device__ __forceinline__ T vinv2h(const Geo<T>& g, const VNbr<VW>& nb, int e) 
   return (PAIR && e == 1 && nb.upper) ? -g.inv2h[1] : g.inv2h[e];
 }
 
+// Three voxels per lane: a run of three values aligned only to one element (one
+// 12-byte or 24-byte access); widths 1, 2 and 4 use naturally aligned vectors.
+template <typename T, int VW>
+struct alignas(sizeof(T)) VRun {
+  T v[VW];
+};
+
 template <typename T, int VW>
 __device__ __forceinline__ void vld(T out[VW], const T* __restrict__ p) {
-  typedef T vec __attribute__((ext_vector_type(VW)));
-  const vec x = *reinterpret_cast<const vec*>(p);
+  if constexpr (VW == 3) {
+    const VRun<T, 3> x = *reinterpret_cast<const VRun<T, 3>*>(p);
 #pragma unroll
-  for (int k = 0; k < VW; ++k) out[k] = x[k];
+    for (int k = 0; k < 3; ++k) out[k] = x.v[k];
+  } else {
+    typedef T vec __attribute__((ext_vector_type(VW)));
+    const vec x = *reinterpret_cast<const vec*>(p);
+#pragma unroll
+    for (int k = 0; k < VW; ++k) out[k] = x[k];
+  }
 }
 
 template <typename T, int VW>
@@ -490,13 +503,20 @@ __device__ __forceinline__ void vload3(T out[3][VW], const T* __restrict__ f, in
 
 template <typename T, int VW>
 __device__ __forceinline__ void vstore3(T* __restrict__ f, const T in[3][VW], int o, int N) {
-  typedef T vec __attribute__((ext_vector_type(VW)));
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    vec x;
+    if constexpr (VW == 3) {
+      VRun<T, 3> x;
 #pragma unroll
-    for (int k = 0; k < VW; ++k) x[k] = in[c][k];
-    *reinterpret_cast<vec*>(f + c * N + o) = x;
+      for (int k = 0; k < 3; ++k) x.v[k] = in[c][k];
+      *reinterpret_cast<VRun<T, 3>*>(f + c * N + o) = x;
+    } else {
+      typedef T vec __attribute__((ext_vector_type(VW)));
+      vec x;
+#pragma unroll
+      for (int k = 0; k < VW; ++k) x[k] = in[c][k];
+      *reinterpret_cast<vec*>(f + c * N + o) = x;
+    }
   }
 }
 
@@ -839,6 +859,10 @@ Geo<T> make_vgeo(const Grid& g, int VW) {
       LDDMM_ROWVEC_AT(kern, 2, true, __VA_ARGS__);                     \
     else if (VW == 2)                                                  \
       LDDMM_ROWVEC_AT(kern, 2, false, __VA_ARGS__);                    \
+    else if (VW == 3 && gv.pair)                                       \
+      LDDMM_ROWVEC_AT(kern, 3, true, __VA_ARGS__);                     \
+    else if (VW == 3)                                                  \
+      LDDMM_ROWVEC_AT(kern, 3, false, __VA_ARGS__);                    \
     else if (gv.pair)                                                  \
       LDDMM_ROWVEC_AT(kern, 4, true, __VA_ARGS__);                     \
     else                                                               \
@@ -862,6 +886,10 @@ Geo<T> make_vgeo(const Grid& g, int VW) {
       LDDMM_ROWVEC_Z_AT(kern, 2, true, z, __VA_ARGS__);                \
     else if (VW == 2)                                                  \
       LDDMM_ROWVEC_Z_AT(kern, 2, false, z, __VA_ARGS__);               \
+    else if (VW == 3 && gv.pair)                                       \
+      LDDMM_ROWVEC_Z_AT(kern, 3, true, z, __VA_ARGS__);                \
+    else if (VW == 3)                                                  \
+      LDDMM_ROWVEC_Z_AT(kern, 3, false, z, __VA_ARGS__);               \
     else if (gv.pair)                                                  \
       LDDMM_ROWVEC_Z_AT(kern, 4, true, z, __VA_ARGS__);                \
     else                                                               \

@@ -267,13 +267,14 @@ int main() {
     check_pairs(4, n1, 32);
   }
   check_pairs(128, 128, 32);
-  for (int RW : {32, 33, 40, 45, 48, 54, 56, 63, 64})
+  for (int RW : {32, 33, 40, 45, 48, 54, 56, 60, 63, 64})
     for (int n1 : {4, 7, 12, 216}) check_row_lanes(4, n1, RW);
-  for (int n2 : {64, 80, 96, 112, 128, 180, 216, 256}) {
+  for (int n2 : {64, 80, 96, 112, 128, 180, 192, 216, 256}) {
     // the widths the engine may take for a row of n2 voxels
-    for (int vw : {1, 2, 4}) {
+    for (int vw : {0, 1, 2, 3, 4, 5}) {
       const bool ok = row_vector_valid(n2, vw);
-      expect(ok == (n2 % vw == 0 && n2 / vw >= 32 && n2 / vw <= 64), "row width validity", n2, vw);
+      expect(ok == (vw >= 1 && vw <= 4 && n2 % vw == 0 && n2 / vw >= 32 && n2 / vw <= 64), "row width validity",
+             n2, vw);
       if (ok) check_tiling(4, 12, n2 / vw);
     }
   }

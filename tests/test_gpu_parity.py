@@ -327,11 +327,12 @@ def test_hessvec_parity(n, dtype):
                                (6, 112, 112)])
 def test_row_vectorised_stencils(n, dtype):
     """Every stencil width a row of N2 voxels allows: one voxel per thread
-    (stencil.rowvec = 0) and VW = 1, 2, 4 voxels per lane with x2 neighbours
-    across lanes (rows of 32 to 64 lanes: N2 = 180 and 216 take 45 and 54 lanes
-    of a wave at VW = 4, N2 = 80, 96 and 112 40, 48 and 56 lanes at VW = 2, N2 =
-    192 48 lanes at VW = 4; N1 = 60 and 112 give 15 and 28 tile rows of 4 x1
-    rows, split over the 8 XCDs in slabs of 1 or 2 and 3 or 4 rows); with
+    (stencil.rowvec = 0) and VW = 1, 2, 3, 4 voxels per lane with x2 neighbours
+    across lanes (rows of 32 to 64 lanes: N2 = 180 takes 60 lanes at VW = 3 and
+    45 at VW = 4, N2 = 216 54 lanes at VW = 4, N2 = 80 and 112 40 and 56 lanes at
+    VW = 2, N2 = 96 32 lanes at VW = 3 and 48 at VW = 2, N2 = 192 64 and 48 lanes
+    at VW = 3 and 4; N1 = 60 and 112 give 15 and 28 tile rows of 4 x1 rows, split
+    over the 8 XCDs in slabs of 1 or 2 and 3 or 4 rows); with
     32-lane rows both with and without the x1 row shared by the two halves of a
     wave (N1 odd: the pairing stays off).  Each against the oracle on shooting,
     the gradient and the Hessian-vector product."""
@@ -343,7 +344,7 @@ def test_row_vectorised_stencils(n, dtype):
     go, lin = O.gradient(v0, I0, I1, p)
     ho = O.hessvec(dv, lin, p)
     hn = O.hessvec_newton(dv, lin, p)
-    widths = [0] + [vw for vw in (1, 2, 4) if n[2] % vw == 0 and 32 <= n[2] // vw <= 64]
+    widths = [0] + [vw for vw in (1, 2, 3, 4) if n[2] % vw == 0 and 32 <= n[2] // vw <= 64]
     shapes = [(vw, pr) for vw in widths for pr in ((0, 1) if vw and n[2] // vw == 32 else (1,))]
     for rowvec, pair in shapes:
         R, _ = make(n, dtype, sigma2=0.05)
@@ -643,7 +644,7 @@ def test_error_paths():
     bad_opts = SolveOpts(2, 2, 2, 7, 1e-4, 1e-3, 0.5)  # unknown method
     rc = R.lib.lddmm_gn_solve(R._ctx, ctypes.c_void_p(v.data_ptr()), ctypes.byref(bad_opts), None, None, 0)
     assert rc == -1
-    for width in (1, 3):  # N2 = 20: no row-vectorised width; 3 is never one
+    for width in (1, 3, 5):  # N2 = 20: no row-vectorised width; 5 is never one
         with pytest.raises(LddmmError) as e:
             R.set_option("stencil.rowvec", width)
         assert e.value.status == -1
