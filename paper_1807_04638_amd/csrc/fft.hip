@@ -52,6 +52,7 @@ __device__ void lds_fft(cplx<T>* buf, const FftPlan& pl, int count, int es, int 
       LDDMM_FFT_STAGE(3)
       LDDMM_FFT_STAGE(5)
       LDDMM_FFT_STAGE(7)
+      LDDMM_FFT_STAGE(9)
       default:
         break;
     }

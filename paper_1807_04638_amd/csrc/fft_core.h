@@ -1,4 +1,4 @@
-// fft_core.h - mixed-radix in-place FFT building blocks (radix 2, 3, 4, 5, 7, 8).
+// fft_core.h - mixed-radix in-place FFT building blocks (radix 2, 3, 4, 5, 7, 8, 9, 16).
 //
 // The spectral operators L = (Id - alpha Laplacian)^s and K = L^-1 (Section 2.1
 // of the paper) are applied as forward FFT -> real symbol -> inverse FFT.  Since
@@ -203,6 +203,42 @@ struct Dft<T, 16, DIR> {
   }
 };
 
+// 9 = 3 x 3: DFT3 over the three stride-3 groups, twiddles W9^(n2 k1), DFT3 over
+// the groups again (Cooley-Tukey; W = exp(DIR 2 pi i / 9)).
+template <typename T, int DIR>
+struct Dft<T, 9, DIR> {
+  // x * (re + DIR im i) for the constant root (re, im)
+  static LD_HD cplx<T> rot(cplx<T> x, T re, T im) {
+    const T si = T(DIR) * im;
+    return {x.x * re - x.y * si, x.x * si + x.y * re};
+  }
+  static LD_HD void run(cplx<T>* a) {
+    // cos and sin of 2 pi m / 9 for m = 1, 2, 4
+    const T c1 = T(0.76604444311897803520), s1 = T(0.64278760968653932632);
+    const T c2 = T(0.17364817766693034885), s2 = T(0.98480775301220805937);
+    const T c4 = T(-0.93969262078590838405), s4 = T(0.34202014332566873304);
+    cplx<T> y[3][3];
+#pragma unroll
+    for (int n2 = 0; n2 < 3; ++n2) {
+      cplx<T> g[3] = {a[n2], a[3 + n2], a[6 + n2]};
+      Dft<T, 3, DIR>::run(g);
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) y[n2][k1] = g[k1];
+    }
+    y[1][1] = rot(y[1][1], c1, s1);  // W^1
+    y[1][2] = rot(y[1][2], c2, s2);  // W^2
+    y[2][1] = rot(y[2][1], c2, s2);  // W^2
+    y[2][2] = rot(y[2][2], c4, s4);  // W^4
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      cplx<T> h[3] = {y[0][k1], y[1][k1], y[2][k1]};
+      Dft<T, 3, DIR>::run(h);
+#pragma unroll
+      for (int k2 = 0; k2 < 3; ++k2) a[k1 + 3 * k2] = h[k2];
+    }
+  }
+};
+
 // Twiddle powers w[q] = W^(j q), q = 1..R-1, from one table read W^j (the
 // rest by complex products in registers: fewer LDS reads, a few ulp of error).
 template <typename T, int R>
@@ -296,16 +332,18 @@ LD_HD int stage_length(const FftPlan& pl, int st) {
 }
 
 // Factor n into radices, largest power-of-two radices first (8s, then one 4 or
-// 2), then 3, 5, 7; with at least two 8s a trailing 8 x 2 becomes 16 and a
-// trailing 8 x 8 x 4 becomes 16 x 16 (one stage fewer).  False if another prime
-// divides n.
+// 2), then a single 3 where 3 divides n an odd number of times, 5s, 7s, and the
+// 3 x 3 pairs as radix 9 last (the stride-1 last stage takes no twiddles, so the
+// largest odd radix goes there); with at least two 8s a trailing 8 x 2 becomes
+// 16 and a trailing 8 x 8 x 4 becomes 16 x 16 (one stage fewer).  False if
+// another prime divides n (or 3, 5, 7 more than 8, 5, 4 times).
 inline bool make_plan(int n, FftPlan& pl) {
   pl.n = n;
   pl.nf = 0;
   for (int i = 0; i < kMaxFactors; ++i) pl.radix[i] = 0;
   if (n < 1) return false;
   int m = n;
-  const int order[] = {8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 4, 2, 3, 3, 3, 3, 3, 3, 3, 3, 5, 5, 5, 5, 5, 7, 7, 7, 7};
+  const int order[] = {8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 4, 2};
   for (int r : order) {
     if (m % r != 0) continue;
     if (r == 2 && m % 4 == 0) continue;
@@ -313,7 +351,16 @@ inline bool make_plan(int n, FftPlan& pl) {
     pl.radix[pl.nf++] = r;
     m /= r;
   }
+  int c3 = 0, c5 = 0, c7 = 0;
+  while (c3 < 8 && m % 3 == 0) ++c3, m /= 3;
+  while (c5 < 5 && m % 5 == 0) ++c5, m /= 5;
+  while (c7 < 4 && m % 7 == 0) ++c7, m /= 7;
   if (m != 1) return false;
+  if (pl.nf + (c3 % 2) + c5 + c7 + c3 / 2 > kMaxFactors) return false;
+  if (c3 % 2) pl.radix[pl.nf++] = 3;
+  for (int i = 0; i < c5; ++i) pl.radix[pl.nf++] = 5;
+  for (int i = 0; i < c7; ++i) pl.radix[pl.nf++] = 7;
+  for (int i = 0; i < c3 / 2; ++i) pl.radix[pl.nf++] = 9;
   int n8 = 0;
   while (n8 < pl.nf && pl.radix[n8] == 8) ++n8;
   const int rest = n8 < pl.nf ? pl.radix[n8] : 1;
@@ -388,12 +435,12 @@ LDDMM_PLAN(40, 8, 5)
 LDDMM_PLAN(48, 8, 2, 3)
 LDDMM_PLAN(56, 8, 7)
 LDDMM_PLAN(80, 8, 2, 5)
-LDDMM_PLAN(90, 2, 3, 3, 5)
+LDDMM_PLAN(90, 2, 5, 9)
 LDDMM_PLAN(96, 8, 4, 3)
-LDDMM_PLAN(108, 4, 3, 3, 3)
+LDDMM_PLAN(108, 4, 3, 9)
 LDDMM_PLAN(112, 8, 2, 7)
-LDDMM_PLAN(180, 4, 3, 3, 5)
-LDDMM_PLAN(216, 8, 3, 3, 3)
+LDDMM_PLAN(180, 4, 5, 9)
+LDDMM_PLAN(216, 8, 3, 9)
 #undef LDDMM_PLAN
 
 // Slot (DIF output position) that holds frequency k: the inverse of

@@ -211,6 +211,7 @@ void run_stages(cplx<double>* buf, const FftPlan& pl, const cplx<double>* tw) {
         case 3: fft_stage_item<double, 3, INV, false>(buf, b, n, L, 1, 1, n, tw); break;
         case 5: fft_stage_item<double, 5, INV, false>(buf, b, n, L, 1, 1, n, tw); break;
         case 7: fft_stage_item<double, 7, INV, false>(buf, b, n, L, 1, 1, n, tw); break;
+        case 9: fft_stage_item<double, 9, INV, false>(buf, b, n, L, 1, 1, n, tw); break;
         default: expect(false, "radix", r); break;
       }
     }
