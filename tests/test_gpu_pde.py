@@ -113,3 +113,85 @@ def test_pde_hessvec_needs_a_linearization():
         R.pde_hessvec(R.empty_velocity(False).zero_(), False)
     assert e.value.status == -6
     R.close()
+
+
+# ------------------------------------------------------------------ full size (128^3, nt = 10)
+def _pair128():
+    import synth
+
+    spec = synth.WORKLOADS["pair128"]
+    n = spec.n
+    p = O.Params(n, spec.alpha, spec.s, spec.nt, spec.sigma2)
+    I0 = synth.phantom(n, spec.n_blobs, spec.sigma_range, spec.classes, 1000)
+    I1 = synth.phantom(n, spec.n_blobs, spec.sigma_range, spec.classes, 1001)
+    return spec, p, I0, I1
+
+
+@pytest.fixture(scope="module")
+def full_stationary():
+    """The oracle's energy, m(1), L2 gradient and Gauss-Newton product at the
+    bench's PDE-LDDMM size (128^3, nt = 10), stationary velocity."""
+    import time
+
+    spec, p, I0, I1 = _pair128()
+    v = random_velocity(spec.n, 2000, 3.0)
+    dv = random_field(spec.n, 5, kc=4.0)
+    t = time.perf_counter()
+    g, lin = PL.gradient(v, I0, I1, p, True)
+    h = PL.hessvec(dv, lin, p)
+    say(f"[oracle] PDE-LDDMM 128^3 stationary gradient + Hv in {time.perf_counter() - t:.1f} s")
+    return spec, I0, I1, v, dv, lin.E, lin.m[-1], g, h
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_pde_full_size_stationary_vs_oracle(full_stationary, dtype):
+    """128^3, nt = 10 in the bench's launch configuration (autotuned): energy,
+    m(1), gradient and Gauss-Newton product against the FP64 oracle."""
+    from paper_1807_04638_amd import Registration
+
+    spec, I0, I1, v, dv, E, m1, g, h = full_stationary
+    say(f"[case] PDE-LDDMM 128^3 stationary {dtype}")
+    R = Registration(spec.n, spec.nt, spec.alpha, spec.s, spec.sigma2, dtype=dtype)
+    R.set_images(T(I0, dtype), T(I1, dtype))
+    R.autotune(reps=2)
+    Eg, mg = R.pde_energy(T(v, dtype), True)
+    gg, _ = R.pde_gradient(T(v, dtype), True)
+    hg = R.pde_hessvec(T(dv, dtype), True)
+    errs = dict(energy=abs(Eg - E) / abs(E), m1=rel(mg, m1), gradient=rel(gg, g), hessvec=rel(hg, h))
+    say("  rel vs oracle:", {k: f"{e:.2e}" for k, e in errs.items()})
+    tol = TOL[dtype]
+    assert errs["energy"] <= tol["shoot"] and errs["m1"] <= tol["shoot"]
+    assert errs["gradient"] <= tol["grad"] and errs["hessvec"] <= tol["hv"]
+    R.close()
+
+
+def test_pde_full_size_non_stationary_energy_and_precision():
+    """128^3, nt = 10, non-stationary: the energy and m(1) against the FP64
+    oracle in both precisions, and the FP32 gradient and Gauss-Newton product
+    against the FP64 path's (the oracle's would take minutes on the host)."""
+    from paper_1807_04638_amd import Registration
+
+    spec, p, I0, I1 = _pair128()
+    nt = spec.nt
+    v = np.stack([(1.0 + 0.4 * k / nt) * random_velocity(spec.n, 2000, 3.0) for k in range(nt + 1)])
+    dv = np.stack([random_field(spec.n, 40 + k, kc=4.0) for k in range(nt + 1)])
+    m = PL.state(PL.velocities(v, p, False), I0, p)
+    Eo = PL.energy(v, I0, I1, p, False, m=m)
+    out = {}
+    for dtype in (torch.float64, torch.float32):
+        say(f"[case] PDE-LDDMM 128^3 non-stationary {dtype}")
+        R = Registration(spec.n, nt, spec.alpha, spec.s, spec.sigma2, dtype=dtype)
+        R.set_images(T(I0, dtype), T(I1, dtype))
+        R.autotune(reps=2)
+        E, m1 = R.pde_energy(T(v, dtype), False)
+        g, _ = R.pde_gradient(T(v, dtype), False)
+        hv = R.pde_hessvec(T(dv, dtype), False)
+        errs = dict(energy=abs(E - Eo) / abs(Eo), m1=rel(m1, m[-1]))
+        say("  rel vs oracle:", {k: f"{e:.2e}" for k, e in errs.items()})
+        assert errs["energy"] <= TOL[dtype]["shoot"] and errs["m1"] <= TOL[dtype]["shoot"]
+        out[dtype] = (g.double().cpu().numpy(), hv.double().cpu().numpy())
+        R.close()
+    eg = rel(out[torch.float32][0], out[torch.float64][0])
+    eh = rel(out[torch.float32][1], out[torch.float64][1])
+    say(f"  FP32 vs FP64 path: gradient {eg:.2e}, Hv {eh:.2e}")
+    assert eg <= TOL[torch.float32]["grad"] and eh <= TOL[torch.float32]["hv"]
