@@ -445,6 +445,75 @@ def pde_bench(args, torch, Registration, spec, I0, I1):
                         f"GN<={spec.gn_iters}, PCG<={spec.cg_iters} in L2 with preconditioner K", **out}
 
 
+def table1_bench(args, torch, synth, Registration, spec, pairs=15):
+    """Table-1-shaped report on seeded synthetic pairs of the pair128 recipe (the
+    paper registers 15 NIREP pairs; these stand in for them): for every method
+    the paper compares (gradient descent in V, stationary and non-stationary
+    PDE-LDDMM, Gauss-Newton in V and in L2) and the Newton-Krylov variant, mean
+    and standard deviation over the pairs of the final MSE_rel (percent), the
+    final infinity-norm gradient relative to the one at v = 0 (each solver's own
+    norm: V for the V methods, L2 for the L2 and PDE ones), the extrema of
+    det(I + D u1) of the inverse map, the Krylov iterations and the outer
+    iterations, with the time per solve.  FP32 fields, the bench's launch shape."""
+    import numpy as np
+
+    dev = torch.device("cuda:0")
+    n = spec.n
+    R64 = Registration(n, spec.nt, spec.alpha, spec.s, spec.sigma2, dtype=torch.float64, device=dev)
+    R = Registration(n, spec.nt, spec.alpha, spec.s, spec.sigma2, dtype=torch.float32, device=dev)
+    methods = ("gd", "pde_stationary", "pde_non_stationary", "gn_v", "gn_l2", "newton")
+    rows = {m: [] for m in methods}
+    tuned = False
+    for i in range(pairs):
+        I0 = synth.phantom(n, spec.n_blobs, spec.sigma_range, spec.classes, 1000 + i, shells=spec.shells)
+        t0 = torch.tensor(I0, dtype=torch.float64, device=dev)
+        R64.set_images(t0, t0)
+        J1 = R64.shoot(torch.tensor(synth.random_velocity(n, 2000 + i, spec.disp_vox), dtype=torch.float64,
+                                    device=dev), want=("J1",))["J1"]
+        I1 = J1 + torch.tensor(synth.noise(n, 3000 + i, spec.noise_sd), dtype=torch.float64, device=dev)
+        R.set_images(t0.float(), I1.float())
+        if not tuned:
+            R.autotune(reps=3)
+            R.set_option("exec.graph", 1)
+            tuned = True
+        zero = torch.zeros((3,) + n, dtype=torch.float32, device=dev)
+        g0v, _ = R.gradient(zero)
+        g0 = {"v": g0v.abs().max().item(), "l2": R.apply_L(g0v).abs().max().item()}
+        for m in methods:
+            pde = m.startswith("pde")
+            st = m == "pde_stationary"
+            v = R.empty_velocity(st).zero_() if pde else zero.clone()
+            if pde:
+                g0p = R.pde_gradient(v, st)[0].abs().max().item()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            tr = R.pde_gn_solve(v, st) if pde else R.gn_solve(v, method=m)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t)
+            if pde:
+                ginf = R.pde_gradient(v, st)[0].abs().max().item() / g0p
+                u1 = R.pde_displacement(v, st)
+            else:
+                g, _ = R.gradient(v)
+                ginf = (R.apply_L(g).abs().max().item() / g0["l2"]) if m == "gn_l2" else g.abs().max().item() / g0["v"]
+                u1 = R.shoot(v, want=("u1",))["u1"]
+            _, dmin, dmax = R.jacobian_det(u1)
+            rep = tr.report
+            rows[m].append([rep["mse_rel_final"], ginf, dmin, dmax, rep["cg_total"], rep["iters"], ms])
+        log(f"[bench] table1 pair {i + 1}/{pairs}: " + ", ".join(f"{m} {rows[m][-1][0]:.2f}%" for m in methods))
+    R.close()
+    R64.close()
+    cols = ("mse_rel", "g_inf_rel", "det_min", "det_max", "krylov_iters", "outer_iters", "ms_per_solve")
+    out = {}
+    for m in methods:
+        a = np.asarray(rows[m], dtype=np.float64)
+        out[m] = {c: {"mean": round(float(a[:, k].mean()), 5), "sd": round(float(a[:, k].std(ddof=1)), 5)}
+                  for k, c in enumerate(cols)}
+    return {"workload": f"{spec.name} recipe, {pairs} seeded pairs (template 1000+i, v0 2000+i, noise 3000+i), FP32, "
+                        f"nt={spec.nt}; GD <= 50 iterations, GN/Newton <= 10, Krylov <= 20",
+            "columns": list(cols), "methods": out}
+
+
 def memory_bench(args, torch, synth, Registration, spec):
     """Trajectory memory policies at 256^3, nt = 32 (FP32): store every step,
     checkpoint every 4 steps, full recompute.  For each: device bytes the
@@ -559,10 +628,13 @@ def main():
     if args.workload == "batch16":
         print(json.dumps(batch_bench(args, torch, synth, Batch, Registration)), flush=True)
         return
-    spec = synth.WORKLOADS[args.workload]
     # everything runs on a dedicated stream so the contexts can replay graphs
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.set_stream(stream)
+    if args.workload == "table1":
+        print(json.dumps(table1_bench(args, torch, synth, Registration, synth.WORKLOADS["pair128"])), flush=True)
+        return
+    spec = synth.WORKLOADS[args.workload]
     if args.workload == "head180x216x180":
         print(json.dumps(precision_bench(args, torch, synth, Registration, spec)), flush=True)
         return
@@ -790,6 +862,7 @@ def main():
             ("batch16", lambda: batch_bench(args, torch, synth, Batch, Registration)),
             ("pair256_memory", lambda: memory_bench(args, torch, synth, Registration, synth.WORKLOADS["pair256"])),
             ("pair128_pde_lddmm", lambda: pde_bench(args, torch, Registration, spec, I0, I1)),
+            ("table1_pair128x15", lambda: table1_bench(args, torch, synth, Registration, spec)),
         ):
             log(f"[bench] extra workload {key}")
             extra[key] = fn()

@@ -242,6 +242,14 @@ int lddmm_pde_hessvec(lddmm_ctx* ctx, int stationary, const void* v, const void*
  * ignored.  Report and log as for lddmm_gn_solve (L2 norms). */
 int lddmm_pde_gn_solve(lddmm_ctx* ctx, int stationary, void* v_inout, const lddmm_solve_opts* opts,
                        lddmm_solve_report* report, lddmm_iter_log* log, int log_cap);
+/* Inverse-map displacement u1 (vector field, caller-owned) of the PDE-LDDMM flow
+ * of v: u_0 = 0, u_{n+1}(x) = u_n(X_n) + X_n - x with the Heun foot X_n of the
+ * state equation (Section 2.3), so that the warped template is I_0 o (id + u1);
+ * det(I + D u1) (lddmm_jacobian_det) gives the Jacobian extrema reported for
+ * every method in Table 1.  Needs no images; does not change the PDE
+ * linearization.  LDDMM_EINVAL for NULL pointers, LDDMM_ENONFINITE for a
+ * non-finite v. */
+int lddmm_pde_displacement(lddmm_ctx* ctx, int stationary, const void* v, void* u1);
 
 /* Jacobian determinant det(I + D_h u) (central differences) of a displacement u
  * (vector field) into det (scalar field), plus its extrema (either may be NULL;

@@ -97,6 +97,19 @@ def state(vs, I0, p):
     return m
 
 
+def displacement(vs, p):
+    """Inverse-map displacement of the PDE-LDDMM flow: u_0 = 0,
+    u_{n+1}(x) = u_n(X_n(x)) + (X_n(x) - x) with the Heun foot X_n of M3, so that
+    the deformed template is I_0 o (id + u_1); det(I + D u_1) gives the Jacobian
+    extrema the paper reports for every method (Table 1)."""
+    x = O.grid_coords(p)
+    u = np.zeros((3,) + tuple(p.n))
+    for n in range(p.nt):
+        X = backtrace(vs[n], vs[n + 1], p, x)
+        u = O.interp(u, X, p) + (X - x)
+    return u
+
+
 def adjoint(vs, lam1, p):
     """lambda_nt = lam1, backward by M4 (eq. FirstOrder2); returns [lambda_0 .. lambda_nt]."""
     x = O.grid_coords(p)

@@ -1712,6 +1712,19 @@ class Engine {
     return hip_status("pde_gn_solve");
   }
 
+  // inverse-map displacement of the PDE-LDDMM flow: ping-pong between u1 and
+  // pacc so that the last step writes u1
+  int pde_displacement(bool stationary, const T* v, T* u1) {
+    if (int rc = ensure_pde()) return rc;
+    if (int rc = check_finite(v, (long long)pde_slices(stationary) * 3 * N, "v")) return rc;
+    T* buf[2] = {P.nt % 2 == 0 ? u1 : pacc, P.nt % 2 == 0 ? pacc : u1};
+    launch_fill<T>(3 * N, T(0), buf[0], st, &prof);
+    for (int n = 0; n < P.nt; ++n)
+      launch_sl_step<T>(g, buf[n & 1], slice(v, n, stationary), slice(v, n + 1, stationary), buf[(n + 1) & 1], dt,
+                        st, &prof);
+    return hip_status("pde_displacement");
+  }
+
   int jacobian(const T* uin, T* det, double* mn, double* mx) {
     T* out = det ? det : tmpS;
     launch_jacobian_det<T>(g, uin, out, st, &prof);
@@ -1878,6 +1891,11 @@ int lddmm_pde_gn_solve(lddmm_ctx* ctx, int stationary, void* v_inout, const lddm
                        lddmm_solve_report* report, lddmm_iter_log* log, int log_cap) {
   if (!v_inout || log_cap < 0) return LDDMM_EINVAL;
   LDDMM_DISPATCH(ctx, E.pde_gn_solve(stationary != 0, static_cast<T*>(v_inout), opts, report, log, log_cap));
+}
+
+int lddmm_pde_displacement(lddmm_ctx* ctx, int stationary, const void* v, void* u1) {
+  if (!v || !u1) return LDDMM_EINVAL;
+  LDDMM_DISPATCH(ctx, E.pde_displacement(stationary != 0, static_cast<const T*>(v), static_cast<T*>(u1)));
 }
 
 int lddmm_jacobian_det(lddmm_ctx* ctx, const void* u, void* det, double* det_min, double* det_max) {

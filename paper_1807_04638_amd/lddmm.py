@@ -114,6 +114,7 @@ SIGNATURES = {
         [_vp, ctypes.c_int, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveReport), ctypes.POINTER(IterLog),
          ctypes.c_int],
     ),
+    "lddmm_pde_displacement": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
     "lddmm_jacobian_det": (ctypes.c_int, [_vp, _vp, _vp, _c_double_p, _c_double_p]),
     "lddmm_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lddmm_profile_read": (
@@ -450,6 +451,15 @@ class Registration:
         rd = {k: getattr(rep, k) for k, _ in SolveReport._fields_}
         log = [{k: getattr(logs[i], k) for k, _ in IterLog._fields_} for i in range(min(rep.iters, cap))]
         return Trace(rd, log)
+
+    def pde_displacement(self, v, stationary=True, out=None):
+        """Inverse-map displacement u1 of the PDE-LDDMM flow of v (warped template
+        I_0 o (id + u1)); feed it to jacobian_det for det(I + D u1)."""
+        self._pde_field(v, stationary, "v")
+        out = self.empty_vector() if out is None else self._field(out, 3, "u1")
+        self._check(self.lib.lddmm_pde_displacement(self._ctx, int(bool(stationary)), _ptr(v), _ptr(out)),
+                    "pde_displacement")
+        return out
 
     def jacobian_det(self, u, out=None):
         out = self.empty_scalar() if out is None else self._field(out, 1, "det")

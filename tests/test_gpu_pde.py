@@ -60,12 +60,17 @@ def test_pde_operators_match_oracle(n, dtype, stationary):
     E, m1 = R.pde_energy(T(v, dtype), stationary)
     g, Eg = R.pde_gradient(T(v, dtype), stationary)
     hv = R.pde_hessvec(T(dv, dtype), stationary)
+    u1 = R.pde_displacement(T(v, dtype), stationary)
+    hv2 = R.pde_hessvec(T(dv, dtype), stationary)  # the displacement leaves the linearization alone
     go, lin = PL.gradient(v, I0, I1, p, stationary)
     ho = PL.hessvec(dv, lin, p)
-    errs = dict(energy=abs(E - lin.E) / abs(lin.E), m1=rel(m1, lin.m[-1]), gradient=rel(g, go), hessvec=rel(hv, ho))
+    uo = PL.displacement(PL.velocities(v, p, stationary), p)
+    assert torch.equal(hv, hv2)
+    errs = dict(energy=abs(E - lin.E) / abs(lin.E), m1=rel(m1, lin.m[-1]), gradient=rel(g, go), hessvec=rel(hv, ho),
+                u1=rel(u1, uo))
     say("  rel vs oracle:", {k: f"{e:.2e}" for k, e in errs.items()})
     tol = TOL[dtype]
-    assert errs["energy"] <= tol["shoot"] and errs["m1"] <= tol["shoot"]
+    assert errs["energy"] <= tol["shoot"] and errs["m1"] <= tol["shoot"] and errs["u1"] <= tol["shoot"]
     assert errs["gradient"] <= tol["grad"] and errs["hessvec"] <= tol["hv"]
     assert Eg == pytest.approx(E, rel=1e-12)
     R.close()

@@ -89,6 +89,9 @@ def test_constant_velocity_translates_state_and_adjoint():
     lam1 = phantom(n, 3, (1.0, 2.0), False, 1003)
     lam = PL.adjoint(vs, lam1, p)
     np.testing.assert_allclose(lam[0], np.roll(lam1, (-p.nt, 2 * p.nt, -p.nt), axis=(0, 1, 2)), atol=1e-13)
+    # the inverse map of a translation by c over unit time is x - c
+    u = PL.displacement(vs, p)
+    np.testing.assert_allclose(u, np.broadcast_to(-c[:, None, None, None], u.shape), atol=1e-13)
 
 
 def _flow(y, t):
@@ -133,6 +136,60 @@ def _adjoint_1d_error(nt, N=4096):
     lam = PL.adjoint(vs, lam1(x[2]), p)
     line = np.arange(N) * p.h[2]
     return np.abs(lam[0][0, 0, :] - _exact_adjoint_1d(lam1, line)).max()
+
+
+def _exact_foot_1d(x1, steps=400):
+    """Foot at t = 0 of the characteristic dy/dt = f(y, t) through x1 at t = 1 (RK4 backward)."""
+    y = x1.copy()
+    h = 1.0 / steps
+    t = 1.0
+    for _ in range(steps):
+        k1 = _flow(y, t)
+        k2 = _flow(y - 0.5 * h * k1, t - 0.5 * h)
+        k3 = _flow(y - 0.5 * h * k2, t - 0.5 * h)
+        k4 = _flow(y - h * k3, t - h)
+        y = y - h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+        t -= h
+    return y
+
+
+def _displacement_1d_error(nt, N=4096):
+    n = (4, 4, N)
+    p = P(n, nt=nt)
+    x = O.grid_coords(p)
+    vs = []
+    for k in range(nt + 1):
+        v = np.zeros((3,) + n)
+        v[2] = _flow(x[2], k / nt)
+        vs.append(v)
+    u = PL.displacement(vs, p)
+    line = np.arange(N) * p.h[2]
+    return np.abs(u[2, 0, 0, :] - (_exact_foot_1d(line) - line)).max(), np.abs(u[:2]).max()
+
+
+def test_displacement_is_the_inverse_flow_map():
+    """The inverse-map displacement of a 1D flow that varies in space and time:
+    u_1(x) converges to (foot of the exact characteristic through x) - x at second
+    order in dt; the components across the flow stay zero."""
+    res = [_displacement_1d_error(nt) for nt in (8, 16, 32)]
+    errs = [e for e, _ in res]
+    r = [errs[k] / errs[k + 1] for k in range(2)]
+    assert errs[0] < 0.05 and all(3.3 <= q <= 4.7 for q in r), (errs, r)
+    assert all(z == 0.0 for _, z in res)
+
+
+def test_displacement_warps_the_template_like_the_state():
+    """I_0 o (id + u_1) and the transported image m(1) are two discretisations of
+    the same deformed template: their gap shrinks as the grid is refined."""
+    gaps = []
+    for N in (32, 64):  # at 16^3 the two first-order errors still partly cancel
+        p, I0, _, v, _ = smooth_case(N, stationary=False)
+        vs = PL.velocities(v, p, False)
+        m1 = PL.state(vs, I0, p)[-1]
+        u = PL.displacement(vs, p)
+        warped = O.interp(I0, O.grid_coords(p) + u, p)
+        gaps.append(np.linalg.norm(warped - m1) / np.linalg.norm(m1 - I0))
+    assert gaps[0] < 0.2 and gaps[1] <= gaps[0] / 1.5, gaps
 
 
 def test_adjoint_transport_of_a_compressible_flow():
@@ -263,14 +320,27 @@ def test_planted_mistakes(monkeypatch):
         L = (lambda f: O.apply_L(f, p)) if stationary else (lambda f: np.stack([O.apply_L(f[k], p) for k in range(p.nt + 1)]))
         return g - L(lin.v), lin
 
+    orig_displacement = M.displacement
+
+    def displacement_forward(vs, p):  # foot traced forward along the flow instead of backward
+        x = O.grid_coords(p)
+        u = np.zeros((3,) + tuple(p.n))
+        for n in range(p.nt):
+            X = M.forward_trace(vs[n], vs[n + 1], p, x)
+            u = O.interp(u, X, p) + (X - x)
+        return u
+
     cases = [
+        ("displacement", displacement_forward, [test_displacement_is_the_inverse_flow_map,
+                                                test_constant_velocity_translates_state_and_adjoint]),
         ("adjoint", adjoint_no_divergence, [test_adjoint_transport_of_a_compressible_flow]),
         ("adjoint", adjoint_backtrace, [test_adjoint_transport_of_a_compressible_flow,
                                         test_constant_velocity_translates_state_and_adjoint]),
         ("weights", weights_rectangle, [lambda: test_zero_velocity_closed_forms(False)]),
         ("gradient", gradient_half_regulariser, [lambda: test_regularisation_gradient_exact(True)]),
     ]
-    originals = {"adjoint": orig_adjoint, "weights": orig_weights, "gradient": orig_gradient}
+    originals = {"adjoint": orig_adjoint, "weights": orig_weights, "gradient": orig_gradient,
+                 "displacement": orig_displacement}
     for name, bad, checks in cases:
         monkeypatch.setattr(M, name, bad)
         monkeypatch.setattr(PL, name, bad)
