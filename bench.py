@@ -191,6 +191,22 @@ def time_events(torch, fn, reps):
     return start.elapsed_time(stop) / reps  # ms
 
 
+def median_events(torch, fn, reps, warmup=3):
+    """Median over `reps` calls of fn, each bracketed by its own pair of events on
+    the current stream, after `warmup` untimed calls (ms)."""
+    for _ in range(warmup):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    t = sorted(a.elapsed_time(b) for a, b in ev)
+    return t[len(t) // 2] if len(t) % 2 else 0.5 * (t[len(t) // 2 - 1] + t[len(t) // 2])
+
+
 def cpu_baseline(spec, I0, I1, v0t, rep):
     """Time the FP64 oracle on the host on a bounded sample of the workload: one
     linearization (shoot with trajectory store, SL transport, final conditions),
@@ -715,9 +731,10 @@ def main():
     g = torch.empty_like(dv)
     R.linearize(vlin)
     R.hessvec(dv, out=hv)
-    hv_ms = time_events(torch, lambda: R.hessvec(dv, out=hv), args.hv_reps)
-    grad_ms = time_events(torch, lambda: R.gradient(vlin, out=g), 5)
-    shoot_ms = time_events(torch, lambda: R.shoot(vlin, want=("J1",)), 5)
+    # medians of single calls after 3 untimed ones: >= 20 Hessian-vector products, 5 gradients, 5 shoots
+    hv_ms = median_events(torch, lambda: R.hessvec(dv, out=hv), max(20, args.hv_reps))
+    grad_ms = median_events(torch, lambda: R.gradient(vlin, out=g), 5)
+    shoot_ms = median_events(torch, lambda: R.shoot(vlin, want=("J1",)), 5)
     log(f"[bench] hessvec {hv_ms:.3f} ms, gradient {grad_ms:.3f} ms, shoot {shoot_ms:.3f} ms")
 
     # per-kernel HIP-event timing over Hessian-vector products -> roofline
