@@ -1541,15 +1541,11 @@ class Engine {
         launch_pde_lambda_grad<T>(g, pm[n], lam, pde_w(n), pacc, st, &prof);
       } else {
         T* o = slice(out, n, false);
-        applyL(slice(base, n, false), o);
-        launch_axpby<T>(V, 0.0, o, 2.0, o, st, &prof);
+        spectral(slice(base, n, false), o, 3, LDDMM_OP_L, nullptr, 0.0, 2.0);  // 2 L base_n
         launch_pde_lambda_grad<T>(g, pm[n], lam, 1.0, o, st, &prof);
       }
     }
-    if (stationary) {
-      applyL(base, out);
-      launch_axpby<T>(V, 1.0, pacc, 2.0, out, st, &prof);
-    }
+    if (stationary) spectral(base, out, 3, LDDMM_OP_L, pacc, 2.0);  // pacc + 2 L base
   }
   int pde_check(bool stationary) {
     if (!have_images) return fail(LDDMM_ESTATE, "images not set");
