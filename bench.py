@@ -882,8 +882,12 @@ def main():
             ("table1_pair128x15", lambda: table1_bench(args, torch, synth, Registration, spec)),
         ):
             log(f"[bench] extra workload {key}")
-            extra[key] = fn()
-            torch.cuda.synchronize()
+            try:
+                extra[key] = fn()
+                torch.cuda.synchronize()
+            except Exception as e:  # an extra workload never costs the headline line
+                log(f"[bench] extra workload {key} failed: {type(e).__name__}: {e}")
+                extra[key] = {"error": f"{type(e).__name__}: {e}"}
             torch.cuda.empty_cache()
 
     cpu = None
