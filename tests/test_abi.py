@@ -106,6 +106,9 @@ def _create(lib, n=(32, 32, 32), nt=10, s=2, alpha=0.01, sigma2=1.0, dtype=0):
         (dict(n=(11, 32, 32)), -2),  # prime factor 11
         (dict(n=(32, 32, 33)), -2),  # odd N2
         (dict(n=(2, 32, 32)), -2),  # below the minimum size
+        (dict(n=(0, 32, 32)), -2),  # empty grid
+        (dict(n=(32, -8, 32)), -2),  # negative extent
+        (dict(n=(1024, 1024, 1024)), -2),  # 3 N beyond a 32-bit index
         (dict(n=(32, 26, 32)), -2),  # 26 = 2 * 13
         (dict(nt=0), -1),
         (dict(s=0), -1),
@@ -126,6 +129,17 @@ def test_null_arguments_are_rejected(lib):
     assert lib.lddmm_hessvec(None, None, None, None) == -1
     assert lib.lddmm_hessvec_newton(None, None, None, None) == -1
     assert lib.lddmm_gn_solve(None, None, None, None, None, 0) == -1
+    assert lib.lddmm_vjp(None, None, None) == -1
+    assert lib.lddmm_apply_operator(None, 0, 3, None, None) == -1
+    for st in (0, 1):
+        assert lib.lddmm_pde_energy(None, st, None, None, None) == -1
+        assert lib.lddmm_pde_gradient(None, st, None, None, None) == -1
+        assert lib.lddmm_pde_hessvec(None, st, None, None, None) == -1
+        assert lib.lddmm_pde_gn_solve(None, st, None, None, None, None, 0) == -1
+        assert lib.lddmm_pde_displacement(None, st, None, None) == -1
+    assert lib.lddmm_batch_create(None, 0, None) == -1
+    assert lib.lddmm_batch_gn_solve(None, None, None, None, 0) == -1
+    assert lib.lddmm_batch_hessvec(None, None, None, 1, 0) == -1
 
 
 def test_strerror(lib):

@@ -242,6 +242,33 @@ def test_operator_single_modes_closed_form(dtype):
         assert rel(R.apply_K(T(f, dtype)), f / lam) <= TOL[dtype]["op"]
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("s", [1, 3])
+def test_symbol_exponents_on_compile_time_kernels(dtype, s):
+    """Exponents other than the usual s = 2 (the symbol's power loop instead of
+    one square) on a grid whose transforms take the compile-time kernels: K, L,
+    the gradient and the Gauss-Newton product against the oracle."""
+    n = (32, 32, 32)
+    R, p = make(n, dtype, alpha=0.02, s=s, sigma2=0.05)
+    f = rounded(random_field(n, 1, kc=8.0), dtype)
+    Lf = O.apply_L(f, p)
+    eK = rel(R.apply_K(T(f, dtype)), O.apply_K(f, p))
+    eL = rel(R.apply_L(T(f, dtype)), Lf)
+    I0, I1 = images(n)
+    R.set_images(T(I0, dtype), T(I1, dtype))
+    v0 = random_velocity(n, 2002, 1.0, kc=2.0)
+    dv = random_field(n, 5, kc=3.0)
+    g, _ = R.gradient(T(v0, dtype))
+    hv = R.hessvec(T(dv, dtype))
+    go, lin = O.gradient(v0, I0, I1, p)
+    errs = dict(K=eK, L=eL, grad=rel(g, go), hv=rel(hv, O.hessvec(dv, lin, p)))
+    say(f"  s={s} static={R.get_option('fft.static_kernels')}", {k: f"{e:.2e}" for k, e in errs.items()})
+    assert R.get_option("fft.static_kernels") > 0
+    assert eK <= TOL[dtype]["op"] and eL <= l_tol(p, f, Lf, dtype)
+    assert errs["grad"] <= TOL[dtype]["grad"] and errs["hv"] <= TOL[dtype]["hv"]
+    R.close()
+
+
 # ------------------------------------------------------------------ FP64 dots
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_dot_parity(dtype):
