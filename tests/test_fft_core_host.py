@@ -11,8 +11,8 @@ import pytest
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SIZES = [2, 3, 4, 5, 7, 8, 9, 16, 18, 27, 30, 32, 40, 45, 48, 56, 63, 64, 72, 81, 90, 105, 108, 128, 135, 180, 216,
-         243, 256, 384, 512, 648, 1024, 2048]
+SIZES = [2, 3, 4, 5, 7, 8, 9, 16, 18, 27, 30, 32, 40, 45, 48, 56, 60, 63, 64, 72, 80, 81, 84, 90, 96, 105, 108, 112,
+         120, 128, 135, 160, 180, 192, 216, 240, 243, 256, 336, 384, 512, 648, 1024, 2048]
 
 
 @pytest.fixture(scope="module")
