@@ -20,7 +20,7 @@ def test_more_than_one_gpu_is_refused(n):
     assert "one GPU" in (r.stdout + r.stderr)
 
 
-def test_floor_bytes_follow_the_survey_model():
+def test_floor_bytes_follow_the_compulsory_traffic_model():
     """32 V nt per Hessian-vector product (V = one vector field): 8.05 GB at 128^3,
     nt = 10, FP32; 4 V per stage launch; 4 V / 3 per transform pass."""
     import bench
