@@ -127,6 +127,17 @@ def test_batch_uneven_sizes_matches_single_contexts(dtype):
         B.hessvec(dvs, hvs, reps=2, mode=mode)
         for i in range(len(sizes)):
             assert torch.equal(hvs[i], B.contexts[i].hessvec(dvs[i])), (mode, i)
+    # one pair of the batch against the oracle: the solve's final v0 and the
+    # batched Hessian-vector product at that v0
+    k = len(sizes) - 1
+    p = O.Params(sizes[k], 0.01, 2, 4, 0.02)
+    vo, _, _ = O.gn_solve(data[k][0], data[k][1], p, gn_iters=3, cg_iters=5)
+    ho = O.hessvec(random_field(sizes[k], 30 + k, kc=2.0), O.linearize(vo, data[k][0], data[k][1], p), p)
+    ev = float((v_batch[k].double().cpu() - torch.from_numpy(vo)).norm() / torch.from_numpy(vo).norm())
+    eh = float((hvs[k].double().cpu() - torch.from_numpy(ho)).norm() / torch.from_numpy(ho).norm())
+    say(f"  pair {k} {sizes[k]} vs oracle: v0 {ev:.2e}, Hv {eh:.2e}")
+    tol = 1e-9 if dtype == torch.float64 else 1e-4
+    assert ev <= tol and eh <= tol
     B.close()
 
 
