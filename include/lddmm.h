@@ -194,8 +194,11 @@ int lddmm_hessvec(lddmm_ctx* ctx, const void* v0, const void* dv, void* hv);
 int lddmm_hessvec_newton(lddmm_ctx* ctx, const void* v0, const void* dv, void* hv);
 
 /* Backward of J_1 w.r.t. v0 at the current linearization for a plain-array
- * cotangent gbar = dl/dJ_1 (scalar field): gbar_v0 = L w_0 with
- * U^(1) = -gbar grad J_1 (the quadrature weights of the pairing cancel). */
+ * cotangent gbar = dl/dJ_1 (scalar field): the adjoint Jacobi sweep of Section 2.2
+ * (the one behind the gradient of Section 3) run as a vector-Jacobian product,
+ * with the data term's final condition replaced by U^(1) = -gbar grad J_1;
+ * gbar_v0 = L w_0 (the quadrature weights of the pairing cancel).  Layouts as
+ * lddmm_gradient; LDDMM_ESTATE without a linearization. */
 int lddmm_vjp(lddmm_ctx* ctx, const void* gbar_J1, void* gbar_v0);
 
 /* CG in V for H x = -g at the current linearization (Section 2.3 reduced
