@@ -9,6 +9,12 @@
   in the autotuned launch configuration the benchmark times; the relative L2
   error of each result against the oracle is printed and bounded by 1e-5
   (shooting outputs) and 1e-4 (gradient, Hv) in FP32, 1e-11 in FP64.
+* 180x216x180 head workload (three shells, 40 tissue-class blobs, alpha =
+  0.0025, s = 2) at its full grid in its autotuned launch configuration, with
+  nt = 2 and a v0 of 2 voxels (one voxel per step, as the workload's 8 voxels
+  over nt = 16 take half a voxel; nt = 2 still runs the first-stage and the
+  regular kernel variants of both sweeps and keeps the host oracle near a
+  minute): the same results and bounds.
 """
 
 import numpy as np
@@ -107,6 +113,57 @@ def test_full_size_nonzero_v0_vs_oracle(full_oracle, dtype):
     R = Registration(FULL, spec.nt, spec.alpha, spec.s, spec.sigma2, dtype=dtype)
     R.set_images(T(o["I0"], dtype), T(o["I1"], dtype))
     R.autotune(reps=5)
+    R.set_option("exec.graph", 0)
+    tv = T(o["v0"], dtype)
+    sh = R.shoot(tv, energy=True)
+    g, E = R.gradient(tv)
+    hv = R.hessvec(T(o["dv"], dtype))
+    errs = dict(J1=rel(sh["J1"], o["J1"]), u1=rel(sh["u1"], o["u1"]), v1=rel(sh["v1"], o["v1"]),
+                gradient=rel(g, o["g"]), hessvec=rel(hv, o["hv"]), energy=abs(E - o["E"]) / abs(o["E"]))
+    say("  rel-L2 vs FP64 oracle:", {k: f"{v:.2e}" for k, v in errs.items()})
+    if dtype == torch.float32:
+        tol = dict(J1=1e-5, u1=1e-5, v1=1e-5, gradient=1e-4, hessvec=1e-4, energy=1e-5)
+    else:
+        tol = dict(J1=1e-11, u1=1e-11, v1=1e-11, gradient=1e-11, hessvec=1e-11, energy=1e-12)
+    for k, e in errs.items():
+        assert e <= tol[k], (k, e, tol[k])
+    R.close()
+
+
+# ------------------------------------------------------------------ 180x216x180, nt = 2, nonzero v0
+HEAD = (180, 216, 180)
+
+
+@pytest.fixture(scope="module")
+def head_oracle():
+    spec = synth.WORKLOADS["head180x216x180"]
+    p = O.Params(HEAD, spec.alpha, spec.s, 2, spec.sigma2)
+    I0 = phantom(HEAD, spec.n_blobs, spec.sigma_range, spec.classes, 1000, shells=spec.shells)
+    I1 = phantom(HEAD, spec.n_blobs, spec.sigma_range, spec.classes, 1001, shells=spec.shells)
+    v0 = random_velocity(HEAD, 2000, 2.0)
+    dv = random_field(HEAD, 12)
+    say("[case] oracle at 180x216x180, nt=2: linearization")
+    lin = O.linearize(v0, I0, I1, p)
+    say("[case] oracle at 180x216x180, nt=2: gradient")
+    g, _ = O.gradient(v0, I0, I1, p, lin)
+    say("[case] oracle at 180x216x180, nt=2: Hv")
+    hv = O.hessvec(dv, lin, p)
+    return dict(spec=spec, p=p, I0=I0, I1=I1, v0=v0, dv=dv, J1=lin.tr.J1, u1=lin.tr.u, v1=lin.tr.v[-1], E=lin.E,
+                g=g, hv=hv)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_head_grid_nonzero_v0_vs_oracle(head_oracle, dtype):
+    from paper_1807_04638_amd import Registration
+
+    o = head_oracle
+    p = o["p"]
+    say(f"[case] 180x216x180 nt=2 nonzero v0, {dtype}")
+    R = Registration(HEAD, p.nt, p.alpha, p.s, p.sigma2, dtype=dtype)
+    R.set_images(T(o["I0"], dtype), T(o["I1"], dtype))
+    R.autotune(reps=3)
+    say("  shape", {k: R.get_option(k) for k in ("fft.plane_threads", "fft.plane_halves_used", "fft.pencil_tb",
+                                                  "stencil.rowvec", "stencil.pair_rows")})
     R.set_option("exec.graph", 0)
     tv = T(o["v0"], dtype)
     sh = R.shoot(tv, energy=True)
