@@ -15,6 +15,12 @@
   over nt = 16 take half a voxel; nt = 2 still runs the first-stage and the
   regular kernel variants of both sweeps and keeps the host oracle near a
   minute): the same results and bounds.
+* 256^3 memory workload (48 tissue-class blobs, alpha = 0.0025, s = 2) at its
+  full grid in the launch configuration its benchmark times (the default shape:
+  half-plane units in FP32, the split transform in FP64), with nt = 3 and a v0
+  of 3 voxels: the same results and bounds, in FP32 under each trajectory
+  policy (store-all, checkpoints every 2 steps with a ragged last segment, full
+  recompute; bitwise the same Hv and gradient) and in FP64.
 """
 
 import numpy as np
@@ -179,3 +185,58 @@ def test_head_grid_nonzero_v0_vs_oracle(head_oracle, dtype):
     for k, e in errs.items():
         assert e <= tol[k], (k, e, tol[k])
     R.close()
+
+
+# ------------------------------------------------------------------ 256^3, nt = 3, trajectory policies
+BIG = (256, 256, 256)
+
+
+@pytest.fixture(scope="module")
+def big_oracle():
+    spec = synth.WORKLOADS["pair256"]
+    p = O.Params(BIG, spec.alpha, spec.s, 3, spec.sigma2)
+    I0 = phantom(BIG, spec.n_blobs, spec.sigma_range, spec.classes, 1000, shells=spec.shells)
+    I1 = phantom(BIG, spec.n_blobs, spec.sigma_range, spec.classes, 1001, shells=spec.shells)
+    v0 = random_velocity(BIG, 2000, 3.0)
+    dv = random_field(BIG, 12)
+    say("[case] oracle at 256^3, nt=3: linearization")
+    lin = O.linearize(v0, I0, I1, p)
+    say("[case] oracle at 256^3, nt=3: gradient")
+    g, _ = O.gradient(v0, I0, I1, p, lin)
+    say("[case] oracle at 256^3, nt=3: Hv")
+    hv = O.hessvec(dv, lin, p)
+    return dict(p=p, I0=I0, I1=I1, v0=v0, dv=dv, J1=lin.tr.J1, u1=lin.tr.u, v1=lin.tr.v[-1], E=lin.E, g=g, hv=hv)
+
+
+def test_pair256_policies_vs_oracle(big_oracle):
+    from paper_1807_04638_amd import Registration
+
+    o = big_oracle
+    p = o["p"]
+    tol32 = dict(J1=1e-5, u1=1e-5, v1=1e-5, gradient=1e-4, hessvec=1e-4, energy=1e-5)
+    tol64 = dict(J1=1e-11, u1=1e-11, v1=1e-11, gradient=1e-11, hessvec=1e-11, energy=1e-12)
+    first = None
+    for dtype, every in ((torch.float32, 0), (torch.float32, 2), (torch.float32, -1), (torch.float64, 0)):
+        say(f"[case] 256^3 nt=3 nonzero v0, {dtype}, checkpoint_every={every}")
+        R = Registration(BIG, p.nt, p.alpha, p.s, p.sigma2, dtype=dtype, checkpoint_every=every)
+        R.set_images(T(o["I0"], dtype), T(o["I1"], dtype))
+        say("  shape", {k: R.get_option(k) for k in ("fft.fused", "fft.plane_halves_used", "stencil.rowvec",
+                                                      "stencil.pair_rows")}, "traj bytes", R.get_option("traj.bytes"))
+        tv = T(o["v0"], dtype)
+        sh = R.shoot(tv, energy=True)
+        g, E = R.gradient(tv)
+        hv = R.hessvec(T(o["dv"], dtype))
+        errs = dict(J1=rel(sh["J1"], o["J1"]), u1=rel(sh["u1"], o["u1"]), v1=rel(sh["v1"], o["v1"]),
+                    gradient=rel(g, o["g"]), hessvec=rel(hv, o["hv"]), energy=abs(E - o["E"]) / abs(o["E"]))
+        say("  rel-L2 vs FP64 oracle:", {k: f"{v:.2e}" for k, v in errs.items()})
+        tol = tol32 if dtype == torch.float32 else tol64
+        for k, e in errs.items():
+            assert e <= tol[k], (k, e, tol[k])
+        if dtype == torch.float32:
+            if first is None:
+                first = (g.clone(), hv.clone())
+            else:  # the trajectory policy changes what is stored, not what is computed
+                assert torch.equal(g, first[0]) and torch.equal(hv, first[1])
+        R.close()
+        del R, sh, g, hv, tv
+        torch.cuda.empty_cache()
