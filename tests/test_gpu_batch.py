@@ -200,3 +200,49 @@ def test_batch_results_are_complete_on_return():
         for i in range(len(sizes)):
             assert torch.equal(vs[i], refs[i]), (mode, i)
     B.close()
+
+
+def test_batch16_workload_lockstep_hv():
+    """The 16-pair workload itself (N drawn from {64, 80, 96, 112, 128} with
+    seed 4000, the phantom recipe scaled by N/128, targets shot in FP64 from a
+    velocity of 6 N/128 voxels, alpha = 0.0025, s = 2, nt = 10, FP32, the
+    batch autotuned as its benchmark does): at a nonzero v0 per pair, the
+    lockstep Hessian-vector products of all pairs are bitwise those of each
+    context alone, and the 112^3 pair's (radix 7) is within 1e-4 of the FP64
+    oracle."""
+    from paper_1807_04638_amd import Batch, Registration
+
+    rng = np.random.default_rng(4000)
+    sizes = [int(x) for x in rng.choice([64, 80, 96, 112, 128], size=16)]
+    specs, imgs, vlin = [], [], []
+    for i, N in enumerate(sizes):
+        f, n = N / 128.0, (N, N, N)
+        I0 = phantom(n, 24, (4.0 * f, 12.0 * f), True, 1000 + i)
+        v0 = random_velocity(n, 2000 + i, 6.0 * f)
+        R = Registration(n, 10, 0.0025, 2, 1.0, dtype=torch.float64)
+        R.set_images(T(I0, torch.float64), T(I0, torch.float64))
+        I1 = R.shoot(T(v0, torch.float64), want=("J1",))["J1"].cpu().numpy()
+        R.close()
+        specs.append(dict(n=n, nt=10, alpha=0.0025, s=2, sigma2=1.0))
+        imgs.append((I0, I1))
+        vlin.append(0.5 * v0)
+    say(f"[case] batch16 workload, sizes {sizes}")
+    B = Batch(specs, dtype=torch.float32)
+    for i, (I0, I1) in enumerate(imgs):
+        B.contexts[i].set_images(T(I0, torch.float32), T(I1, torch.float32))
+    B.autotune(reps=2)
+    for i in range(len(sizes)):
+        B.contexts[i].linearize(T(vlin[i], torch.float32))
+    dvs = [T(random_field(sp["n"], 60 + i), torch.float32) for i, sp in enumerate(specs)]
+    hvs = [torch.empty_like(d) for d in dvs]
+    B.hessvec(dvs, hvs, reps=2, mode="lockstep")
+    for i in range(len(sizes)):
+        assert torch.equal(hvs[i], B.contexts[i].hessvec(dvs[i])), i
+    k = sizes.index(112)
+    p = O.Params(specs[k]["n"], 0.0025, 2, 10, 1.0)
+    say(f"  oracle Hv of pair {k} (112^3)")
+    ho = O.hessvec(random_field(specs[k]["n"], 60 + k), O.linearize(vlin[k], imgs[k][0], imgs[k][1], p), p)
+    eh = float((hvs[k].double().cpu() - torch.from_numpy(ho)).norm() / torch.from_numpy(ho).norm())
+    say(f"  pair {k} (112^3) lockstep Hv vs oracle: {eh:.2e}")
+    assert eh <= 1e-4
+    B.close()
