@@ -422,7 +422,7 @@ def precision_bench(args, torch, synth, Registration, spec):
         "solve_s": {"fp32": round(a["s"], 3), "fp64": round(b["s"], 3)},
         "hv_ms": {"fp32": round(a["hv_ms"], 3), "fp64": round(b["hv_ms"], 3)},
         "fp32_speedup_vs_fp64": round(b["s"] / a["s"], 3),
-        "reference": "FP64 GPU path (oracle-pinned at small sizes)",
+        "reference": "FP64 GPU path (checked against the FP64 oracle on this grid at nt = 2 and on small grids)",
     }
     return line
 
