@@ -617,6 +617,12 @@ __device__ __forceinline__ PlaneLds<T> carve_static(unsigned char* smem, int row
 // next plane's first stage are loaded into registers while the current plane
 // is transformed and stored, so with fewer workgroups than planes the memory
 // phases of consecutive planes overlap inside one workgroup.
+// Runs of consecutive units each XCD takes (xcd_grouped): the two half planes
+// of a plane, which share the cache lines at their rows' ends, and 8 pencil
+// tiles, which share lines where an x0 plane of the spectrum is not a whole
+// number of lines (180 x 216 x 180: 9828 complex values).
+constexpr int kPlaneXcdRun = 2, kPencilXcdRun = 8;
+
 template <typename T, int H, int N1, int NT, bool WALK, int XS = 1>
 __global__ void __launch_bounds__(NT) k_plane_fwd_s(const T* __restrict__ in, cplx<T>* __restrict__ spec,
                                                     PlaneArgs<T> a) {
@@ -630,7 +636,9 @@ __global__ void __launch_bounds__(NT) k_plane_fwd_s(const T* __restrict__ in, cp
     const int comp = q / per_comp, r = q - comp * per_comp, x0 = r / XS, h = r - x0 * XS;
     return reinterpret_cast<const cplx<T>*>(in + comp * a.N + x0 * plane_len + h * 2 * H);
   };
-  int p = WALK ? int(blockIdx.x) : int(blockIdx.y) * per_comp + int(blockIdx.x);
+  // one unit per workgroup, the even and odd rows of a plane on one XCD
+  int p = WALK ? int(blockIdx.x)
+               : xcd_grouped(int(blockIdx.y) * per_comp + int(blockIdx.x), int(gridDim.x * gridDim.y), kPlaneXcdRun);
   // the first plane's row twiddles come from global memory: the LDS copy is
   // complete only after the first barrier
   const cplx<T>* tw_first = a.tw2;
@@ -773,7 +781,8 @@ __global__ void __launch_bounds__(NT) k_plane_inv_s(const cplx<T>* __restrict__ 
   PlaneLds<T> L = carve_static<T, H, N1>(smem, N1, a, true);
   const long long plane_len = (long long)N1 * XS * 2 * H;
   const int per_comp = a.n0 * XS;
-  int p = WALK ? int(blockIdx.x) : int(blockIdx.y) * per_comp + int(blockIdx.x);
+  int p = WALK ? int(blockIdx.x)
+               : xcd_grouped(int(blockIdx.y) * per_comp + int(blockIdx.x), int(gridDim.x * gridDim.y), kPlaneXcdRun);
   // first column stage straight from the spectrum, consecutive threads on
   // consecutive columns; one plane per workgroup loads and transforms in one go
   // (fewer live registers), the walk keeps the next plane's inputs in registers
@@ -869,7 +878,9 @@ __global__ void __launch_bounds__(NT) k_pencil_s(cplx<T>* __restrict__ spec, Pen
   T* ksq0 = reinterpret_cast<T*>(tw + N);
   T* ksq12 = ksq0 + N;
   for (int i = threadIdx.x; i < N; i += NT) tw[i] = a.tw[i];
-  const int q0 = blockIdx.x * TB;
+  // runs of neighbouring tiles on one XCD
+  const int lin = xcd_grouped(int(blockIdx.y * gridDim.x + blockIdx.x), int(gridDim.x * gridDim.y), kPencilXcdRun);
+  const int comp = lin / int(gridDim.x), q0 = (lin - comp * int(gridDim.x)) * TB;
   const int cnt = (a.nin - q0) < TB ? (a.nin - q0) : TB;
   if (MODE >= 2) {
     for (int i = threadIdx.x; i < N; i += NT) ksq0[i] = a.ksq0[i];
@@ -881,7 +892,7 @@ __global__ void __launch_bounds__(NT) k_pencil_s(cplx<T>* __restrict__ spec, Pen
     }
   }
   const int t = int(threadIdx.x) % TB;
-  cplx<T>* base = spec + blockIdx.y * a.outer_stride + q0;
+  cplx<T>* base = spec + comp * a.outer_stride + q0;
   const bool live = t < cnt;
   constexpr int R0 = PN::radix(0), S0 = N / R0;  // first DIF / last DIT stage
   constexpr int total0 = TB * S0;

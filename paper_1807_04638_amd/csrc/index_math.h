@@ -4,6 +4,8 @@
 //   field_tiling / tile_voxel_at   voxel tiling of the stencil and SL kernels
 //                                  (XCD-aware order of the x1 tiles)
 //   periodic_next / periodic_prev  neighbours on the periodic grid
+//   xcd_grouped                    unit of a block so that each XCD takes runs
+//                                  of consecutive units
 //   row_lanes                      x2 neighbours inside a row of lanes of the
 //                                  row-vectorised stencils
 //   sl_axis                        cell and weight of a displaced point along one
@@ -81,6 +83,20 @@ LDI_HD bool tile_voxel_at(const FieldTiling& t, int b, int tx, int ty, int n1, i
   i2 = bx * t.BX + tx;
   i1 = by * t.BY + ty;
   return own && i2 < n2 && i1 < n1;
+}
+
+// Unit of block b (of B) such that each XCD takes runs of g consecutive units:
+// blocks go to the 8 XCDs round-robin (block b to XCD b mod 8), so within each
+// span of 8 g blocks XCD x gets units [x g, x g + g) of the span, in order; a
+// last span of fewer than 8 g blocks keeps unit = block.  Units next to each
+// other in memory then share an L2 (a cache line split between two of them is
+// fetched once), while the units in flight stay as close together as in
+// round-robin order.
+LDI_HD int xcd_grouped(int b, int B, int g) {
+  const int span = 8 * g, s = b / span;
+  if ((s + 1) * span > B) return b;
+  const int r = b - s * span;
+  return s * span + (r & 7) * g + (r >> 3);
 }
 
 LDI_HD int periodic_next(int i, int n) { return i + 1 == n ? 0 : i + 1; }

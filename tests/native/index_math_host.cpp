@@ -7,6 +7,7 @@
 // checks passed; the last line names the number of checks.
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <limits>
@@ -113,6 +114,26 @@ void check_row_lanes(int n0, int n1, int RW) {
       const int lane = tid & 63, pos = lane - lane / seg * seg;
       expect(pos == j, "lane position = x2 lane index", lane, j);
     }
+}
+
+// XCD-grouped units: a bijection of [0, B); in every whole span of 8 g blocks
+// each XCD (block b mod 8) takes g consecutive units in the order of its
+// blocks; a last partial span keeps unit = block.
+void check_xcd_grouped(int B, int g) {
+  std::vector<int> seen(B, 0), xcd(B, -1);
+  for (int b = 0; b < B; ++b) {
+    const int u = xcd_grouped(b, B, g);
+    expect(u >= 0 && u < B, "unit in range", 100LL * B + g, b, u);
+    if (u < 0 || u >= B) continue;
+    ++seen[u];
+    xcd[u] = b & 7;
+    if (b >= 8 && u >= 1 && (b / (8 * g) + 1) * 8 * g <= B && (b / 8) % g != 0)
+      expect(xcd_grouped(b - 8, B, g) == u - 1, "an XCD's units consecutive in block order", 100LL * B + g, b, u);
+  }
+  for (int u = 0; u < B; ++u) expect(seen[u] == 1, "every unit exactly once", B, g, u);
+  const int whole = B / (8 * g) * 8 * g;
+  for (int u = 0; u + 1 < whole; ++u)
+    if ((u + 1) % g != 0) expect(xcd[u] == xcd[u + 1], "units of a run on one XCD", B, g, u);
 }
 
 void check_periodic(int n) {
@@ -280,6 +301,9 @@ int main() {
     }
   }
   for (int n : {4, 5, 6, 7, 8, 12, 64, 128, 180, 216, 256, 512}) check_periodic(n);
+  // unit counts of the transform launches: planes and half planes, pencil tiles
+  for (int B : {1, 3, 7, 8, 9, 15, 16, 17, 384, 768, 780, 1080, 1083, 1536, 2457, 4096, 4113})
+    for (int g : {1, 2, 4, 8}) check_xcd_grouped(B, g);
   for (int n : {4, 5, 7, 20, 64, 128, 180, 216, 256}) {
     check_sl_axis<float>(n, rng);
     check_sl_axis<double>(n, rng);
