@@ -121,7 +121,8 @@ TUNED_KEYS = (
     "stencil.pair_rows",
 )
 KERNEL_SOURCES = {
-    "fft": ("paper_1807_04638_amd/csrc/fft.hip", "paper_1807_04638_amd/csrc/fft_core.h"),
+    "fft": ("paper_1807_04638_amd/csrc/fft.hip", "paper_1807_04638_amd/csrc/fft_core.h",
+            "paper_1807_04638_amd/csrc/index_math.h"),
     "stencil": ("paper_1807_04638_amd/csrc/stencil.hip", "paper_1807_04638_amd/csrc/index_math.h"),
 }
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_pair128_fp32.md")
@@ -620,8 +621,8 @@ def main():
         type=int,
         default=0,
         metavar="K",
-        help="profiling mode: K Hessian-vector products at the workload's linearization, then "
-        "4 plain copies of 256 MiB (counter calibration), and exit",
+        help="profiling mode: K Hessian-vector products at the workload's linearization (pair128 or "
+        "head180x216x180), then 4 plain copies of 256 MiB (counter calibration), and exit",
     )
     args = ap.parse_args()
 
@@ -651,7 +652,7 @@ def main():
         print(json.dumps(table1_bench(args, torch, synth, Registration, synth.WORKLOADS["pair128"])), flush=True)
         return
     spec = synth.WORKLOADS[args.workload]
-    if args.workload == "head180x216x180":
+    if args.workload == "head180x216x180" and not args.profile_hv:
         print(json.dumps(precision_bench(args, torch, synth, Registration, spec)), flush=True)
         return
     if args.workload == "pair256":
