@@ -279,6 +279,12 @@ struct PencilArgs {
   const cplx<T>* twx;
 };
 
+// Runs of consecutive units each XCD takes (xcd_grouped): the two half planes
+// of a plane, which share the cache lines at their rows' ends, and 8 pencil
+// tiles, which share lines where an x0 plane of the spectrum is not a whole
+// number of lines (180 x 216 x 180: 9828 complex values).
+constexpr int kPlaneXcdRun = 2, kPencilXcdRun = 8;
+
 // MODE 0: forward only, 1: inverse only, 2: forward, symbol, inverse.
 template <typename T, int MODE, int NT>
 __global__ void __launch_bounds__(NT) k_pencil(cplx<T>* __restrict__ spec, PencilArgs<T> a) {
@@ -290,9 +296,11 @@ __global__ void __launch_bounds__(NT) k_pencil(cplx<T>* __restrict__ spec, Penci
   load_table(tw, a.tw, n);
   if (MODE == 2)
     for (int i = threadIdx.x; i < n; i += blockDim.x) ksq0[i] = a.ksq0[i];
-  const int q0 = blockIdx.x * tb;
+  // runs of neighbouring tiles on one XCD
+  const int lin = xcd_grouped(int(blockIdx.y * gridDim.x + blockIdx.x), int(gridDim.x * gridDim.y), kPencilXcdRun);
+  const int outer = lin / int(gridDim.x), q0 = (lin - outer * int(gridDim.x)) * tb;
   const int cnt = (a.nin - q0) < tb ? (a.nin - q0) : tb;
-  cplx<T>* base = spec + blockIdx.y * a.outer_stride + q0;
+  cplx<T>* base = spec + outer * a.outer_stride + q0;
   for (int idx = threadIdx.x; idx < n * tb; idx += blockDim.x) {
     const int j = idx / tb, t = idx - j * tb;
     A[idx] = t < cnt ? base[(long long)j * a.es + t] : cplx<T>{T(0), T(0)};
@@ -617,12 +625,6 @@ __device__ __forceinline__ PlaneLds<T> carve_static(unsigned char* smem, int row
 // next plane's first stage are loaded into registers while the current plane
 // is transformed and stored, so with fewer workgroups than planes the memory
 // phases of consecutive planes overlap inside one workgroup.
-// Runs of consecutive units each XCD takes (xcd_grouped): the two half planes
-// of a plane, which share the cache lines at their rows' ends, and 8 pencil
-// tiles, which share lines where an x0 plane of the spectrum is not a whole
-// number of lines (180 x 216 x 180: 9828 complex values).
-constexpr int kPlaneXcdRun = 2, kPencilXcdRun = 8;
-
 template <typename T, int H, int N1, int NT, bool WALK, int XS = 1>
 __global__ void __launch_bounds__(NT) k_plane_fwd_s(const T* __restrict__ in, cplx<T>* __restrict__ spec,
                                                     PlaneArgs<T> a) {
