@@ -328,9 +328,9 @@ int lddmm_get_option(lddmm_ctx* ctx, const char* key, int64_t* value);
  * (reps repetitions each; a transform shape is timed as a K application followed
  * by a tangent stage, the way the sweeps use it) and keep the fastest; the shape
  * in place when the call starts is kept unless another is more than 3 % faster
- * (1.5 % for "exec.branch_k", whose two graphs are replayed in turn three times
- * and compared by their fastest replay), so repeated calls settle on the same
- * shape.  *tried = variants timed,
+ * (0.5 % for "exec.branch_k", whose two graphs of at least 8 K applications are
+ * replayed in turn three times and compared by their fastest replay), so
+ * repeated calls settle on the same shape.  *tried = variants timed,
  * *ms_per_apply = one K application of a vector field with the chosen shape
  * (either may be NULL).  Synchronises. */
 int lddmm_autotune(lddmm_ctx* ctx, int reps, int* tried, double* ms_per_apply);
