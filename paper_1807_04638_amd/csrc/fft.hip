@@ -139,6 +139,7 @@ struct PlaneArgs {
   const int* slot2;
   const T* add;  // inverse pass with an addend: out = add + add_scale * (transform)
   T add_scale;
+  int xcd_run;   // units per XCD run (xcd_grouped); 1: round-robin order
 };
 
 // LDS carve-up shared by the plane and row kernels: A | tw1 | tw2 | twr | slot2
@@ -277,12 +278,15 @@ struct PencilArgs {
   int hs;
   int k1half;
   const cplx<T>* twx;
+  int xcd_run;  // tiles per XCD run (xcd_grouped); 1: round-robin order
 };
 
-// Runs of consecutive units each XCD takes (xcd_grouped): the two half planes
-// of a plane, which share the cache lines at their rows' ends, and 8 pencil
-// tiles, which share lines where an x0 plane of the spectrum is not a whole
-// number of lines (180 x 216 x 180: 9828 complex values).
+// Runs of consecutive units each XCD takes (xcd_grouped) where neighbouring
+// units share cache lines: the two half planes of a plane where a row is not a
+// whole number of 128-byte lines (180 FP32 values), and 8 pencil tiles where an
+// x0 plane of the spectrum is not (180 x 216 x 180: 9828 complex values).  On
+// aligned grids (128^3) the units keep the round-robin order, which measured
+// 1 % faster there.
 constexpr int kPlaneXcdRun = 2, kPencilXcdRun = 8;
 
 // MODE 0: forward only, 1: inverse only, 2: forward, symbol, inverse.
@@ -296,8 +300,10 @@ __global__ void __launch_bounds__(NT) k_pencil(cplx<T>* __restrict__ spec, Penci
   load_table(tw, a.tw, n);
   if (MODE == 2)
     for (int i = threadIdx.x; i < n; i += blockDim.x) ksq0[i] = a.ksq0[i];
-  // runs of neighbouring tiles on one XCD
-  const int lin = xcd_grouped(int(blockIdx.y * gridDim.x + blockIdx.x), int(gridDim.x * gridDim.y), kPencilXcdRun);
+  // runs of neighbouring tiles on one XCD where they share cache lines
+  const int lin = a.xcd_run > 1 ? xcd_grouped(int(blockIdx.y * gridDim.x + blockIdx.x), int(gridDim.x * gridDim.y),
+                                              a.xcd_run)
+                                : int(blockIdx.y * gridDim.x + blockIdx.x);
   const int outer = lin / int(gridDim.x), q0 = (lin - outer * int(gridDim.x)) * tb;
   const int cnt = (a.nin - q0) < tb ? (a.nin - q0) : tb;
   cplx<T>* base = spec + outer * a.outer_stride + q0;
@@ -638,9 +644,12 @@ __global__ void __launch_bounds__(NT) k_plane_fwd_s(const T* __restrict__ in, cp
     const int comp = q / per_comp, r = q - comp * per_comp, x0 = r / XS, h = r - x0 * XS;
     return reinterpret_cast<const cplx<T>*>(in + comp * a.N + x0 * plane_len + h * 2 * H);
   };
-  // one unit per workgroup, the even and odd rows of a plane on one XCD
-  int p = WALK ? int(blockIdx.x)
-               : xcd_grouped(int(blockIdx.y) * per_comp + int(blockIdx.x), int(gridDim.x * gridDim.y), kPlaneXcdRun);
+  // one unit per workgroup; where rows share cache lines, the even and odd rows
+  // of a plane on one XCD
+  int p = WALK              ? int(blockIdx.x)
+          : a.xcd_run > 1 ? xcd_grouped(int(blockIdx.y) * per_comp + int(blockIdx.x), int(gridDim.x * gridDim.y),
+                                        a.xcd_run)
+                            : int(blockIdx.y) * per_comp + int(blockIdx.x);
   // the first plane's row twiddles come from global memory: the LDS copy is
   // complete only after the first barrier
   const cplx<T>* tw_first = a.tw2;
@@ -783,8 +792,10 @@ __global__ void __launch_bounds__(NT) k_plane_inv_s(const cplx<T>* __restrict__ 
   PlaneLds<T> L = carve_static<T, H, N1>(smem, N1, a, true);
   const long long plane_len = (long long)N1 * XS * 2 * H;
   const int per_comp = a.n0 * XS;
-  int p = WALK ? int(blockIdx.x)
-               : xcd_grouped(int(blockIdx.y) * per_comp + int(blockIdx.x), int(gridDim.x * gridDim.y), kPlaneXcdRun);
+  int p = WALK              ? int(blockIdx.x)
+          : a.xcd_run > 1 ? xcd_grouped(int(blockIdx.y) * per_comp + int(blockIdx.x), int(gridDim.x * gridDim.y),
+                                        a.xcd_run)
+                            : int(blockIdx.y) * per_comp + int(blockIdx.x);
   // first column stage straight from the spectrum, consecutive threads on
   // consecutive columns; one plane per workgroup loads and transforms in one go
   // (fewer live registers), the walk keeps the next plane's inputs in registers
@@ -880,8 +891,10 @@ __global__ void __launch_bounds__(NT) k_pencil_s(cplx<T>* __restrict__ spec, Pen
   T* ksq0 = reinterpret_cast<T*>(tw + N);
   T* ksq12 = ksq0 + N;
   for (int i = threadIdx.x; i < N; i += NT) tw[i] = a.tw[i];
-  // runs of neighbouring tiles on one XCD
-  const int lin = xcd_grouped(int(blockIdx.y * gridDim.x + blockIdx.x), int(gridDim.x * gridDim.y), kPencilXcdRun);
+  // runs of neighbouring tiles on one XCD where they share cache lines
+  const int lin = a.xcd_run > 1 ? xcd_grouped(int(blockIdx.y * gridDim.x + blockIdx.x), int(gridDim.x * gridDim.y),
+                                              a.xcd_run)
+                                : int(blockIdx.y * gridDim.x + blockIdx.x);
   const int comp = lin / int(gridDim.x), q0 = (lin - comp * int(gridDim.x)) * TB;
   const int cnt = (a.nin - q0) < TB ? (a.nin - q0) : TB;
   if (MODE >= 2) {
@@ -1499,6 +1512,16 @@ void spectral_free(SpectralPlan<T>& sp) {
   sp = SpectralPlan<T>();
 }
 
+// Neighbouring pencil tiles share cache lines unless every tile's run starts on
+// a 128-byte line: then they take runs of kPencilXcdRun per XCD.
+template <typename T>
+int pencil_xcd_run(const PencilArgs<T>& k) {
+  const long long c = sizeof(cplx<T>);
+  const bool aligned = (k.tb * c) % 128 == 0 && (k.es * c) % 128 == 0 && (k.hs * c) % 128 == 0 &&
+                       (k.outer_stride * c) % 128 == 0;
+  return aligned ? 1 : kPencilXcdRun;
+}
+
 template <typename T>
 void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, double alpha, int s, int op,
                     hipStream_t st, Profiler* prof, const T* add, double add_scale, double out_scale) {
@@ -1518,6 +1541,8 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   pa.slot2 = sp.slot2;
   pa.add = add;
   pa.add_scale = T(add_scale);
+  // half planes share the cache line at a row's end unless rows are whole lines
+  pa.xcd_run = (sp.halves && (sp.n2 * sizeof(T)) % 128 != 0) ? kPlaneXcdRun : 1;
   const FftTuning& tu = sp.tune;
 
   const int P = sp.n1 * sp.M;
@@ -1553,6 +1578,7 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
     k0.twx = sp.twx;
     g0 = dim3((pairs + tbp - 1) / tbp, ncomp);
   }
+  k0.xcd_run = pencil_xcd_run(k0);
   const PencilFn<T> pencil0 = (PencilFn<T>)sp.kfn[KF_PENCIL0];
 
   if (sp.fused) {
@@ -1586,6 +1612,7 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   k1.nin = sp.M;
   k1.outer_stride = (long long)sp.n1 * sp.M;
   k1.tw = sp.tw1;
+  k1.xcd_run = pencil_xcd_run(k1);
   const dim3 g1((sp.M + tu.pencil_tb - 1) / tu.pencil_tb, ncomp * sp.n0);
   const long long rows = (long long)sp.n0 * sp.n1;
   const dim3 gr((unsigned)((rows + tu.rows_rb - 1) / tu.rows_rb), ncomp);
