@@ -1517,9 +1517,7 @@ void spectral_free(SpectralPlan<T>& sp) {
 template <typename T>
 int pencil_xcd_run(const PencilArgs<T>& k) {
   const long long c = sizeof(cplx<T>);
-  const bool aligned = (k.tb * c) % 128 == 0 && (k.es * c) % 128 == 0 && (k.hs * c) % 128 == 0 &&
-                       (k.outer_stride * c) % 128 == 0;
-  return aligned ? 1 : kPencilXcdRun;
+  return xcd_run_if_split(k.tb * c, k.es * c, k.hs * c, k.outer_stride * c, kPencilXcdRun);
 }
 
 template <typename T>
@@ -1542,7 +1540,7 @@ void spectral_apply(const SpectralPlan<T>& sp, const T* in, T* out, int ncomp, d
   pa.add = add;
   pa.add_scale = T(add_scale);
   // half planes share the cache line at a row's end unless rows are whole lines
-  pa.xcd_run = (sp.halves && (sp.n2 * sizeof(T)) % 128 != 0) ? kPlaneXcdRun : 1;
+  pa.xcd_run = sp.halves ? xcd_run_if_split((long long)sp.n2 * sizeof(T), 0, 0, 0, kPlaneXcdRun) : 1;
   const FftTuning& tu = sp.tune;
 
   const int P = sp.n1 * sp.M;

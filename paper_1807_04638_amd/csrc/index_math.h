@@ -4,8 +4,8 @@
 //   field_tiling / tile_voxel_at   voxel tiling of the stencil and SL kernels
 //                                  (XCD-aware order of the x1 tiles)
 //   periodic_next / periodic_prev  neighbours on the periodic grid
-//   xcd_grouped                    unit of a block so that each XCD takes runs
-//                                  of consecutive units
+//   xcd_grouped, xcd_run_if_split  unit of a block so that each XCD takes runs
+//                                  of consecutive units that share cache lines
 //   row_lanes                      x2 neighbours inside a row of lanes of the
 //                                  row-vectorised stencils
 //   sl_axis                        cell and weight of a displaced point along one
@@ -97,6 +97,14 @@ LDI_HD int xcd_grouped(int b, int B, int g) {
   if ((s + 1) * span > B) return b;
   const int r = b - s * span;
   return s * span + (r & 7) * g + (r >> 3);
+}
+
+// Host: run length for xcd_grouped.  Units share a 128-byte cache line with
+// their neighbours unless every byte offset and stride that places them (a row,
+// a tile, a plane of the spectrum) is a whole number of lines: then `run`, else
+// 1 (round-robin order).
+inline int xcd_run_if_split(long long a, long long b, long long c, long long d, int run) {
+  return (a % 128 == 0 && b % 128 == 0 && c % 128 == 0 && d % 128 == 0) ? 1 : run;
 }
 
 LDI_HD int periodic_next(int i, int n) { return i + 1 == n ? 0 : i + 1; }

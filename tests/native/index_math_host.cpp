@@ -136,6 +136,34 @@ void check_xcd_grouped(int B, int g) {
     if ((u + 1) % g != 0) expect(xcd[u] == xcd[u + 1], "units of a run on one XCD", B, g, u);
 }
 
+// Run lengths of the transform passes from their alignment: rows of N2 reals
+// (plane passes), and the pencil pass's tile, x0-plane, half and component
+// strides in complex values (half planes: tiles of TB pairs, x0 stride N1 M,
+// halves N1 M / 2 apart, components N0 N1 M apart, M = N2 / 2 + 1).
+void check_xcd_runs() {
+  struct Case {
+    int n0, n1, n2, esize, tb, plane_run, pencil_run;
+  };
+  const Case cases[] = {
+      {128, 128, 128, 4, 16, 1, 1},  // 512-byte rows, 4160-value halves: aligned
+      {128, 128, 128, 8, 8, 1, 1},
+      {256, 256, 256, 4, 16, 1, 1},
+      {180, 216, 180, 4, 16, 2, 8},  // 720-byte rows, 9828-value halves
+      {180, 216, 180, 8, 8, 2, 8},
+      {96, 96, 96, 4, 16, 1, 1},     // 384-byte rows, 2352-value halves
+      {80, 80, 80, 4, 16, 2, 8},     // 320-byte rows, 1640-value halves
+      {112, 112, 112, 4, 16, 2, 8},
+      {128, 128, 128, 4, 4, 1, 8},   // tiles of 4 pairs: 32-byte runs share lines
+  };
+  for (const Case& c : cases) {
+    const long long M = c.n2 / 2 + 1, cs = 2LL * c.esize, P = (long long)c.n1 * M;
+    const int plane = xcd_run_if_split((long long)c.n2 * c.esize, 0, 0, 0, 2);
+    const int pencil = xcd_run_if_split(c.tb * cs, P * cs, P / 2 * cs, (long long)c.n0 * P * cs, 8);
+    expect(plane == c.plane_run, "plane pass run length", c.n2, c.esize, plane);
+    expect(pencil == c.pencil_run, "pencil pass run length", c.n1 * 1000LL + c.n2, c.tb, pencil);
+  }
+}
+
 void check_periodic(int n) {
   for (int i = 0; i < n; ++i) {
     const int p = periodic_next(i, n), m = periodic_prev(i, n);
@@ -304,6 +332,7 @@ int main() {
   // unit counts of the transform launches: planes and half planes, pencil tiles
   for (int B : {1, 3, 7, 8, 9, 15, 16, 17, 384, 768, 780, 1080, 1083, 1536, 2457, 4096, 4113})
     for (int g : {1, 2, 4, 8}) check_xcd_grouped(B, g);
+  check_xcd_runs();
   for (int n : {4, 5, 7, 20, 64, 128, 180, 216, 256}) {
     check_sl_axis<float>(n, rng);
     check_sl_axis<double>(n, rng);
